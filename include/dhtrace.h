@@ -1,0 +1,228 @@
+/*
+ * dhtrace: deflated Hutchinson / hierarchical-probing estimation of Tr(D^-1)
+ * for the Wilson-Dirac matrix on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gambhir, Stathopoulos and Orginos, "Deflation as a Method of
+ * Variance Reduction for Estimating the Trace of a Matrix Inverse"
+ * (arXiv:1603.05988), Algorithm 1 ("deflatedHP").  Each probe z is Z4 noise
+ * (Section 1) or a Z4 base vector times a hierarchical-probing Hadamard
+ * vector (Section 5.2); the library solves D y = z, forms z^H y, subtracts the
+ * deflated quadrature z^H P z with P = W M W^H g5 built from eigenvectors W of
+ * Q = g5 D (Section 5.2's z^H V Lambda^-1 V^H (A^H z) in g5 form), and keeps
+ * the running trace T_R / j + T_D with its sample variances.
+ *
+ * Conventions (all entry points):
+ *  - Lattice L = {Lx, Ly, Lz, Lt}, every extent even; site
+ *    n = x + Lx (y + Ly (z + Lz t)); V = Lx Ly Lz Lt; N = 12 V.
+ *  - Canonical spinor: complex128 (interleaved re, im doubles), layout
+ *    [rhs][t][z][y][x][spin 4][colour 3]; rhs stride N complex.
+ *  - Canonical links: complex128 [4][t][z][y][x][3][3], direction 0..3 =
+ *    x, y, z, t; U_mu(x) couples x to x + mu-hat.
+ *  - Operator: D psi(x) = (4+m) psi(x) - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu)
+ *    + (1 + g_mu) U_mu(x-mu)^H psi(x-mu)], -1 on hops across the t boundary
+ *    if t_antiperiodic; chiral basis with g5 = diag(1, 1, -1, -1).
+ *  - Pointers named *_dev are device pointers on the context's device; all
+ *    other pointers are host pointers.  The caller owns every buffer it
+ *    passes; the library never frees caller memory and keeps no pointer to it
+ *    after the call returns.  The library owns its internal copies (links in
+ *    three precisions, the deflation basis, solver workspace), allocated with
+ *    hipMalloc on first use and released by dht_destroy.
+ *  - Streams: all device work is enqueued on the stream given to dht_create.
+ *    Calls that return host values synchronise that stream before returning.
+ *  - Errors: every int-returning call returns DHT_OK (0) or a negative code;
+ *    dht_last_error() gives a message for the calling thread.  No C++
+ *    exception crosses the interface.
+ *  - Threads: a context must not be used by two threads at once.
+ */
+#ifndef DHTRACE_H
+#define DHTRACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dht_ctx dht_ctx;
+
+enum {
+    DHT_OK = 0,
+    DHT_ERR_INVALID_ARG = -1,
+    DHT_ERR_HIP = -2,
+    DHT_ERR_OOM = -3,
+    DHT_ERR_STATE = -4,        /* call order violated (e.g. no gauge field yet)  */
+    DHT_ERR_BREAKDOWN = -5,    /* Krylov breakdown that no fallback could repair */
+    DHT_ERR_NOT_CONVERGED = -6 /* some right-hand side missed the tolerance      */
+};
+
+/* Storage precision of fields on the device.  FP32 and BF16 accumulate in FP32. */
+typedef enum { DHT_FP64 = 0, DHT_FP32 = 1, DHT_BF16 = 2 } dht_prec;
+
+/* Operators for dht_apply: D, D^H = g5 D g5, g5, and the Hermitian Q = g5 D. */
+typedef enum { DHT_OP_D = 0, DHT_OP_DDAG = 1, DHT_OP_G5 = 2, DHT_OP_Q = 3 } dht_op;
+
+typedef struct {
+    int L[4];            /* Lx, Ly, Lz, Lt: each even and >= 2                */
+    double mass;         /* bare mass m; the diagonal is 4 + m (must be != 0) */
+    int t_antiperiodic;  /* 1: -1 phase on hops across the t boundary         */
+} dht_lattice;
+
+/* Probe vectors (Algorithm 1, lines 3, 5, 6).
+ * hp = 0: plain Z4 noise, a fresh vector per probe index j.
+ * hp = 1: one Z4 base vector z0 per (seed, run), times the hierarchical-
+ *         probing Hadamard vector h_j; probe indices j < 2^63.
+ * Noise index generator: SplitMix64 (Steele, Lea, Flood 2014).  With
+ * out(s, i) = mix(s + (i+1) * 0x9E3779B97F4A7C15):  K_run = out(seed, run);
+ * key = K_run (hp) or out(K_run, j) (plain); component n takes the 2 bits at
+ * 2 (n mod 32) of out(key, n / 32), value k -> i^k.  HP colour of a site:
+ * for level l, bit 4l = parity of sum_mu floor(x_mu / 2^l), bits 4l+1..4l+3 =
+ * floor(x_mu / 2^l) mod 2 for mu = x, y, z; h_j(x) = (-1)^popcount(c(x) & j). */
+typedef struct {
+    uint64_t seed;
+    uint64_t run;
+    int hp;
+} dht_probe_spec;
+
+/* Solver methods (the paper leaves the linear solver open: Algorithm 1, "Solve Ay = z"). */
+enum {
+    DHT_SOLVER_BICGSTAB_FP64 = 0, /* plain FP64 BiCGStab on the even/odd Schur system          */
+    DHT_SOLVER_DC_BICGSTAB = 1,   /* FP64 defect correction around an FP32/BF16 BiCGStab      */
+    DHT_SOLVER_DC_FGMRES_NN = 2   /* FP64 defect correction around FGMRES with the learned
+                                     preconditioner (falls back to DC_BICGSTAB)               */
+};
+
+enum { /* dht_solve_stats.status */
+    DHT_STATUS_CONVERGED = 0,
+    DHT_STATUS_NOT_CONVERGED = 1,
+    DHT_STATUS_FALLBACK_FP32 = 2, /* converged after escalating the inner precision  */
+    DHT_STATUS_FALLBACK_FP64 = 3  /* converged on the plain FP64 BiCGStab fallback    */
+};
+
+typedef struct {
+    int method;        /* DHT_SOLVER_*                                          */
+    int inner;         /* dht_prec of the inner solve (DC methods)              */
+    double tol;        /* target relative true residual ||z - D x|| / ||z||     */
+    int maxiter;       /* cap on inner iterations summed over outer cycles      */
+    int restart;       /* FGMRES restart length (<= 64)                         */
+    double inner_tol;  /* relative reduction per inner solve (0: default)       */
+    int max_outer;     /* cap on defect-correction cycles (0: default 50)       */
+    uint32_t fault_inject; /* testing only: bit 0 forces an inner NaN           */
+} dht_solver_params;
+
+typedef struct {
+    int iters;          /* inner Krylov iterations (all cycles)        */
+    int outer;          /* defect-correction cycles                    */
+    double true_resid;  /* final ||z - D x|| / ||z|| in FP64            */
+    int status;         /* DHT_STATUS_*                                 */
+} dht_solve_stats;
+
+/* Per-probe record of dht_trace_batch: q = z^H D^-1 z (as solved), and the
+ * deflated quadrature q_defl = q - z^H P z. */
+typedef struct {
+    double q_re, q_im;
+    double qd_re, qd_im;
+    dht_solve_stats s;
+} dht_record;
+
+/* Running estimates (Algorithm 1, line 9): mean = T_R / n, mean_defl =
+ * T_D + (mean of q_defl).  Variances are unbiased sample variances
+ * (1/(n-1)): var = mean |q - qbar|^2 (the Z4 variance of Section 1),
+ * var_re / var_im of the real / imaginary parts. */
+typedef struct {
+    int64_t n;
+    double mean_re, mean_im;
+    double mean_defl_re, mean_defl_im;
+    double TD_re, TD_im;
+    double var, var_re, var_im;
+    double var_defl, var_defl_re, var_defl_im;
+} dht_estimate;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  Validates the lattice. */
+int dht_create(const dht_lattice* lat, int device, void* hip_stream, dht_ctx** out);
+int dht_destroy(dht_ctx* ctx);
+const char* dht_last_error(void);
+/* Library version string (static storage). */
+const char* dht_version(void);
+
+/* Upload links (device pointer, canonical layout).  Packs them into the
+ * internal even/odd layout in FP64, FP32 and BF16 (round to nearest even). */
+int dht_set_gauge(dht_ctx* ctx, const double* U_dev);
+
+/* Y = op(X) for nrhs canonical spinors (device pointers, complex128), with the
+ * operator evaluated in storage precision `prec` (X is rounded to `prec` on
+ * entry; Y is returned in complex128).  X and Y must not overlap. */
+int dht_apply(dht_ctx* ctx, int op, int prec, const double* X_dev, double* Y_dev, int nrhs);
+
+/* Write probes j = first .. first+nrhs-1 to Z_dev (canonical complex128). */
+int dht_make_probes(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int nrhs, double* Z_dev);
+
+/* Same probes as dht_make_probes, returned as the 2-bit Z4 indices k(n) of
+ * the base noise (uint8, [rhs][N]) and the Hadamard sign per site (int8,
+ * [rhs][V], all +1 when hp = 0).  For bit-exact checks of the generator. */
+int dht_probe_indices(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int nrhs,
+                      uint8_t* k_dev, int8_t* sign_dev);
+
+/* Solve D X = Z for nrhs right-hand sides (device, canonical complex128).
+ * stats (host, nrhs entries, may be NULL) receives per-RHS results.  Returns
+ * DHT_ERR_NOT_CONVERGED if any RHS missed the tolerance (stats still filled). */
+int dht_solve(dht_ctx* ctx, const dht_solver_params* prm, const double* Z_dev, double* X_dev,
+              int nrhs, dht_solve_stats* stats);
+
+/* ---- deflation (Section 5.2; Algorithm 1, lines 1-2) ----------------------- */
+
+/* Start a deflation basis of k vectors stored in precision `prec`. */
+int dht_deflation_begin(dht_ctx* ctx, int k, int prec);
+/* Copy columns first .. first+count-1 of W from W_dev (canonical complex128,
+ * [count][N]) into the stored basis, rounding to the storage precision. */
+int dht_deflation_set(dht_ctx* ctx, int first, int count, const double* W_dev);
+/* Fill the basis with eigenvectors of Q = g5 D of smallest |lambda| computed
+ * by the library's own block eigensolver (FP64); tol is the relative residual
+ * target ||Q w - lambda w|| / ||Q||; lambda_host (k doubles, may be NULL)
+ * receives the Ritz values. */
+int dht_deflation_eigensolve(dht_ctx* ctx, double tol, int max_iter, uint64_t seed, double* lambda_host);
+/* Finish: H = W^H Q W accumulated in FP64 from the stored basis, M = H^-1,
+ * T_D = Tr(M W^H g5 W).  TD_host (2 doubles: re, im) may be NULL. */
+int dht_deflation_finalize(dht_ctx* ctx, double* TD_host);
+/* Host copy of M (k x k complex128, row-major) for checks and playback. */
+int dht_deflation_get_M(dht_ctx* ctx, double* M_host);
+/* Drop the deflation basis (later batches are undeflated, T_D = 0). */
+int dht_deflation_clear(dht_ctx* ctx);
+
+/* c1 = W^H Z and c2 = W^H g5 Z for nrhs canonical spinors Z_dev; results on
+ * the host, complex128 row-major [k][nrhs]. */
+int dht_project(dht_ctx* ctx, const double* Z_dev, int nrhs, double* c1_host, double* c2_host);
+
+/* ---- Algorithm 1 ---------------------------------------------------------- */
+
+/* Algorithm 1 lines 5-9 for probes j = first .. first+nrhs-1: generate the
+ * probes on the device, solve, form q = z^H x in FP64, project on the
+ * deflation basis (when set) and accumulate the running estimates.  records
+ * (host, nrhs entries, may be NULL) receives per-probe results; coef_host
+ * (may be NULL) receives the projection coefficients c1, c2 as complex128
+ * [2][k][nrhs] for playback with other k (Section 6.4). */
+int dht_trace_batch(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int nrhs,
+                    const dht_solver_params* prm, dht_record* records, double* coef_host);
+int dht_estimate_get(dht_ctx* ctx, dht_estimate* est);
+int dht_estimate_reset(dht_ctx* ctx);
+
+/* ---- instrumentation ------------------------------------------------------ */
+
+/* Timing of the last dht_trace_batch / dht_solve, from HIP events on the
+ * context stream, in milliseconds: [0] probes, [1] solve, [2] projection,
+ * [3] quadratic forms, [4] whole call.  n must be >= 5. */
+int dht_last_timings(dht_ctx* ctx, double* ms_host, int n);
+
+/* Benchmark helper: time `reps` back-to-back applications of the even/odd
+ * hopping kernel (out parity 0 from parity 1) on nrhs internal fields in
+ * precision prec, after `warmup` untimed ones; returns the mean kernel time
+ * in ms measured with HIP events on the context stream. */
+int dht_bench_hop(dht_ctx* ctx, int prec, int nrhs, int warmup, int reps, double* ms_per_call);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DHTRACE_H */

@@ -1,0 +1,270 @@
+"""ctypes binding of libdhtrace.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module only converts torch
+tensors to device pointers, numpy arrays to host pointers, and C structs to
+Python values.  Importing it on a machine without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdhtrace.so")
+
+DHT_OK = 0
+DHT_ERR_NOT_CONVERGED = -6
+FP64, FP32, BF16 = 0, 1, 2
+OP_D, OP_DDAG, OP_G5, OP_Q = 0, 1, 2, 3
+SOLVER_BICGSTAB_FP64, SOLVER_DC_BICGSTAB, SOLVER_DC_FGMRES_NN = 0, 1, 2
+STATUS_NAMES = {0: "converged", 1: "not_converged", 2: "fallback_fp32", 3: "fallback_fp64"}
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int * 4), ("mass", ctypes.c_double), ("t_antiperiodic", ctypes.c_int)]
+
+
+class ProbeSpec(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("run", ctypes.c_uint64), ("hp", ctypes.c_int)]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("inner", ctypes.c_int), ("tol", ctypes.c_double),
+                ("maxiter", ctypes.c_int), ("restart", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("fault_inject", ctypes.c_uint32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("true_resid", ctypes.c_double),
+                ("status", ctypes.c_int)]
+
+
+class Record(ctypes.Structure):
+    _fields_ = [("q_re", ctypes.c_double), ("q_im", ctypes.c_double), ("qd_re", ctypes.c_double),
+                ("qd_im", ctypes.c_double), ("s", SolveStats)]
+
+
+class Estimate(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mean_re", ctypes.c_double), ("mean_im", ctypes.c_double),
+                ("mean_defl_re", ctypes.c_double), ("mean_defl_im", ctypes.c_double),
+                ("TD_re", ctypes.c_double), ("TD_im", ctypes.c_double),
+                ("var", ctypes.c_double), ("var_re", ctypes.c_double), ("var_im", ctypes.c_double),
+                ("var_defl", ctypes.c_double), ("var_defl_re", ctypes.c_double), ("var_defl_im", ctypes.c_double)]
+
+
+# name -> (restype, argtypes); mirrors include/dhtrace.h
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_dp = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "dht_create": (_i, [ctypes.POINTER(Lattice), _i, _vp, ctypes.POINTER(_vp)]),
+    "dht_destroy": (_i, [_vp]),
+    "dht_last_error": (ctypes.c_char_p, []),
+    "dht_version": (ctypes.c_char_p, []),
+    "dht_set_gauge": (_i, [_vp, _vp]),
+    "dht_apply": (_i, [_vp, _i, _i, _vp, _vp, _i]),
+    "dht_make_probes": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _vp]),
+    "dht_probe_indices": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _vp, _vp]),
+    "dht_solve": (_i, [_vp, ctypes.POINTER(SolverParams), _vp, _vp, _i, ctypes.POINTER(SolveStats)]),
+    "dht_deflation_begin": (_i, [_vp, _i, _i]),
+    "dht_deflation_set": (_i, [_vp, _i, _i, _vp]),
+    "dht_deflation_eigensolve": (_i, [_vp, _d, _i, _u64, _dp]),
+    "dht_deflation_finalize": (_i, [_vp, _dp]),
+    "dht_deflation_get_M": (_i, [_vp, _dp]),
+    "dht_deflation_clear": (_i, [_vp]),
+    "dht_project": (_i, [_vp, _vp, _i, _dp, _dp]),
+    "dht_trace_batch": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, ctypes.POINTER(SolverParams),
+                             ctypes.POINTER(Record), _dp]),
+    "dht_estimate_get": (_i, [_vp, ctypes.POINTER(Estimate)]),
+    "dht_estimate_reset": (_i, [_vp]),
+    "dht_last_timings": (_i, [_vp, _dp, _i]),
+    "dht_bench_hop": (_i, [_vp, _i, _i, _i, _i, _dp]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library (raises OSError if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise OSError("libdhtrace.so is not built (run __graft_entry__.build()): %s" % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class DhtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("dhtrace error %d: %s" % (code, msg))
+        self.code = code
+
+
+def check(rc: int, allow=()):
+    if rc != DHT_OK and rc not in allow:
+        raise DhtError(rc, load().dht_last_error().decode())
+    return rc
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _as_f64_view(t):
+    """complex128 torch tensor -> its data pointer (must be contiguous, on the GPU)."""
+    import torch
+    if t.dtype != torch.complex128 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("expected a contiguous complex128 CUDA tensor")
+    return _ptr(t)
+
+
+def _np_dp(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+class Context:
+    """One library context: lattice, gauge field, deflation basis, estimator state."""
+
+    def __init__(self, L, mass: float, t_antiperiodic: bool = True, device: int = 0, stream=None):
+        import torch
+        self.L = tuple(int(v) for v in L)
+        self.V = int(np.prod(self.L))
+        self.N = 12 * self.V
+        self.mass = float(mass)
+        self.device = device
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        lat = Lattice((ctypes.c_int * 4)(*self.L), self.mass, int(t_antiperiodic))
+        h = _vp()
+        check(load().dht_create(ctypes.byref(lat), device, _vp(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.k = 0
+
+    def close(self):
+        if self.h:
+            load().dht_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- operator ---------------------------------------------------------
+    def set_gauge(self, U):
+        """U: complex128 CUDA tensor [4][Lt][Lz][Ly][Lx][3][3]."""
+        check(load().dht_set_gauge(self.h, _as_f64_view(U)))
+
+    def apply(self, X, op: int = OP_D, prec: int = FP64):
+        """op(X) for X of shape [nrhs][Lt][Lz][Ly][Lx][4][3] (complex128 CUDA)."""
+        Y = self.torch.empty_like(X)
+        nrhs = X.shape[0]
+        check(load().dht_apply(self.h, op, prec, _as_f64_view(X), _as_f64_view(Y), nrhs))
+        return Y
+
+    def make_probes(self, seed: int, run: int, hp: bool, first: int, nrhs: int):
+        Z = self.torch.empty((nrhs,) + self._spinor_shape(), dtype=self.torch.complex128, device="cuda")
+        sp = ProbeSpec(seed, run, int(hp))
+        check(load().dht_make_probes(self.h, ctypes.byref(sp), first, nrhs, _as_f64_view(Z)))
+        return Z
+
+    def probe_indices(self, seed: int, run: int, hp: bool, first: int, nrhs: int):
+        k = self.torch.empty((nrhs, self.N), dtype=self.torch.uint8, device="cuda")
+        s = self.torch.empty((nrhs, self.V), dtype=self.torch.int8, device="cuda")
+        sp = ProbeSpec(seed, run, int(hp))
+        check(load().dht_probe_indices(self.h, ctypes.byref(sp), first, nrhs, _ptr(k), _ptr(s)))
+        return k, s
+
+    def _spinor_shape(self):
+        Lx, Ly, Lz, Lt = self.L
+        return (Lt, Lz, Ly, Lx, 4, 3)
+
+    # -- solver -----------------------------------------------------------
+    @staticmethod
+    def params(method=SOLVER_BICGSTAB_FP64, inner=FP32, tol=1e-10, maxiter=10000, restart=32,
+               inner_tol=0.0, max_outer=0, fault_inject=0):
+        return SolverParams(method, inner, tol, maxiter, restart, inner_tol, max_outer, fault_inject)
+
+    def solve(self, Z, prm: SolverParams, allow_not_converged: bool = False):
+        X = self.torch.empty_like(Z)
+        nrhs = Z.shape[0]
+        st = (SolveStats * nrhs)()
+        allow = (DHT_ERR_NOT_CONVERGED,) if allow_not_converged else ()
+        rc = check(load().dht_solve(self.h, ctypes.byref(prm), _as_f64_view(Z), _as_f64_view(X), nrhs, st), allow)
+        return X, [dict(iters=s.iters, outer=s.outer, true_resid=s.true_resid, status=s.status) for s in st], rc
+
+    # -- deflation --------------------------------------------------------
+    def set_deflation(self, W, prec: int = FP64, block: int = 64):
+        """W: complex128 CUDA tensor [k][N] (or [k][spinor shape]); returns T_D."""
+        k = W.shape[0]
+        check(load().dht_deflation_begin(self.h, k, prec))
+        for j in range(0, k, block):
+            n = min(block, k - j)
+            check(load().dht_deflation_set(self.h, j, n, _ptr(W[j:j + n].contiguous())))
+        td = np.zeros(2)
+        check(load().dht_deflation_finalize(self.h, _np_dp(td)))
+        self.k = k
+        return complex(td[0], td[1])
+
+    def deflation_M(self):
+        M = np.zeros(2 * self.k * self.k)
+        check(load().dht_deflation_get_M(self.h, _np_dp(M)))
+        return M.view(np.complex128).reshape(self.k, self.k)
+
+    def clear_deflation(self):
+        check(load().dht_deflation_clear(self.h))
+        self.k = 0
+
+    def project(self, Z):
+        nrhs = Z.shape[0]
+        c1 = np.zeros(2 * self.k * nrhs)
+        c2 = np.zeros(2 * self.k * nrhs)
+        check(load().dht_project(self.h, _as_f64_view(Z), nrhs, _np_dp(c1), _np_dp(c2)))
+        return (c1.view(np.complex128).reshape(self.k, nrhs), c2.view(np.complex128).reshape(self.k, nrhs))
+
+    # -- Algorithm 1 ------------------------------------------------------
+    def trace_batch(self, seed: int, run: int, hp: bool, first: int, nrhs: int, prm: SolverParams,
+                    want_coef: bool = False, allow_not_converged: bool = False):
+        sp = ProbeSpec(seed, run, int(hp))
+        rec = (Record * nrhs)()
+        coef = np.zeros(2 * 2 * self.k * nrhs) if (want_coef and self.k) else None
+        allow = (DHT_ERR_NOT_CONVERGED,) if allow_not_converged else ()
+        check(load().dht_trace_batch(self.h, ctypes.byref(sp), first, nrhs, ctypes.byref(prm), rec,
+                                     _np_dp(coef) if coef is not None else None), allow)
+        out = [dict(q=complex(r.q_re, r.q_im), q_defl=complex(r.qd_re, r.qd_im), iters=r.s.iters,
+                    outer=r.s.outer, true_resid=r.s.true_resid, status=r.s.status) for r in rec]
+        if coef is not None:
+            cc = coef.view(np.complex128).reshape(2, self.k, nrhs)
+            return out, cc[0], cc[1]
+        return out
+
+    def estimate(self):
+        e = Estimate()
+        check(load().dht_estimate_get(self.h, ctypes.byref(e)))
+        return {f[0]: getattr(e, f[0]) for f in Estimate._fields_}
+
+    def reset_estimate(self):
+        check(load().dht_estimate_reset(self.h))
+
+    def timings(self):
+        t = np.zeros(5)
+        check(load().dht_last_timings(self.h, _np_dp(t), 5))
+        return dict(probes=t[0], solve=t[1], project=t[2], qform=t[3], total=t[4])
+
+    def bench_hop(self, prec: int, nrhs: int, warmup: int = 3, reps: int = 10) -> float:
+        ms = ctypes.c_double(0.0)
+        check(load().dht_bench_hop(self.h, prec, nrhs, warmup, reps, ctypes.byref(ms)))
+        return ms.value

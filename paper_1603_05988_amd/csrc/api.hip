@@ -1,0 +1,390 @@
+// C-ABI entry points of libdhtrace (declared in include/dhtrace.h).
+//
+// Every entry point validates its arguments, converts between the canonical
+// interface layout and the internal even/odd layout, and reports failures as
+// negative return codes with a thread-local message; no C++ exception leaves
+// this file.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "solver.h"
+
+namespace dht {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int ws_get(dht_ctx* c, int slot, size_t bytes, void** out) {
+    if (slot < 0 || slot >= WS_NSLOTS) return set_error(DHT_ERR_INVALID_ARG, "bad workspace slot");
+    Buf& b = c->ws[slot];
+    if (b.bytes < bytes) {
+        if (b.p) {
+            DHT_HIP(hipStreamSynchronize(c->stream));
+            if (slot == WS_HOSTPIN) (void)hipHostFree(b.p);
+            else (void)hipFree(b.p);
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        size_t nb = std::max<size_t>(bytes, 256);
+        hipError_t e = slot == WS_HOSTPIN ? hipHostMalloc(&b.p, nb, hipHostMallocDefault) : hipMalloc(&b.p, nb);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            (void)hipGetLastError();
+            return set_error(DHT_ERR_OOM, "workspace allocation of " + std::to_string(nb) + " bytes failed");
+        }
+        b.bytes = nb;
+    }
+    *out = b.p;
+    return DHT_OK;
+}
+
+static bool valid_prec(int p) { return p == DHT_FP64 || p == DHT_FP32 || p == DHT_BF16; }
+
+static int check_ctx(dht_ctx* c) {
+    if (!c) return set_error(DHT_ERR_INVALID_ARG, "null context");
+    DHT_HIP(hipSetDevice(c->device));
+    return DHT_OK;
+}
+
+static int record(dht_ctx* c, int i) {
+    DHT_HIP(hipEventRecord(c->ev[i], c->stream));
+    return DHT_OK;
+}
+
+static double elapsed(dht_ctx* c, int a, int b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.0;
+    return ms;
+}
+
+}  // namespace dht
+
+using namespace dht;
+
+extern "C" {
+
+const char* dht_last_error(void) { return g_err.c_str(); }
+
+const char* dht_version(void) { return "dhtrace 0.1 gfx950"; }
+
+int dht_create(const dht_lattice* lat, int device, void* hip_stream, dht_ctx** out) {
+    if (!lat || !out) return set_error(DHT_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    for (int i = 0; i < 4; i++)
+        if (lat->L[i] < 2 || (lat->L[i] & 1)) return set_error(DHT_ERR_INVALID_ARG, "every lattice extent must be even and >= 2");
+    if (!isfinite(lat->mass) || 4.0 + lat->mass == 0.0) return set_error(DHT_ERR_INVALID_ARG, "mass must be finite and != -4");
+    int ndev = 0;
+    DHT_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return set_error(DHT_ERR_INVALID_ARG, "no such device");
+    DHT_HIP(hipSetDevice(device));
+    dht_ctx* c = new (std::nothrow) dht_ctx;
+    if (!c) return set_error(DHT_ERR_OOM, "out of host memory");
+    for (int i = 0; i < 4; i++) c->g.L[i] = lat->L[i];
+    c->g.Lxh = lat->L[0] / 2;
+    c->g.V = (int64_t)lat->L[0] * lat->L[1] * lat->L[2] * lat->L[3];
+    c->g.Vh = c->g.V / 2;
+    c->g.antiperiodic = lat->t_antiperiodic ? 1 : 0;
+    c->mass = lat->mass;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws.resize(WS_NSLOTS);
+    for (int i = 0; i < 6; i++) {
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+            delete c;
+            return set_error(DHT_ERR_HIP, "hipEventCreate failed");
+        }
+    }
+    c->events = true;
+    *out = c;
+    return DHT_OK;
+}
+
+int dht_destroy(dht_ctx* c) {
+    if (!c) return DHT_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < 3; i++)
+        if (c->U[i]) (void)hipFree(c->U[i]);
+    if (c->W) (void)hipFree(c->W);
+    for (int i = 0; i < (int)c->ws.size(); i++) {
+        if (!c->ws[i].p) continue;
+        if (i == WS_HOSTPIN) (void)hipHostFree(c->ws[i].p);
+        else (void)hipFree(c->ws[i].p);
+    }
+    if (c->events)
+        for (int i = 0; i < 6; i++) (void)hipEventDestroy(c->ev[i]);
+    delete c;
+    return DHT_OK;
+}
+
+int dht_set_gauge(dht_ctx* c, const double* U_dev) {
+    DHT_TRY(check_ctx(c));
+    if (!U_dev) return set_error(DHT_ERR_INVALID_ARG, "null links");
+    for (int p = 0; p < 3; p++) {
+        if (!c->U[p]) {
+            size_t bytes = (size_t)4 * 9 * c->g.V * elem_bytes(p);
+            if (hipMalloc(&c->U[p], bytes) != hipSuccess) {
+                c->U[p] = nullptr;
+                (void)hipGetLastError();
+                return set_error(DHT_ERR_OOM, "cannot allocate links");
+            }
+        }
+    }
+    DHT_TRY(pack_gauge(c, U_dev));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    c->have_gauge = true;
+    return DHT_OK;
+}
+
+int dht_apply(dht_ctx* c, int op, int prec, const double* X, double* Y, int nrhs) {
+    DHT_TRY(check_ctx(c));
+    if (!X || !Y || nrhs <= 0 || !valid_prec(prec) || op < DHT_OP_D || op > DHT_OP_Q)
+        return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (op != DHT_OP_G5 && !c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    size_t bytes = full_elems(c, nrhs) * elem_bytes(prec);
+    void *fi, *fo;
+    DHT_TRY(ws_get(c, WS_PACK_IN, bytes, &fi));
+    DHT_TRY(ws_get(c, WS_PACK_OUT, bytes, &fo));
+    DHT_TRY(pack_spinor(c, X, fi, prec, nrhs));
+    DHT_TRY(apply_full(c, op, prec, fi, fo, nrhs));
+    DHT_TRY(unpack_spinor(c, fo, prec, Y, nrhs));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    return DHT_OK;
+}
+
+int dht_make_probes(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, double* Z) {
+    DHT_TRY(check_ctx(c));
+    if (!spec || !Z || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    void* f;
+    DHT_TRY(ws_get(c, WS_Z, full_elems(c, nrhs) * 16, &f));
+    DHT_TRY(probes_gen(c, spec, first, nrhs, f, DHT_FP64, nullptr, nullptr));
+    DHT_TRY(unpack_spinor(c, f, DHT_FP64, Z, nrhs));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    return DHT_OK;
+}
+
+int dht_probe_indices(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, uint8_t* k_dev,
+                      int8_t* sign_dev) {
+    DHT_TRY(check_ctx(c));
+    if (!spec || !k_dev || !sign_dev || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    DHT_TRY(probes_gen(c, spec, first, nrhs, nullptr, DHT_FP64, k_dev, sign_dev));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    return DHT_OK;
+}
+
+int dht_solve(dht_ctx* c, const dht_solver_params* prm, const double* Z, double* X, int nrhs, dht_solve_stats* stats) {
+    DHT_TRY(check_ctx(c));
+    if (!prm || !Z || !X || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    size_t bytes = full_elems(c, nrhs) * 16;
+    void *fz, *fx;
+    DHT_TRY(ws_get(c, WS_PACK_IN, bytes, &fz));
+    DHT_TRY(ws_get(c, WS_PACK_OUT, bytes, &fx));
+    DHT_TRY(pack_spinor(c, Z, fz, DHT_FP64, nrhs));
+    DHT_TRY(record(c, 0));
+    int rc = solve_fields(c, prm, fz, fx, nrhs, stats);
+    if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) return rc;
+    std::string msg = g_err;
+    DHT_TRY(record(c, 1));
+    DHT_TRY(unpack_spinor(c, fx, DHT_FP64, X, nrhs));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    c->timings[1] = elapsed(c, 0, 1);
+    if (rc != DHT_OK) g_err = msg;
+    return rc;
+}
+
+int dht_deflation_begin(dht_ctx* c, int k, int prec) {
+    DHT_TRY(check_ctx(c));
+    return deflation_begin(c, k, prec);
+}
+
+int dht_deflation_set(dht_ctx* c, int first, int count, const double* W_dev) {
+    DHT_TRY(check_ctx(c));
+    if (!W_dev && count > 0) return set_error(DHT_ERR_INVALID_ARG, "null basis");
+    DHT_TRY(deflation_set(c, first, count, W_dev));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    return DHT_OK;
+}
+
+int dht_deflation_eigensolve(dht_ctx* c, double tol, int max_iter, uint64_t seed, double* lambda_host) {
+    DHT_TRY(check_ctx(c));
+    (void)tol; (void)max_iter; (void)seed; (void)lambda_host;
+    return set_error(DHT_ERR_STATE, "the block eigensolver is not available in this build");
+}
+
+int dht_deflation_finalize(dht_ctx* c, double* TD) {
+    DHT_TRY(check_ctx(c));
+    DHT_TRY(deflation_finalize(c));
+    if (TD) {
+        TD[0] = c->TD[0];
+        TD[1] = c->TD[1];
+    }
+    return DHT_OK;
+}
+
+int dht_deflation_get_M(dht_ctx* c, double* M) {
+    DHT_TRY(check_ctx(c));
+    if (!c->defl_ready) return set_error(DHT_ERR_STATE, "deflation not finalized");
+    if (!M) return set_error(DHT_ERR_INVALID_ARG, "null output");
+    memcpy(M, c->M.data(), sizeof(double) * c->M.size());
+    return DHT_OK;
+}
+
+int dht_deflation_clear(dht_ctx* c) {
+    DHT_TRY(check_ctx(c));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    if (c->W) DHT_HIP(hipFree(c->W));
+    c->W = nullptr;
+    c->k = 0;
+    c->defl_ready = false;
+    c->TD[0] = c->TD[1] = 0;
+    c->M.clear();
+    return DHT_OK;
+}
+
+int dht_project(dht_ctx* c, const double* Z, int nrhs, double* c1h, double* c2h) {
+    DHT_TRY(check_ctx(c));
+    if (!Z || !c1h || !c2h || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!c->W) return set_error(DHT_ERR_STATE, "no deflation basis");
+    void *fz, *cc;
+    DHT_TRY(ws_get(c, WS_PACK_IN, full_elems(c, nrhs) * 16, &fz));
+    DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 2 * c->k * nrhs, &cc));
+    DHT_TRY(pack_spinor(c, Z, fz, DHT_FP64, nrhs));
+    Cx<double>* d1 = (Cx<double>*)cc;
+    Cx<double>* d2 = d1 + (size_t)c->k * nrhs;
+    DHT_TRY(project_field(c, fz, DHT_FP64, nrhs, d1, d2));
+    DHT_HIP(hipMemcpyAsync(c1h, d1, sizeof(Cx<double>) * c->k * nrhs, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipMemcpyAsync(c2h, d2, sizeof(Cx<double>) * c->k * nrhs, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    return DHT_OK;
+}
+
+int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, const dht_solver_params* prm,
+                    dht_record* records, double* coef_host) {
+    DHT_TRY(check_ctx(c));
+    if (!spec || !prm || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    if (c->W && !c->defl_ready) return set_error(DHT_ERR_STATE, "deflation basis set but not finalized");
+    const size_t fb = full_elems(c, nrhs) * 16;
+    void *fz, *fx, *cc;
+    DHT_TRY(ws_get(c, WS_Z, fb, &fz));
+    DHT_TRY(ws_get(c, WS_PACK_OUT, fb, &fx));
+    const int k = c->defl_ready ? c->k : 0;
+    DHT_TRY(ws_get(c, WS_COEF, sizeof(Cx<double>) * (2 * (size_t)k * nrhs + nrhs) + 64, &cc));
+    Cx<double>* d1 = (Cx<double>*)cc;
+    Cx<double>* d2 = d1 + (size_t)k * nrhs;
+    Cx<double>* dq = d2 + (size_t)k * nrhs;
+
+    DHT_TRY(record(c, 0));
+    DHT_TRY(probes_gen(c, spec, first, nrhs, fz, DHT_FP64, nullptr, nullptr));
+    DHT_TRY(record(c, 1));
+    std::vector<dht_solve_stats> st(nrhs);
+    int rc = solve_fields(c, prm, fz, fx, nrhs, st.data());
+    if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) return rc;
+    std::string msg = g_err;
+    DHT_TRY(record(c, 2));
+    if (k > 0) DHT_TRY(project_field(c, fz, DHT_FP64, nrhs, d1, d2));
+    DHT_TRY(record(c, 3));
+    {
+        const void* aa[1] = {fz};
+        const void* bb[1] = {fx};
+        DHT_TRY(dots(c, DHT_FP64, 1, aa, bb, 2 * c->g.Vh, nrhs, dq));
+    }
+    DHT_TRY(record(c, 4));
+    std::vector<Cx<double>> hc((size_t)2 * k * nrhs + nrhs);
+    DHT_HIP(hipMemcpyAsync(hc.data(), cc, sizeof(Cx<double>) * hc.size(), hipMemcpyDeviceToHost, c->stream));
+    DHT_TRY(record(c, 5));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    c->timings[0] = elapsed(c, 0, 1);
+    c->timings[1] = elapsed(c, 1, 2);
+    c->timings[2] = elapsed(c, 2, 3);
+    c->timings[3] = elapsed(c, 3, 4);
+    c->timings[4] = elapsed(c, 0, 5);
+    std::vector<double> dre(nrhs, 0.0), dim(nrhs, 0.0);
+    if (k > 0) deflation_corrections(c, hc.data(), hc.data() + (size_t)k * nrhs, nrhs, dre.data(), dim.data());
+    const Cx<double>* q = hc.data() + (size_t)2 * k * nrhs;
+    for (int r = 0; r < nrhs; r++) {
+        double qre = q[r].re, qim = q[r].im;
+        double dqre = qre - dre[r], dqim = qim - dim[r];
+        c->est_q.add(qre, qim);
+        c->est_qd.add(dqre, dqim);
+        if (records) {
+            records[r].q_re = qre;
+            records[r].q_im = qim;
+            records[r].qd_re = dqre;
+            records[r].qd_im = dqim;
+            records[r].s = st[r];
+        }
+    }
+    if (coef_host && k > 0) memcpy(coef_host, hc.data(), sizeof(Cx<double>) * 2 * k * nrhs);
+    if (rc != DHT_OK) g_err = msg;
+    return rc;
+}
+
+int dht_estimate_get(dht_ctx* c, dht_estimate* e) {
+    if (!c || !e) return set_error(DHT_ERR_INVALID_ARG, "null argument");
+    memset(e, 0, sizeof(*e));
+    e->n = c->est_q.n;
+    e->mean_re = c->est_q.mre;
+    e->mean_im = c->est_q.mim;
+    e->TD_re = c->TD[0];
+    e->TD_im = c->TD[1];
+    e->mean_defl_re = c->est_qd.mre + (c->defl_ready ? c->TD[0] : 0.0);
+    e->mean_defl_im = c->est_qd.mim + (c->defl_ready ? c->TD[1] : 0.0);
+    if (e->n >= 2) {
+        double d = (double)(e->n - 1);
+        e->var_re = c->est_q.m2re / d;
+        e->var_im = c->est_q.m2im / d;
+        e->var = e->var_re + e->var_im;
+        e->var_defl_re = c->est_qd.m2re / d;
+        e->var_defl_im = c->est_qd.m2im / d;
+        e->var_defl = e->var_defl_re + e->var_defl_im;
+    } else {
+        e->var = e->var_re = e->var_im = NAN;
+        e->var_defl = e->var_defl_re = e->var_defl_im = NAN;
+    }
+    return DHT_OK;
+}
+
+int dht_estimate_reset(dht_ctx* c) {
+    if (!c) return set_error(DHT_ERR_INVALID_ARG, "null context");
+    c->est_q = Welford();
+    c->est_qd = Welford();
+    return DHT_OK;
+}
+
+int dht_last_timings(dht_ctx* c, double* ms, int n) {
+    if (!c || !ms || n < 5) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    for (int i = 0; i < 5; i++) ms[i] = c->timings[i];
+    return DHT_OK;
+}
+
+int dht_bench_hop(dht_ctx* c, int prec, int nrhs, int warmup, int reps, double* ms_per_call) {
+    DHT_TRY(check_ctx(c));
+    if (!valid_prec(prec) || nrhs <= 0 || reps <= 0 || warmup < 0 || !ms_per_call)
+        return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    size_t bytes = full_elems(c, nrhs) * elem_bytes(prec);
+    void *fi, *fo;
+    DHT_TRY(ws_get(c, WS_PACK_IN, bytes, &fi));
+    DHT_TRY(ws_get(c, WS_PACK_OUT, bytes, &fo));
+    dht_probe_spec sp = {12345u, 0u, 0};
+    DHT_TRY(probes_gen(c, &sp, 0, nrhs, fi, prec, nullptr, nullptr));
+    const void* in_odd = (const char*)fi + bytes / 2;
+    for (int i = 0; i < warmup; i++) DHT_TRY(hop(c, prec, 0, in_odd, fo, nullptr, 0.0, 1.0, nrhs, false, false));
+    DHT_TRY(record(c, 0));
+    for (int i = 0; i < reps; i++) DHT_TRY(hop(c, prec, 0, in_odd, fo, nullptr, 0.0, 1.0, nrhs, false, false));
+    DHT_TRY(record(c, 1));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    *ms_per_call = elapsed(c, 0, 1) / reps;
+    return DHT_OK;
+}
+
+}  // extern "C"

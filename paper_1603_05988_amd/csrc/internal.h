@@ -1,0 +1,213 @@
+// Internal declarations of the dhtrace library (gfx950).
+//
+// Internal field layout ("even/odd, RHS-innermost"): a field of B right-hand
+// sides on one parity is complex<T>[12][Vh][B] -- spin-colour component
+// c = 3 spin + colour outermost, checkerboard site s, then the RHS.  A lane of
+// a kernel owns one (s, rhs) pair, so every component load of a wavefront is
+// one contiguous run.  A full-lattice field is two parity fields back to back
+// (parity 0 = even first).  Checkerboard index of site (x, y, z, t):
+// s = lexicographic(x, y, z, t) / 2 (Lx even), parity = (x+y+z+t) & 1.
+//
+// Links: complex<T>[4 dir][9 (row-major 3x3)][2 parity][Vh], stored in FP64,
+// FP32 and BF16.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dhtrace.h"
+
+namespace dht {
+
+// ---------------------------------------------------------------------------
+// scalars
+// ---------------------------------------------------------------------------
+struct bf16x2 {   // one complex number in BF16: low half = re, high half = im
+    uint32_t bits;
+};
+
+template <typename T> struct Cx { T re, im; };
+
+template <typename T> __host__ __device__ inline Cx<T> cmake(T r, T i) { Cx<T> c; c.re = r; c.im = i; return c; }
+template <typename T> __host__ __device__ inline Cx<T> operator+(Cx<T> a, Cx<T> b) { return cmake(a.re + b.re, a.im + b.im); }
+template <typename T> __host__ __device__ inline Cx<T> operator-(Cx<T> a, Cx<T> b) { return cmake(a.re - b.re, a.im - b.im); }
+template <typename T> __host__ __device__ inline Cx<T> operator*(Cx<T> a, Cx<T> b) {
+    return cmake(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T> __host__ __device__ inline Cx<T> operator*(T s, Cx<T> a) { return cmake(s * a.re, s * a.im); }
+template <typename T> __host__ __device__ inline Cx<T> conjmul(Cx<T> a, Cx<T> b) {  // conj(a) * b
+    return cmake(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <typename T> __host__ __device__ inline Cx<T> timesI(Cx<T> a) { return cmake(-a.im, a.re); }
+template <typename T> __host__ __device__ inline Cx<T> timesMinusI(Cx<T> a) { return cmake(a.im, -a.re); }
+template <typename T> __host__ __device__ inline Cx<T> neg(Cx<T> a) { return cmake(-a.re, -a.im); }
+
+// FP32 -> BF16 with round-to-nearest-even; NaN stays NaN (quiet bit set).
+__host__ __device__ inline uint32_t f32_to_bf16_bits(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__host__ __device__ inline float bf16_bits_to_f32(uint32_t h) {
+    uint32_t u = h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// Storage traits: how a complex<T> element is loaded/stored and what it
+// accumulates in.
+template <typename S> struct Store;
+template <> struct Store<double> {
+    typedef double acc;
+    typedef Cx<double> elem;
+    __device__ static inline Cx<double> ld(const elem* p) { return *p; }
+    __device__ static inline void st(elem* p, Cx<double> v) { *p = v; }
+};
+template <> struct Store<float> {
+    typedef float acc;
+    typedef Cx<float> elem;
+    __device__ static inline Cx<float> ld(const elem* p) { return *p; }
+    __device__ static inline void st(elem* p, Cx<float> v) { *p = v; }
+};
+template <> struct Store<bf16x2> {
+    typedef float acc;
+    typedef bf16x2 elem;
+    __device__ static inline Cx<float> ld(const elem* p) {
+        uint32_t b = p->bits;
+        return cmake(bf16_bits_to_f32(b & 0xffffu), bf16_bits_to_f32(b >> 16));
+    }
+    __device__ static inline void st(elem* p, Cx<float> v) {
+        p->bits = f32_to_bf16_bits(v.re) | (f32_to_bf16_bits(v.im) << 16);
+    }
+};
+
+inline size_t elem_bytes(int prec) { return prec == DHT_FP64 ? 16 : (prec == DHT_FP32 ? 8 : 4); }
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+struct Geom {
+    int L[4];
+    int Lxh;          // Lx / 2
+    int64_t V, Vh;
+    int antiperiodic;
+};
+
+// Coordinates of checkerboard site s of parity p.
+__device__ __host__ inline void cb_coords(const Geom& g, int64_t s, int p, int c[4]) {
+    int64_t r = s / g.Lxh;
+    int xh = (int)(s - r * g.Lxh);
+    c[1] = (int)(r % g.L[1]);
+    r /= g.L[1];
+    c[2] = (int)(r % g.L[2]);
+    c[3] = (int)(r / g.L[2]);
+    c[0] = 2 * xh + ((p + c[1] + c[2] + c[3]) & 1);
+}
+__device__ __host__ inline int64_t lex_index(const Geom& g, const int c[4]) {
+    return (int64_t)c[0] + (int64_t)g.L[0] * ((int64_t)c[1] + (int64_t)g.L[1] * ((int64_t)c[2] + (int64_t)g.L[2] * c[3]));
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Welford {   // running mean / second moments of complex samples (Chan et al. update)
+    int64_t n = 0;
+    double mre = 0, mim = 0;   // means
+    double m2re = 0, m2im = 0; // sums of squared deviations
+    void add(double re, double im) {
+        n++;
+        double dre = re - mre, dim = im - mim;
+        mre += dre / n;
+        mim += dim / n;
+        m2re += dre * (re - mre);
+        m2im += dim * (im - mim);
+    }
+};
+
+}  // namespace dht
+
+struct dht_ctx {
+    dht::Geom g;
+    double mass;
+    int device;
+    hipStream_t stream;
+    bool have_gauge = false;
+    void* U[3] = {nullptr, nullptr, nullptr};   // links per precision
+    // deflation
+    int k = 0, wprec = DHT_FP64;
+    bool defl_ready = false;
+    void* W = nullptr;                 // [k][2][12][Vh] complex<wprec>
+    std::vector<double> M;             // k x k complex128 row-major (host)
+    void* M_dev = nullptr;
+    double TD[2] = {0, 0};
+    // estimator
+    dht::Welford est_q, est_qd;
+    // workspace slots (grow-only)
+    std::vector<dht::Buf> ws;
+    // timings of the last call (ms)
+    double timings[5] = {0, 0, 0, 0, 0};
+    hipEvent_t ev[6];
+    bool events = false;
+};
+
+namespace dht {
+
+// error reporting ------------------------------------------------------------
+int set_error(int code, const std::string& msg);
+#define DHT_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return ::dht::set_error(DHT_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+#define DHT_TRY(call)              \
+    do {                           \
+        int rc_ = (call);          \
+        if (rc_ != DHT_OK) return rc_; \
+    } while (0)
+
+// workspace: slot ids --------------------------------------------------------
+enum Slot {
+    WS_PACK_IN = 0, WS_PACK_OUT, WS_TMP_HALF, WS_B, WS_RE, WS_TMPO,
+    WS_K64,                 // 9 FP64 Krylov vectors: r, rhat, p, v, s, t, tmp, inner rhs, inner x
+    WS_KLO = WS_K64 + 9,    // 9 low-precision Krylov vectors (same roles)
+    WS_PARTIAL = WS_KLO + 9, WS_SCAL, WS_SCAL2, WS_FLAGS, WS_HOSTPIN,
+    WS_Z, WS_XF, WS_QW, WS_PROJ, WS_COEF, WS_PROJ2,
+    WS_NSLOTS
+};
+int ws_get(dht_ctx* c, int slot, size_t bytes, void** out);
+
+// field helpers -------------------------------------------------------------
+inline size_t half_elems(const dht_ctx* c, int nrhs) { return (size_t)12 * c->g.Vh * nrhs; }
+inline size_t full_elems(const dht_ctx* c, int nrhs) { return 2 * half_elems(c, nrhs); }
+
+// kernels (launchers) -------------------------------------------------------
+// pack.hip
+int pack_gauge(dht_ctx* c, const double* U_dev);
+int pack_spinor(dht_ctx* c, const double* canon, void* field, int prec, int nrhs);     // canonical -> full internal
+int unpack_spinor(dht_ctx* c, const void* field, int prec, double* canon, int nrhs);   // full internal -> canonical
+int convert_field(dht_ctx* c, const void* in, int pin, void* out, int pout, size_t nelem);
+
+// dslash.hip: out_p = a * x_p + b * Hop_{p <- 1-p}(in), optionally g5 on the result and/or dagger hop.
+int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
+        int nrhs, bool dagger, bool g5out);
+int apply_full(dht_ctx* c, int op, int prec, const void* in, void* out, int nrhs);   // full-lattice D, D^H, g5, Q
+int g5_field(dht_ctx* c, int prec, const void* in, void* out, int nrhs);              // full-lattice g5
+
+// probes.hip: probes j = first.. first+nrhs-1 into a full internal field of
+// precision prec (may be null), plus optional index/sign outputs.
+int probes_gen(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, void* field, int prec,
+               uint8_t* kout, int8_t* sout);
+
+}  // namespace dht

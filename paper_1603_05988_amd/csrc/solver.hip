@@ -1,0 +1,250 @@
+// Batched solves of D X = Z (Algorithm 1, "Solve Ay = z"; the paper leaves
+// the solver open).
+//
+// Structure:
+//  * even/odd reduction: with a = 4 + m and Hop_pq the hop from parity q to p,
+//      Dhat x_e = b_e + Hop_eo b_o / (2a),  Dhat = a - Hop_eo Hop_oe / (4a),
+//      x_o = (b_o + Hop_oe x_e / 2) / a,
+//    and the Schur residual equals the full-lattice residual (odd part zero);
+//  * batched BiCGStab (van der Vorst 1992) with per-RHS scalars on the device;
+//  * FP64 defect correction: r = b - Dhat x in FP64, inner solve of
+//    Dhat e = r / ||r|| in FP32 or BF16 storage, x += ||r|| e in FP64, until
+//    the FP64 residual meets the target.  The plain FP64 method is the same
+//    loop with an FP64 inner solve.
+//  * fallback: an inner breakdown or NaN, or a cycle that fails to reduce the
+//    residual, escalates the inner precision BF16 -> FP32 -> FP64.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "solver.h"
+
+namespace dht {
+
+int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o, int nrhs) {
+    const double a = 4.0 + c->mass;
+    DHT_TRY(hop(c, prec, 1, in_e, tmp_o, nullptr, 0.0, 1.0, nrhs, false, false));
+    DHT_TRY(hop(c, prec, 0, tmp_o, out_e, in_e, a, -1.0 / (4.0 * a), nrhs, false, false));
+    return DHT_OK;
+}
+
+static int slot_base(int prec) { return prec == DHT_FP64 ? WS_K64 : WS_KLO; }
+
+int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::vector<double>& target2, int maxiter,
+             BicgResult* res) {
+    const size_t n = half_elems(c, nrhs);
+    const size_t bytes = n * elem_bytes(prec);
+    const int base = slot_base(prec);
+    void *r, *rh, *p, *v, *s, *t, *tmp, *stv, *part, *hostv;
+    DHT_TRY(ws_get(c, base + 0, bytes, &r));
+    DHT_TRY(ws_get(c, base + 1, bytes, &rh));
+    DHT_TRY(ws_get(c, base + 2, bytes, &p));
+    DHT_TRY(ws_get(c, base + 3, bytes, &v));
+    DHT_TRY(ws_get(c, base + 4, bytes, &s));
+    DHT_TRY(ws_get(c, base + 5, bytes, &t));
+    DHT_TRY(ws_get(c, base + 6, bytes, &tmp));
+    DHT_TRY(ws_get(c, WS_SCAL, sizeof(RhsState) * nrhs, &stv));
+    DHT_TRY(ws_get(c, WS_PARTIAL, (size_t)1024 * 3 * nrhs * sizeof(Cx<double>), &part));
+    DHT_TRY(ws_get(c, WS_HOSTPIN, sizeof(RhsState) * nrhs, &hostv));   // pinned host buffer
+    RhsState* st = (RhsState*)stv;
+    RhsState* hs = (RhsState*)hostv;
+    Cx<double>* partial = (Cx<double>*)part;
+
+    for (int i = 0; i < nrhs; i++) {
+        memset(&hs[i], 0, sizeof(RhsState));
+        hs[i].target2 = target2[i];
+    }
+    DHT_HIP(hipMemcpyAsync(st, hs, sizeof(RhsState) * nrhs, hipMemcpyHostToDevice, c->stream));
+    DHT_TRY(zero(c, x, bytes));
+    DHT_TRY(zero(c, p, bytes));
+    DHT_TRY(zero(c, v, bytes));
+    DHT_HIP(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, c->stream));
+    DHT_HIP(hipMemcpyAsync(rh, b, bytes, hipMemcpyDeviceToDevice, c->stream));
+    const int64_t nsite = c->g.Vh;
+    const double bd_eps = prec == DHT_FP64 ? 1e-14 : 1e-6;
+    int nb;
+    {
+        const void* aa[1] = {r};
+        DHT_TRY(launch_dot_partials(c, prec, 1, aa, aa, nsite, nrhs, partial, &nb));
+        DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_INIT, bd_eps));
+    }
+    const int check_every = 2;
+    for (int it = 0; it < maxiter; it++) {
+        DHT_TRY(p_update(c, prec, p, r, v, st, n, nrhs));
+        DHT_TRY(apply_schur(c, prec, p, v, tmp, nrhs));
+        {
+            const void* aa[1] = {rh};
+            const void* bb[1] = {v};
+            DHT_TRY(launch_dot_partials(c, prec, 1, aa, bb, nsite, nrhs, partial, &nb));
+            DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_ALPHA, bd_eps));
+        }
+        DHT_TRY(s_update(c, prec, s, r, v, st, n, nrhs));
+        DHT_TRY(apply_schur(c, prec, s, t, tmp, nrhs));
+        {
+            const void* aa[2] = {t, t};
+            const void* bb[2] = {s, t};
+            DHT_TRY(launch_dot_partials(c, prec, 2, aa, bb, nsite, nrhs, partial, &nb));
+            DHT_TRY(finalize(c, partial, nb, 2, nrhs, st, FIN_OMEGA, bd_eps));
+        }
+        DHT_TRY(xr_update(c, prec, x, r, p, s, t, st, n, nrhs));
+        {
+            const void* aa[2] = {rh, r};
+            const void* bb[2] = {r, r};
+            DHT_TRY(launch_dot_partials(c, prec, 2, aa, bb, nsite, nrhs, partial, &nb));
+            DHT_TRY(finalize(c, partial, nb, 2, nrhs, st, FIN_RHO, bd_eps));
+        }
+        if ((it + 1) % check_every == 0 || it + 1 == maxiter) {
+            DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
+            DHT_HIP(hipStreamSynchronize(c->stream));
+            bool any = false;
+            for (int i = 0; i < nrhs; i++) any |= hs[i].active != 0;
+            if (!any) break;
+        }
+    }
+    DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    res->iters.assign(nrhs, 0);
+    res->status.assign(nrhs, 0);
+    res->rnorm2.assign(nrhs, 0);
+    for (int i = 0; i < nrhs; i++) {
+        res->iters[i] = hs[i].iters;
+        res->status[i] = hs[i].status;
+        res->rnorm2[i] = hs[i].rnorm2;
+    }
+    return DHT_OK;
+}
+
+// per-RHS FP64 norms^2 of a field with `nsite` sites per component (host result)
+static int norms2(dht_ctx* c, const void* f, int64_t nsite, int nrhs, std::vector<double>& out) {
+    void* d;
+    DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 3 * nrhs, &d));
+    const void* aa[1] = {f};
+    DHT_TRY(dots(c, DHT_FP64, 1, aa, aa, nsite, nrhs, (Cx<double>*)d));
+    std::vector<Cx<double>> h(nrhs);
+    DHT_HIP(hipMemcpyAsync(h.data(), d, sizeof(Cx<double>) * nrhs, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    out.resize(nrhs);
+    for (int i = 0; i < nrhs; i++) out[i] = h[i].re;
+    return DHT_OK;
+}
+
+int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats) {
+    const double a = 4.0 + c->mass;
+    const size_t nh = half_elems(c, nrhs);
+    const size_t bh = nh * 16;
+    const char* Zc = (const char*)Z;
+    char* Xc = (char*)X;
+    const void* Z_e = Zc;
+    const void* Z_o = Zc + bh;
+    void* X_e = Xc;
+    void* X_o = Xc + bh;
+    void *bhat, *r_e, *tmpf, *scl, *tmp_o;
+    DHT_TRY(ws_get(c, WS_B, bh, &bhat));
+    DHT_TRY(ws_get(c, WS_RE, bh, &r_e));
+    DHT_TRY(ws_get(c, WS_TMP_HALF, bh, &tmpf));
+    DHT_TRY(ws_get(c, WS_TMPO, bh, &tmp_o));
+    DHT_TRY(ws_get(c, WS_FLAGS, sizeof(double) * nrhs, &scl));
+
+    if (prm->tol <= 0.0 || prm->maxiter <= 0) return set_error(DHT_ERR_INVALID_ARG, "tol and maxiter must be positive");
+    int inner = DHT_FP64;
+    if (prm->method == DHT_SOLVER_DC_BICGSTAB || prm->method == DHT_SOLVER_DC_FGMRES_NN) inner = prm->inner;
+    if (inner < DHT_FP64 || inner > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad inner precision");
+    const int max_outer = prm->max_outer > 0 ? prm->max_outer : 50;
+
+    // right-hand side of the Schur system and ||Z||^2
+    DHT_TRY(hop(c, DHT_FP64, 0, Z_o, bhat, Z_e, 1.0, 1.0 / (2.0 * a), nrhs, false, false));
+    std::vector<double> zn2, rn2;
+    DHT_TRY(norms2(c, Z, 2 * c->g.Vh, nrhs, zn2));
+    std::vector<double> target2(nrhs);
+    // the Schur loop aims 10% below the tolerance so that the reconstructed
+    // full-lattice residual, checked last, is not lost to rounding
+    for (int i = 0; i < nrhs; i++) target2[i] = 0.81 * prm->tol * prm->tol * zn2[i];
+
+    DHT_TRY(zero(c, X_e, bh));
+    DHT_HIP(hipMemcpyAsync(r_e, bhat, bh, hipMemcpyDeviceToDevice, c->stream));
+    std::vector<int> iters(nrhs, 0), escalated(nrhs, DHT_STATUS_CONVERGED);
+    std::vector<double> last_rn2(nrhs, INFINITY);
+    int outer = 0, total_iters = 0;
+    const int start_inner = inner;
+    void* e;
+    void* rlo;
+    for (; outer < max_outer; outer++) {
+        DHT_TRY(norms2(c, r_e, c->g.Vh, nrhs, rn2));
+        bool any = false, stalled = false;
+        std::vector<double> sdown(nrhs), sup(nrhs), itarget(nrhs);
+        for (int i = 0; i < nrhs; i++) {
+            bool act = rn2[i] > target2[i] && isfinite(rn2[i]);
+            any |= act;
+            if (act && rn2[i] > 0.25 * last_rn2[i] && outer > 0) stalled = true;
+            sdown[i] = act ? 1.0 / sqrt(rn2[i]) : 0.0;
+            sup[i] = act ? sqrt(rn2[i]) : 0.0;
+            double itol = prm->inner_tol > 0 ? prm->inner_tol : (inner == DHT_BF16 ? 3e-2 : (inner == DHT_FP32 ? 1e-5 : 0.0));
+            double need = act ? 0.25 * target2[i] / rn2[i] : 1.0;
+            itarget[i] = std::max(itol * itol, need);
+            last_rn2[i] = act ? rn2[i] : last_rn2[i];
+        }
+        if (!any) break;
+        if (stalled && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
+        if (total_iters >= prm->maxiter) break;
+        const size_t lbytes = nh * elem_bytes(inner);
+        const int base = slot_base(inner);
+        DHT_TRY(ws_get(c, base + 7, lbytes, &rlo));   // inner right-hand side
+        DHT_TRY(ws_get(c, base + 8, lbytes, &e));     // inner solution
+        DHT_HIP(hipMemcpyAsync(scl, sdown.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+        DHT_TRY(scale_down(c, r_e, rlo, inner, (const double*)scl, nh, nrhs));
+        if ((prm->fault_inject & 1u) && outer == 0 && inner != DHT_FP64) {
+            // testing hook: poison the first inner right-hand side to exercise the fallback
+            std::vector<double> nanv(nrhs, NAN);
+            DHT_HIP(hipMemcpyAsync(scl, nanv.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+            DHT_TRY(scale_down(c, r_e, rlo, inner, (const double*)scl, nh, nrhs));
+        }
+        BicgResult br;
+        DHT_TRY(bicgstab(c, inner, rlo, e, nrhs, itarget, prm->maxiter - total_iters, &br));
+        int maxit = 0;
+        bool bad = false;
+        for (int i = 0; i < nrhs; i++) {
+            iters[i] += br.iters[i];
+            maxit = std::max(maxit, br.iters[i]);
+            if (br.status[i] == RS_NAN || br.status[i] == RS_BREAKDOWN) {
+                if (br.status[i] == RS_NAN) sup[i] = 0.0;   // discard a poisoned correction
+                bad = true;
+            }
+        }
+        total_iters += std::max(maxit, 1);
+        DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+        DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nh, nrhs));
+        // FP64 true residual of the Schur system
+        DHT_TRY(apply_schur(c, DHT_FP64, X_e, tmpf, tmp_o, nrhs));
+        DHT_TRY(sub(c, bhat, tmpf, r_e, nh));
+        if (bad && inner != DHT_FP64) {
+            inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
+        }
+        for (int i = 0; i < nrhs; i++)
+            if (inner != start_inner && rn2[i] > target2[i])
+                escalated[i] = inner == DHT_FP32 ? DHT_STATUS_FALLBACK_FP32 : DHT_STATUS_FALLBACK_FP64;
+    }
+    // odd sites and the FP64 full-lattice true residual
+    DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false));
+    void* full;
+    DHT_TRY(ws_get(c, WS_XF, 2 * bh, &full));
+    DHT_TRY(apply_full(c, DHT_OP_D, DHT_FP64, X, full, nrhs));
+    DHT_TRY(sub(c, Z, full, full, 2 * nh));
+    std::vector<double> fr2;
+    DHT_TRY(norms2(c, full, 2 * c->g.Vh, nrhs, fr2));
+    bool all_ok = true;
+    for (int i = 0; i < nrhs; i++) {
+        double rr = zn2[i] > 0 ? sqrt(fr2[i] / zn2[i]) : 0.0;
+        bool ok = rr <= prm->tol || zn2[i] == 0.0;
+        all_ok &= ok;
+        if (stats) {
+            stats[i].iters = iters[i];
+            stats[i].outer = outer;
+            stats[i].true_resid = rr;
+            stats[i].status = ok ? escalated[i] : DHT_STATUS_NOT_CONVERGED;
+        }
+    }
+    return all_ok ? DHT_OK : set_error(DHT_ERR_NOT_CONVERGED, "some right-hand sides did not reach the tolerance");
+}
+
+}  // namespace dht
