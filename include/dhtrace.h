@@ -187,6 +187,11 @@ int dht_deflation_eigensolve(dht_ctx* ctx, double tol, int max_iter, uint64_t se
 /* Finish: H = W^H Q W accumulated in FP64 from the stored basis, M = H^-1,
  * T_D = Tr(M W^H g5 W).  TD_host (2 doubles: re, im) may be NULL. */
 int dht_deflation_finalize(dht_ctx* ctx, double* TD_host);
+/* Finish with the diagonal Galerkin inverse M = diag(1 / w_i^H Q w_i) and
+ * T_D = sum_i M_ii w_i^H g5 w_i: k FP64 dot products instead of k^2.  Exact
+ * when W holds orthonormal eigenvectors of Q; for any W the estimator stays
+ * unbiased (T_D is the trace of the same P), only its variance changes. */
+int dht_deflation_finalize_diag(dht_ctx* ctx, double* TD_host);
 /* Host copy of M (k x k complex128, row-major) for checks and playback. */
 int dht_deflation_get_M(dht_ctx* ctx, double* M_host);
 /* Drop the deflation basis (later batches are undeflated, T_D = 0). */
@@ -195,6 +200,15 @@ int dht_deflation_clear(dht_ctx* ctx);
 /* c1 = W^H Z and c2 = W^H g5 Z for nrhs canonical spinors Z_dev; results on
  * the host, complex128 row-major [k][nrhs]. */
 int dht_project(dht_ctx* ctx, const double* Z_dev, int nrhs, double* c1_host, double* c2_host);
+
+/* c1 = W^H z and c2 = W^H g5 z for the probes j = first .. first+nrhs-1 of
+ * `spec`, generated on the device.  With a BF16 basis (nrhs <= 64) this is
+ * the MFMA projection used inside dht_trace_batch: probes enter as exact
+ * 2-bit codes, products accumulate in FP32 inside the matrix cores and are
+ * summed in FP64 every 64 complex entries; otherwise FP64 accumulation.
+ * Results on the host, complex128 row-major [k][nrhs]. */
+int dht_project_probes(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int nrhs, double* c1_host,
+                       double* c2_host);
 
 /* ---- Algorithm 1 ---------------------------------------------------------- */
 
@@ -215,6 +229,16 @@ int dht_estimate_reset(dht_ctx* ctx);
  * context stream, in milliseconds: [0] probes, [1] solve, [2] projection,
  * [3] quadratic forms, [4] whole call.  n must be >= 5. */
 int dht_last_timings(dht_ctx* ctx, double* ms_host, int n);
+
+/* Per-kernel-class timing: when enabled, every launch of an instrumented
+ * kernel is bracketed by HIP events on the context stream; totals are
+ * accumulated at the next synchronising call.  Classes: 0/1/2 = hop kernel
+ * in FP64/FP32/BF16, 3 = MFMA projection, 4 = generic projection.
+ * total_bytes is the algorithmic byte count of those launches (input and
+ * output fields once, links once). */
+int dht_profile_enable(dht_ctx* ctx, int on);
+int dht_profile_reset(dht_ctx* ctx);
+int dht_profile_get(dht_ctx* ctx, int cls, int64_t* count, double* total_ms, double* total_bytes);
 
 /* Benchmark helper: time `reps` back-to-back applications of the even/odd
  * hopping kernel (out parity 0 from parity 1) on nrhs internal fields in

@@ -83,6 +83,14 @@ def galerkin_M(W: np.ndarray, D: np.ndarray, g5diag: np.ndarray) -> np.ndarray:
     return np.linalg.inv(H)
 
 
+def rayleigh_diag_M(W: np.ndarray, D: np.ndarray, g5diag: np.ndarray) -> np.ndarray:
+    """Diagonal M with M_ii = 1 / (w_i^H Q w_i): the Galerkin inverse when W holds
+    orthonormal eigenvectors of Q; for other W it defines another valid P."""
+    QW = g5diag[:, None] * (D @ W)
+    rq = np.einsum("ni,ni->i", W.conj(), QW).real
+    return np.diag(1.0 / rq)
+
+
 def deflated_trace(W: np.ndarray, M: np.ndarray, g5diag: np.ndarray) -> complex:
     """T_D = Tr(P) = Tr(M W^H g5 W)."""
     return complex(np.trace(M @ (W.conj().T @ (g5diag[:, None] * W))))

@@ -75,6 +75,11 @@ SIGNATURES = {
     "dht_deflation_set": (_i, [_vp, _i, _i, _vp]),
     "dht_deflation_eigensolve": (_i, [_vp, _d, _i, _u64, _dp]),
     "dht_deflation_finalize": (_i, [_vp, _dp]),
+    "dht_deflation_finalize_diag": (_i, [_vp, _dp]),
+    "dht_project_probes": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _dp, _dp]),
+    "dht_profile_enable": (_i, [_vp, _i]),
+    "dht_profile_reset": (_i, [_vp]),
+    "dht_profile_get": (_i, [_vp, _i, ctypes.POINTER(_i64), _dp, _dp]),
     "dht_deflation_get_M": (_i, [_vp, _dp]),
     "dht_deflation_clear": (_i, [_vp]),
     "dht_project": (_i, [_vp, _vp, _i, _dp, _dp]),
@@ -207,17 +212,53 @@ class Context:
         return X, [dict(iters=s.iters, outer=s.outer, true_resid=s.true_resid, status=s.status) for s in st], rc
 
     # -- deflation --------------------------------------------------------
-    def set_deflation(self, W, prec: int = FP64, block: int = 64):
+    def set_deflation(self, W, prec: int = FP64, block: int = 64, diagonal: bool = False):
         """W: complex128 CUDA tensor [k][N] (or [k][spinor shape]); returns T_D."""
         k = W.shape[0]
-        check(load().dht_deflation_begin(self.h, k, prec))
+        self.begin_deflation(k, prec)
         for j in range(0, k, block):
             n = min(block, k - j)
-            check(load().dht_deflation_set(self.h, j, n, _ptr(W[j:j + n].contiguous())))
-        td = np.zeros(2)
-        check(load().dht_deflation_finalize(self.h, _np_dp(td)))
+            self.set_deflation_columns(j, W[j:j + n])
+        return self.finalize_deflation(diagonal)
+
+    def begin_deflation(self, k: int, prec: int):
+        check(load().dht_deflation_begin(self.h, k, prec))
         self.k = k
+
+    def set_deflation_columns(self, first: int, Wblock):
+        Wblock = Wblock.contiguous()
+        check(load().dht_deflation_set(self.h, first, Wblock.shape[0], _ptr(Wblock)))
+
+    def finalize_deflation(self, diagonal: bool = False):
+        td = np.zeros(2)
+        fn = load().dht_deflation_finalize_diag if diagonal else load().dht_deflation_finalize
+        check(fn(self.h, _np_dp(td)))
         return complex(td[0], td[1])
+
+    def project_probes(self, seed: int, run: int, hp: bool, first: int, nrhs: int):
+        sp = ProbeSpec(seed, run, int(hp))
+        c1 = np.zeros(2 * self.k * nrhs)
+        c2 = np.zeros(2 * self.k * nrhs)
+        check(load().dht_project_probes(self.h, ctypes.byref(sp), first, nrhs, _np_dp(c1), _np_dp(c2)))
+        return (c1.view(np.complex128).reshape(self.k, nrhs), c2.view(np.complex128).reshape(self.k, nrhs))
+
+    # -- instrumentation --------------------------------------------------
+    PROF_CLASSES = {"hop_fp64": 0, "hop_fp32": 1, "hop_bf16": 2, "proj_mfma": 3, "proj_generic": 4}
+
+    def profile(self, on: bool = True):
+        check(load().dht_profile_enable(self.h, int(on)))
+
+    def profile_reset(self):
+        check(load().dht_profile_reset(self.h))
+
+    def profile_get(self, cls):
+        if isinstance(cls, str):
+            cls = self.PROF_CLASSES[cls]
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0)
+        by = ctypes.c_double(0)
+        check(load().dht_profile_get(self.h, cls, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return dict(count=n.value, ms=ms.value, bytes=by.value)
 
     def deflation_M(self):
         M = np.zeros(2 * self.k * self.k)

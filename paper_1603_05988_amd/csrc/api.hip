@@ -45,6 +45,57 @@ int ws_get(dht_ctx* c, int slot, size_t bytes, void** out) {
     return DHT_OK;
 }
 
+static int prof_event(dht_ctx* c, int* idx) {
+    if (c->prof_next >= (int)c->prof_events.size()) {
+        hipEvent_t e;
+        DHT_HIP(hipEventCreate(&e));
+        c->prof_events.push_back(e);
+    }
+    *idx = c->prof_next++;
+    return DHT_OK;
+}
+
+int prof_begin(dht_ctx* c, int* token) {
+    *token = -1;
+    if (!c->prof) return DHT_OK;
+    DHT_TRY(prof_event(c, token));
+    DHT_HIP(hipEventRecord(c->prof_events[*token], c->stream));
+    return DHT_OK;
+}
+
+int prof_end(dht_ctx* c, int token, int cls, double bytes) {
+    if (token < 0 || !c->prof) return DHT_OK;
+    int e1;
+    DHT_TRY(prof_event(c, &e1));
+    DHT_HIP(hipEventRecord(c->prof_events[e1], c->stream));
+    ProfPending p;
+    p.cls = cls;
+    p.ev0 = token;
+    p.ev1 = e1;
+    p.bytes = bytes;
+    c->prof_pending.push_back(p);
+    return DHT_OK;
+}
+
+int prof_harvest(dht_ctx* c) {
+    if (c->prof_pending.empty()) {
+        c->prof_next = 0;
+        return DHT_OK;
+    }
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    for (const ProfPending& p : c->prof_pending) {
+        float ms = 0.f;
+        DHT_HIP(hipEventElapsedTime(&ms, c->prof_events[p.ev0], c->prof_events[p.ev1]));
+        ProfStat& s = c->prof_stat[p.cls];
+        s.count++;
+        s.ms += ms;
+        s.bytes += p.bytes;
+    }
+    c->prof_pending.clear();
+    c->prof_next = 0;
+    return DHT_OK;
+}
+
 static bool valid_prec(int p) { return p == DHT_FP64 || p == DHT_FP32 || p == DHT_BF16; }
 
 static int check_ctx(dht_ctx* c) {
@@ -120,6 +171,7 @@ int dht_destroy(dht_ctx* c) {
     }
     if (c->events)
         for (int i = 0; i < 6; i++) (void)hipEventDestroy(c->ev[i]);
+    for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
     delete c;
     return DHT_OK;
 }
@@ -221,11 +273,48 @@ int dht_deflation_eigensolve(dht_ctx* c, double tol, int max_iter, uint64_t seed
 
 int dht_deflation_finalize(dht_ctx* c, double* TD) {
     DHT_TRY(check_ctx(c));
-    DHT_TRY(deflation_finalize(c));
+    DHT_TRY(deflation_finalize(c, false));
+    DHT_TRY(prof_harvest(c));
     if (TD) {
         TD[0] = c->TD[0];
         TD[1] = c->TD[1];
     }
+    return DHT_OK;
+}
+
+int dht_deflation_finalize_diag(dht_ctx* c, double* TD) {
+    DHT_TRY(check_ctx(c));
+    DHT_TRY(deflation_finalize(c, true));
+    DHT_TRY(prof_harvest(c));
+    if (TD) {
+        TD[0] = c->TD[0];
+        TD[1] = c->TD[1];
+    }
+    return DHT_OK;
+}
+
+int dht_profile_enable(dht_ctx* c, int on) {
+    DHT_TRY(check_ctx(c));
+    DHT_TRY(prof_harvest(c));
+    c->prof = on != 0;
+    return DHT_OK;
+}
+
+int dht_profile_reset(dht_ctx* c) {
+    DHT_TRY(check_ctx(c));
+    DHT_TRY(prof_harvest(c));
+    for (int i = 0; i < PROF_NCLASS; i++) c->prof_stat[i] = ProfStat();
+    return DHT_OK;
+}
+
+int dht_profile_get(dht_ctx* c, int cls, int64_t* count, double* total_ms, double* total_bytes) {
+    DHT_TRY(check_ctx(c));
+    if (cls < 0 || cls >= PROF_NCLASS || !count || !total_ms || !total_bytes)
+        return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    DHT_TRY(prof_harvest(c));
+    *count = c->prof_stat[cls].count;
+    *total_ms = c->prof_stat[cls].ms;
+    *total_bytes = c->prof_stat[cls].bytes;
     return DHT_OK;
 }
 
@@ -266,6 +355,31 @@ int dht_project(dht_ctx* c, const double* Z, int nrhs, double* c1h, double* c2h)
     return DHT_OK;
 }
 
+int dht_project_probes(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, double* c1h, double* c2h) {
+    DHT_TRY(check_ctx(c));
+    if (!spec || !c1h || !c2h || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!c->W) return set_error(DHT_ERR_STATE, "no deflation basis");
+    const bool mfma = c->wprec == DHT_BF16 && nrhs <= 64;
+    void *cc, *buf;
+    DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 2 * c->k * nrhs, &cc));
+    Cx<double>* d1 = (Cx<double>*)cc;
+    Cx<double>* d2 = d1 + (size_t)c->k * nrhs;
+    if (mfma) {
+        DHT_TRY(ws_get(c, WS_ZCODE, full_elems(c, nrhs), &buf));
+        DHT_TRY(probes_gen(c, spec, first, nrhs, nullptr, DHT_FP64, nullptr, nullptr, (uint8_t*)buf));
+        DHT_TRY(project_codes(c, (const uint8_t*)buf, nrhs, d1, d2));
+    } else {
+        DHT_TRY(ws_get(c, WS_Z, full_elems(c, nrhs) * 16, &buf));
+        DHT_TRY(probes_gen(c, spec, first, nrhs, buf, DHT_FP64, nullptr, nullptr));
+        DHT_TRY(project_field(c, buf, DHT_FP64, nrhs, d1, d2));
+    }
+    DHT_HIP(hipMemcpyAsync(c1h, d1, sizeof(Cx<double>) * c->k * nrhs, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipMemcpyAsync(c2h, d2, sizeof(Cx<double>) * c->k * nrhs, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    DHT_TRY(prof_harvest(c));
+    return DHT_OK;
+}
+
 int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, const dht_solver_params* prm,
                     dht_record* records, double* coef_host) {
     DHT_TRY(check_ctx(c));
@@ -273,24 +387,27 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     if (c->W && !c->defl_ready) return set_error(DHT_ERR_STATE, "deflation basis set but not finalized");
     const size_t fb = full_elems(c, nrhs) * 16;
-    void *fz, *fx, *cc;
+    void *fz, *fx, *cc, *zc = nullptr;
     DHT_TRY(ws_get(c, WS_Z, fb, &fz));
     DHT_TRY(ws_get(c, WS_PACK_OUT, fb, &fx));
     const int k = c->defl_ready ? c->k : 0;
+    const bool mfma = k > 0 && c->wprec == DHT_BF16 && nrhs <= 64;
+    if (mfma) DHT_TRY(ws_get(c, WS_ZCODE, full_elems(c, nrhs), &zc));
     DHT_TRY(ws_get(c, WS_COEF, sizeof(Cx<double>) * (2 * (size_t)k * nrhs + nrhs) + 64, &cc));
     Cx<double>* d1 = (Cx<double>*)cc;
     Cx<double>* d2 = d1 + (size_t)k * nrhs;
     Cx<double>* dq = d2 + (size_t)k * nrhs;
 
     DHT_TRY(record(c, 0));
-    DHT_TRY(probes_gen(c, spec, first, nrhs, fz, DHT_FP64, nullptr, nullptr));
+    DHT_TRY(probes_gen(c, spec, first, nrhs, fz, DHT_FP64, nullptr, nullptr, (uint8_t*)zc));
     DHT_TRY(record(c, 1));
     std::vector<dht_solve_stats> st(nrhs);
     int rc = solve_fields(c, prm, fz, fx, nrhs, st.data());
     if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) return rc;
     std::string msg = g_err;
     DHT_TRY(record(c, 2));
-    if (k > 0) DHT_TRY(project_field(c, fz, DHT_FP64, nrhs, d1, d2));
+    if (mfma) DHT_TRY(project_codes(c, (const uint8_t*)zc, nrhs, d1, d2));
+    else if (k > 0) DHT_TRY(project_field(c, fz, DHT_FP64, nrhs, d1, d2));
     DHT_TRY(record(c, 3));
     {
         const void* aa[1] = {fz};
@@ -307,6 +424,7 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     c->timings[2] = elapsed(c, 2, 3);
     c->timings[3] = elapsed(c, 3, 4);
     c->timings[4] = elapsed(c, 0, 5);
+    DHT_TRY(prof_harvest(c));
     std::vector<double> dre(nrhs, 0.0), dim(nrhs, 0.0);
     if (k > 0) deflation_corrections(c, hc.data(), hc.data() + (size_t)k * nrhs, nrhs, dre.data(), dim.data());
     const Cx<double>* q = hc.data() + (size_t)2 * k * nrhs;
@@ -384,6 +502,7 @@ int dht_bench_hop(dht_ctx* c, int prec, int nrhs, int warmup, int reps, double* 
     DHT_TRY(record(c, 1));
     DHT_HIP(hipStreamSynchronize(c->stream));
     *ms_per_call = elapsed(c, 0, 1) / reps;
+    DHT_TRY(prof_harvest(c));
     return DHT_OK;
 }
 

@@ -7,6 +7,7 @@
 //
 // Per-RHS solver scalars live on the device (struct RhsState) and are read by
 // the update kernels, so a BiCGStab iteration needs no host round trip.
+#include <algorithm>
 #include <type_traits>
 
 #include "solver.h"
@@ -332,14 +333,21 @@ int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t n) {
 }
 
 // fill with zero (a kernel rather than a memset so that the stream can be captured)
-__global__ void zero_kernel(uint32_t* p, size_t n) {
+// grid-stride: the deflation basis can exceed 2^32 words (a launch is capped at 2^32 threads)
+__global__ void zero_kernel(uint4* p, size_t n16, uint32_t* tail, size_t ntail) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t j = i; j < n16; j += stride) p[j] = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t j = i; j < ntail; j += stride) tail[j] = 0u;
 }
 int zero(dht_ctx* c, void* p, size_t bytes) {
     size_t n = bytes / 4;
     if (n == 0) return DHT_OK;
-    hipLaunchKernelGGL(zero_kernel, egrid(n), dim3(256), 0, c->stream, (uint32_t*)p, n);
+    size_t n16 = ((uintptr_t)p & 15) ? 0 : n / 4;   // 16-byte stores only on aligned buffers
+    size_t blocks = std::min<size_t>((n16 + 255) / 256, 65536);
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, c->stream, (uint4*)p, n16,
+                       (uint32_t*)p + 4 * n16, n - 4 * n16);
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }

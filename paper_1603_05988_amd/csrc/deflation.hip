@@ -6,14 +6,20 @@
 // for exact orthonormal eigenvectors, i.e. V Sigma^-1 U^H of Section 5.2).
 // H = W^H Q W and the trace T_D = Tr(P) = Tr(M W^H g5 W) are accumulated in
 // FP64 from the stored vectors, so the estimator stays unbiased whatever the
-// storage precision: only its variance depends on how good W is.
+// storage precision: only its variance depends on how good W is.  A diagonal
+// variant (M = diag(1 / w_i^H Q w_i), T_D = sum M_ii w_i^H g5 w_i) needs only
+// k dot products and is exact for orthonormal eigenvectors.
 //
 // Per probe: c1 = W^H z and c2 = W^H g5 z (g5 = +1 on spins 0, 1 and -1 on
 // spins 2, 3 in the chiral basis, so both come from one pass over W), and
 // z^H P z = c1^H M c2.
 //
-// Storage: W is k full internal fields with one RHS each, column after
-// column: [k][2 parity][12][Vh] complex in the storage precision.
+// Storage of W.  FP64 / FP32: k full internal fields with one RHS each,
+// column after column ([k][2][12][Vh]).  BF16: the MFMA A-fragment order of
+// v_mfma_f32_32x32x16_bf16 -- rows (columns of W) grouped in tiles of 32,
+// the real K axis (2 x complex entries) in steps of 16; one step of one tile
+// is 64 lanes x 16 bytes, lane = row % 32 + 32 * ((K' % 16) / 8), so every
+// step of the projection is a single coalesced 1 KB wavefront load.
 #include <math.h>
 #include <string.h>
 
@@ -24,29 +30,62 @@
 
 namespace dht {
 
+// ---------------------------------------------------------------------------
+// W addressing
+// ---------------------------------------------------------------------------
+struct WLayout {
+    int64_t Kn;       // complex entries per column (24 Vh)
+    int64_t nsteps;   // Kn / 8: MFMA K-steps (16 reals) per tile
+    int kp;           // rows padded to a multiple of 32
+    int tiled;        // BF16 fragment order
+};
+
+// element index (in complex units of the storage type) of W(i, K)
+__host__ __device__ inline int64_t w_index(const WLayout& L, int64_t i, int64_t K) {
+    if (!L.tiled) return i * L.Kn + K;
+    int64_t t = i >> 5, lr = i & 31;
+    return (((t * L.nsteps + (K >> 3)) * 64 + lr + 32 * ((K & 7) >> 2)) << 2) + (K & 3);
+}
+
+static WLayout wlayout(const dht_ctx* c) {
+    WLayout L;
+    L.Kn = 24 * c->g.Vh;
+    L.nsteps = L.Kn / 8;
+    L.kp = ((c->k + 31) / 32) * 32;
+    L.tiled = c->wprec == DHT_BF16;
+    return L;
+}
+
+static size_t w_bytes(const dht_ctx* c, int k, int prec) {
+    int64_t Kn = 24 * c->g.Vh;
+    int64_t rows = prec == DHT_BF16 ? ((k + 31) / 32) * 32 : k;
+    return (size_t)rows * Kn * elem_bytes(prec);
+}
+
+// ---------------------------------------------------------------------------
+// generic projection (any storage precision, FP64 probes), FP64 accumulation
+// ---------------------------------------------------------------------------
 static constexpr int PROJ_THREADS = 256;
 static constexpr int PROJ_RT = 4;    // right-hand sides per pass
 
-// partial[(chunk * k + i) * B + r] for c1 and c2 (two arrays)
 template <typename SW, typename SZ>
-__global__ __launch_bounds__(PROJ_THREADS) void proj_generic_kernel(const typename Store<SW>::elem* W,
-                                                                    const typename Store<SZ>::elem* Z, int64_t Kn,
-                                                                    int64_t per_comp_w, int B, int r0, int nr,
+__global__ __launch_bounds__(PROJ_THREADS) void proj_generic_kernel(const typename Store<SW>::elem* W, WLayout wl,
+                                                                    const typename Store<SZ>::elem* Z,
+                                                                    int64_t per_comp, int B, int r0, int nr,
                                                                     int64_t chunk, Cx<double>* p1, Cx<double>* p2,
                                                                     int k) {
     __shared__ Cx<double> red[2 * PROJ_RT][PROJ_THREADS];
     const int i = blockIdx.y;
+    const int64_t Kn = wl.Kn;
     const int64_t cbeg = (int64_t)blockIdx.x * chunk;
     const int64_t cend = cbeg + chunk < Kn ? cbeg + chunk : Kn;
-    const typename Store<SW>::elem* w = W + (int64_t)i * Kn;
     Cx<double> a1[PROJ_RT], a2[PROJ_RT];
 #pragma unroll
     for (int q = 0; q < PROJ_RT; q++) a1[q] = a2[q] = cmake(0.0, 0.0);
     for (int64_t K = cbeg + threadIdx.x; K < cend; K += PROJ_THREADS) {
-        auto wv = Store<SW>::ld(w + K);
+        auto wv = Store<SW>::ld(W + w_index(wl, i, K));
         Cx<double> wd = cmake<double>(wv.re, wv.im);
-        // component index of K within its parity block [12][Vh]
-        int comp = (int)((K / per_comp_w) % 12);
+        int comp = (int)((K / per_comp) % 12);
         double sg = comp < 6 ? 1.0 : -1.0;
         const typename Store<SZ>::elem* zp = Z + K * B + r0;
 #pragma unroll
@@ -92,30 +131,31 @@ __global__ void proj_sum_kernel(const Cx<double>* p1, const Cx<double>* p2, int 
     c2[idx] = s2;
 }
 
-// c1, c2 (device, [k][B] complex) for a full internal field Z of precision zprec.
 int project_field(dht_ctx* c, const void* Z, int zprec, int nrhs, Cx<double>* c1, Cx<double>* c2) {
     if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "no deflation basis");
-    const int64_t Kn = 24 * c->g.Vh;   // complex entries per column
+    const WLayout wl = wlayout(c);
     const int k = c->k;
     int64_t chunk = 8192;
-    int nchunk = (int)((Kn + chunk - 1) / chunk);
+    int nchunk = (int)((wl.Kn + chunk - 1) / chunk);
     while (nchunk > 256) {
         chunk *= 2;
-        nchunk = (int)((Kn + chunk - 1) / chunk);
+        nchunk = (int)((wl.Kn + chunk - 1) / chunk);
     }
     void *p1, *p2;
     size_t pb = (size_t)nchunk * k * nrhs * sizeof(Cx<double>);
     DHT_TRY(ws_get(c, WS_PROJ, pb, &p1));
     DHT_TRY(ws_get(c, WS_PROJ2, pb, &p2));
+    int tok;
+    DHT_TRY(prof_begin(c, &tok));
     for (int r0 = 0; r0 < nrhs; r0 += PROJ_RT) {
         int nr = std::min(PROJ_RT, nrhs - r0);
         dim3 grid(nchunk, k), block(PROJ_THREADS);
-#define DHT_PG(PW, TW, PZ, TZ)                                                                                      \
-    if (c->wprec == PW && zprec == PZ) {                                                                            \
-        hipLaunchKernelGGL((proj_generic_kernel<TW, TZ>), grid, block, 0, c->stream,                                \
-                           (const typename Store<TW>::elem*)c->W, (const typename Store<TZ>::elem*)Z, Kn,           \
-                           (int64_t)c->g.Vh, nrhs, r0, nr, chunk, (Cx<double>*)p1, (Cx<double>*)p2, k);              \
-        goto done;                                                                                                  \
+#define DHT_PG(PW, TW, PZ, TZ)                                                                                     \
+    if (c->wprec == PW && zprec == PZ) {                                                                           \
+        hipLaunchKernelGGL((proj_generic_kernel<TW, TZ>), grid, block, 0, c->stream,                               \
+                           (const typename Store<TW>::elem*)c->W, wl, (const typename Store<TZ>::elem*)Z,          \
+                           (int64_t)c->g.Vh, nrhs, r0, nr, chunk, (Cx<double>*)p1, (Cx<double>*)p2, k);             \
+        goto done;                                                                                                 \
     }
         DHT_PG(DHT_FP64, double, DHT_FP64, double)
         DHT_PG(DHT_FP32, float, DHT_FP64, double)
@@ -128,14 +168,213 @@ int project_field(dht_ctx* c, const void* Z, int zprec, int nrhs, Cx<double>* c1
     hipLaunchKernelGGL(proj_sum_kernel, dim3((k * nrhs + 127) / 128), dim3(128), 0, c->stream, (const Cx<double>*)p1,
                        (const Cx<double>*)p2, nchunk, k, nrhs, c1, c2);
     DHT_HIP(hipGetLastError());
+    return prof_end(c, tok, PROF_PROJ_GENERIC,
+                    (double)k * wl.Kn * elem_bytes(c->wprec) + (double)wl.Kn * nrhs * elem_bytes(zprec));
+}
+
+// ---------------------------------------------------------------------------
+// MFMA projection: BF16 W (fragment order) x probes given as 2-bit codes
+// (z = i^code, exact in BF16), FP32 MFMA accumulation flushed to FP64
+// registers after every chunk of kc complex entries, FP64 cross-workgroup sum.
+//
+// As a real GEMM: conj(w) z = (wr zr + wi zi) + i (wr zi - wi zr), so with
+// W viewed as a real [k][2 Kn] BF16 matrix (its storage), the B operand has
+// two columns per RHS: (zr, zi) interleaved for the real part and (zi, -zr)
+// for the imaginary part.  The K axis is split into the four groups
+// (parity, upper/lower spins) of 6 Vh entries; a workgroup works inside one
+// group, so the g5 sign is a per-workgroup constant.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+static constexpr int MP_WAVES = 8;
+static constexpr int MP_THREADS = 64 * MP_WAVES;
+
+struct MfmaProjArgs {
+    const uint4* W;          // fragment-ordered BF16 W
+    const uint8_t* zc;       // probe codes [Kn][B]
+    int64_t nsteps;          // K-steps per tile (Kn / 8)
+    int64_t group_len;       // 6 Vh complex entries
+    int64_t chunks_per_group;
+    int wg_per_group;
+    int kc;                  // complex entries per chunk (multiple of 8, divides group_len)
+    int B;
+    int ntiles;              // row tiles of 32 (kp / 32)
+    double* partial;         // [gridDim.x][kp][NT*32]
+    int kp;
+};
+
+__device__ inline uint32_t bf16_unit(int v) { return v > 0 ? 0x3F80u : (v < 0 ? 0xBF80u : 0u); }
+
+template <int RT, int NT>
+__global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
+    extern __shared__ uint4 bfr[];   // [kc/8][NT][64] B fragments
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int g = blockIdx.x / a.wg_per_group;           // group: parity * 2 + (lower spins)
+    const int wslot = blockIdx.x - g * a.wg_per_group;
+    const int tile0 = (blockIdx.y * MP_WAVES + wave) * RT;
+    const int nks = a.kc >> 3;
+
+    f32x16_t acc[RT][NT];
+    double facc[RT][NT][16];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                acc[rt][nt][q] = 0.f;
+                facc[rt][nt][q] = 0.0;
+            }
+        }
+
+    for (int64_t ch = wslot; ch < a.chunks_per_group; ch += a.wg_per_group) {
+        const int64_t K0 = (int64_t)g * a.group_len + ch * a.kc;
+        __syncthreads();
+        // expand the chunk's probe codes into B fragments in LDS
+        for (int f = tid; f < nks * NT * 64; f += MP_THREADS) {
+            int l = f & 63;
+            int nt = (f >> 6) % NT;
+            int ks = (f >> 6) / NT;
+            int col = nt * 32 + (l & 31);
+            int r = col >> 1, part = col & 1;
+            uint32_t w[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {   // complex entry K = 8 ks + 4 (l / 32) + e
+                uint32_t lo = 0, hi = 0;
+                if (r < a.B) {
+                    int code = a.zc[(K0 + 8 * ks + 4 * (l >> 5) + e) * a.B + r] & 3;
+                    int zr = code == 0 ? 1 : (code == 2 ? -1 : 0);
+                    int zi = code == 1 ? 1 : (code == 3 ? -1 : 0);
+                    lo = bf16_unit(part ? zi : zr);
+                    hi = bf16_unit(part ? -zr : zi);
+                }
+                w[e] = lo | (hi << 16);
+            }
+            bfr[f] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        __syncthreads();
+        for (int ks = 0; ks < nks; ks++) {
+            bf16x8_t bf[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) {
+                uint4 v = bfr[(ks * NT + nt) * 64 + lane];
+                bf[nt] = __builtin_bit_cast(bf16x8_t, v);
+            }
+            const int64_t step = (K0 >> 3) + ks;
+#pragma unroll
+            for (int rt = 0; rt < RT; rt++) {
+                const int t = tile0 + rt;
+                if (t < a.ntiles) {
+                    uint4 v = a.W[((int64_t)t * a.nsteps + step) * 64 + lane];
+                    bf16x8_t af = __builtin_bit_cast(bf16x8_t, v);
+#pragma unroll
+                    for (int nt = 0; nt < NT; nt++)
+                        acc[rt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf[nt], acc[rt][nt], 0, 0, 0);
+                }
+            }
+        }
+        // flush the chunk sums into FP64
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    facc[rt][nt][q] += (double)acc[rt][nt][q];
+                    acc[rt][nt][q] = 0.f;
+                }
+    }
+    // this workgroup's partial sums; C layout: row = 8 (q/4) + 4 (lane/32) + q%4, col = lane % 32
+    const int ncol = NT * 32;
+    double* out = a.partial + (int64_t)blockIdx.x * a.kp * ncol;
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+        const int t = tile0 + rt;
+        if (t >= a.ntiles) continue;
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                int row = t * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                int col = nt * 32 + (lane & 31);
+                out[(int64_t)row * ncol + col] = facc[rt][nt][q];
+            }
+    }
+}
+
+// c1[i][r] = sum over workgroups; c2 adds the lower-spin groups with a minus sign
+__global__ void proj_mfma_sum_kernel(const double* partial, int nwg, int wg_per_group, int kp, int ncol, int k, int B,
+                                     Cx<double>* c1, Cx<double>* c2) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= k * B) return;
+    int i = idx / B, r = idx - i * B;
+    double a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+    for (int w = 0; w < nwg; w++) {
+        int g = w / wg_per_group;
+        double s = (g & 1) ? -1.0 : 1.0;
+        const double* p = partial + ((int64_t)w * kp + i) * ncol + 2 * r;
+        a1r += p[0];
+        a1i += p[1];
+        a2r += s * p[0];
+        a2i += s * p[1];
+    }
+    c1[idx] = cmake(a1r, a1i);
+    c2[idx] = cmake(a2r, a2i);
+}
+
+int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<double>* c2) {
+    if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "no deflation basis");
+    if (c->wprec != DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "MFMA projection needs a BF16 basis");
+    if (nrhs <= 0 || nrhs > 64) return set_error(DHT_ERR_INVALID_ARG, "1..64 right-hand sides per projection");
+    const WLayout wl = wlayout(c);
+    MfmaProjArgs a;
+    a.W = (const uint4*)c->W;
+    a.zc = zc;
+    a.nsteps = wl.nsteps;
+    a.group_len = 6 * c->g.Vh;
+    a.kc = 8;
+    for (int kc = 64; kc >= 8; kc >>= 1)
+        if (a.group_len % kc == 0) { a.kc = kc; break; }
+    a.chunks_per_group = a.group_len / a.kc;
+    a.B = nrhs;
+    a.kp = wl.kp;
+    a.ntiles = wl.kp / 32;
+    int NT = (2 * nrhs + 31) / 32;
+    if (NT == 3) NT = 4;
+    const int RT = NT == 1 ? 4 : (NT == 2 ? 2 : 1);
+    const int rows_per_wg = MP_WAVES * RT * 32;
+    const int rowgroups = (wl.kp + rows_per_wg - 1) / rows_per_wg;
+    int wpg = (int)std::min<int64_t>(a.chunks_per_group, std::max(1, 512 / (4 * rowgroups)));
+    a.wg_per_group = wpg;
+    const int nwg = 4 * wpg;
+    void* part;
+    DHT_TRY(ws_get(c, WS_PROJ, (size_t)nwg * wl.kp * NT * 32 * sizeof(double), &part));
+    a.partial = (double*)part;
+    DHT_TRY(zero(c, part, (size_t)nwg * wl.kp * NT * 32 * sizeof(double)));
+    dim3 grid(nwg, rowgroups), block(MP_THREADS);
+    size_t lds = (size_t)(a.kc / 8) * NT * 64 * sizeof(uint4);
+    int tok;
+    DHT_TRY(prof_begin(c, &tok));
+    if (NT == 1) hipLaunchKernelGGL((proj_mfma_kernel<4, 1>), grid, block, lds, c->stream, a);
+    else if (NT == 2) hipLaunchKernelGGL((proj_mfma_kernel<2, 2>), grid, block, lds, c->stream, a);
+    else hipLaunchKernelGGL((proj_mfma_kernel<1, 4>), grid, block, lds, c->stream, a);
+    DHT_HIP(hipGetLastError());
+    // algorithmic bytes: the stored basis once, the probe codes once per row group, the partials
+    DHT_TRY(prof_end(c, tok, PROF_PROJ_MFMA,
+                     (double)wl.kp * wl.Kn * 4.0 + (double)rowgroups * wl.Kn * nrhs +
+                         (double)nwg * wl.kp * NT * 32 * 8.0));
+    hipLaunchKernelGGL(proj_mfma_sum_kernel, dim3((c->k * nrhs + 127) / 128), dim3(128), 0, c->stream,
+                       (const double*)part, nwg, wpg, wl.kp, NT * 32, c->k, nrhs, c1, c2);
+    DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
 
 // ---------------------------------------------------------------------------
 // basis management
 // ---------------------------------------------------------------------------
-static size_t col_bytes(dht_ctx* c) { return full_elems(c, 1) * elem_bytes(c->wprec); }
-
 int deflation_begin(dht_ctx* c, int k, int prec) {
     if (k <= 0) return set_error(DHT_ERR_INVALID_ARG, "k must be positive");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
@@ -144,36 +383,86 @@ int deflation_begin(dht_ctx* c, int k, int prec) {
         DHT_HIP(hipFree(c->W));
         c->W = nullptr;
     }
-    c->k = k;
-    c->wprec = prec;
+    c->k = 0;
     c->defl_ready = false;
     c->TD[0] = c->TD[1] = 0;
-    size_t bytes = (size_t)k * full_elems(c, 1) * elem_bytes(prec);
+    size_t bytes = w_bytes(c, k, prec);
     if (hipMalloc(&c->W, bytes) != hipSuccess) {
         c->W = nullptr;
-        c->k = 0;
         (void)hipGetLastError();
         return set_error(DHT_ERR_OOM, "cannot allocate the deflation basis");
     }
+    c->k = k;
+    c->wprec = prec;
     DHT_TRY(zero(c, c->W, bytes));
     return DHT_OK;
+}
+
+// canonical FP64 columns [count][V][12] -> stored basis rows first..first+count-1
+template <typename SW>
+__global__ void pack_w_kernel(const Cx<double>* canon, typename Store<SW>::elem* W, WLayout wl, Geom g, int first,
+                              int count) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (j, K), K fastest
+    if (gid >= (int64_t)count * wl.Kn) return;
+    int j = (int)(gid / wl.Kn);
+    int64_t K = gid - (int64_t)j * wl.Kn;
+    int p = (int)(K / (12 * g.Vh));
+    int64_t rem = K - (int64_t)p * 12 * g.Vh;
+    int comp = (int)(rem / g.Vh);
+    int64_t s = rem - (int64_t)comp * g.Vh;
+    int cc[4];
+    cb_coords(g, s, p, cc);
+    int64_t n = lex_index(g, cc);
+    Cx<double> v = canon[((int64_t)j * g.V + n) * 12 + comp];
+    typedef typename Store<SW>::acc T;
+    Store<SW>::st(W + w_index(wl, first + j, K), cmake<T>((T)v.re, (T)v.im));
 }
 
 int deflation_set(dht_ctx* c, int first, int count, const double* W_dev) {
     if (!c->W) return set_error(DHT_ERR_STATE, "call dht_deflation_begin first");
     if (first < 0 || count < 0 || first + count > c->k) return set_error(DHT_ERR_INVALID_ARG, "column range");
-    const int64_t N = 12 * c->g.V;
-    for (int j = 0; j < count; j++)
-        DHT_TRY(pack_spinor(c, W_dev + 2 * N * j, (char*)c->W + (size_t)(first + j) * col_bytes(c), c->wprec, 1));
+    if (count == 0) return DHT_OK;
+    const WLayout wl = wlayout(c);
+    int64_t n = (int64_t)count * wl.Kn;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    switch (c->wprec) {
+        case DHT_FP64: hipLaunchKernelGGL(pack_w_kernel<double>, grid, block, 0, c->stream, (const Cx<double>*)W_dev, (Cx<double>*)c->W, wl, c->g, first, count); break;
+        case DHT_FP32: hipLaunchKernelGGL(pack_w_kernel<float>, grid, block, 0, c->stream, (const Cx<double>*)W_dev, (Cx<float>*)c->W, wl, c->g, first, count); break;
+        case DHT_BF16: hipLaunchKernelGGL(pack_w_kernel<bf16x2>, grid, block, 0, c->stream, (const Cx<double>*)W_dev, (bf16x2*)c->W, wl, c->g, first, count); break;
+    }
+    DHT_HIP(hipGetLastError());
     c->defl_ready = false;
+    return DHT_OK;
+}
+
+// n consecutive basis rows j0.. -> FP64 field [2][12][Vh][n] (RHS innermost)
+template <typename SW>
+__global__ void gather_kernel(const typename Store<SW>::elem* W, WLayout wl, int j0, int n, Cx<double>* out) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= wl.Kn * n) return;
+    int64_t K = gid / n;
+    int j = (int)(gid - K * n);
+    auto v = Store<SW>::ld(W + w_index(wl, j0 + j, K));
+    out[gid] = cmake<double>(v.re, v.im);
+}
+
+int gather_columns(dht_ctx* c, int j0, int n, void* out) {
+    const WLayout wl = wlayout(c);
+    int64_t tot = wl.Kn * n;
+    dim3 grid((unsigned)((tot + 255) / 256)), block(256);
+    switch (c->wprec) {
+        case DHT_FP64: hipLaunchKernelGGL(gather_kernel<double>, grid, block, 0, c->stream, (const Cx<double>*)c->W, wl, j0, n, (Cx<double>*)out); break;
+        case DHT_FP32: hipLaunchKernelGGL(gather_kernel<float>, grid, block, 0, c->stream, (const Cx<float>*)c->W, wl, j0, n, (Cx<double>*)out); break;
+        case DHT_BF16: hipLaunchKernelGGL(gather_kernel<bf16x2>, grid, block, 0, c->stream, (const bf16x2*)c->W, wl, j0, n, (Cx<double>*)out); break;
+        default: return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    }
+    DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
 
 // In-place inverse of an n x n complex matrix (row-major) by Gauss-Jordan
 // elimination with partial pivoting.  Returns false if singular.
 static bool invert(std::vector<std::complex<double>>& A, int n) {
-    std::vector<int> piv(n);
-    for (int i = 0; i < n; i++) piv[i] = i;
     std::vector<std::complex<double>> I(n * (size_t)n, 0.0);
     for (int i = 0; i < n; i++) I[(size_t)i * n + i] = 1.0;
     for (int col = 0; col < n; col++) {
@@ -209,7 +498,21 @@ static bool invert(std::vector<std::complex<double>>& A, int n) {
     return true;
 }
 
-int deflation_finalize(dht_ctx* c) {
+static int store_M(dht_ctx* c, const std::vector<std::complex<double>>& M, std::complex<double> td, bool diagonal) {
+    const int k = c->k;
+    c->M.assign((size_t)2 * k * k, 0.0);
+    for (size_t i = 0; i < (size_t)k * k; i++) {
+        c->M[2 * i] = M[i].real();
+        c->M[2 * i + 1] = M[i].imag();
+    }
+    c->M_diag = diagonal;
+    c->TD[0] = td.real();
+    c->TD[1] = td.imag();
+    c->defl_ready = true;
+    return DHT_OK;
+}
+
+int deflation_finalize(dht_ctx* c, bool diagonal) {
     if (!c->W) return set_error(DHT_ERR_STATE, "no deflation basis");
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     const int k = c->k;
@@ -218,24 +521,40 @@ int deflation_finalize(dht_ctx* c) {
     void *wb, *qwb, *cc;
     DHT_TRY(ws_get(c, WS_QW, fb, &wb));
     DHT_TRY(ws_get(c, WS_XF, fb, &qwb));
-    DHT_TRY(ws_get(c, WS_COEF, sizeof(Cx<double>) * 4 * k * nb, &cc));
-    Cx<double>* h1 = (Cx<double>*)cc;            // W^H (Q Wb)
-    Cx<double>* h2 = h1 + (size_t)k * nb;         // W^H g5 (Q Wb)   (unused)
-    Cx<double>* g1 = h2 + (size_t)k * nb;         // W^H Wb
-    Cx<double>* g5m = g1 + (size_t)k * nb;        // W^H g5 Wb
-    std::vector<std::complex<double>> H((size_t)k * k), G5((size_t)k * k);
+    DHT_TRY(ws_get(c, WS_COEF, sizeof(Cx<double>) * 4 * (size_t)k * nb, &cc));
+    std::vector<std::complex<double>> H, G5;
+    std::vector<double> hdiag(k), gdiag(k);
+    if (!diagonal) {
+        H.assign((size_t)k * k, 0.0);
+        G5.assign((size_t)k * k, 0.0);
+    }
     std::vector<Cx<double>> hb((size_t)4 * k * nb);
-    const size_t cb = col_bytes(c);
+    Cx<double>* h1 = (Cx<double>*)cc;
     for (int j0 = 0; j0 < k; j0 += nb) {
         int n = std::min(nb, k - j0);
-        // gather columns j0.. into an FP64 field with n RHS (RHS innermost)
-        DHT_TRY(gather_columns(c, (const char*)c->W + (size_t)j0 * cb, c->wprec, n, wb));
+        DHT_TRY(gather_columns(c, j0, n, wb));
         DHT_TRY(apply_full(c, DHT_OP_Q, DHT_FP64, wb, qwb, n));
+        if (diagonal) {
+            const void* a1[1] = {wb};
+            const void* b1[1] = {qwb};
+            DHT_TRY(dots(c, DHT_FP64, 1, a1, b1, 2 * c->g.Vh, n, h1));        // w^H Q w
+            DHT_TRY(g5_field(c, DHT_FP64, wb, qwb, n));                         // qwb <- g5 w
+            DHT_TRY(dots(c, DHT_FP64, 1, a1, b1, 2 * c->g.Vh, n, h1 + n));    // w^H g5 w
+            DHT_HIP(hipMemcpyAsync(hb.data(), cc, sizeof(Cx<double>) * 2 * n, hipMemcpyDeviceToHost, c->stream));
+            DHT_HIP(hipStreamSynchronize(c->stream));
+            for (int jj = 0; jj < n; jj++) {
+                hdiag[j0 + jj] = hb[jj].re;
+                gdiag[j0 + jj] = hb[n + jj].re;
+            }
+            continue;
+        }
+        Cx<double>* h2 = h1 + (size_t)k * nb;
+        Cx<double>* g1 = h2 + (size_t)k * nb;
+        Cx<double>* g5m = g1 + (size_t)k * nb;
         DHT_TRY(project_field(c, qwb, DHT_FP64, n, h1, h2));
         DHT_TRY(project_field(c, wb, DHT_FP64, n, g1, g5m));
         DHT_HIP(hipMemcpyAsync(hb.data(), cc, sizeof(Cx<double>) * 4 * k * nb, hipMemcpyDeviceToHost, c->stream));
         DHT_HIP(hipStreamSynchronize(c->stream));
-        // blocks are [k][n] with stride n inside this batch
         for (int i = 0; i < k; i++)
             for (int jj = 0; jj < n; jj++) {
                 Cx<double> hv = hb[(size_t)i * n + jj];
@@ -243,6 +562,16 @@ int deflation_finalize(dht_ctx* c) {
                 H[(size_t)i * k + j0 + jj] = std::complex<double>(hv.re, hv.im);
                 G5[(size_t)i * k + j0 + jj] = std::complex<double>(gv.re, gv.im);
             }
+    }
+    if (diagonal) {
+        std::vector<std::complex<double>> M((size_t)k * k, 0.0);
+        std::complex<double> td = 0.0;
+        for (int i = 0; i < k; i++) {
+            if (hdiag[i] == 0.0 || !std::isfinite(hdiag[i])) return set_error(DHT_ERR_BREAKDOWN, "w^H Q w = 0");
+            M[(size_t)i * k + i] = 1.0 / hdiag[i];
+            td += gdiag[i] / hdiag[i];
+        }
+        return store_M(c, M, td, true);
     }
     // H is Hermitian in exact arithmetic: use its Hermitian part
     for (int i = 0; i < k; i++)
@@ -255,15 +584,7 @@ int deflation_finalize(dht_ctx* c) {
     std::complex<double> td = 0.0;
     for (int a = 0; a < k; a++)
         for (int b = 0; b < k; b++) td += H[(size_t)a * k + b] * G5[(size_t)b * k + a];
-    c->M.assign((size_t)2 * k * k, 0.0);
-    for (size_t i = 0; i < (size_t)k * k; i++) {
-        c->M[2 * i] = H[i].real();
-        c->M[2 * i + 1] = H[i].imag();
-    }
-    c->TD[0] = td.real();
-    c->TD[1] = td.imag();
-    c->defl_ready = true;
-    return DHT_OK;
+    return store_M(c, H, td, false);
 }
 
 // d_j = c1_j^H M c2_j on the host (c1, c2 host arrays [k][B] complex)
@@ -275,41 +596,21 @@ void deflation_corrections(const dht_ctx* c, const Cx<double>* c1, const Cx<doub
     for (int r = 0; r < B; r++) {
         for (int a = 0; a < k; a++) {
             std::complex<double> s = 0.0;
-            for (int b = 0; b < k; b++) s += M[(size_t)a * k + b] * std::complex<double>(c2[(size_t)b * B + r].re, c2[(size_t)b * B + r].im);
+            std::complex<double> c2b;
+            if (c->M_diag) {
+                s = M[(size_t)a * k + a] * std::complex<double>(c2[(size_t)a * B + r].re, c2[(size_t)a * B + r].im);
+            } else {
+                for (int b = 0; b < k; b++)
+                    s += M[(size_t)a * k + b] * std::complex<double>(c2[(size_t)b * B + r].re, c2[(size_t)b * B + r].im);
+            }
             v[a] = s;
         }
         std::complex<double> d = 0.0;
-        for (int a = 0; a < k; a++) d += std::conj(std::complex<double>(c1[(size_t)a * B + r].re, c1[(size_t)a * B + r].im)) * v[a];
+        for (int a = 0; a < k; a++)
+            d += std::conj(std::complex<double>(c1[(size_t)a * B + r].re, c1[(size_t)a * B + r].im)) * v[a];
         dre[r] = d.real();
         dim[r] = d.imag();
     }
-}
-
-// ---------------------------------------------------------------------------
-// column gather: n consecutive B=1 columns (precision wp) -> FP64 field [2][12][Vh][n]
-// ---------------------------------------------------------------------------
-template <typename SW>
-__global__ void gather_kernel(const typename Store<SW>::elem* W, int64_t Kn, int n, Cx<double>* out) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= Kn * n) return;
-    int64_t K = gid / n;
-    int j = (int)(gid - K * n);
-    auto v = Store<SW>::ld(W + (int64_t)j * Kn + K);
-    out[gid] = cmake<double>(v.re, v.im);
-}
-
-int gather_columns(dht_ctx* c, const void* W, int wprec, int n, void* out) {
-    const int64_t Kn = 24 * c->g.Vh;
-    int64_t tot = Kn * n;
-    dim3 grid((unsigned)((tot + 255) / 256)), block(256);
-    switch (wprec) {
-        case DHT_FP64: hipLaunchKernelGGL(gather_kernel<double>, grid, block, 0, c->stream, (const Cx<double>*)W, Kn, n, (Cx<double>*)out); break;
-        case DHT_FP32: hipLaunchKernelGGL(gather_kernel<float>, grid, block, 0, c->stream, (const Cx<float>*)W, Kn, n, (Cx<double>*)out); break;
-        case DHT_BF16: hipLaunchKernelGGL(gather_kernel<bf16x2>, grid, block, 0, c->stream, (const bf16x2*)W, Kn, n, (Cx<double>*)out); break;
-        default: return set_error(DHT_ERR_INVALID_ARG, "bad precision");
-    }
-    DHT_HIP(hipGetLastError());
-    return DHT_OK;
 }
 
 }  // namespace dht

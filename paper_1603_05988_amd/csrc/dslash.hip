@@ -224,12 +224,21 @@ launched:
 int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
         int nrhs, bool dagger, bool g5out) {
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    int tok;
+    DHT_TRY(prof_begin(c, &tok));
+    int rc = DHT_OK;
     switch (prec) {
-        case DHT_FP64: return launch_hop<double>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out);
-        case DHT_FP32: return launch_hop<float>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out);
-        case DHT_BF16: return launch_hop<bf16x2>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out);
+        case DHT_FP64: rc = launch_hop<double>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out); break;
+        case DHT_FP32: rc = launch_hop<float>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out); break;
+        case DHT_BF16: rc = launch_hop<bf16x2>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out); break;
     }
-    return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    if (rc != DHT_OK) return rc;
+    // algorithmic bytes: read the input half field (and the xpay source), write
+    // the output, read each of the 8 Vh link matrices of this parity once
+    const double eb = (double)elem_bytes(prec);
+    const double bytes = (2.0 + (x ? 1.0 : 0.0)) * 12.0 * c->g.Vh * nrhs * eb + 72.0 * c->g.Vh * eb;
+    return prof_end(c, tok, PROF_HOP64 + prec, bytes);
 }
 
 // g5 on a full field: copy, negating spin components 2 and 3 (c >= 6)

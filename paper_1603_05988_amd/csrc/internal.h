@@ -121,6 +121,19 @@ struct Buf {
     size_t bytes = 0;
 };
 
+// kernel classes for the instrumentation (dht_profile_get)
+enum { PROF_HOP64 = 0, PROF_HOP32, PROF_HOP16, PROF_PROJ_MFMA, PROF_PROJ_GENERIC, PROF_NCLASS };
+struct ProfPending {
+    int cls;
+    int ev0, ev1;       // indices into the event pool
+    double bytes;       // algorithmic bytes of the launch
+};
+struct ProfStat {
+    int64_t count = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+};
+
 struct Welford {   // running mean / second moments of complex samples (Chan et al. update)
     int64_t n = 0;
     double mre = 0, mim = 0;   // means
@@ -149,8 +162,14 @@ struct dht_ctx {
     bool defl_ready = false;
     void* W = nullptr;                 // [k][2][12][Vh] complex<wprec>
     std::vector<double> M;             // k x k complex128 row-major (host)
-    void* M_dev = nullptr;
+    bool M_diag = false;               // M is diagonal (Rayleigh-quotient finalize)
     double TD[2] = {0, 0};
+    // per-kernel-class timing with HIP events (off unless enabled)
+    bool prof = false;
+    std::vector<hipEvent_t> prof_events;           // pool
+    int prof_next = 0;                             // next free event of the pool
+    std::vector<dht::ProfPending> prof_pending;    // launches not yet harvested
+    dht::ProfStat prof_stat[dht::PROF_NCLASS];
     // estimator
     dht::Welford est_q, est_qd;
     // workspace slots (grow-only)
@@ -183,10 +202,15 @@ enum Slot {
     WS_K64,                 // 9 FP64 Krylov vectors: r, rhat, p, v, s, t, tmp, inner rhs, inner x
     WS_KLO = WS_K64 + 9,    // 9 low-precision Krylov vectors (same roles)
     WS_PARTIAL = WS_KLO + 9, WS_SCAL, WS_SCAL2, WS_FLAGS, WS_HOSTPIN,
-    WS_Z, WS_XF, WS_QW, WS_PROJ, WS_COEF, WS_PROJ2,
+    WS_Z, WS_XF, WS_QW, WS_PROJ, WS_COEF, WS_PROJ2, WS_ZCODE,
     WS_NSLOTS
 };
 int ws_get(dht_ctx* c, int slot, size_t bytes, void** out);
+
+// instrumentation: bracket one launch of class `cls` (no-op unless profiling)
+int prof_begin(dht_ctx* c, int* token);
+int prof_end(dht_ctx* c, int token, int cls, double bytes);
+int prof_harvest(dht_ctx* c);   // after a stream synchronisation
 
 // field helpers -------------------------------------------------------------
 inline size_t half_elems(const dht_ctx* c, int nrhs) { return (size_t)12 * c->g.Vh * nrhs; }
@@ -207,7 +231,9 @@ int g5_field(dht_ctx* c, int prec, const void* in, void* out, int nrhs);        
 
 // probes.hip: probes j = first.. first+nrhs-1 into a full internal field of
 // precision prec (may be null), plus optional index/sign outputs.
+// zcode (may be null): per (complex entry K of the full internal field, RHS) the
+// 2-bit code k' with z = i^k' ([24 Vh][nrhs] bytes), the input of the MFMA projection.
 int probes_gen(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, void* field, int prec,
-               uint8_t* kout, int8_t* sout);
+               uint8_t* kout, int8_t* sout, uint8_t* zcode = nullptr);
 
 }  // namespace dht

@@ -51,6 +51,7 @@ struct ProbeArgs {
     int prec;
     uint8_t* kout;
     int8_t* sout;
+    uint8_t* zcode;
 };
 
 template <typename S>
@@ -80,6 +81,9 @@ __global__ void probe_kernel(ProbeArgs a) {
         }
         int k = (int)((word >> (2 * (nc & 31))) & 3ull);
         if (a.kout) a.kout[(int64_t)r * N + (int64_t)nc] = (uint8_t)k;
+        if (a.zcode)   // z = i^k * sign = i^(k + 2 [sign < 0])
+            a.zcode[((int64_t)p * 12 * a.g.Vh + (int64_t)comp * a.g.Vh + s) * a.B + r] =
+                (uint8_t)((k + (sign < 0.0f ? 2 : 0)) & 3);
         if (f) {
             typedef typename Store<S>::acc T;
             T re = (k == 0) ? T(1) : (k == 2 ? T(-1) : T(0));
@@ -91,7 +95,7 @@ __global__ void probe_kernel(ProbeArgs a) {
 }
 
 int probes_gen(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, void* field, int prec, uint8_t* kout,
-               int8_t* sout) {
+               int8_t* sout, uint8_t* zcode) {
     if (first < 0) return set_error(DHT_ERR_INVALID_ARG, "negative probe index");
     ProbeArgs a;
     a.g = c->g;
@@ -103,6 +107,7 @@ int probes_gen(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, 
     a.prec = prec;
     a.kout = kout;
     a.sout = sout;
+    a.zcode = zcode;
     int64_t n = c->g.V * (int64_t)nrhs;
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     switch (prec) {

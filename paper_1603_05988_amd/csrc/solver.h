@@ -65,9 +65,10 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
 int project_field(dht_ctx* c, const void* Z, int zprec, int nrhs, Cx<double>* c1, Cx<double>* c2);
 int deflation_begin(dht_ctx* c, int k, int prec);
 int deflation_set(dht_ctx* c, int first, int count, const double* W_dev);
-int deflation_finalize(dht_ctx* c);
+int deflation_finalize(dht_ctx* c, bool diagonal);
 void deflation_corrections(const dht_ctx* c, const Cx<double>* c1, const Cx<double>* c2, int B, double* dre,
                            double* dim);
-int gather_columns(dht_ctx* c, const void* W, int wprec, int n, void* out);
+int gather_columns(dht_ctx* c, int j0, int n, void* out);
+int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<double>* c2);
 
 }  // namespace dht

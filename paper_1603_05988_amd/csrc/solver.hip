@@ -97,6 +97,7 @@ int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::
         if ((it + 1) % check_every == 0 || it + 1 == maxiter) {
             DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
             DHT_HIP(hipStreamSynchronize(c->stream));
+            DHT_TRY(prof_harvest(c));
             bool any = false;
             for (int i = 0; i < nrhs; i++) any |= hs[i].active != 0;
             if (!any) break;

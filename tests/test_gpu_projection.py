@@ -1,0 +1,138 @@
+"""GPU parity of the deflation projection (Section 5.2: c1 = W^H z, c2 = W^H g5 z).
+
+The MFMA path stores W in BF16 and takes the probes as exact 2-bit codes, so
+every product is exact in FP32; the only error is the FP32 accumulation inside
+the matrix cores over at most 64 complex entries (8 MFMA steps) before each
+FP64 flush.  Bound used: |dc| <= 32 * 2^-24 * sum_K |w_K| |z_K| (a factor 4 of
+headroom over 8 accumulation steps), plus FP64 rounding.  The reference is the
+oracle's FP64 projection with the same BF16-rounded W.
+"""
+import numpy as np
+import pytest
+
+from oracle import estimator, lattice, rng
+from paper_1603_05988_amd.workloads import WORKLOADS, gauge_links
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_1603_05988_amd import _lib as L
+    return L
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def round_bf16(W):
+    f = np.stack([W.real, W.imag], axis=-1).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    f = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return f[..., 0] + 1j * f[..., 1]
+
+
+def random_basis(N, k, seed):
+    rs = np.random.default_rng(seed)
+    W = rs.standard_normal((N, k)) + 1j * rs.standard_normal((N, k))
+    return W / np.linalg.norm(W, axis=0)
+
+
+CASES = [
+    ((4, 4, 4, 4), 16, 1, False),
+    ((4, 4, 4, 4), 16, 5, True),
+    ((4, 4, 4, 4), 16, 16, True),
+    ((4, 4, 4, 4), 40, 32, False),
+    ((4, 4, 4, 4), 16, 64, True),
+    ((2, 4, 2, 6), 3, 3, True),
+    ((8, 8, 8, 16), 40, 16, True),
+]
+
+
+@pytest.mark.parametrize("L,k,nrhs,hp", CASES)
+def test_mfma_projection_matches_oracle(L, k, nrhs, hp):
+    V = int(np.prod(L))
+    N = 12 * V
+    U = gauge_links(L, 0.4, 1)
+    ctx = _lib().Context(L, -0.1)
+    ctx.set_gauge(cuda(U))
+    W = random_basis(N, k, 7)
+    ctx.begin_deflation(k, _lib().BF16)
+    ctx.set_deflation_columns(0, cuda(W.T))
+    c1, c2 = ctx.project_probes(5, 2, hp, 3, nrhs)
+    Wr = round_bf16(W)
+    Z = rng.probes(L, 5, 2, hp, 3, nrhs)
+    g5 = lattice.gamma5_full(V)
+    r1, r2 = estimator.projection_coefficients(Wr, Z, g5)
+    bound = 32 * 2.0 ** -24 * np.abs(Wr).sum(axis=0)[:, None] + 1e-12
+    assert np.all(np.abs(c1 - r1) <= bound), np.abs(c1 - r1).max()
+    assert np.all(np.abs(c2 - r2) <= bound), np.abs(c2 - r2).max()
+    ctx.close()
+
+
+def test_generic_projection_with_bf16_basis_matches_oracle():
+    L = (4, 4, 4, 8)
+    V = int(np.prod(L))
+    ctx = _lib().Context(L, -0.1)
+    ctx.set_gauge(cuda(gauge_links(L, 0.4, 2)))
+    W = random_basis(12 * V, 33, 3)
+    ctx.begin_deflation(33, _lib().BF16)
+    ctx.set_deflation_columns(0, cuda(W.T))
+    Z = rng.probes(L, 1, 0, False, 0, 3)
+    c1, c2 = ctx.project(cuda(Z.reshape((3,) + ctx._spinor_shape())))
+    r1, r2 = estimator.projection_coefficients(round_bf16(W), Z, lattice.gamma5_full(V))
+    assert np.abs(c1 - r1).max() <= 1e-13 * np.abs(r1).max()
+    assert np.abs(c2 - r2).max() <= 1e-13 * np.abs(r2).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_diagonal_finalize(prec):
+    w = WORKLOADS["c1"]
+    U = gauge_links(w.L, w.eps, w.seed)
+    D = lattice.dense_wilson(U, w.L, w.mass)
+    g5 = lattice.gamma5_full(w.V)
+    lam, W = estimator.q_eigenpairs(D, g5, w.k)
+    ctx = _lib().Context(w.L, w.mass)
+    ctx.set_gauge(cuda(U))
+    TD = ctx.set_deflation(cuda(W.T), prec, diagonal=True)
+    Wr = round_bf16(W) if prec == 2 else W
+    M = estimator.rayleigh_diag_M(Wr, D, g5)
+    TD_ref = estimator.deflated_trace(Wr, M, g5)
+    assert abs(TD - TD_ref) <= 1e-10 * abs(TD_ref)
+    assert np.abs(ctx.deflation_M() - M).max() <= 1e-10 * np.abs(M).max()
+    if prec == 0:   # exact eigenvectors: the diagonal form equals the full Galerkin inverse
+        assert abs(TD - np.sum((1.0 / lam) * np.einsum("ni,n,ni->i", W.conj(), g5, W))) <= 1e-10 * abs(TD)
+    ctx.close()
+
+
+def test_trace_batch_bf16_basis_c2():
+    """Algorithm 1 with a BF16 basis (MFMA projection) and a mixed-precision solve."""
+    w = WORKLOADS["c2"]
+    L_ = _lib()
+    U = gauge_links(w.L, w.eps, w.seed)
+    ctx = L_.Context(w.L, w.mass)
+    ctx.set_gauge(cuda(U))
+    k = 48
+    W = random_basis(w.N, k, 11)
+    TD = ctx.set_deflation(cuda(W.T), L_.BF16)
+    prm = ctx.params(L_.SOLVER_DC_BICGSTAB, inner=L_.FP32, tol=1e-10)
+    nrhs = 8
+    recs, c1, c2 = ctx.trace_batch(w.seed, 0, True, 0, nrhs, prm, want_coef=True)
+    Wr = round_bf16(W)
+    g5 = lattice.gamma5_full(w.V)
+    Z = rng.probes(w.L, w.seed, 0, True, 0, nrhs)
+    r1, r2 = estimator.projection_coefficients(Wr, Z, g5)
+    bound = 32 * 2.0 ** -24 * np.abs(Wr).sum(axis=0)[:, None] + 1e-12
+    assert np.all(np.abs(c1 - r1) <= bound) and np.all(np.abs(c2 - r2) <= bound)
+    M = ctx.deflation_M()
+    d_ref = estimator.deflation_corrections(r1, r2, M)
+    q = np.array([r["q"] for r in recs])
+    qd = np.array([r["q_defl"] for r in recs])
+    # the FP64 reduction of d from the device coefficients is exact to rounding
+    assert np.abs((q - qd) - estimator.deflation_corrections(c1, c2, M)).max() <= 1e-10 * np.abs(q).max()
+    dM = np.abs(M).sum()
+    assert np.abs((q - qd) - d_ref).max() <= 4 * bound.max() * dM * max(np.abs(r1).max(), np.abs(r2).max())
+    ctx.close()
