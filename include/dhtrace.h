@@ -46,6 +46,11 @@ extern "C" {
 
 typedef struct dht_ctx dht_ctx;
 
+/* Largest batch (right-hand sides per call) of dht_make_probes, dht_solve,
+ * dht_project*, dht_trace_batch; batches are padded internally to the next
+ * power of two with zero right-hand sides.  dht_apply takes any count. */
+#define DHT_MAX_BATCH 256
+
 enum {
     DHT_OK = 0,
     DHT_ERR_INVALID_ARG = -1,
@@ -88,15 +93,19 @@ typedef struct {
 enum {
     DHT_SOLVER_BICGSTAB_FP64 = 0, /* plain FP64 BiCGStab on the even/odd Schur system          */
     DHT_SOLVER_DC_BICGSTAB = 1,   /* FP64 defect correction around an FP32/BF16 BiCGStab      */
-    DHT_SOLVER_DC_FGMRES_NN = 2   /* FP64 defect correction around FGMRES with the learned
-                                     preconditioner (falls back to DC_BICGSTAB)               */
+    DHT_SOLVER_DC_FGMRES_NN = 2,  /* FP64 defect correction, one FP32 FGMRES(restart) cycle
+                                     per correction, the learned network as right
+                                     preconditioner (needs dht_nn_init / _set_weights);
+                                     falls back to DC_BICGSTAB if maxiter is exhausted      */
+    DHT_SOLVER_DC_FGMRES = 3      /* the same with the identity preconditioner              */
 };
 
 enum { /* dht_solve_stats.status */
     DHT_STATUS_CONVERGED = 0,
     DHT_STATUS_NOT_CONVERGED = 1,
-    DHT_STATUS_FALLBACK_FP32 = 2, /* converged after escalating the inner precision  */
-    DHT_STATUS_FALLBACK_FP64 = 3  /* converged on the plain FP64 BiCGStab fallback    */
+    DHT_STATUS_FALLBACK_FP32 = 2,     /* converged after escalating the inner precision   */
+    DHT_STATUS_FALLBACK_FP64 = 3,     /* converged on the FP64 inner solve                 */
+    DHT_STATUS_FALLBACK_BICGSTAB = 4  /* FGMRES missed the target; BiCGStab finished      */
 };
 
 typedef struct {
@@ -222,6 +231,41 @@ int dht_trace_batch(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int
                     const dht_solver_params* prm, dht_record* records, double* coef_host);
 int dht_estimate_get(dht_ctx* ctx, dht_estimate* est);
 int dht_estimate_reset(dht_ctx* ctx);
+
+/* ---- learned preconditioner ----------------------------------------------- */
+/* A 3-layer 4D convolutional network (3^4 taps, 24 -> 48 -> 48 -> 24 real
+ * channels = real and imaginary parts of the 12 spin-colour components,
+ * ReLU after layers 1 and 2, no bias, periodic padding) approximating
+ * r -> D^-1 r, used as the right preconditioner of FGMRES.  Weights:
+ * float [3 layers][81 taps][Cout][Cin] concatenated (dht_nn_num_weights()
+ * floats); tap t = (dx+1) + 3 (dy+1) + 9 (dz+1) + 27 (dt+1) and
+ * out[x] = sum_t W[t] in[x + d_t].  Inference and training run on BF16
+ * matrix cores with FP32 accumulation and an FP32 master copy of the
+ * weights.  R and E are canonical complex128 spinors (device), read as
+ * [n][V][24] reals. */
+int64_t dht_nn_num_weights(void);
+/* He-normal initial weights (std sqrt(2 / (81 Cin)), the last layer scaled
+ * by 0.1) from a seeded SplitMix64/Box-Muller generator; resets the optimiser. */
+int dht_nn_init(dht_ctx* ctx, uint64_t seed);
+int dht_nn_set_weights(dht_ctx* ctx, const float* w_host);
+int dht_nn_get_weights(dht_ctx* ctx, float* w_host);
+/* E = M(R) for n spinors. */
+int dht_nn_forward(dht_ctx* ctx, const double* R_dev, double* E_dev, int n);
+/* Loss sum_b ||M(R_b) - E_b||^2 / ||E_b||^2 / n and its weight gradient
+ * (grad_host: dht_nn_num_weights() floats, may be NULL); n <= 64. */
+int dht_nn_grad(dht_ctx* ctx, const double* R_dev, const double* E_dev, int n, float* grad_host, double* loss);
+/* Adam (beta 0.9 / 0.999, eps 1e-8) over npairs pairs in minibatches of
+ * `batch` (<= 64) for `epochs` passes; final_loss (may be NULL) receives the
+ * mean loss of the last epoch. */
+int dht_nn_train(dht_ctx* ctx, const double* R_dev, const double* E_dev, int npairs, int epochs, int batch, float lr,
+                 double* final_loss);
+/* Training pairs from FGMRES restarts: for probes j = first .. first+nrhs-1
+ * of `spec`, x* is solved to 1e-12 (FP64 BiCGStab), then FGMRES(restart)
+ * cycles with the identity preconditioner run to 1e-8; at every restart k the
+ * pair (r_k / ||r_k||, (x* - x_k) / ||r_k||) is written to R_dev / E_dev
+ * (capacity `cap` spinors each).  *count receives the number written. */
+int dht_nn_make_pairs(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int nrhs, int restart, double* R_dev,
+                      double* E_dev, int cap, int* count);
 
 /* ---- instrumentation ------------------------------------------------------ */
 

@@ -89,7 +89,18 @@ SIGNATURES = {
     "dht_estimate_reset": (_i, [_vp]),
     "dht_last_timings": (_i, [_vp, _dp, _i]),
     "dht_bench_hop": (_i, [_vp, _i, _i, _i, _i, _dp]),
+    "dht_nn_num_weights": (_i64, []),
+    "dht_nn_init": (_i, [_vp, _u64]),
+    "dht_nn_set_weights": (_i, [_vp, ctypes.POINTER(ctypes.c_float)]),
+    "dht_nn_get_weights": (_i, [_vp, ctypes.POINTER(ctypes.c_float)]),
+    "dht_nn_forward": (_i, [_vp, _vp, _vp, _i]),
+    "dht_nn_grad": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(ctypes.c_float), _dp]),
+    "dht_nn_train": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _dp]),
+    "dht_nn_make_pairs": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _i, _vp, _vp, _i, ctypes.POINTER(_i)]),
 }
+
+SOLVER_DC_FGMRES = 3
+NN_CHANNELS = (24, 48, 48, 24)
 
 _lib = None
 
@@ -304,6 +315,61 @@ class Context:
         t = np.zeros(5)
         check(load().dht_last_timings(self.h, _np_dp(t), 5))
         return dict(probes=t[0], solve=t[1], project=t[2], qform=t[3], total=t[4])
+
+    # -- learned preconditioner ------------------------------------------
+    @staticmethod
+    def _flat_weights(Ws):
+        return np.ascontiguousarray(np.concatenate([np.asarray(W, dtype=np.float32).ravel() for W in Ws]))
+
+    @staticmethod
+    def _split_weights(flat):
+        out, off = [], 0
+        for l in range(3):
+            cin, cout = NN_CHANNELS[l], NN_CHANNELS[l + 1]
+            n = 81 * cout * cin
+            out.append(flat[off:off + n].reshape(81, cout, cin).astype(np.float64))
+            off += n
+        return out
+
+    def nn_init(self, seed: int):
+        check(load().dht_nn_init(self.h, seed))
+
+    def nn_set_weights(self, Ws):
+        flat = self._flat_weights(Ws)
+        check(load().dht_nn_set_weights(self.h, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def nn_get_weights(self):
+        flat = np.zeros(load().dht_nn_num_weights(), dtype=np.float32)
+        check(load().dht_nn_get_weights(self.h, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return self._split_weights(flat)
+
+    def nn_forward(self, R):
+        E = self.torch.empty_like(R)
+        check(load().dht_nn_forward(self.h, _as_f64_view(R), _as_f64_view(E), R.shape[0]))
+        return E
+
+    def nn_grad(self, R, E):
+        flat = np.zeros(load().dht_nn_num_weights(), dtype=np.float32)
+        loss = ctypes.c_double(0)
+        check(load().dht_nn_grad(self.h, _as_f64_view(R), _as_f64_view(E), R.shape[0],
+                                 flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss)))
+        return loss.value, self._split_weights(flat)
+
+    def nn_train(self, R, E, epochs: int = 1, batch: int = 16, lr: float = 1e-3) -> float:
+        loss = ctypes.c_double(0)
+        check(load().dht_nn_train(self.h, _as_f64_view(R), _as_f64_view(E), R.shape[0], epochs, batch, lr,
+                                  ctypes.byref(loss)))
+        return loss.value
+
+    def nn_make_pairs(self, seed: int, run: int, hp: bool, first: int, nrhs: int, restart: int, cap: int):
+        shape = (cap,) + self._spinor_shape()
+        R = self.torch.zeros(shape, dtype=self.torch.complex128, device="cuda")
+        E = self.torch.zeros(shape, dtype=self.torch.complex128, device="cuda")
+        sp = ProbeSpec(seed, run, int(hp))
+        cnt = ctypes.c_int(0)
+        check(load().dht_nn_make_pairs(self.h, ctypes.byref(sp), first, nrhs, restart, _as_f64_view(R),
+                                       _as_f64_view(E), cap, ctypes.byref(cnt)))
+        return R[:cnt.value], E[:cnt.value]
 
     def bench_hop(self, prec: int, nrhs: int, warmup: int = 3, reps: int = 10) -> float:
         ms = ctypes.c_double(0.0)

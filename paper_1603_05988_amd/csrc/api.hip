@@ -98,6 +98,24 @@ int prof_harvest(dht_ctx* c) {
 
 static bool valid_prec(int p) { return p == DHT_FP64 || p == DHT_FP32 || p == DHT_BF16; }
 
+// device coefficients [k][bp] -> host [k][n] (first n columns), after a sync
+static int copy_coefs(dht_ctx* c, const Cx<double>* d1, const Cx<double>* d2, int bp, int n, double* c1h, double* c2h) {
+    const size_t kb = (size_t)c->k * bp;
+    std::vector<Cx<double>> h(2 * kb);
+    DHT_HIP(hipMemcpyAsync(h.data(), d1, sizeof(Cx<double>) * kb, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipMemcpyAsync(h.data() + kb, d2, sizeof(Cx<double>) * kb, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    DHT_TRY(prof_harvest(c));
+    for (int i = 0; i < c->k; i++)
+        for (int r = 0; r < n; r++) {
+            c1h[2 * ((size_t)i * n + r)] = h[(size_t)i * bp + r].re;
+            c1h[2 * ((size_t)i * n + r) + 1] = h[(size_t)i * bp + r].im;
+            c2h[2 * ((size_t)i * n + r)] = h[kb + (size_t)i * bp + r].re;
+            c2h[2 * ((size_t)i * n + r) + 1] = h[kb + (size_t)i * bp + r].im;
+        }
+    return DHT_OK;
+}
+
 static int check_ctx(dht_ctx* c) {
     if (!c) return set_error(DHT_ERR_INVALID_ARG, "null context");
     DHT_HIP(hipSetDevice(c->device));
@@ -164,6 +182,7 @@ int dht_destroy(dht_ctx* c) {
     for (int i = 0; i < 3; i++)
         if (c->U[i]) (void)hipFree(c->U[i]);
     if (c->W) (void)hipFree(c->W);
+    if (c->nn.mem) (void)hipFree(c->nn.mem);
     for (int i = 0; i < (int)c->ws.size(); i++) {
         if (!c->ws[i].p) continue;
         if (i == WS_HOSTPIN) (void)hipHostFree(c->ws[i].p);
@@ -181,7 +200,8 @@ int dht_set_gauge(dht_ctx* c, const double* U_dev) {
     if (!U_dev) return set_error(DHT_ERR_INVALID_ARG, "null links");
     for (int p = 0; p < 3; p++) {
         if (!c->U[p]) {
-            size_t bytes = (size_t)4 * 9 * c->g.V * elem_bytes(p);
+            // [4][2][Vh] link matrices of link_vecs(p) 16-byte vectors each
+            size_t bytes = (size_t)4 * c->g.V * link_vecs(p) * 16;
             if (hipMalloc(&c->U[p], bytes) != hipSuccess) {
                 c->U[p] = nullptr;
                 (void)hipGetLastError();
@@ -200,24 +220,30 @@ int dht_apply(dht_ctx* c, int op, int prec, const double* X, double* Y, int nrhs
     if (!X || !Y || nrhs <= 0 || !valid_prec(prec) || op < DHT_OP_D || op > DHT_OP_Q)
         return set_error(DHT_ERR_INVALID_ARG, "bad argument");
     if (op != DHT_OP_G5 && !c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
-    size_t bytes = full_elems(c, nrhs) * elem_bytes(prec);
-    void *fi, *fo;
-    DHT_TRY(ws_get(c, WS_PACK_IN, bytes, &fi));
-    DHT_TRY(ws_get(c, WS_PACK_OUT, bytes, &fo));
-    DHT_TRY(pack_spinor(c, X, fi, prec, nrhs));
-    DHT_TRY(apply_full(c, op, prec, fi, fo, nrhs));
-    DHT_TRY(unpack_spinor(c, fo, prec, Y, nrhs));
+    const int64_t N = 12 * c->g.V;
+    for (int r0 = 0; r0 < nrhs; r0 += 64) {   // chunks of at most 64 right-hand sides
+        const int n = std::min(64, nrhs - r0), bp = pad_rhs(n);
+        size_t bytes = full_elems(c, bp) * elem_bytes(prec);
+        void *fi, *fo;
+        DHT_TRY(ws_get(c, WS_PACK_IN, bytes, &fi));
+        DHT_TRY(ws_get(c, WS_PACK_OUT, bytes, &fo));
+        DHT_TRY(pack_spinor(c, X + 2 * N * r0, fi, prec, n, bp));
+        DHT_TRY(apply_full(c, op, prec, fi, fo, bp));
+        DHT_TRY(unpack_spinor(c, fo, prec, Y + 2 * N * r0, n, bp));
+    }
     DHT_HIP(hipStreamSynchronize(c->stream));
+    DHT_TRY(prof_harvest(c));
     return DHT_OK;
 }
 
 int dht_make_probes(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, double* Z) {
     DHT_TRY(check_ctx(c));
-    if (!spec || !Z || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!spec || !Z || nrhs <= 0 || nrhs > DHT_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    const int bp = pad_rhs(nrhs);
     void* f;
-    DHT_TRY(ws_get(c, WS_Z, full_elems(c, nrhs) * 16, &f));
-    DHT_TRY(probes_gen(c, spec, first, nrhs, f, DHT_FP64, nullptr, nullptr));
-    DHT_TRY(unpack_spinor(c, f, DHT_FP64, Z, nrhs));
+    DHT_TRY(ws_get(c, WS_Z, full_elems(c, bp) * 16, &f));
+    DHT_TRY(probes_gen(c, spec, first, nrhs, bp, f, DHT_FP64, nullptr, nullptr));
+    DHT_TRY(unpack_spinor(c, f, DHT_FP64, Z, nrhs, bp));
     DHT_HIP(hipStreamSynchronize(c->stream));
     return DHT_OK;
 }
@@ -225,29 +251,35 @@ int dht_make_probes(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
 int dht_probe_indices(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, uint8_t* k_dev,
                       int8_t* sign_dev) {
     DHT_TRY(check_ctx(c));
-    if (!spec || !k_dev || !sign_dev || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
-    DHT_TRY(probes_gen(c, spec, first, nrhs, nullptr, DHT_FP64, k_dev, sign_dev));
+    if (!spec || !k_dev || !sign_dev || nrhs <= 0 || nrhs > DHT_MAX_BATCH)
+        return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    DHT_TRY(probes_gen(c, spec, first, nrhs, pad_rhs(nrhs), nullptr, DHT_FP64, k_dev, sign_dev));
     DHT_HIP(hipStreamSynchronize(c->stream));
     return DHT_OK;
 }
 
 int dht_solve(dht_ctx* c, const dht_solver_params* prm, const double* Z, double* X, int nrhs, dht_solve_stats* stats) {
     DHT_TRY(check_ctx(c));
-    if (!prm || !Z || !X || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!prm || !Z || !X || nrhs <= 0 || nrhs > DHT_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
-    size_t bytes = full_elems(c, nrhs) * 16;
+    const int bp = pad_rhs(nrhs);
+    size_t bytes = full_elems(c, bp) * 16;
     void *fz, *fx;
     DHT_TRY(ws_get(c, WS_PACK_IN, bytes, &fz));
     DHT_TRY(ws_get(c, WS_PACK_OUT, bytes, &fx));
-    DHT_TRY(pack_spinor(c, Z, fz, DHT_FP64, nrhs));
+    DHT_TRY(pack_spinor(c, Z, fz, DHT_FP64, nrhs, bp));
     DHT_TRY(record(c, 0));
-    int rc = solve_fields(c, prm, fz, fx, nrhs, stats);
+    std::vector<dht_solve_stats> st(bp);
+    int rc = solve_fields(c, prm, fz, fx, bp, st.data());
     if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) return rc;
     std::string msg = g_err;
     DHT_TRY(record(c, 1));
-    DHT_TRY(unpack_spinor(c, fx, DHT_FP64, X, nrhs));
+    DHT_TRY(unpack_spinor(c, fx, DHT_FP64, X, nrhs, bp));
     DHT_HIP(hipStreamSynchronize(c->stream));
     c->timings[1] = elapsed(c, 0, 1);
+    DHT_TRY(prof_harvest(c));
+    if (stats)
+        for (int i = 0; i < nrhs; i++) stats[i] = st[i];
     if (rc != DHT_OK) g_err = msg;
     return rc;
 }
@@ -340,82 +372,78 @@ int dht_deflation_clear(dht_ctx* c) {
 
 int dht_project(dht_ctx* c, const double* Z, int nrhs, double* c1h, double* c2h) {
     DHT_TRY(check_ctx(c));
-    if (!Z || !c1h || !c2h || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!Z || !c1h || !c2h || nrhs <= 0 || nrhs > DHT_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
     if (!c->W) return set_error(DHT_ERR_STATE, "no deflation basis");
+    const int bp = pad_rhs(nrhs);
     void *fz, *cc;
-    DHT_TRY(ws_get(c, WS_PACK_IN, full_elems(c, nrhs) * 16, &fz));
-    DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 2 * c->k * nrhs, &cc));
-    DHT_TRY(pack_spinor(c, Z, fz, DHT_FP64, nrhs));
+    DHT_TRY(ws_get(c, WS_PACK_IN, full_elems(c, bp) * 16, &fz));
+    DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 2 * c->k * bp, &cc));
+    DHT_TRY(pack_spinor(c, Z, fz, DHT_FP64, nrhs, bp));
     Cx<double>* d1 = (Cx<double>*)cc;
-    Cx<double>* d2 = d1 + (size_t)c->k * nrhs;
-    DHT_TRY(project_field(c, fz, DHT_FP64, nrhs, d1, d2));
-    DHT_HIP(hipMemcpyAsync(c1h, d1, sizeof(Cx<double>) * c->k * nrhs, hipMemcpyDeviceToHost, c->stream));
-    DHT_HIP(hipMemcpyAsync(c2h, d2, sizeof(Cx<double>) * c->k * nrhs, hipMemcpyDeviceToHost, c->stream));
-    DHT_HIP(hipStreamSynchronize(c->stream));
-    return DHT_OK;
+    Cx<double>* d2 = d1 + (size_t)c->k * bp;
+    DHT_TRY(project_field(c, fz, DHT_FP64, bp, d1, d2));
+    return copy_coefs(c, d1, d2, bp, nrhs, c1h, c2h);
 }
 
 int dht_project_probes(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, double* c1h, double* c2h) {
     DHT_TRY(check_ctx(c));
-    if (!spec || !c1h || !c2h || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!spec || !c1h || !c2h || nrhs <= 0 || nrhs > DHT_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
     if (!c->W) return set_error(DHT_ERR_STATE, "no deflation basis");
-    const bool mfma = c->wprec == DHT_BF16 && nrhs <= 64;
+    const int bp = pad_rhs(nrhs);
+    const bool mfma = c->wprec == DHT_BF16 && bp <= 64;
     void *cc, *buf;
-    DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 2 * c->k * nrhs, &cc));
+    DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 2 * c->k * bp, &cc));
     Cx<double>* d1 = (Cx<double>*)cc;
-    Cx<double>* d2 = d1 + (size_t)c->k * nrhs;
+    Cx<double>* d2 = d1 + (size_t)c->k * bp;
     if (mfma) {
-        DHT_TRY(ws_get(c, WS_ZCODE, full_elems(c, nrhs), &buf));
-        DHT_TRY(probes_gen(c, spec, first, nrhs, nullptr, DHT_FP64, nullptr, nullptr, (uint8_t*)buf));
-        DHT_TRY(project_codes(c, (const uint8_t*)buf, nrhs, d1, d2));
+        DHT_TRY(ws_get(c, WS_ZCODE, full_elems(c, bp), &buf));
+        DHT_TRY(probes_gen(c, spec, first, nrhs, bp, nullptr, DHT_FP64, nullptr, nullptr, (uint8_t*)buf));
+        DHT_TRY(project_codes(c, (const uint8_t*)buf, bp, d1, d2));
     } else {
-        DHT_TRY(ws_get(c, WS_Z, full_elems(c, nrhs) * 16, &buf));
-        DHT_TRY(probes_gen(c, spec, first, nrhs, buf, DHT_FP64, nullptr, nullptr));
-        DHT_TRY(project_field(c, buf, DHT_FP64, nrhs, d1, d2));
+        DHT_TRY(ws_get(c, WS_Z, full_elems(c, bp) * 16, &buf));
+        DHT_TRY(probes_gen(c, spec, first, nrhs, bp, buf, DHT_FP64, nullptr, nullptr));
+        DHT_TRY(project_field(c, buf, DHT_FP64, bp, d1, d2));
     }
-    DHT_HIP(hipMemcpyAsync(c1h, d1, sizeof(Cx<double>) * c->k * nrhs, hipMemcpyDeviceToHost, c->stream));
-    DHT_HIP(hipMemcpyAsync(c2h, d2, sizeof(Cx<double>) * c->k * nrhs, hipMemcpyDeviceToHost, c->stream));
-    DHT_HIP(hipStreamSynchronize(c->stream));
-    DHT_TRY(prof_harvest(c));
-    return DHT_OK;
+    return copy_coefs(c, d1, d2, bp, nrhs, c1h, c2h);
 }
 
 int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, const dht_solver_params* prm,
                     dht_record* records, double* coef_host) {
     DHT_TRY(check_ctx(c));
-    if (!spec || !prm || nrhs <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!spec || !prm || nrhs <= 0 || nrhs > DHT_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     if (c->W && !c->defl_ready) return set_error(DHT_ERR_STATE, "deflation basis set but not finalized");
-    const size_t fb = full_elems(c, nrhs) * 16;
+    const int bp = pad_rhs(nrhs);
+    const size_t fb = full_elems(c, bp) * 16;
     void *fz, *fx, *cc, *zc = nullptr;
     DHT_TRY(ws_get(c, WS_Z, fb, &fz));
     DHT_TRY(ws_get(c, WS_PACK_OUT, fb, &fx));
     const int k = c->defl_ready ? c->k : 0;
-    const bool mfma = k > 0 && c->wprec == DHT_BF16 && nrhs <= 64;
-    if (mfma) DHT_TRY(ws_get(c, WS_ZCODE, full_elems(c, nrhs), &zc));
-    DHT_TRY(ws_get(c, WS_COEF, sizeof(Cx<double>) * (2 * (size_t)k * nrhs + nrhs) + 64, &cc));
+    const bool mfma = k > 0 && c->wprec == DHT_BF16 && bp <= 64;
+    if (mfma) DHT_TRY(ws_get(c, WS_ZCODE, full_elems(c, bp), &zc));
+    DHT_TRY(ws_get(c, WS_COEF, sizeof(Cx<double>) * (2 * (size_t)k * bp + bp) + 64, &cc));
     Cx<double>* d1 = (Cx<double>*)cc;
-    Cx<double>* d2 = d1 + (size_t)k * nrhs;
-    Cx<double>* dq = d2 + (size_t)k * nrhs;
+    Cx<double>* d2 = d1 + (size_t)k * bp;
+    Cx<double>* dq = d2 + (size_t)k * bp;
 
     DHT_TRY(record(c, 0));
-    DHT_TRY(probes_gen(c, spec, first, nrhs, fz, DHT_FP64, nullptr, nullptr, (uint8_t*)zc));
+    DHT_TRY(probes_gen(c, spec, first, nrhs, bp, fz, DHT_FP64, nullptr, nullptr, (uint8_t*)zc));
     DHT_TRY(record(c, 1));
-    std::vector<dht_solve_stats> st(nrhs);
-    int rc = solve_fields(c, prm, fz, fx, nrhs, st.data());
+    std::vector<dht_solve_stats> st(bp);
+    int rc = solve_fields(c, prm, fz, fx, bp, st.data());
     if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) return rc;
     std::string msg = g_err;
     DHT_TRY(record(c, 2));
-    if (mfma) DHT_TRY(project_codes(c, (const uint8_t*)zc, nrhs, d1, d2));
-    else if (k > 0) DHT_TRY(project_field(c, fz, DHT_FP64, nrhs, d1, d2));
+    if (mfma) DHT_TRY(project_codes(c, (const uint8_t*)zc, bp, d1, d2));
+    else if (k > 0) DHT_TRY(project_field(c, fz, DHT_FP64, bp, d1, d2));
     DHT_TRY(record(c, 3));
     {
         const void* aa[1] = {fz};
         const void* bb[1] = {fx};
-        DHT_TRY(dots(c, DHT_FP64, 1, aa, bb, 2 * c->g.Vh, nrhs, dq));
+        DHT_TRY(dots(c, DHT_FP64, 1, aa, bb, full_elems(c, bp), bp, dq));
     }
     DHT_TRY(record(c, 4));
-    std::vector<Cx<double>> hc((size_t)2 * k * nrhs + nrhs);
+    std::vector<Cx<double>> hc((size_t)2 * k * bp + bp);
     DHT_HIP(hipMemcpyAsync(hc.data(), cc, sizeof(Cx<double>) * hc.size(), hipMemcpyDeviceToHost, c->stream));
     DHT_TRY(record(c, 5));
     DHT_HIP(hipStreamSynchronize(c->stream));
@@ -425,9 +453,15 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     c->timings[3] = elapsed(c, 3, 4);
     c->timings[4] = elapsed(c, 0, 5);
     DHT_TRY(prof_harvest(c));
-    std::vector<double> dre(nrhs, 0.0), dim(nrhs, 0.0);
-    if (k > 0) deflation_corrections(c, hc.data(), hc.data() + (size_t)k * nrhs, nrhs, dre.data(), dim.data());
-    const Cx<double>* q = hc.data() + (size_t)2 * k * nrhs;
+    std::vector<double> dre(bp, 0.0), dim(bp, 0.0);
+    if (k > 0) deflation_corrections(c, hc.data(), hc.data() + (size_t)k * bp, bp, nrhs, dre.data(), dim.data());
+    const Cx<double>* q = hc.data() + (size_t)2 * k * bp;
+    // a padding slot that failed cannot fail the batch: only real probes count
+    if (rc == DHT_ERR_NOT_CONVERGED) {
+        bool any = false;
+        for (int r = 0; r < nrhs; r++) any |= st[r].status == DHT_STATUS_NOT_CONVERGED;
+        if (!any) rc = DHT_OK;
+    }
     for (int r = 0; r < nrhs; r++) {
         double qre = q[r].re, qim = q[r].im;
         double dqre = qre - dre[r], dqim = qim - dim[r];
@@ -441,7 +475,16 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
             records[r].s = st[r];
         }
     }
-    if (coef_host && k > 0) memcpy(coef_host, hc.data(), sizeof(Cx<double>) * 2 * k * nrhs);
+    if (coef_host && k > 0) {
+        for (int part = 0; part < 2; part++)
+            for (int i = 0; i < k; i++)
+                for (int r = 0; r < nrhs; r++) {
+                    const Cx<double>& v = hc[(size_t)part * k * bp + (size_t)i * bp + r];
+                    size_t o = 2 * ((size_t)part * k * nrhs + (size_t)i * nrhs + r);
+                    coef_host[o] = v.re;
+                    coef_host[o + 1] = v.im;
+                }
+    }
     if (rc != DHT_OK) g_err = msg;
     return rc;
 }
@@ -484,17 +527,120 @@ int dht_last_timings(dht_ctx* c, double* ms, int n) {
     return DHT_OK;
 }
 
+int64_t dht_nn_num_weights(void) { return nn_num_weights(); }
+
+int dht_nn_init(dht_ctx* c, uint64_t seed) {
+    DHT_TRY(check_ctx(c));
+    // He-normal: std = sqrt(2 / fan_in), fan_in = 81 Cin; SplitMix64 -> Box-Muller
+    static const int ch[4] = {24, 48, 48, 24};
+    std::vector<float> w((size_t)nn_num_weights());
+    uint64_t st = seed;
+    auto next = [&]() {
+        st += 0x9E3779B97F4A7C15ull;
+        uint64_t z = st;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);   // (0, 1)
+    };
+    size_t off = 0;
+    for (int l = 0; l < 3; l++) {
+        // the last layer starts 10x smaller so that the initial output is small
+        const double sd = sqrt(2.0 / (81.0 * ch[l])) * (l == 2 ? 0.1 : 1.0);
+        const size_t n = (size_t)81 * ch[l] * ch[l + 1];
+        for (size_t i = 0; i < n; i++) {
+            double u1 = next(), u2 = next();
+            w[off + i] = (float)(sd * sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+        }
+        off += n;
+    }
+    return nn_set_weights(c, w.data());
+}
+
+int dht_nn_set_weights(dht_ctx* c, const float* w) {
+    DHT_TRY(check_ctx(c));
+    if (!w) return set_error(DHT_ERR_INVALID_ARG, "null weights");
+    return nn_set_weights(c, w);
+}
+
+int dht_nn_get_weights(dht_ctx* c, float* w) {
+    DHT_TRY(check_ctx(c));
+    if (!w) return set_error(DHT_ERR_INVALID_ARG, "null weights");
+    return nn_get_weights(c, w, false);
+}
+
+int dht_nn_forward(dht_ctx* c, const double* R, double* E, int n) {
+    DHT_TRY(check_ctx(c));
+    if (!R || !E || n <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    return nn_forward_canon(c, R, E, n);
+}
+
+int dht_nn_grad(dht_ctx* c, const double* R, const double* E, int n, float* grad, double* loss) {
+    DHT_TRY(check_ctx(c));
+    if (!R || !E || n <= 0 || n > NN_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    DHT_TRY(nn_grad_canon(c, R, E, n, loss));
+    if (grad) DHT_TRY(nn_get_weights(c, grad, true));
+    return DHT_OK;
+}
+
+int dht_nn_train(dht_ctx* c, const double* R, const double* E, int npairs, int epochs, int batch, float lr,
+                 double* final_loss) {
+    DHT_TRY(check_ctx(c));
+    if (!R || !E || npairs <= 0 || epochs < 0 || !(lr > 0)) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    return nn_train_canon(c, R, E, npairs, epochs, batch, lr, final_loss);
+}
+
+int dht_nn_make_pairs(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, int restart, double* R,
+                      double* E, int cap, int* count) {
+    DHT_TRY(check_ctx(c));
+    if (!spec || !R || !E || !count || nrhs <= 0 || nrhs > NN_MAX_BATCH || cap < 0 || restart <= 0)
+        return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    const int bp = pad_rhs(nrhs);
+    const size_t fb = full_elems(c, bp) * 16;
+    void *fz, *fx, *xs;
+    DHT_TRY(ws_get(c, WS_Z, fb, &fz));
+    DHT_TRY(ws_get(c, WS_PACK_OUT, fb, &fx));
+    DHT_TRY(ws_get(c, WS_XSTAR, fb, &xs));
+    DHT_TRY(probes_gen(c, spec, first, nrhs, bp, fz, DHT_FP64, nullptr, nullptr));
+    dht_solver_params p{};
+    p.method = DHT_SOLVER_BICGSTAB_FP64;
+    p.tol = 1e-12;
+    p.maxiter = 100000;
+    std::vector<dht_solve_stats> st(bp);
+    int rc = solve_fields(c, &p, fz, xs, bp, st.data());
+    if (rc != DHT_OK) return rc;
+    PairSink sink;
+    sink.xstar = xs;
+    sink.R = R;
+    sink.E = E;
+    sink.cap = cap;
+    sink.nreal = nrhs;
+    dht_solver_params q{};
+    q.method = DHT_SOLVER_DC_FGMRES;
+    q.tol = 1e-8;
+    q.maxiter = 100000;
+    q.restart = restart;
+    q.inner_tol = 1e-6;
+    rc = solve_fgmres(c, &q, fz, fx, bp, nullptr, false, &sink);
+    if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) return rc;
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    *count = sink.count;
+    return DHT_OK;
+}
+
 int dht_bench_hop(dht_ctx* c, int prec, int nrhs, int warmup, int reps, double* ms_per_call) {
     DHT_TRY(check_ctx(c));
-    if (!valid_prec(prec) || nrhs <= 0 || reps <= 0 || warmup < 0 || !ms_per_call)
-        return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!valid_prec(prec) || nrhs <= 0 || nrhs > DHT_MAX_BATCH || (nrhs & (nrhs - 1)) || reps <= 0 || warmup < 0 ||
+        !ms_per_call)
+        return set_error(DHT_ERR_INVALID_ARG, "bad argument (nrhs must be a power of two)");
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     size_t bytes = full_elems(c, nrhs) * elem_bytes(prec);
     void *fi, *fo;
     DHT_TRY(ws_get(c, WS_PACK_IN, bytes, &fi));
     DHT_TRY(ws_get(c, WS_PACK_OUT, bytes, &fo));
     dht_probe_spec sp = {12345u, 0u, 0};
-    DHT_TRY(probes_gen(c, &sp, 0, nrhs, fi, prec, nullptr, nullptr));
+    DHT_TRY(probes_gen(c, &sp, 0, nrhs, nrhs, fi, prec, nullptr, nullptr));
     const void* in_odd = (const char*)fi + bytes / 2;
     for (int i = 0; i < warmup; i++) DHT_TRY(hop(c, prec, 0, in_odd, fo, nullptr, 0.0, 1.0, nrhs, false, false));
     DHT_TRY(record(c, 0));

@@ -1,12 +1,16 @@
 // Reductions and vector updates for the batched Krylov solvers.
 //
-// Every dot product is accumulated in FP64: each lane converts its products
-// to double, lanes of one RHS are combined by a fixed-order tree in LDS, and
-// the per-workgroup partial sums are added in workgroup order by a one-block
-// finalise kernel.  The result is therefore deterministic for a fixed grid.
+// Fields are arrays of 16-byte vectors (VW complex numbers of one site and
+// RHS); with the batch B a power of two the RHS of vector v is v & (B - 1),
+// so these kernels do not depend on the site layout.
 //
-// Per-RHS solver scalars live on the device (struct RhsState) and are read by
-// the update kernels, so a BiCGStab iteration needs no host round trip.
+// Every dot product is accumulated in FP64: each lane converts its products
+// to double, the lanes of one RHS are combined by a fixed-order tree in LDS,
+// and the per-workgroup partial sums are added in workgroup order by the
+// finalise kernel (one workgroup per RHS).  Results are deterministic for a
+// fixed grid.  Per-RHS solver scalars live on the device (struct RhsState)
+// and are read by the update kernels, so a BiCGStab iteration needs no host
+// round trip.
 #include <algorithm>
 #include <type_traits>
 
@@ -17,121 +21,89 @@ namespace dht {
 static constexpr int RED_THREADS = 256;
 static constexpr int RED_MAX_BLOCKS = 1024;
 
-static int pow2_at_least(int b) {
-    int p = 1;
-    while (p < b) p <<= 1;
-    return p;
+static int red_blocks(size_t nvec) {
+    size_t nb = (nvec + RED_THREADS - 1) / RED_THREADS;
+    return (int)std::max<size_t>(1, std::min<size_t>(nb, RED_MAX_BLOCKS));
 }
 
-// --------------------------------------------------------------------------
-// generic multi-dot: out[pair][r] = sum conj(a_pair) b_pair over one field
-// --------------------------------------------------------------------------
-template <typename S, int NP>
-__global__ __launch_bounds__(RED_THREADS) void dot_partials_kernel(DotArgs d) {
-    typedef typename Store<S>::elem E;
-    __shared__ Cx<double> red[NP][RED_THREADS];
-    const int tid = threadIdx.x;
-    const int Bp = d.Bp;
-    const int r = tid & (Bp - 1);
-    const int sites_per_block = RED_THREADS / Bp;
-    Cx<double> acc[NP];
-#pragma unroll
-    for (int i = 0; i < NP; i++) acc[i] = cmake(0.0, 0.0);
-    if (r < d.B) {
-        for (int64_t s = (int64_t)blockIdx.x * sites_per_block + tid / Bp; s < d.nsite;
-             s += (int64_t)gridDim.x * sites_per_block) {
-            for (int c = 0; c < 12; c++) {
-                int64_t o = ((int64_t)c * d.nsite + s) * d.B + r;
-#pragma unroll
-                for (int i = 0; i < NP; i++) {
-                    auto x = Store<S>::ld((const E*)d.a[i] + o);
-                    auto y = Store<S>::ld((const E*)d.b[i] + o);
-                    acc[i] = acc[i] + conjmul(cmake<double>(x.re, x.im), cmake<double>(y.re, y.im));
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NP; i++) red[i][tid] = acc[i];
+// fixed-order tree over the RED_THREADS lanes down to B entries (lane r keeps RHS r)
+template <int NP>
+__device__ inline void block_reduce_rhs(Cx<double> (*red)[RED_THREADS], int B) {
     __syncthreads();
-    for (int st = RED_THREADS / 2; st >= Bp; st >>= 1) {
-        if (tid < st) {
+    for (int w = RED_THREADS / 2; w >= B; w >>= 1) {
+        if ((int)threadIdx.x < w) {
 #pragma unroll
-            for (int i = 0; i < NP; i++) red[i][tid] = red[i][tid] + red[i][tid + st];
+            for (int q = 0; q < NP; q++) red[q][threadIdx.x] = red[q][threadIdx.x] + red[q][threadIdx.x + w];
         }
         __syncthreads();
     }
-    if (tid < d.B) {
+}
+
+// --------------------------------------------------------------------------
+// generic multi-dot: partial[block][pair][r] = sum conj(a_pair) b_pair
+// --------------------------------------------------------------------------
+template <typename S, int NP>
+__global__ __launch_bounds__(RED_THREADS) void dot_partials_kernel(DotArgs d) {
+    typedef typename Store<S>::acc T;
+    constexpr int VW = Store<S>::VW;
+    __shared__ Cx<double> red[NP][RED_THREADS];
+    Cx<double> acc[NP];
 #pragma unroll
-        for (int i = 0; i < NP; i++) d.partial[((int64_t)blockIdx.x * NP + i) * d.B + tid] = red[i][tid];
+    for (int i = 0; i < NP; i++) acc[i] = cmake(0.0, 0.0);
+    const size_t stride = (size_t)gridDim.x * RED_THREADS;
+    for (size_t v = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; v < d.nvec; v += stride) {
+#pragma unroll
+        for (int i = 0; i < NP; i++) {
+            Cx<T> x[VW], y[VW];
+            Store<S>::ldv(d.a[i], v, x);
+            Store<S>::ldv(d.b[i], v, y);
+#pragma unroll
+            for (int j = 0; j < VW; j++)
+                acc[i] = acc[i] + conjmul(cmake<double>(x[j].re, x[j].im), cmake<double>(y[j].re, y[j].im));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NP; i++) red[i][threadIdx.x] = acc[i];
+    block_reduce_rhs<NP>(red, d.B);
+    if ((int)threadIdx.x < d.B) {
+#pragma unroll
+        for (int i = 0; i < NP; i++) d.partial[((int64_t)blockIdx.x * NP + i) * d.B + threadIdx.x] = red[i][threadIdx.x];
     }
 }
 
-int dot_blocks(int64_t nsite, int Bp) {
-    int64_t spb = RED_THREADS / Bp;
-    int64_t nb = (nsite + spb - 1) / spb;
-    return (int)(nb < RED_MAX_BLOCKS ? nb : RED_MAX_BLOCKS);
-}
-
-template <typename S>
-static int launch_dots_t(dht_ctx* c, DotArgs& d, int np, hipStream_t st) {
-    dim3 grid(d.nblocks), block(RED_THREADS);
-    switch (np) {
-        case 1: hipLaunchKernelGGL((dot_partials_kernel<S, 1>), grid, block, 0, st, d); break;
-        case 2: hipLaunchKernelGGL((dot_partials_kernel<S, 2>), grid, block, 0, st, d); break;
-        case 3: hipLaunchKernelGGL((dot_partials_kernel<S, 3>), grid, block, 0, st, d); break;
-        default: return set_error(DHT_ERR_INVALID_ARG, "npair must be 1..3");
-    }
-    DHT_HIP(hipGetLastError());
-    return DHT_OK;
-}
-
-int launch_dot_partials(dht_ctx* c, int prec, int np, const void* const* a, const void* const* b, int64_t nsite,
+int launch_dot_partials(dht_ctx* c, int prec, int np, const void* const* a, const void* const* b, size_t nvec,
                         int nrhs, Cx<double>* partial, int* nblocks_out) {
+    if (nrhs > RED_THREADS || (nrhs & (nrhs - 1))) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
     DotArgs d;
     for (int i = 0; i < 3; i++) {
         d.a[i] = i < np ? a[i] : nullptr;
         d.b[i] = i < np ? b[i] : nullptr;
     }
-    d.nsite = nsite;
+    d.nvec = nvec;
     d.B = nrhs;
-    d.Bp = pow2_at_least(nrhs);
-    if (d.Bp > RED_THREADS) return set_error(DHT_ERR_INVALID_ARG, "too many right-hand sides for a reduction");
     d.partial = partial;
-    d.nblocks = dot_blocks(nsite, d.Bp);
+    d.nblocks = red_blocks(nvec);
     *nblocks_out = d.nblocks;
-    switch (prec) {
-        case DHT_FP64: return launch_dots_t<double>(c, d, np, c->stream);
-        case DHT_FP32: return launch_dots_t<float>(c, d, np, c->stream);
-        case DHT_BF16: return launch_dots_t<bf16x2>(c, d, np, c->stream);
+    dim3 grid(d.nblocks), block(RED_THREADS);
+#define DHT_DOT(P, T)                                                                              \
+    if (prec == P) {                                                                               \
+        if (np == 1) hipLaunchKernelGGL((dot_partials_kernel<T, 1>), grid, block, 0, c->stream, d); \
+        else if (np == 2) hipLaunchKernelGGL((dot_partials_kernel<T, 2>), grid, block, 0, c->stream, d); \
+        else hipLaunchKernelGGL((dot_partials_kernel<T, 3>), grid, block, 0, c->stream, d);       \
+        DHT_HIP(hipGetLastError());                                                                \
+        return DHT_OK;                                                                             \
     }
+    if (np < 1 || np > 3) return set_error(DHT_ERR_INVALID_ARG, "npair must be 1..3");
+    DHT_DOT(DHT_FP64, double)
+    DHT_DOT(DHT_FP32, float)
+    DHT_DOT(DHT_BF16, bf16x2)
+#undef DHT_DOT
     return set_error(DHT_ERR_INVALID_ARG, "bad precision");
 }
 
-// sum partials over blocks: out[pair][r]
-__global__ void sum_partials_kernel(const Cx<double>* partial, int nblocks, int np, int B, Cx<double>* out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np * B) return;
-    int pair = i / B, r = i - pair * B;
-    Cx<double> s = cmake(0.0, 0.0);
-    for (int b = 0; b < nblocks; b++) s = s + partial[((int64_t)b * np + pair) * B + r];
-    out[i] = s;
-}
-
-int dots(dht_ctx* c, int prec, int np, const void* const* a, const void* const* b, int64_t nsite, int nrhs,
-         Cx<double>* out_dev) {
-    void* part;
-    DHT_TRY(ws_get(c, WS_PARTIAL, (size_t)RED_MAX_BLOCKS * 3 * nrhs * sizeof(Cx<double>), &part));
-    int nb;
-    DHT_TRY(launch_dot_partials(c, prec, np, a, b, nsite, nrhs, (Cx<double>*)part, &nb));
-    hipLaunchKernelGGL(sum_partials_kernel, dim3((np * nrhs + 63) / 64), dim3(64), 0, c->stream,
-                       (const Cx<double>*)part, nb, np, nrhs, out_dev);
-    DHT_HIP(hipGetLastError());
-    return DHT_OK;
-}
-
 // --------------------------------------------------------------------------
-// BiCGStab scalar updates (one thread per RHS)
+// finalise: one workgroup per RHS sums the partials in a fixed order, then
+// (op != FIN_SUM) applies the BiCGStab scalar update for that RHS
 // --------------------------------------------------------------------------
 __device__ inline Cx<double> cdiv(Cx<double> a, Cx<double> b) {
     double d = b.re * b.re + b.im * b.im;
@@ -140,17 +112,7 @@ __device__ inline Cx<double> cdiv(Cx<double> a, Cx<double> b) {
 __device__ inline double cabs2(Cx<double> a) { return a.re * a.re + a.im * a.im; }
 __device__ inline bool cfinite(Cx<double> a) { return isfinite(a.re) && isfinite(a.im); }
 
-__global__ void finalize_kernel(const Cx<double>* partial, int nblocks, int np, int B, RhsState* st, int op,
-                                double bd_eps) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= B) return;
-    Cx<double> v[3];
-    for (int pair = 0; pair < np; pair++) {
-        Cx<double> s = cmake(0.0, 0.0);
-        for (int b = 0; b < nblocks; b++) s = s + partial[((int64_t)b * np + pair) * B + r];
-        v[pair] = s;
-    }
-    RhsState& x = st[r];
+__device__ void state_update(RhsState& x, const Cx<double>* v, int op, double bd_eps) {
     if (op == FIN_INIT) {   // v0 = (r, r) with rhat = r = b
         x.rnorm2 = v[0].re;
         x.rhat2 = v[0].re;
@@ -185,136 +147,216 @@ __global__ void finalize_kernel(const Cx<double>* partial, int nblocks, int np, 
     }
 }
 
-int finalize(dht_ctx* c, const Cx<double>* partial, int nblocks, int np, int nrhs, RhsState* st, int op, double bd_eps) {
-    hipLaunchKernelGGL(finalize_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, partial, nblocks, np, nrhs, st,
-                       op, bd_eps);
+__global__ __launch_bounds__(RED_THREADS) void finalize_kernel(const Cx<double>* partial, int nblocks, int np, int B,
+                                                               RhsState* st, int op, double bd_eps, Cx<double>* sums) {
+    __shared__ Cx<double> red[RED_THREADS];
+    __shared__ Cx<double> v[3];
+    const int r = blockIdx.x;
+    for (int pair = 0; pair < np; pair++) {
+        Cx<double> s = cmake(0.0, 0.0);
+        for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) s = s + partial[((int64_t)b * np + pair) * B + r];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) v[pair] = red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (sums)
+            for (int pair = 0; pair < np; pair++) sums[pair * B + r] = v[pair];
+        if (op != FIN_SUM) state_update(st[r], v, op, bd_eps);
+    }
+}
+
+int finalize(dht_ctx* c, const Cx<double>* partial, int nblocks, int np, int nrhs, RhsState* st, int op, double bd_eps,
+             Cx<double>* sums) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(RED_THREADS), 0, c->stream, partial, nblocks, np, nrhs, st,
+                       op, bd_eps, sums);
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
 
+int dots(dht_ctx* c, int prec, int np, const void* const* a, const void* const* b, size_t nvec, int nrhs,
+         Cx<double>* out_dev) {
+    void* part;
+    DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
+    int nb;
+    DHT_TRY(launch_dot_partials(c, prec, np, a, b, nvec, nrhs, (Cx<double>*)part, &nb));
+    return finalize(c, (const Cx<double>*)part, nb, np, nrhs, nullptr, FIN_SUM, 0.0, out_dev);
+}
+
+size_t partial_bytes(const dht_ctx* c, int nrhs) {
+    // enough for a fused hop epilogue (one partial per hop workgroup) with 3 pairs
+    size_t nb = std::max<size_t>(RED_MAX_BLOCKS, (size_t)hop_blocks(c, nrhs));
+    return nb * 3 * nrhs * sizeof(Cx<double>);
+}
+
 // --------------------------------------------------------------------------
-// vector updates (elementwise over [12][nsite][B]; r = index mod B)
+// vector updates (one lane per 16-byte vector; r = v & (B - 1))
 // --------------------------------------------------------------------------
+template <typename T> __device__ inline Cx<T> cscal(Cx<double> a) { return cmake<T>((T)a.re, (T)a.im); }
+
 template <typename S>
-__global__ void p_update_kernel(typename Store<S>::elem* p, const typename Store<S>::elem* r_,
-                                const typename Store<S>::elem* v, const RhsState* st, size_t n, int B) {
+__global__ void p_update_kernel(void* p, const void* r_, const void* v, const RhsState* st, size_t nvec, int B) {
     typedef typename Store<S>::acc T;
+    constexpr int VW = Store<S>::VW;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int r = (int)(i % B);
-    const RhsState& x = st[r];
+    if (i >= nvec) return;
+    const RhsState& x = st[i & (B - 1)];
     if (!x.active) return;
-    Cx<T> beta = cmake<T>((T)x.beta.re, (T)x.beta.im), om = cmake<T>((T)x.omega.re, (T)x.omega.im);
-    Cx<T> pv = Store<S>::ld(p + i), rv = Store<S>::ld(r_ + i), vv = Store<S>::ld(v + i);
-    Store<S>::st(p + i, rv + beta * (pv - om * vv));
+    Cx<T> beta = cscal<T>(x.beta), om = cscal<T>(x.omega);
+    Cx<T> pv[VW], rv[VW], vv[VW];
+    Store<S>::ldv(p, i, pv);
+    Store<S>::ldv(r_, i, rv);
+    Store<S>::ldv(v, i, vv);
+#pragma unroll
+    for (int j = 0; j < VW; j++) pv[j] = rv[j] + beta * (pv[j] - om * vv[j]);
+    Store<S>::stv(p, i, pv);
 }
 
 template <typename S>
-__global__ void s_update_kernel(typename Store<S>::elem* s, const typename Store<S>::elem* r_,
-                                const typename Store<S>::elem* v, const RhsState* st, size_t n, int B) {
+__global__ void s_update_kernel(void* s, const void* r_, const void* v, const RhsState* st, size_t nvec, int B) {
     typedef typename Store<S>::acc T;
+    constexpr int VW = Store<S>::VW;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int r = (int)(i % B);
-    const RhsState& x = st[r];
+    if (i >= nvec) return;
+    const RhsState& x = st[i & (B - 1)];
     if (!x.active) return;
-    Cx<T> al = cmake<T>((T)x.alpha.re, (T)x.alpha.im);
-    Store<S>::st(s + i, Store<S>::ld(r_ + i) - al * Store<S>::ld(v + i));
+    Cx<T> al = cscal<T>(x.alpha);
+    Cx<T> rv[VW], vv[VW];
+    Store<S>::ldv(r_, i, rv);
+    Store<S>::ldv(v, i, vv);
+#pragma unroll
+    for (int j = 0; j < VW; j++) rv[j] = rv[j] - al * vv[j];
+    Store<S>::stv(s, i, rv);
 }
 
+// x += alpha p + omega s;  r = s - omega t;  partials of (rhat, r) and (r, r)
 template <typename S>
-__global__ void xr_update_kernel(typename Store<S>::elem* x_, typename Store<S>::elem* r_,
-                                 const typename Store<S>::elem* p, const typename Store<S>::elem* s,
-                                 const typename Store<S>::elem* t, const RhsState* st, size_t n, int B) {
+__global__ __launch_bounds__(RED_THREADS) void xr_update_kernel(void* x_, void* r_, const void* p, const void* s,
+                                                                const void* t, const void* rh, const RhsState* st,
+                                                                size_t nvec, int B, Cx<double>* partial) {
     typedef typename Store<S>::acc T;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int r = (int)(i % B);
-    const RhsState& x = st[r];
-    if (!x.active) return;
-    Cx<T> al = cmake<T>((T)x.alpha.re, (T)x.alpha.im), om = cmake<T>((T)x.omega.re, (T)x.omega.im);
-    Cx<T> sv = Store<S>::ld(s + i);
-    Store<S>::st(x_ + i, Store<S>::ld(x_ + i) + al * Store<S>::ld(p + i) + om * sv);
-    Store<S>::st(r_ + i, sv - om * Store<S>::ld(t + i));
+    constexpr int VW = Store<S>::VW;
+    __shared__ Cx<double> red[2][RED_THREADS];
+    Cx<double> d0 = cmake(0.0, 0.0), d1 = cmake(0.0, 0.0);
+    const size_t stride = (size_t)gridDim.x * RED_THREADS;
+    const RhsState& x = st[threadIdx.x & (B - 1)];   // the stride keeps each lane on one RHS
+    if (x.active) {
+        Cx<T> al = cscal<T>(x.alpha), om = cscal<T>(x.omega);
+        for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nvec; i += stride) {
+            Cx<T> xv[VW], pv[VW], sv[VW], tv[VW], hv[VW];
+            Store<S>::ldv(x_, i, xv);
+            Store<S>::ldv(p, i, pv);
+            Store<S>::ldv(s, i, sv);
+            Store<S>::ldv(t, i, tv);
+            Store<S>::ldv(rh, i, hv);
+#pragma unroll
+            for (int j = 0; j < VW; j++) {
+                xv[j] = xv[j] + al * pv[j] + om * sv[j];
+                sv[j] = Store<S>::round(sv[j] - om * tv[j]);   // the new r, as stored
+                Cx<double> rd = cmake<double>(sv[j].re, sv[j].im);
+                d0 = d0 + conjmul(cmake<double>(hv[j].re, hv[j].im), rd);
+                d1.re += rd.re * rd.re + rd.im * rd.im;
+            }
+            Store<S>::stv(x_, i, xv);
+            Store<S>::stv(r_, i, sv);
+        }
+    }
+    red[0][threadIdx.x] = d0;
+    red[1][threadIdx.x] = d1;
+    block_reduce_rhs<2>(red, B);
+    if ((int)threadIdx.x < B) {
+        partial[((int64_t)blockIdx.x * 2 + 0) * B + threadIdx.x] = red[0][threadIdx.x];
+        partial[((int64_t)blockIdx.x * 2 + 1) * B + threadIdx.x] = red[1][threadIdx.x];
+    }
 }
 
 static dim3 egrid(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
-int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const RhsState* st, size_t n, int B) {
-    switch (prec) {
-#define C_(P, T) case P: hipLaunchKernelGGL((p_update_kernel<T>), egrid(n), dim3(256), 0, c->stream, \
-        (typename Store<T>::elem*)p, (const typename Store<T>::elem*)r, (const typename Store<T>::elem*)v, st, n, B); break;
-        C_(DHT_FP64, double) C_(DHT_FP32, float) C_(DHT_BF16, bf16x2)
-#undef C_
+#define DHT_PREC_SWITCH(prec, LAUNCH)                 \
+    switch (prec) {                                   \
+        case DHT_FP64: { typedef double T_; LAUNCH; } break; \
+        case DHT_FP32: { typedef float T_; LAUNCH; } break;  \
+        case DHT_BF16: { typedef bf16x2 T_; LAUNCH; } break; \
+        default: return set_error(DHT_ERR_INVALID_ARG, "bad precision"); \
     }
+
+int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const RhsState* st, size_t nvec, int B) {
+    DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(p_update_kernel<T_>, egrid(nvec), dim3(256), 0, c->stream, p, r, v, st, nvec, B))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
-int s_update(dht_ctx* c, int prec, void* s, const void* r, const void* v, const RhsState* st, size_t n, int B) {
-    switch (prec) {
-#define C_(P, T) case P: hipLaunchKernelGGL((s_update_kernel<T>), egrid(n), dim3(256), 0, c->stream, \
-        (typename Store<T>::elem*)s, (const typename Store<T>::elem*)r, (const typename Store<T>::elem*)v, st, n, B); break;
-        C_(DHT_FP64, double) C_(DHT_FP32, float) C_(DHT_BF16, bf16x2)
-#undef C_
-    }
+int s_update(dht_ctx* c, int prec, void* s, const void* r, const void* v, const RhsState* st, size_t nvec, int B) {
+    DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(s_update_kernel<T_>, egrid(nvec), dim3(256), 0, c->stream, s, r, v, st, nvec, B))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
-int xr_update(dht_ctx* c, int prec, void* x, void* r, const void* p, const void* s, const void* t, const RhsState* st,
-              size_t n, int B) {
-    switch (prec) {
-#define C_(P, T) case P: hipLaunchKernelGGL((xr_update_kernel<T>), egrid(n), dim3(256), 0, c->stream, \
-        (typename Store<T>::elem*)x, (typename Store<T>::elem*)r, (const typename Store<T>::elem*)p, \
-        (const typename Store<T>::elem*)s, (const typename Store<T>::elem*)t, st, n, B); break;
-        C_(DHT_FP64, double) C_(DHT_FP32, float) C_(DHT_BF16, bf16x2)
-#undef C_
-    }
+int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const void* s, const void* t, const void* rh,
+                   const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks) {
+    int nb = red_blocks(nvec);
+    *nblocks = nb;
+    DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(xr_update_kernel<T_>, dim3(nb), dim3(RED_THREADS), 0, c->stream, x, r, p, s,
+                                             t, rh, st, nvec, B, partial))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
 
 // --------------------------------------------------------------------------
-// defect-correction helpers
+// defect-correction helpers (FP64 half field <-> low-precision half field)
 // --------------------------------------------------------------------------
-// out_lo = scale[r] * in_hi  (scale = 1 / ||r||, 0 for finished RHS)
+// low vector v = (cv, site-rhs sr) holds components cv*VW .. cv*VW+VW-1;
+// the FP64 vector of component c is c * SB + sr.
 template <typename SO>
-__global__ void scale_down_kernel(const Cx<double>* in, typename Store<SO>::elem* out, const double* scale, size_t n,
-                                  int B) {
+__global__ void scale_down_kernel(const Cx<double>* in, void* out, const double* scale, size_t nlo, int64_t SB, int B) {
     typedef typename Store<SO>::acc T;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double sc = scale[i % B];
-    Cx<double> v = in[i];
-    Store<SO>::st(out + i, cmake<T>((T)(sc * v.re), (T)(sc * v.im)));
+    constexpr int VW = Store<SO>::VW;
+    size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nlo) return;
+    int64_t cv = v / SB, sr = v - cv * SB;
+    double sc = scale[sr & (B - 1)];
+    Cx<T> e[VW];
+#pragma unroll
+    for (int j = 0; j < VW; j++) {
+        Cx<double> d = in[(cv * VW + j) * SB + sr];
+        e[j] = cmake<T>((T)(sc * d.re), (T)(sc * d.im));
+    }
+    Store<SO>::stv(out, v, e);
 }
-// x_hi += scale[r] * e_lo
 template <typename SI>
-__global__ void accum_up_kernel(Cx<double>* x, const typename Store<SI>::elem* e, const double* scale, size_t n, int B) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double sc = scale[i % B];
+__global__ void accum_up_kernel(Cx<double>* x, const void* e_, const double* scale, size_t nlo, int64_t SB, int B) {
+    typedef typename Store<SI>::acc T;
+    constexpr int VW = Store<SI>::VW;
+    size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nlo) return;
+    int64_t cv = v / SB, sr = v - cv * SB;
+    double sc = scale[sr & (B - 1)];
     if (sc == 0.0) return;
-    auto v = Store<SI>::ld(e + i);
-    x[i] = cmake(x[i].re + sc * (double)v.re, x[i].im + sc * (double)v.im);
+    Cx<T> e[VW];
+    Store<SI>::ldv(e_, v, e);
+#pragma unroll
+    for (int j = 0; j < VW; j++) {
+        Cx<double>& xd = x[(cv * VW + j) * SB + sr];
+        xd = cmake(xd.re + sc * (double)e[j].re, xd.im + sc * (double)e[j].im);
+    }
 }
 
-int scale_down(dht_ctx* c, const void* in, void* out, int pout, const double* scale, size_t n, int B) {
-    switch (pout) {
-#define C_(P, T) case P: hipLaunchKernelGGL((scale_down_kernel<T>), egrid(n), dim3(256), 0, c->stream, \
-        (const Cx<double>*)in, (typename Store<T>::elem*)out, scale, n, B); break;
-        C_(DHT_FP64, double) C_(DHT_FP32, float) C_(DHT_BF16, bf16x2)
-#undef C_
-    }
+int scale_down(dht_ctx* c, const void* in, void* out, int pout, const double* scale, int nrhs) {
+    const int64_t SB = c->g.Vh * (int64_t)nrhs;
+    size_t nlo = half_elems(c, nrhs) / vec_width(pout);
+    DHT_PREC_SWITCH(pout, hipLaunchKernelGGL(scale_down_kernel<T_>, egrid(nlo), dim3(256), 0, c->stream,
+                                             (const Cx<double>*)in, out, scale, nlo, SB, nrhs))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
-int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, size_t n, int B) {
-    switch (pin) {
-#define C_(P, T) case P: hipLaunchKernelGGL((accum_up_kernel<T>), egrid(n), dim3(256), 0, c->stream, \
-        (Cx<double>*)x, (const typename Store<T>::elem*)e, scale, n, B); break;
-        C_(DHT_FP64, double) C_(DHT_FP32, float) C_(DHT_BF16, bf16x2)
-#undef C_
-    }
+int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, int nrhs) {
+    const int64_t SB = c->g.Vh * (int64_t)nrhs;
+    size_t nlo = half_elems(c, nrhs) / vec_width(pin);
+    DHT_PREC_SWITCH(pin, hipLaunchKernelGGL(accum_up_kernel<T_>, egrid(nlo), dim3(256), 0, c->stream,
+                                            (Cx<double>*)x, e, scale, nlo, SB, nrhs))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
@@ -332,8 +374,8 @@ int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t n) {
     return DHT_OK;
 }
 
-// fill with zero (a kernel rather than a memset so that the stream can be captured)
-// grid-stride: the deflation basis can exceed 2^32 words (a launch is capped at 2^32 threads)
+// fill with zero (a kernel rather than a memset so that the stream can be
+// captured); grid-stride because the deflation basis can exceed 2^32 words
 __global__ void zero_kernel(uint4* p, size_t n16, uint32_t* tail, size_t ntail) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -344,7 +386,7 @@ int zero(dht_ctx* c, void* p, size_t bytes) {
     size_t n = bytes / 4;
     if (n == 0) return DHT_OK;
     size_t n16 = ((uintptr_t)p & 15) ? 0 : n / 4;   // 16-byte stores only on aligned buffers
-    size_t blocks = std::min<size_t>((n16 + 255) / 256, 65536);
+    size_t blocks = std::min<size_t>((std::max(n16, n - 4 * n16) + 255) / 256, 65536);
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, c->stream, (uint4*)p, n16,
                        (uint32_t*)p + 4 * n16, n - 4 * n16);

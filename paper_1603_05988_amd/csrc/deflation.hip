@@ -435,25 +435,30 @@ int deflation_set(dht_ctx* c, int first, int count, const double* W_dev) {
     return DHT_OK;
 }
 
-// n consecutive basis rows j0.. -> FP64 field [2][12][Vh][n] (RHS innermost)
+// n consecutive basis rows j0.. -> FP64 field [2][12][Vh][bp] (RHS innermost,
+// slots n..bp-1 zero)
 template <typename SW>
-__global__ void gather_kernel(const typename Store<SW>::elem* W, WLayout wl, int j0, int n, Cx<double>* out) {
+__global__ void gather_kernel(const typename Store<SW>::elem* W, WLayout wl, int j0, int n, int bp, Cx<double>* out) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= wl.Kn * n) return;
-    int64_t K = gid / n;
-    int j = (int)(gid - K * n);
+    if (gid >= wl.Kn * bp) return;
+    int64_t K = gid / bp;
+    int j = (int)(gid - K * bp);
+    if (j >= n) {
+        out[gid] = cmake(0.0, 0.0);
+        return;
+    }
     auto v = Store<SW>::ld(W + w_index(wl, j0 + j, K));
     out[gid] = cmake<double>(v.re, v.im);
 }
 
-int gather_columns(dht_ctx* c, int j0, int n, void* out) {
+int gather_columns(dht_ctx* c, int j0, int n, int bp, void* out) {
     const WLayout wl = wlayout(c);
-    int64_t tot = wl.Kn * n;
+    int64_t tot = wl.Kn * bp;
     dim3 grid((unsigned)((tot + 255) / 256)), block(256);
     switch (c->wprec) {
-        case DHT_FP64: hipLaunchKernelGGL(gather_kernel<double>, grid, block, 0, c->stream, (const Cx<double>*)c->W, wl, j0, n, (Cx<double>*)out); break;
-        case DHT_FP32: hipLaunchKernelGGL(gather_kernel<float>, grid, block, 0, c->stream, (const Cx<float>*)c->W, wl, j0, n, (Cx<double>*)out); break;
-        case DHT_BF16: hipLaunchKernelGGL(gather_kernel<bf16x2>, grid, block, 0, c->stream, (const bf16x2*)c->W, wl, j0, n, (Cx<double>*)out); break;
+        case DHT_FP64: hipLaunchKernelGGL(gather_kernel<double>, grid, block, 0, c->stream, (const Cx<double>*)c->W, wl, j0, n, bp, (Cx<double>*)out); break;
+        case DHT_FP32: hipLaunchKernelGGL(gather_kernel<float>, grid, block, 0, c->stream, (const Cx<float>*)c->W, wl, j0, n, bp, (Cx<double>*)out); break;
+        case DHT_BF16: hipLaunchKernelGGL(gather_kernel<bf16x2>, grid, block, 0, c->stream, (const bf16x2*)c->W, wl, j0, n, bp, (Cx<double>*)out); break;
         default: return set_error(DHT_ERR_INVALID_ARG, "bad precision");
     }
     DHT_HIP(hipGetLastError());
@@ -517,7 +522,8 @@ int deflation_finalize(dht_ctx* c, bool diagonal) {
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     const int k = c->k;
     const int nb = std::min(k, 32);
-    const size_t fb = full_elems(c, nb) * 16;
+    const int nbp = pad_rhs(nb);   // array stride: every block is padded to a power of two
+    const size_t fb = full_elems(c, nbp) * 16;
     void *wb, *qwb, *cc;
     DHT_TRY(ws_get(c, WS_QW, fb, &wb));
     DHT_TRY(ws_get(c, WS_XF, fb, &qwb));
@@ -528,37 +534,39 @@ int deflation_finalize(dht_ctx* c, bool diagonal) {
         H.assign((size_t)k * k, 0.0);
         G5.assign((size_t)k * k, 0.0);
     }
-    std::vector<Cx<double>> hb((size_t)4 * k * nb);
+    std::vector<Cx<double>> hb((size_t)4 * k * nbp);
     Cx<double>* h1 = (Cx<double>*)cc;
+    const size_t fvec = full_elems(c, 1);   // FP64 vectors per column
     for (int j0 = 0; j0 < k; j0 += nb) {
-        int n = std::min(nb, k - j0);
-        DHT_TRY(gather_columns(c, j0, n, wb));
-        DHT_TRY(apply_full(c, DHT_OP_Q, DHT_FP64, wb, qwb, n));
+        const int n = std::min(nb, k - j0);
+        const int bp = pad_rhs(n);
+        DHT_TRY(gather_columns(c, j0, n, bp, wb));
+        DHT_TRY(apply_full(c, DHT_OP_Q, DHT_FP64, wb, qwb, bp));
         if (diagonal) {
             const void* a1[1] = {wb};
             const void* b1[1] = {qwb};
-            DHT_TRY(dots(c, DHT_FP64, 1, a1, b1, 2 * c->g.Vh, n, h1));        // w^H Q w
-            DHT_TRY(g5_field(c, DHT_FP64, wb, qwb, n));                         // qwb <- g5 w
-            DHT_TRY(dots(c, DHT_FP64, 1, a1, b1, 2 * c->g.Vh, n, h1 + n));    // w^H g5 w
-            DHT_HIP(hipMemcpyAsync(hb.data(), cc, sizeof(Cx<double>) * 2 * n, hipMemcpyDeviceToHost, c->stream));
+            DHT_TRY(dots(c, DHT_FP64, 1, a1, b1, fvec * bp, bp, h1));        // w^H Q w
+            DHT_TRY(g5_field(c, DHT_FP64, wb, qwb, bp));                       // qwb <- g5 w
+            DHT_TRY(dots(c, DHT_FP64, 1, a1, b1, fvec * bp, bp, h1 + bp));   // w^H g5 w
+            DHT_HIP(hipMemcpyAsync(hb.data(), cc, sizeof(Cx<double>) * 2 * bp, hipMemcpyDeviceToHost, c->stream));
             DHT_HIP(hipStreamSynchronize(c->stream));
             for (int jj = 0; jj < n; jj++) {
                 hdiag[j0 + jj] = hb[jj].re;
-                gdiag[j0 + jj] = hb[n + jj].re;
+                gdiag[j0 + jj] = hb[bp + jj].re;
             }
             continue;
         }
-        Cx<double>* h2 = h1 + (size_t)k * nb;
-        Cx<double>* g1 = h2 + (size_t)k * nb;
-        Cx<double>* g5m = g1 + (size_t)k * nb;
-        DHT_TRY(project_field(c, qwb, DHT_FP64, n, h1, h2));
-        DHT_TRY(project_field(c, wb, DHT_FP64, n, g1, g5m));
-        DHT_HIP(hipMemcpyAsync(hb.data(), cc, sizeof(Cx<double>) * 4 * k * nb, hipMemcpyDeviceToHost, c->stream));
+        Cx<double>* h2 = h1 + (size_t)k * nbp;
+        Cx<double>* g1 = h2 + (size_t)k * nbp;
+        Cx<double>* g5m = g1 + (size_t)k * nbp;
+        DHT_TRY(project_field(c, qwb, DHT_FP64, bp, h1, h2));
+        DHT_TRY(project_field(c, wb, DHT_FP64, bp, g1, g5m));
+        DHT_HIP(hipMemcpyAsync(hb.data(), cc, sizeof(Cx<double>) * 4 * k * nbp, hipMemcpyDeviceToHost, c->stream));
         DHT_HIP(hipStreamSynchronize(c->stream));
         for (int i = 0; i < k; i++)
             for (int jj = 0; jj < n; jj++) {
-                Cx<double> hv = hb[(size_t)i * n + jj];
-                Cx<double> gv = hb[(size_t)3 * k * nb + (size_t)i * n + jj];
+                Cx<double> hv = hb[(size_t)i * bp + jj];
+                Cx<double> gv = hb[(size_t)3 * k * nbp + (size_t)i * bp + jj];
                 H[(size_t)i * k + j0 + jj] = std::complex<double>(hv.re, hv.im);
                 G5[(size_t)i * k + j0 + jj] = std::complex<double>(gv.re, gv.im);
             }
@@ -587,13 +595,13 @@ int deflation_finalize(dht_ctx* c, bool diagonal) {
     return store_M(c, H, td, false);
 }
 
-// d_j = c1_j^H M c2_j on the host (c1, c2 host arrays [k][B] complex)
-void deflation_corrections(const dht_ctx* c, const Cx<double>* c1, const Cx<double>* c2, int B, double* dre,
+// d_j = c1_j^H M c2_j on the host for columns r < nuse (c1, c2 host arrays [k][B] complex)
+void deflation_corrections(const dht_ctx* c, const Cx<double>* c1, const Cx<double>* c2, int B, int nuse, double* dre,
                            double* dim) {
     const int k = c->k;
     const std::complex<double>* M = (const std::complex<double>*)c->M.data();
     std::vector<std::complex<double>> v(k);
-    for (int r = 0; r < B; r++) {
+    for (int r = 0; r < nuse; r++) {
         for (int a = 0; a < k; a++) {
             std::complex<double> s = 0.0;
             std::complex<double> c2b;

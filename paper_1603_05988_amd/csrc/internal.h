@@ -1,15 +1,20 @@
 // Internal declarations of the dhtrace library (gfx950).
 //
-// Internal field layout ("even/odd, RHS-innermost"): a field of B right-hand
-// sides on one parity is complex<T>[12][Vh][B] -- spin-colour component
-// c = 3 spin + colour outermost, checkerboard site s, then the RHS.  A lane of
-// a kernel owns one (s, rhs) pair, so every component load of a wavefront is
-// one contiguous run.  A full-lattice field is two parity fields back to back
-// (parity 0 = even first).  Checkerboard index of site (x, y, z, t):
-// s = lexicographic(x, y, z, t) / 2 (Lx even), parity = (x+y+z+t) & 1.
+// Internal field layout ("even/odd, RHS-innermost, 16-byte vectors"): a
+// field of B right-hand sides on one parity is complex<T>[12/VW][Vh][B][VW],
+// where VW = 16 / sizeof(complex<T>) spin-colour components (c = 3 spin +
+// colour) share one 16-byte vector: 1 in FP64, 2 in FP32, 4 in BF16.  A lane
+// owns one (site s, RHS r) pair and reads each group of VW components with a
+// single 16-byte load; the lanes of a wavefront read one contiguous run.  B is
+// always a power of two (callers' batches are padded with zero right-hand
+// sides), so the RHS of vector v is v & (B - 1).  A full-lattice field is two
+// parity fields back to back (parity 0 = even first).  Checkerboard index of
+// site (x, y, z, t): s = lexicographic(x, y, z, t) / 2 (Lx even), parity =
+// (x+y+z+t) & 1.
 //
-// Links: complex<T>[4 dir][9 (row-major 3x3)][2 parity][Vh], stored in FP64,
-// FP32 and BF16.
+// Links: for each (direction mu, parity, site) one 3x3 complex matrix
+// (row-major) in ceil(9 / VW) consecutive 16-byte vectors, stored in FP64,
+// FP32 and BF16: [4][2][Vh][nvec].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -60,34 +65,69 @@ __host__ __device__ inline float bf16_bits_to_f32(uint32_t h) {
     return f;
 }
 
-// Storage traits: how a complex<T> element is loaded/stored and what it
-// accumulates in.
+// Storage traits: how a complex<T> element is loaded/stored, what it
+// accumulates in, and how VW of them pack into one 16-byte vector.
 template <typename S> struct Store;
 template <> struct Store<double> {
     typedef double acc;
     typedef Cx<double> elem;
+    static constexpr int VW = 1;
+    __device__ static inline Cx<double> round(Cx<double> v) { return v; }
     __device__ static inline Cx<double> ld(const elem* p) { return *p; }
     __device__ static inline void st(elem* p, Cx<double> v) { *p = v; }
+    __device__ static inline void ldv(const void* base, int64_t v, Cx<double>* o) {
+        double2 d = ((const double2*)base)[v];
+        o[0] = cmake(d.x, d.y);
+    }
+    __device__ static inline void stv(void* base, int64_t v, const Cx<double>* i) {
+        ((double2*)base)[v] = make_double2(i[0].re, i[0].im);
+    }
 };
 template <> struct Store<float> {
     typedef float acc;
     typedef Cx<float> elem;
+    static constexpr int VW = 2;
+    __device__ static inline Cx<float> round(Cx<float> v) { return v; }
     __device__ static inline Cx<float> ld(const elem* p) { return *p; }
     __device__ static inline void st(elem* p, Cx<float> v) { *p = v; }
+    __device__ static inline void ldv(const void* base, int64_t v, Cx<float>* o) {
+        float4 d = ((const float4*)base)[v];
+        o[0] = cmake(d.x, d.y);
+        o[1] = cmake(d.z, d.w);
+    }
+    __device__ static inline void stv(void* base, int64_t v, const Cx<float>* i) {
+        ((float4*)base)[v] = make_float4(i[0].re, i[0].im, i[1].re, i[1].im);
+    }
 };
 template <> struct Store<bf16x2> {
     typedef float acc;
     typedef bf16x2 elem;
-    __device__ static inline Cx<float> ld(const elem* p) {
-        uint32_t b = p->bits;
+    static constexpr int VW = 4;
+    __device__ static inline Cx<float> unpack(uint32_t b) {
         return cmake(bf16_bits_to_f32(b & 0xffffu), bf16_bits_to_f32(b >> 16));
     }
-    __device__ static inline void st(elem* p, Cx<float> v) {
-        p->bits = f32_to_bf16_bits(v.re) | (f32_to_bf16_bits(v.im) << 16);
+    __device__ static inline uint32_t pack(Cx<float> v) {
+        return f32_to_bf16_bits(v.re) | (f32_to_bf16_bits(v.im) << 16);
+    }
+    __device__ static inline Cx<float> round(Cx<float> v) { return unpack(pack(v)); }
+    __device__ static inline Cx<float> ld(const elem* p) { return unpack(p->bits); }
+    __device__ static inline void st(elem* p, Cx<float> v) { p->bits = pack(v); }
+    __device__ static inline void ldv(const void* base, int64_t v, Cx<float>* o) {
+        uint4 d = ((const uint4*)base)[v];
+        o[0] = unpack(d.x);
+        o[1] = unpack(d.y);
+        o[2] = unpack(d.z);
+        o[3] = unpack(d.w);
+    }
+    __device__ static inline void stv(void* base, int64_t v, const Cx<float>* i) {
+        ((uint4*)base)[v] = make_uint4(pack(i[0]), pack(i[1]), pack(i[2]), pack(i[3]));
     }
 };
 
 inline size_t elem_bytes(int prec) { return prec == DHT_FP64 ? 16 : (prec == DHT_FP32 ? 8 : 4); }
+inline int vec_width(int prec) { return prec == DHT_FP64 ? 1 : (prec == DHT_FP32 ? 2 : 4); }
+// 16-byte vectors holding one link matrix (9 complex, padded)
+inline int link_vecs(int prec) { return (9 + vec_width(prec) - 1) / vec_width(prec); }
 
 // ---------------------------------------------------------------------------
 // geometry
@@ -134,6 +174,19 @@ struct ProfStat {
     double bytes = 0.0;
 };
 
+// learned preconditioner weights (device)
+struct NNState {
+    bool ready = false;
+    void* mem = nullptr;
+    float* w[3] = {nullptr, nullptr, nullptr};     // FP32 master [81][Cout][Cin]
+    float* g[3] = {nullptr, nullptr, nullptr};     // gradients
+    float* m[3] = {nullptr, nullptr, nullptr};     // Adam first moments
+    float* v[3] = {nullptr, nullptr, nullptr};     // Adam second moments
+    uint16_t* wf[3] = {nullptr, nullptr, nullptr}; // BF16 forward copy
+    uint16_t* wb[3] = {nullptr, nullptr, nullptr}; // BF16 reflected/transposed copy
+    int64_t step = 0;
+};
+
 struct Welford {   // running mean / second moments of complex samples (Chan et al. update)
     int64_t n = 0;
     double mre = 0, mim = 0;   // means
@@ -172,6 +225,8 @@ struct dht_ctx {
     dht::ProfStat prof_stat[dht::PROF_NCLASS];
     // estimator
     dht::Welford est_q, est_qd;
+    // learned preconditioner
+    dht::NNState nn;
     // workspace slots (grow-only)
     std::vector<dht::Buf> ws;
     // timings of the last call (ms)
@@ -203,6 +258,7 @@ enum Slot {
     WS_KLO = WS_K64 + 9,    // 9 low-precision Krylov vectors (same roles)
     WS_PARTIAL = WS_KLO + 9, WS_SCAL, WS_SCAL2, WS_FLAGS, WS_HOSTPIN,
     WS_Z, WS_XF, WS_QW, WS_PROJ, WS_COEF, WS_PROJ2, WS_ZCODE,
+    WS_NN_PART, WS_NN_ACT, WS_NN_SCAL, WS_FG_V, WS_FG_Z, WS_FG_W, WS_FG_COEF, WS_FG_R, WS_FG_E, WS_XSTAR,
     WS_NSLOTS
 };
 int ws_get(dht_ctx* c, int slot, size_t bytes, void** out);
@@ -213,27 +269,48 @@ int prof_end(dht_ctx* c, int token, int cls, double bytes);
 int prof_harvest(dht_ctx* c);   // after a stream synchronisation
 
 // field helpers -------------------------------------------------------------
+// (nrhs is the padded power-of-two batch in every internal call)
 inline size_t half_elems(const dht_ctx* c, int nrhs) { return (size_t)12 * c->g.Vh * nrhs; }
 inline size_t full_elems(const dht_ctx* c, int nrhs) { return 2 * half_elems(c, nrhs); }
+inline int pad_rhs(int n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
 
 // kernels (launchers) -------------------------------------------------------
 // pack.hip
 int pack_gauge(dht_ctx* c, const double* U_dev);
-int pack_spinor(dht_ctx* c, const double* canon, void* field, int prec, int nrhs);     // canonical -> full internal
-int unpack_spinor(dht_ctx* c, const void* field, int prec, double* canon, int nrhs);   // full internal -> canonical
-int convert_field(dht_ctx* c, const void* in, int pin, void* out, int pout, size_t nelem);
+// canonical [n][V][12] complex128 <-> full internal field with bp >= n RHS slots
+// (pack writes zeros into slots n..bp-1; unpack reads slots < n only)
+int pack_spinor(dht_ctx* c, const double* canon, void* field, int prec, int n, int bp);
+int unpack_spinor(dht_ctx* c, const void* field, int prec, double* canon, int n, int bp);
 
 // dslash.hip: out_p = a * x_p + b * Hop_{p <- 1-p}(in), optionally g5 on the result and/or dagger hop.
+// A per-RHS FP64 reduction can be fused into the epilogue: HOPDOT_A_OUT gives
+// (a, out) = sum conj(a) out; HOPDOT_OUT_X gives (out, x) and (out, out).
+// Partial sums go to partial[block][pair][nrhs]; *nblocks receives the count.
+enum { HOPDOT_NONE = 0, HOPDOT_A_OUT = 1, HOPDOT_OUT_X = 2 };
+struct HopDot {
+    int kind = HOPDOT_NONE;
+    const void* a = nullptr;
+    Cx<double>* partial = nullptr;
+    int nblocks = 0;
+};
 int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
-        int nrhs, bool dagger, bool g5out);
+        int nrhs, bool dagger, bool g5out, HopDot* dot = nullptr);
+int hop_blocks(const dht_ctx* c, int nrhs);   // workgroups of one hop launch
 int apply_full(dht_ctx* c, int op, int prec, const void* in, void* out, int nrhs);   // full-lattice D, D^H, g5, Q
 int g5_field(dht_ctx* c, int prec, const void* in, void* out, int nrhs);              // full-lattice g5
 
 // probes.hip: probes j = first.. first+nrhs-1 into a full internal field of
 // precision prec (may be null), plus optional index/sign outputs.
-// zcode (may be null): per (complex entry K of the full internal field, RHS) the
-// 2-bit code k' with z = i^k' ([24 Vh][nrhs] bytes), the input of the MFMA projection.
-int probes_gen(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, void* field, int prec,
+// Probes j = first .. first+n-1 into the first n of bp RHS slots of a full
+// internal field (slots n..bp-1 are zero).  kout [n][N] and sout [n][V] are the
+// raw noise indices and Hadamard signs; zcode (may be null) holds per (complex
+// entry K of the full field in FP64 order, slot) the 2-bit code k' with
+// z = i^k' ([24 Vh][bp] bytes), the input of the MFMA projection.
+int probes_gen(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n, int bp, void* field, int prec,
                uint8_t* kout, int8_t* sout, uint8_t* zcode = nullptr);
 
 }  // namespace dht

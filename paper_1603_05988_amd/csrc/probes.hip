@@ -43,7 +43,8 @@ __device__ inline uint64_t hp_colour_bits(const int c[4], uint64_t j) {
 
 struct ProbeArgs {
     Geom g;
-    int B;
+    int n;      // real probes
+    int B;      // padded slots (power of two)
     int hp;
     uint64_t krun;
     int64_t first;
@@ -56,12 +57,15 @@ struct ProbeArgs {
 
 template <typename S>
 __global__ void probe_kernel(ProbeArgs a) {
+    typedef typename Store<S>::acc T;
+    constexpr int VW = Store<S>::VW;
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (p, s, r), r fastest
     if (gid >= a.g.V * (int64_t)a.B) return;
     int64_t ps = gid / a.B;
     int r = (int)(gid - ps * a.B);
     int p = (int)(ps / a.g.Vh);
     int64_t s = ps - (int64_t)p * a.g.Vh;
+    const bool real = r < a.n;
     int c[4];
     cb_coords(a.g, s, p, c);
     int64_t n = lex_index(a.g, c);
@@ -69,10 +73,10 @@ __global__ void probe_kernel(ProbeArgs a) {
     uint64_t key = a.hp ? a.krun : sm64_out(a.krun, j);
     float sign = 1.0f;
     if (a.hp) sign = (__popcll(hp_colour_bits(c, j) & j) & 1) ? -1.0f : 1.0f;
-    if (a.sout) a.sout[(int64_t)r * a.g.V + n] = (int8_t)sign;
+    if (a.sout && real) a.sout[(int64_t)r * a.g.V + n] = (int8_t)sign;
     const int64_t N = 12 * a.g.V;
     uint64_t widx = ~0ull, word = 0;
-    typename Store<S>::elem* f = (typename Store<S>::elem*)a.field;
+    Cx<T> e[12];
     for (int comp = 0; comp < 12; comp++) {
         uint64_t nc = (uint64_t)(12 * n + comp);
         if ((nc >> 5) != widx) {
@@ -80,25 +84,30 @@ __global__ void probe_kernel(ProbeArgs a) {
             word = sm64_out(key, widx);
         }
         int k = (int)((word >> (2 * (nc & 31))) & 3ull);
-        if (a.kout) a.kout[(int64_t)r * N + (int64_t)nc] = (uint8_t)k;
-        if (a.zcode)   // z = i^k * sign = i^(k + 2 [sign < 0])
+        if (a.kout && real) a.kout[(int64_t)r * N + (int64_t)nc] = (uint8_t)k;
+        if (a.zcode)   // z = i^k * sign = i^(k + 2 [sign < 0]); padding slots hold code 0 but are never read
             a.zcode[((int64_t)p * 12 * a.g.Vh + (int64_t)comp * a.g.Vh + s) * a.B + r] =
                 (uint8_t)((k + (sign < 0.0f ? 2 : 0)) & 3);
-        if (f) {
-            typedef typename Store<S>::acc T;
-            T re = (k == 0) ? T(1) : (k == 2 ? T(-1) : T(0));
-            T im = (k == 1) ? T(1) : (k == 3 ? T(-1) : T(0));
-            Store<S>::st(f + ((int64_t)p * 12 * a.g.Vh + (int64_t)comp * a.g.Vh + s) * a.B + r,
-                         cmake<T>((T)sign * re, (T)sign * im));
-        }
+        T re = (k == 0) ? T(1) : (k == 2 ? T(-1) : T(0));
+        T im = (k == 1) ? T(1) : (k == 3 ? T(-1) : T(0));
+        e[comp] = real ? cmake<T>((T)sign * re, (T)sign * im) : cmake<T>(0, 0);
+    }
+    if (a.field) {
+        const int64_t SB = a.g.Vh * a.B;
+        const int64_t vbase = (int64_t)p * (12 / VW) * SB + s * a.B + r;
+#pragma unroll
+        for (int q = 0; q < 12 / VW; q++) Store<S>::stv(a.field, vbase + q * SB, e + q * VW);
     }
 }
 
-int probes_gen(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, void* field, int prec, uint8_t* kout,
-               int8_t* sout, uint8_t* zcode) {
+int probes_gen(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n, int bp, void* field, int prec,
+               uint8_t* kout, int8_t* sout, uint8_t* zcode) {
     if (first < 0) return set_error(DHT_ERR_INVALID_ARG, "negative probe index");
+    if (n > bp) return set_error(DHT_ERR_INVALID_ARG, "batch exceeds its padded size");
+    const int nrhs = bp;
     ProbeArgs a;
     a.g = c->g;
+    a.n = n;
     a.B = nrhs;
     a.hp = spec->hp ? 1 : 0;
     a.krun = sm64_out(spec->seed, spec->run);
@@ -108,8 +117,8 @@ int probes_gen(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, 
     a.kout = kout;
     a.sout = sout;
     a.zcode = zcode;
-    int64_t n = c->g.V * (int64_t)nrhs;
-    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    int64_t nthreads = c->g.V * (int64_t)nrhs;
+    dim3 grid((unsigned)((nthreads + 255) / 256)), block(256);
     switch (prec) {
         case DHT_FP64: hipLaunchKernelGGL(probe_kernel<double>, grid, block, 0, c->stream, a); break;
         case DHT_FP32: hipLaunchKernelGGL(probe_kernel<float>, grid, block, 0, c->stream, a); break;

@@ -1,4 +1,7 @@
 // Batched Krylov solvers: shared declarations.
+//
+// Every internal batch size `nrhs` below is a power of two (<= 256); the
+// interface pads callers' batches with zero right-hand sides.
 #pragma once
 
 #include "internal.h"
@@ -6,7 +9,7 @@
 namespace dht {
 
 enum { RS_RUNNING = 0, RS_CONVERGED = 1, RS_BREAKDOWN = 2, RS_NAN = 3 };
-enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_OMEGA = 2, FIN_RHO = 3 };
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_OMEGA = 2, FIN_RHO = 3, FIN_SUM = 4 };
 
 // Per-RHS BiCGStab state, resident on the device.
 struct RhsState {
@@ -23,29 +26,39 @@ struct RhsState {
 struct DotArgs {
     const void* a[3];
     const void* b[3];
-    int64_t nsite;
-    int B, Bp;
+    size_t nvec;        // 16-byte vectors per operand
+    int B;
     Cx<double>* partial;
     int nblocks;
 };
 
-int launch_dot_partials(dht_ctx* c, int prec, int np, const void* const* a, const void* const* b, int64_t nsite,
+// workspace bytes for reduction partials (generic dots and fused hop epilogues)
+size_t partial_bytes(const dht_ctx* c, int nrhs);
+int launch_dot_partials(dht_ctx* c, int prec, int np, const void* const* a, const void* const* b, size_t nvec,
                         int nrhs, Cx<double>* partial, int* nblocks_out);
+// sum partials per (pair, RHS) into sums[pair][r] (if non-null) and apply the
+// BiCGStab scalar update `op` to st (unless op == FIN_SUM)
 int finalize(dht_ctx* c, const Cx<double>* partial, int nblocks, int np, int nrhs, RhsState* st, int op,
-             double bd_eps);
-int dots(dht_ctx* c, int prec, int np, const void* const* a, const void* const* b, int64_t nsite, int nrhs,
+             double bd_eps, Cx<double>* sums = nullptr);
+// out_dev[pair][r] = sum conj(a_pair) b_pair over nvec vectors
+int dots(dht_ctx* c, int prec, int np, const void* const* a, const void* const* b, size_t nvec, int nrhs,
          Cx<double>* out_dev);
-int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const RhsState* st, size_t n, int B);
-int s_update(dht_ctx* c, int prec, void* s, const void* r, const void* v, const RhsState* st, size_t n, int B);
-int xr_update(dht_ctx* c, int prec, void* x, void* r, const void* p, const void* s, const void* t,
-              const RhsState* st, size_t n, int B);
-int scale_down(dht_ctx* c, const void* in, void* out, int pout, const double* scale, size_t n, int B);
-int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, size_t n, int B);
-int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t n);
+int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const RhsState* st, size_t nvec, int B);
+int s_update(dht_ctx* c, int prec, void* s, const void* r, const void* v, const RhsState* st, size_t nvec, int B);
+int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const void* s, const void* t, const void* rh,
+                   const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks);
+// half fields: out_low = scale[r] * in_fp64 ; x_fp64 += scale[r] * e_low
+int scale_down(dht_ctx* c, const void* in, void* out, int pout, const double* scale, int nrhs);
+int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, int nrhs);
+int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t ncomplex);
 int zero(dht_ctx* c, void* p, size_t bytes);
 
-// Schur operator on even sites: out = (4+m) in - Hop_eo Hop_oe in / (4 (4+m)).
-int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o, int nrhs);
+inline size_t half_vecs(const dht_ctx* c, int nrhs, int prec) { return half_elems(c, nrhs) / vec_width(prec); }
+inline size_t full_vecs(const dht_ctx* c, int nrhs, int prec) { return full_elems(c, nrhs) / vec_width(prec); }
+
+// Schur operator on even sites: out = (4+m) in - Hop_eo Hop_oe in / (4 (4+m)),
+// optionally with a fused reduction in the second hop.
+int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o, int nrhs, HopDot* dot = nullptr);
 
 // Batched BiCGStab on the Schur system in storage precision `prec`:
 //   solves  Dhat x = b  for nrhs columns (half fields), x overwritten (starts at 0),
@@ -58,17 +71,44 @@ struct BicgResult {
 int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::vector<double>& target2, int maxiter,
              BicgResult* res);
 
-// Top-level solve of D X = Z on internal full FP64 fields (Z, X: [2][12][Vh][B]).
+// Top-level solve of D X = Z on internal full FP64 fields (Z, X: [2][12][Vh][B]);
+// stats has nrhs entries (the padded batch).
 int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats);
+
+// fgmres.hip: FP64 defect correction around FGMRES(m) cycles (FP32) on the
+// full lattice with the network (use_nn) or the identity as right
+// preconditioner.  A PairSink, if given, records (r_k / ||r_k||,
+// (x* - x_k) / ||r_k||) at every restart k for the first n real RHS.
+struct PairSink {
+    const void* xstar = nullptr;   // full FP64 field of reference solutions
+    double* R = nullptr;           // canonical complex128 outputs [cap][V][12]
+    double* E = nullptr;
+    int cap = 0, count = 0, nreal = 0;
+    int take(dht_ctx* c, const void* r, const void* x, const std::vector<bool>& act, const std::vector<double>& rn2);
+};
+int solve_fgmres(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int B, dht_solve_stats* stats,
+                 bool use_nn, PairSink* sink);
+
+// nn.hip
+static constexpr int NN_MAX_BATCH = 64;
+int nn_alloc(dht_ctx* c);
+int nn_set_weights(dht_ctx* c, const float* host);
+int nn_get_weights(dht_ctx* c, float* host, bool grads);
+int64_t nn_num_weights();
+int nn_forward_canon(dht_ctx* c, const double* R, double* E, int n);
+int nn_grad_canon(dht_ctx* c, const double* R, const double* E, int n, double* loss);
+int nn_train_canon(dht_ctx* c, const double* R, const double* E, int npairs, int epochs, int batch, float lr,
+                   double* final_loss);
+int nn_apply_field(dht_ctx* c, const void* in, void* out, int nrhs);   // FP32 full fields
 
 // deflation.hip
 int project_field(dht_ctx* c, const void* Z, int zprec, int nrhs, Cx<double>* c1, Cx<double>* c2);
 int deflation_begin(dht_ctx* c, int k, int prec);
 int deflation_set(dht_ctx* c, int first, int count, const double* W_dev);
 int deflation_finalize(dht_ctx* c, bool diagonal);
-void deflation_corrections(const dht_ctx* c, const Cx<double>* c1, const Cx<double>* c2, int B, double* dre,
-                           double* dim);
-int gather_columns(dht_ctx* c, int j0, int n, void* out);
+void deflation_corrections(const dht_ctx* c, const Cx<double>* c1, const Cx<double>* c2, int B, int nuse,
+                           double* dre, double* dim);
+int gather_columns(dht_ctx* c, int j0, int n, int bp, void* out);
 int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<double>* c2);
 
 }  // namespace dht

@@ -7,6 +7,9 @@
 //      x_o = (b_o + Hop_oe x_e / 2) / a,
 //    and the Schur residual equals the full-lattice residual (odd part zero);
 //  * batched BiCGStab (van der Vorst 1992) with per-RHS scalars on the device;
+//    its five reductions per iteration ride on the epilogues of the second
+//    hop of each operator application and of the x/r update, so an iteration
+//    is 4 hop launches + 3 vector passes + 3 one-workgroup-per-RHS finalises;
 //  * FP64 defect correction: r = b - Dhat x in FP64, inner solve of
 //    Dhat e = r / ||r|| in FP32 or BF16 storage, x += ||r|| e in FP64, until
 //    the FP64 residual meets the target.  The plain FP64 method is the same
@@ -22,10 +25,10 @@
 
 namespace dht {
 
-int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o, int nrhs) {
+int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o, int nrhs, HopDot* dot) {
     const double a = 4.0 + c->mass;
     DHT_TRY(hop(c, prec, 1, in_e, tmp_o, nullptr, 0.0, 1.0, nrhs, false, false));
-    DHT_TRY(hop(c, prec, 0, tmp_o, out_e, in_e, a, -1.0 / (4.0 * a), nrhs, false, false));
+    DHT_TRY(hop(c, prec, 0, tmp_o, out_e, in_e, a, -1.0 / (4.0 * a), nrhs, false, false, dot));
     return DHT_OK;
 }
 
@@ -33,8 +36,8 @@ static int slot_base(int prec) { return prec == DHT_FP64 ? WS_K64 : WS_KLO; }
 
 int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::vector<double>& target2, int maxiter,
              BicgResult* res) {
-    const size_t n = half_elems(c, nrhs);
-    const size_t bytes = n * elem_bytes(prec);
+    const size_t nvec = half_vecs(c, nrhs, prec);
+    const size_t bytes = nvec * 16;
     const int base = slot_base(prec);
     void *r, *rh, *p, *v, *s, *t, *tmp, *stv, *part, *hostv;
     DHT_TRY(ws_get(c, base + 0, bytes, &r));
@@ -45,7 +48,7 @@ int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::
     DHT_TRY(ws_get(c, base + 5, bytes, &t));
     DHT_TRY(ws_get(c, base + 6, bytes, &tmp));
     DHT_TRY(ws_get(c, WS_SCAL, sizeof(RhsState) * nrhs, &stv));
-    DHT_TRY(ws_get(c, WS_PARTIAL, (size_t)1024 * 3 * nrhs * sizeof(Cx<double>), &part));
+    DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
     DHT_TRY(ws_get(c, WS_HOSTPIN, sizeof(RhsState) * nrhs, &hostv));   // pinned host buffer
     RhsState* st = (RhsState*)stv;
     RhsState* hs = (RhsState*)hostv;
@@ -61,39 +64,30 @@ int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::
     DHT_TRY(zero(c, v, bytes));
     DHT_HIP(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, c->stream));
     DHT_HIP(hipMemcpyAsync(rh, b, bytes, hipMemcpyDeviceToDevice, c->stream));
-    const int64_t nsite = c->g.Vh;
     const double bd_eps = prec == DHT_FP64 ? 1e-14 : 1e-6;
     int nb;
     {
         const void* aa[1] = {r};
-        DHT_TRY(launch_dot_partials(c, prec, 1, aa, aa, nsite, nrhs, partial, &nb));
+        DHT_TRY(launch_dot_partials(c, prec, 1, aa, aa, nvec, nrhs, partial, &nb));
         DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_INIT, bd_eps));
     }
     const int check_every = 2;
     for (int it = 0; it < maxiter; it++) {
-        DHT_TRY(p_update(c, prec, p, r, v, st, n, nrhs));
-        DHT_TRY(apply_schur(c, prec, p, v, tmp, nrhs));
-        {
-            const void* aa[1] = {rh};
-            const void* bb[1] = {v};
-            DHT_TRY(launch_dot_partials(c, prec, 1, aa, bb, nsite, nrhs, partial, &nb));
-            DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_ALPHA, bd_eps));
-        }
-        DHT_TRY(s_update(c, prec, s, r, v, st, n, nrhs));
-        DHT_TRY(apply_schur(c, prec, s, t, tmp, nrhs));
-        {
-            const void* aa[2] = {t, t};
-            const void* bb[2] = {s, t};
-            DHT_TRY(launch_dot_partials(c, prec, 2, aa, bb, nsite, nrhs, partial, &nb));
-            DHT_TRY(finalize(c, partial, nb, 2, nrhs, st, FIN_OMEGA, bd_eps));
-        }
-        DHT_TRY(xr_update(c, prec, x, r, p, s, t, st, n, nrhs));
-        {
-            const void* aa[2] = {rh, r};
-            const void* bb[2] = {r, r};
-            DHT_TRY(launch_dot_partials(c, prec, 2, aa, bb, nsite, nrhs, partial, &nb));
-            DHT_TRY(finalize(c, partial, nb, 2, nrhs, st, FIN_RHO, bd_eps));
-        }
+        DHT_TRY(p_update(c, prec, p, r, v, st, nvec, nrhs));
+        HopDot d1;
+        d1.kind = HOPDOT_A_OUT;   // (rhat, v)
+        d1.a = rh;
+        d1.partial = partial;
+        DHT_TRY(apply_schur(c, prec, p, v, tmp, nrhs, &d1));
+        DHT_TRY(finalize(c, partial, d1.nblocks, 1, nrhs, st, FIN_ALPHA, bd_eps));
+        DHT_TRY(s_update(c, prec, s, r, v, st, nvec, nrhs));
+        HopDot d2;
+        d2.kind = HOPDOT_OUT_X;   // (t, s), (t, t)
+        d2.partial = partial;
+        DHT_TRY(apply_schur(c, prec, s, t, tmp, nrhs, &d2));
+        DHT_TRY(finalize(c, partial, d2.nblocks, 2, nrhs, st, FIN_OMEGA, bd_eps));
+        DHT_TRY(xr_update_dots(c, prec, x, r, p, s, t, rh, st, nvec, nrhs, partial, &nb));   // (rhat, r), (r, r)
+        DHT_TRY(finalize(c, partial, nb, 2, nrhs, st, FIN_RHO, bd_eps));
         if ((it + 1) % check_every == 0 || it + 1 == maxiter) {
             DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
             DHT_HIP(hipStreamSynchronize(c->stream));
@@ -116,12 +110,12 @@ int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::
     return DHT_OK;
 }
 
-// per-RHS FP64 norms^2 of a field with `nsite` sites per component (host result)
-static int norms2(dht_ctx* c, const void* f, int64_t nsite, int nrhs, std::vector<double>& out) {
+// per-RHS FP64 norms^2 of an FP64 field of nvec vectors (host result)
+static int norms2(dht_ctx* c, const void* f, size_t nvec, int nrhs, std::vector<double>& out) {
     void* d;
     DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 3 * nrhs, &d));
     const void* aa[1] = {f};
-    DHT_TRY(dots(c, DHT_FP64, 1, aa, aa, nsite, nrhs, (Cx<double>*)d));
+    DHT_TRY(dots(c, DHT_FP64, 1, aa, aa, nvec, nrhs, (Cx<double>*)d));
     std::vector<Cx<double>> h(nrhs);
     DHT_HIP(hipMemcpyAsync(h.data(), d, sizeof(Cx<double>) * nrhs, hipMemcpyDeviceToHost, c->stream));
     DHT_HIP(hipStreamSynchronize(c->stream));
@@ -132,7 +126,7 @@ static int norms2(dht_ctx* c, const void* f, int64_t nsite, int nrhs, std::vecto
 
 int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats) {
     const double a = 4.0 + c->mass;
-    const size_t nh = half_elems(c, nrhs);
+    const size_t nh = half_elems(c, nrhs);   // complex entries (= FP64 vectors) per half field
     const size_t bh = nh * 16;
     const char* Zc = (const char*)Z;
     char* Xc = (char*)X;
@@ -148,15 +142,37 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     DHT_TRY(ws_get(c, WS_FLAGS, sizeof(double) * nrhs, &scl));
 
     if (prm->tol <= 0.0 || prm->maxiter <= 0) return set_error(DHT_ERR_INVALID_ARG, "tol and maxiter must be positive");
+    if (prm->method == DHT_SOLVER_DC_FGMRES_NN || prm->method == DHT_SOLVER_DC_FGMRES) {
+        const bool use_nn = prm->method == DHT_SOLVER_DC_FGMRES_NN;
+        int rc = solve_fgmres(c, prm, Z, X, nrhs, stats, use_nn, nullptr);
+        if (rc != DHT_ERR_NOT_CONVERGED) return rc;
+        // fallback: plain BiCGStab (FP32 inner, FP64 defect correction) for the whole batch
+        dht_solver_params p2 = *prm;
+        p2.method = DHT_SOLVER_DC_BICGSTAB;
+        p2.inner = DHT_FP32;
+        std::vector<dht_solve_stats> st2(nrhs);
+        std::vector<dht_solve_stats> st1(stats ? stats : st2.data(), (stats ? stats : st2.data()) + nrhs);
+        rc = solve_fields(c, &p2, Z, X, nrhs, st2.data());
+        if (stats)
+            for (int i = 0; i < nrhs; i++) {
+                stats[i] = st2[i];
+                stats[i].iters += st1[i].iters;
+                stats[i].outer += st1[i].outer;
+                if (st2[i].status != DHT_STATUS_NOT_CONVERGED) stats[i].status = DHT_STATUS_FALLBACK_BICGSTAB;
+            }
+        return rc;
+    }
+    if (prm->method != DHT_SOLVER_BICGSTAB_FP64 && prm->method != DHT_SOLVER_DC_BICGSTAB)
+        return set_error(DHT_ERR_INVALID_ARG, "unknown solver method");
     int inner = DHT_FP64;
-    if (prm->method == DHT_SOLVER_DC_BICGSTAB || prm->method == DHT_SOLVER_DC_FGMRES_NN) inner = prm->inner;
+    if (prm->method == DHT_SOLVER_DC_BICGSTAB) inner = prm->inner;
     if (inner < DHT_FP64 || inner > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad inner precision");
     const int max_outer = prm->max_outer > 0 ? prm->max_outer : 50;
 
     // right-hand side of the Schur system and ||Z||^2
     DHT_TRY(hop(c, DHT_FP64, 0, Z_o, bhat, Z_e, 1.0, 1.0 / (2.0 * a), nrhs, false, false));
     std::vector<double> zn2, rn2;
-    DHT_TRY(norms2(c, Z, 2 * c->g.Vh, nrhs, zn2));
+    DHT_TRY(norms2(c, Z, 2 * nh, nrhs, zn2));
     std::vector<double> target2(nrhs);
     // the Schur loop aims 10% below the tolerance so that the reconstructed
     // full-lattice residual, checked last, is not lost to rounding
@@ -168,37 +184,41 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     std::vector<double> last_rn2(nrhs, INFINITY);
     int outer = 0, total_iters = 0;
     const int start_inner = inner;
+    bool last_bad = false;
     void* e;
     void* rlo;
     for (; outer < max_outer; outer++) {
-        DHT_TRY(norms2(c, r_e, c->g.Vh, nrhs, rn2));
+        DHT_TRY(norms2(c, r_e, nh, nrhs, rn2));
         bool any = false, stalled = false;
         std::vector<double> sdown(nrhs), sup(nrhs), itarget(nrhs);
         for (int i = 0; i < nrhs; i++) {
             bool act = rn2[i] > target2[i] && isfinite(rn2[i]);
             any |= act;
-            if (act && rn2[i] > 0.25 * last_rn2[i] && outer > 0) stalled = true;
+            if (act && rn2[i] > 0.25 * last_rn2[i] && outer > 0 && !last_bad) stalled = true;
             sdown[i] = act ? 1.0 / sqrt(rn2[i]) : 0.0;
             sup[i] = act ? sqrt(rn2[i]) : 0.0;
-            double itol = prm->inner_tol > 0 ? prm->inner_tol : (inner == DHT_BF16 ? 3e-2 : (inner == DHT_FP32 ? 1e-5 : 0.0));
-            double need = act ? 0.25 * target2[i] / rn2[i] : 1.0;
-            itarget[i] = std::max(itol * itol, need);
             last_rn2[i] = act ? rn2[i] : last_rn2[i];
         }
         if (!any) break;
         if (stalled && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
         if (total_iters >= prm->maxiter) break;
+        for (int i = 0; i < nrhs; i++) {
+            double itol = prm->inner_tol > 0 ? prm->inner_tol
+                                             : (inner == DHT_BF16 ? 3e-2 : (inner == DHT_FP32 ? 1e-5 : 0.0));
+            double need = sup[i] > 0 ? 0.25 * target2[i] / rn2[i] : 1.0;
+            itarget[i] = std::max(itol * itol, need);
+        }
         const size_t lbytes = nh * elem_bytes(inner);
         const int base = slot_base(inner);
         DHT_TRY(ws_get(c, base + 7, lbytes, &rlo));   // inner right-hand side
         DHT_TRY(ws_get(c, base + 8, lbytes, &e));     // inner solution
         DHT_HIP(hipMemcpyAsync(scl, sdown.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-        DHT_TRY(scale_down(c, r_e, rlo, inner, (const double*)scl, nh, nrhs));
+        DHT_TRY(scale_down(c, r_e, rlo, inner, (const double*)scl, nrhs));
         if ((prm->fault_inject & 1u) && outer == 0 && inner != DHT_FP64) {
             // testing hook: poison the first inner right-hand side to exercise the fallback
             std::vector<double> nanv(nrhs, NAN);
             DHT_HIP(hipMemcpyAsync(scl, nanv.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-            DHT_TRY(scale_down(c, r_e, rlo, inner, (const double*)scl, nh, nrhs));
+            DHT_TRY(scale_down(c, r_e, rlo, inner, (const double*)scl, nrhs));
         }
         BicgResult br;
         DHT_TRY(bicgstab(c, inner, rlo, e, nrhs, itarget, prm->maxiter - total_iters, &br));
@@ -214,13 +234,12 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         }
         total_iters += std::max(maxit, 1);
         DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-        DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nh, nrhs));
+        DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nrhs));
         // FP64 true residual of the Schur system
         DHT_TRY(apply_schur(c, DHT_FP64, X_e, tmpf, tmp_o, nrhs));
         DHT_TRY(sub(c, bhat, tmpf, r_e, nh));
-        if (bad && inner != DHT_FP64) {
-            inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
-        }
+        if (bad && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
+        last_bad = bad;
         for (int i = 0; i < nrhs; i++)
             if (inner != start_inner && rn2[i] > target2[i])
                 escalated[i] = inner == DHT_FP32 ? DHT_STATUS_FALLBACK_FP32 : DHT_STATUS_FALLBACK_FP64;
@@ -232,7 +251,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     DHT_TRY(apply_full(c, DHT_OP_D, DHT_FP64, X, full, nrhs));
     DHT_TRY(sub(c, Z, full, full, 2 * nh));
     std::vector<double> fr2;
-    DHT_TRY(norms2(c, full, 2 * c->g.Vh, nrhs, fr2));
+    DHT_TRY(norms2(c, full, 2 * nh, nrhs, fr2));
     bool all_ok = true;
     for (int i = 0; i < nrhs; i++) {
         double rr = zn2[i] > 0 ? sqrt(fr2[i] / zn2[i]) : 0.0;
