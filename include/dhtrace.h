@@ -290,6 +290,50 @@ int dht_profile_get(dht_ctx* ctx, int cls, int64_t* count, double* total_ms, dou
  * in ms measured with HIP events on the context stream. */
 int dht_bench_hop(dht_ctx* ctx, int prec, int nrhs, int warmup, int reps, double* ms_per_call);
 
+/* ---- launch-shape autotuning ---------------------------------------------- */
+
+/* Form of the even/odd hopping kernel (the stencil of Section 1 applied on one
+ * parity); all forms compute the same sums in a different order of
+ * accumulation (results agree to rounding).
+ *   DHT_HOP_SITE      one lane per (site, RHS), links read per lane;
+ *   DHT_HOP_SITE_LDS  as SITE, the workgroup's links copied once into LDS
+ *                     (needs 256 / nrhs <= 32, i.e. nrhs >= 8);
+ *   DHT_HOP_TMARCH    one lane per (x, y, z column, RHS) walking t_chunk
+ *                     slices in t, the backward t-neighbour kept in registers
+ *                     (t_chunk even, divides Lt; 0 = automatic).
+ * streaming_stores = 1 writes the output with non-temporal stores. */
+enum { DHT_HOP_SITE = 0, DHT_HOP_SITE_LDS = 1, DHT_HOP_TMARCH = 2 };
+typedef struct dht_hop_config {
+    int form;
+    int streaming_stores;
+    int t_chunk;
+} dht_hop_config;
+
+/* Set the hopping-kernel shape used for (prec, nrhs) on this context; cfg =
+ * NULL restores the built-in default.  Errors: DHT_ERR_INVALID_ARG for a shape
+ * that does not fit the lattice or batch (nrhs: power of two <= 256). */
+int dht_hop_config_set(dht_ctx* ctx, int prec, int nrhs, const dht_hop_config* cfg);
+/* The shape in effect for (prec, nrhs) (t_chunk resolved). */
+int dht_hop_config_get(dht_ctx* ctx, int prec, int nrhs, dht_hop_config* out);
+
+typedef struct dht_tune_result {
+    dht_hop_config best;     /* fastest candidate that passed the parity check */
+    double best_ms;          /* its mean time per hop application */
+    double default_ms;       /* the built-in default's time */
+    int candidates;          /* shapes timed */
+    int rejected;            /* shapes whose output differed from the default's beyond rounding */
+    double max_rel_diff;     /* largest max|out - out_default| / max|out_default| among accepted shapes */
+} dht_tune_result;
+
+/* Autotuner: time every hopping-kernel shape valid for (prec, nrhs) on this
+ * lattice (reps applications each, HIP events on the context stream, after
+ * warm-up), check each output against the default shape's (relative max-norm
+ * difference <= 1e-12 FP64, 1e-5 FP32, 1.6e-2 BF16, i.e. a few units in the last place of
+ * the storage format), and install the fastest accepted shape for
+ * (prec, nrhs) on the context.  Needs the gauge field; uses the context
+ * workspace (three half fields of nrhs RHS). */
+int dht_autotune_hop(dht_ctx* ctx, int prec, int nrhs, int reps, dht_tune_result* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,7 @@ Python values.  Importing it on a machine without the built library raises.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -44,6 +45,19 @@ class SolveStats(ctypes.Structure):
 class Record(ctypes.Structure):
     _fields_ = [("q_re", ctypes.c_double), ("q_im", ctypes.c_double), ("qd_re", ctypes.c_double),
                 ("qd_im", ctypes.c_double), ("s", SolveStats)]
+
+
+class HopConfig(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int), ("streaming_stores", ctypes.c_int), ("t_chunk", ctypes.c_int)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", HopConfig), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("candidates", ctypes.c_int), ("rejected", ctypes.c_int), ("max_rel_diff", ctypes.c_double)]
+
+
+HOP_SITE, HOP_SITE_LDS, HOP_TMARCH = 0, 1, 2
+HOP_FORMS = {HOP_SITE: "site", HOP_SITE_LDS: "site_lds", HOP_TMARCH: "tmarch"}
 
 
 class Estimate(ctypes.Structure):
@@ -97,6 +111,9 @@ SIGNATURES = {
     "dht_nn_grad": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(ctypes.c_float), _dp]),
     "dht_nn_train": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _dp]),
     "dht_nn_make_pairs": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _i, _vp, _vp, _i, ctypes.POINTER(_i)]),
+    "dht_hop_config_set": (_i, [_vp, _i, _i, ctypes.POINTER(HopConfig)]),
+    "dht_hop_config_get": (_i, [_vp, _i, _i, ctypes.POINTER(HopConfig)]),
+    "dht_autotune_hop": (_i, [_vp, _i, _i, _i, ctypes.POINTER(TuneResult)]),
 }
 
 SOLVER_DC_FGMRES = 3
@@ -154,6 +171,7 @@ class Context:
     def __init__(self, L, mass: float, t_antiperiodic: bool = True, device: int = 0, stream=None):
         import torch
         self.L = tuple(int(v) for v in L)
+        self._tuned = {}
         self.V = int(np.prod(self.L))
         self.N = 12 * self.V
         self.mass = float(mass)
@@ -370,6 +388,56 @@ class Context:
         check(load().dht_nn_make_pairs(self.h, ctypes.byref(sp), first, nrhs, restart, _as_f64_view(R),
                                        _as_f64_view(E), cap, ctypes.byref(cnt)))
         return R[:cnt.value], E[:cnt.value]
+
+    # ---- launch-shape autotuning -------------------------------------------
+    def hop_config(self, prec: int, nrhs: int) -> dict:
+        h = HopConfig()
+        check(load().dht_hop_config_get(self.h, prec, nrhs, ctypes.byref(h)))
+        return {"form": h.form, "streaming_stores": h.streaming_stores, "t_chunk": h.t_chunk}
+
+    def set_hop_config(self, prec: int, nrhs: int, cfg: dict | None):
+        """Install a hopping-kernel shape for (prec, nrhs); None restores the default."""
+        if cfg is None:
+            check(load().dht_hop_config_set(self.h, prec, nrhs, None))
+            return
+        h = HopConfig(int(cfg["form"]), int(cfg.get("streaming_stores", 1)), int(cfg.get("t_chunk", 0)))
+        check(load().dht_hop_config_set(self.h, prec, nrhs, ctypes.byref(h)))
+
+    def autotune_hop(self, prec: int, nrhs: int, reps: int = 10) -> dict:
+        """Time every valid hopping-kernel shape for (prec, nrhs), keep the
+        fastest one whose output matches the default's to rounding."""
+        r = TuneResult()
+        check(load().dht_autotune_hop(self.h, prec, nrhs, reps, ctypes.byref(r)))
+        best = {"form": r.best.form, "streaming_stores": r.best.streaming_stores, "t_chunk": r.best.t_chunk}
+        out = {"prec": prec, "nrhs": nrhs, "best": best, "best_form": HOP_FORMS[r.best.form],
+               "best_ms": r.best_ms, "default_ms": r.default_ms, "candidates": r.candidates,
+               "rejected": r.rejected, "max_rel_diff": r.max_rel_diff}
+        self._tuned[(prec, nrhs)] = out
+        return out
+
+    def tuning_table(self) -> dict:
+        """The shapes installed by autotune_hop / load_tuning, keyed
+        "prec:nrhs", with the lattice they were measured on (JSON-ready)."""
+        return {"lattice": list(self.L), "entries": {"%d:%d" % k: v for k, v in self._tuned.items()}}
+
+    def save_tuning(self, path: str):
+        with open(path, "w") as f:
+            json.dump(self.tuning_table(), f, indent=1)
+
+    def load_tuning(self, path: str) -> int:
+        """Install the shapes of a saved table if it was measured on this
+        lattice; returns the number installed."""
+        with open(path) as f:
+            tab = json.load(f)
+        if list(tab.get("lattice", [])) != list(self.L):
+            return 0
+        n = 0
+        for key, ent in tab.get("entries", {}).items():
+            prec, nrhs = (int(v) for v in key.split(":"))
+            self.set_hop_config(prec, nrhs, ent["best"])
+            self._tuned[(prec, nrhs)] = ent
+            n += 1
+        return n
 
     def bench_hop(self, prec: int, nrhs: int, warmup: int = 3, reps: int = 10) -> float:
         ms = ctypes.c_double(0.0)

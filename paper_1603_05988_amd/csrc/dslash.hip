@@ -39,8 +39,12 @@ struct HopArgs {
     int antiperiodic;
     int out_parity;
     int bshift;          // log2(B)
+    int tc, nchunk;      // t-marching: slices per chunk (even, divides Lt) and chunks
+    int nt;              // non-temporal (streaming) output stores
     double ca, cb;       // out = ca * x + cb * Hop(in)
 };
+
+static constexpr int HOP_THREADS = HOP_LANES;
 
 // h = psi_up - SGN * A_mu psi_lo  (SGN = +1 for (1 - g), -1 for (1 + g))
 template <int MU, int SGN, typename T>
@@ -84,6 +88,7 @@ __device__ inline void load_spinor(const void* base, int64_t v0, int64_t vstride
     for (int j = 0; j < 12 / VW; j++) Store<S>::ldv(base, v0 + j * vstride, p + j * VW);
 }
 
+
 template <typename S>
 __device__ inline void load_link(const void* base, int64_t v0, Cx<typename Store<S>::acc>* u) {
     constexpr int VW = Store<S>::VW;
@@ -116,42 +121,85 @@ __device__ inline void mul_link(const Cx<T>* u, const Cx<T>* h, Cx<T>* w) {
 // Ordering fence for the accumulation: the accumulators pass through an
 // empty asm (so the arithmetic producing them cannot sink below it) that also
 // clobbers memory (so later loads cannot rise above it).  Emits no code.
-template <typename T>
-__device__ inline void fence_acc(Cx<T>* acc) {
+template <int N, typename T>
+__device__ inline void fence_n(Cx<T>* v) {
 #pragma unroll
-    for (int i = 0; i < 12; i++) asm volatile("" : "+v"(acc[i].re), "+v"(acc[i].im) : : "memory");
+    for (int i = 0; i < N; i++) asm volatile("" : "+v"(v[i].re), "+v"(v[i].im) : : "memory");
 }
+template <typename T>
+__device__ inline void fence_acc(Cx<T>* acc) { fence_n<12>(acc); }
 
-// one direction: forward neighbour sf (link at this site), backward sb (link at sb, other parity)
+// one direction: forward neighbour sf with its link at (lf, lfv), backward
+// neighbour sb with its link at (lb, lbv) (16-byte vector indices; the links
+// come from global memory or from the workgroup's LDS copy)
 template <typename S, int MU, bool DAG>
-__device__ inline void hop_dir(const HopArgs& a, int s, int sf, int sb, int r, bool phf, bool phb,
-                               Cx<typename Store<S>::acc>* acc) {
+__device__ inline void hop_dir(const HopArgs& a, int sf, int sb, int r, bool phf, bool phb, const void* lf,
+                               int64_t lfv, const void* lb, int64_t lbv, Cx<typename Store<S>::acc>* acc) {
     typedef typename Store<S>::acc T;
-    constexpr int VW = Store<S>::VW;
-    constexpr int NV = (9 + VW - 1) / VW;
-    const int p = a.out_parity;
     const int64_t vstride = (int64_t)a.Vh << a.bshift;
     constexpr int SF = DAG ? -1 : 1;   // sign of the forward projector (1 - SF g)
     {
         Cx<T> psi[12], h[6], u[9], w[6];
         load_spinor<S>(a.in, ((int64_t)sf << a.bshift) + r, vstride, psi);
         project<MU, SF>(psi, h);
-        load_link<S>(a.U, ((int64_t)(MU * 2 + p) * a.Vh + s) * NV, u);
+        load_link<S>(lf, lfv, u);
         mul_link<false>(u, h, w);
         reconstruct<MU, SF>(acc, w, phf ? T(-1) : T(1));
     }
-    // keep each half-direction's loads next to their use: unfenced, the
-    // optimiser issues all sixteen neighbour/link loads first and exhausts registers
+    // keep loads next to their use: unfenced, the optimiser issues all sixteen
+    // neighbour/link loads first and exhausts registers
     fence_acc(acc);
     {
         Cx<T> psi[12], h[6], u[9], w[6];
         load_spinor<S>(a.in, ((int64_t)sb << a.bshift) + r, vstride, psi);
         project<MU, -SF>(psi, h);
-        load_link<S>(a.U, ((int64_t)(MU * 2 + (1 - p)) * a.Vh + sb) * NV, u);
+        load_link<S>(lb, lbv, u);
         mul_link<true>(u, h, w);
         reconstruct<MU, -SF>(acc, w, phb ? T(-1) : T(1));
     }
     fence_acc(acc);
+}
+
+// checkerboard index of the backward neighbour x - mu of site s (parity p)
+__device__ inline int bwd_site(const HopArgs& a, int s, int mu) {
+    const int xh = s % a.Lxh;
+    int rest = s / a.Lxh;
+    const int y = rest % a.Ly;
+    rest /= a.Ly;
+    const int z = rest % a.Lz;
+    const int t = rest / a.Lz;
+    const int sy = a.Lxh, sz = a.Lxh * a.Ly, st = sz * a.Lz;
+    if (mu == 0) {
+        const int x = 2 * xh + ((a.out_parity + y + z + t) & 1);
+        return s - xh + ((x == 0 ? a.Lx - 1 : x - 1) >> 1);
+    }
+    if (mu == 1) return y == 0 ? s + (a.Ly - 1) * sy : s - sy;
+    if (mu == 2) return z == 0 ? s + (a.Lz - 1) * sz : s - sz;
+    return t == 0 ? s + (a.Lt - 1) * st : s - st;
+}
+
+// Cooperative copy of the links a workgroup needs into LDS: slot
+// ((d * ns + k) * NV + j), d = 2 mu (forward: U_mu at site k) or 2 mu + 1
+// (backward: U_mu at the neighbour k - mu, other parity).  site(k) gives the
+// checkerboard index of local site k, or -1 for an idle slot.  One coalesced
+// pass replaces the per-lane link loads that the B lanes of a site would
+// otherwise each issue.
+template <typename S, typename SiteFn>
+__device__ inline void stage_links(const HopArgs& a, uint4* lds, int ns, SiteFn site) {
+    constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
+    const int total = 8 * ns * NV;
+    const int p = a.out_parity;
+    for (int k = threadIdx.x; k < total; k += HOP_THREADS) {
+        const int d = k / (ns * NV);
+        const int rem = k - d * ns * NV;
+        const int sl = rem / NV, j = rem - sl * NV;
+        const int s = site(sl);
+        if (s < 0) continue;
+        const int mu = d >> 1;
+        const int ls = (d & 1) ? bwd_site(a, s, mu) : s;
+        const int par = (d & 1) ? 1 - p : p;
+        lds[k] = ((const uint4*)a.U)[((int64_t)(mu * 2 + par) * a.Vh + ls) * NV + j];
+    }
 }
 
 // Workgroup index remap: hardware dispatches workgroup i to XCD i mod 8;
@@ -165,77 +213,57 @@ __device__ inline int xcd_remap(int bid, int nblocks) {
     return start + k;
 }
 
-static constexpr int HOP_THREADS = 256;
+// t-marching default: halve the chunk while the grid holds fewer lanes than this
+static constexpr int64_t HOP_MIN_LANES = 1 << 20;
 
-template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT>
-__global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
+// out = cb * acc + ca * x (g5 applied on request), stored; the fused dot
+// products use the stored (rounded) values, so they match a separate pass
+template <typename S, bool G5OUT, bool XPAY, int DOT>
+__device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename Store<S>::acc>* acc, Cx<double>& d0,
+                                    Cx<double>& d1) {
     typedef typename Store<S>::acc T;
     constexpr int VW = Store<S>::VW;
-    constexpr int NP = DOT == HOPDOT_A_OUT ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int gid = blk * HOP_THREADS + threadIdx.x;
-    const int B = 1 << a.bshift;
-    const int s = gid >> a.bshift;
-    const int r = gid & (B - 1);
-    const bool live = s < a.Vh;
-    Cx<double> d0 = cmake(0.0, 0.0), d1 = cmake(0.0, 0.0);
-    if (live) {
-        // coordinates of checkerboard site s
-        const int xh = s % a.Lxh;
-        int rest = s / a.Lxh;
-        const int y = rest % a.Ly;
-        rest /= a.Ly;
-        const int z = rest % a.Lz;
-        const int t = rest / a.Lz;
-        const int x = 2 * xh + ((a.out_parity + y + z + t) & 1);
-        const int row = s - xh;   // index of (x = 0, y, z, t) / 2
-        const int sy = a.Lxh, sz = a.Lxh * a.Ly, st = sz * a.Lz;
-        const int xf = x + 1 == a.Lx ? 0 : x + 1, xb = x == 0 ? a.Lx - 1 : x - 1;
-        Cx<T> acc[12];
+    const int64_t vstride = (int64_t)a.Vh << a.bshift;
+    const int64_t v0 = ((int64_t)s << a.bshift) + r;
+    const T cb = (T)a.cb, ca = (T)a.ca;
+    Cx<T> xv[12];
+    if (XPAY) load_spinor<S>(a.x, v0, vstride, xv);
 #pragma unroll
-        for (int i = 0; i < 12; i++) acc[i] = cmake<T>(0, 0);
-        hop_dir<S, 0, DAG>(a, s, row + (xf >> 1), row + (xb >> 1), r, false, false, acc);
-        hop_dir<S, 1, DAG>(a, s, y == a.Ly - 1 ? s - (a.Ly - 1) * sy : s + sy, y == 0 ? s + (a.Ly - 1) * sy : s - sy,
-                           r, false, false, acc);
-        hop_dir<S, 2, DAG>(a, s, z == a.Lz - 1 ? s - (a.Lz - 1) * sz : s + sz, z == 0 ? s + (a.Lz - 1) * sz : s - sz,
-                           r, false, false, acc);
-        hop_dir<S, 3, DAG>(a, s, t == a.Lt - 1 ? s - (a.Lt - 1) * st : s + st, t == 0 ? s + (a.Lt - 1) * st : s - st,
-                           r, a.antiperiodic && t == a.Lt - 1, a.antiperiodic && t == 0, acc);
-        const int64_t vstride = (int64_t)a.Vh << a.bshift;
-        const int64_t v0 = ((int64_t)s << a.bshift) + r;
-        const T cb = (T)a.cb, ca = (T)a.ca;
-        Cx<T> xv[12];
-        if (XPAY) load_spinor<S>(a.x, v0, vstride, xv);
+    for (int i = 0; i < 12; i++) {
+        Cx<T> v = cb * acc[i];
+        if (XPAY) v = v + ca * xv[i];
+        if (G5OUT && i >= 6) v = neg(v);
+        acc[i] = v;
+    }
 #pragma unroll
-        for (int i = 0; i < 12; i++) {
-            Cx<T> v = cb * acc[i];
-            if (XPAY) v = v + ca * xv[i];
-            if (G5OUT && i >= 6) v = neg(v);
-            acc[i] = v;
-        }
+    for (int j = 0; j < 12 / VW; j++) {
+        if (a.nt) Store<S>::stv_nt(a.out, v0 + j * vstride, acc + j * VW);
+        else Store<S>::stv(a.out, v0 + j * vstride, acc + j * VW);
+    }
+    if (DOT != HOPDOT_NONE) {
+        Cx<T> ov[12];
 #pragma unroll
-        for (int j = 0; j < 12 / VW; j++) Store<S>::stv(a.out, v0 + j * vstride, acc + j * VW);
-        if (DOT != HOPDOT_NONE) {
-            // the stored (rounded) values, so the sums match a separate pass
-            Cx<T> ov[12];
+        for (int i = 0; i < 12; i++) ov[i] = Store<S>::round(acc[i]);
+        if (DOT == HOPDOT_A_OUT) {
+            Cx<T> av[12];
+            load_spinor<S>(a.da, v0, vstride, av);
 #pragma unroll
-            for (int i = 0; i < 12; i++) ov[i] = Store<S>::round(acc[i]);
-            if (DOT == HOPDOT_A_OUT) {
-                Cx<T> av[12];
-                load_spinor<S>(a.da, v0, vstride, av);
+            for (int i = 0; i < 12; i++)
+                d0 = d0 + conjmul(cmake<double>(av[i].re, av[i].im), cmake<double>(ov[i].re, ov[i].im));
+        } else {
 #pragma unroll
-                for (int i = 0; i < 12; i++)
-                    d0 = d0 + conjmul(cmake<double>(av[i].re, av[i].im), cmake<double>(ov[i].re, ov[i].im));
-            } else {
-#pragma unroll
-                for (int i = 0; i < 12; i++) {
-                    Cx<double> o = cmake<double>(ov[i].re, ov[i].im);
-                    d0 = d0 + conjmul(o, cmake<double>(xv[i].re, xv[i].im));
-                    d1.re += o.re * o.re + o.im * o.im;
-                }
+            for (int i = 0; i < 12; i++) {
+                Cx<double> o = cmake<double>(ov[i].re, ov[i].im);
+                d0 = d0 + conjmul(o, cmake<double>(xv[i].re, xv[i].im));
+                d1.re += o.re * o.re + o.im * o.im;
             }
         }
     }
+}
+
+// workgroup tree over the lanes of equal RHS, partial[blk][q][B]
+template <int NP>
+__device__ inline void hop_block_reduce(const HopArgs& a, int blk, int B, Cx<double> d0, Cx<double> d1) {
     if (NP > 0) {
         __shared__ Cx<double> red[NP > 0 ? NP : 1][HOP_THREADS];
         red[0][threadIdx.x] = d0;
@@ -253,6 +281,219 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
             for (int q = 0; q < NP; q++) a.partial[((int64_t)blk * NP + q) * B + threadIdx.x] = red[q][threadIdx.x];
         }
     }
+}
+
+// Site-parallel form: one lane per (site, RHS), RHS fastest.  With LDSL the
+// workgroup's ns = 256 / B sites take their links from LDS.
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, bool LDSL>
+__global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
+    typedef typename Store<S>::acc T;
+    constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
+    constexpr int NP = DOT == HOPDOT_A_OUT ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
+    extern __shared__ uint4 hop_lds[];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int B = 1 << a.bshift;
+    const int ns = HOP_THREADS >> a.bshift;
+    const int sl = threadIdx.x >> a.bshift;
+    const int s = blk * ns + sl;
+    const int r = threadIdx.x & (B - 1);
+    const int p = a.out_parity;
+    if (LDSL) {
+        const int s0 = blk * ns;
+        stage_links<S>(a, hop_lds, ns, [&](int k) { return s0 + k < a.Vh ? s0 + k : -1; });
+        __syncthreads();
+    }
+    Cx<double> d0 = cmake(0.0, 0.0), d1 = cmake(0.0, 0.0);
+    if (s < a.Vh) {
+        const int xh = s % a.Lxh;
+        int rest = s / a.Lxh;
+        const int y = rest % a.Ly;
+        rest /= a.Ly;
+        const int z = rest % a.Lz;
+        const int t = rest / a.Lz;
+        const int x = 2 * xh + ((p + y + z + t) & 1);
+        const int row = s - xh;   // index of (x = 0, y, z, t) / 2
+        const int sy = a.Lxh, sz = a.Lxh * a.Ly, st = sz * a.Lz;
+        const int xf = x + 1 == a.Lx ? 0 : x + 1, xb = x == 0 ? a.Lx - 1 : x - 1;
+        const int sn[8] = {row + (xf >> 1), row + (xb >> 1),
+                           y == a.Ly - 1 ? s - (a.Ly - 1) * sy : s + sy, y == 0 ? s + (a.Ly - 1) * sy : s - sy,
+                           z == a.Lz - 1 ? s - (a.Lz - 1) * sz : s + sz, z == 0 ? s + (a.Lz - 1) * sz : s - sz,
+                           t == a.Lt - 1 ? s - (a.Lt - 1) * st : s + st, t == 0 ? s + (a.Lt - 1) * st : s - st};
+        Cx<T> acc[12];
+#pragma unroll
+        for (int i = 0; i < 12; i++) acc[i] = cmake<T>(0, 0);
+#define DHT_DIR(MU, PHF, PHB)                                                                              \
+    if (LDSL)                                                                                            \
+        hop_dir<S, MU, DAG>(a, sn[2 * MU], sn[2 * MU + 1], r, PHF, PHB, hop_lds,                         \
+                            (int64_t)((2 * MU) * ns + sl) * NV, hop_lds, (int64_t)((2 * MU + 1) * ns + sl) * NV, acc); \
+    else                                                                                                 \
+        hop_dir<S, MU, DAG>(a, sn[2 * MU], sn[2 * MU + 1], r, PHF, PHB, a.U,                             \
+                            ((int64_t)(MU * 2 + p) * a.Vh + s) * NV, a.U,                                \
+                            ((int64_t)(MU * 2 + 1 - p) * a.Vh + sn[2 * MU + 1]) * NV, acc);
+        DHT_DIR(0, false, false)
+        DHT_DIR(1, false, false)
+        DHT_DIR(2, false, false)
+        DHT_DIR(3, a.antiperiodic && t == a.Lt - 1, a.antiperiodic && t == 0)
+#undef DHT_DIR
+        hop_epilogue<S, G5OUT, XPAY, DOT>(a, s, r, acc, d0, d1);
+    }
+    hop_block_reduce<NP>(a, blk, B, d0, d1);
+}
+
+// ---------------------------------------------------------------------------
+// t-marching form.  A lane owns one (x, y, z) column of the output parity and
+// one RHS and walks t upward through a chunk of tc slices.  The t-forward
+// neighbour psi(t+1) read at step t is also the t-backward neighbour of the
+// output two slices later (same x), so its other projection times U_t^H is
+// kept in registers for step t + 2: every input site is fetched once for the
+// t direction, and the x, y, z neighbours of a step all lie in one slice that
+// the step before has just brought into the caches.
+// ---------------------------------------------------------------------------
+template <typename S, int SGN>
+__device__ inline void t_back(const HopArgs& a, int sin, int r, int64_t vstride, typename Store<S>::acc ph,
+                              Cx<typename Store<S>::acc>* wb) {
+    typedef typename Store<S>::acc T;
+    constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
+    Cx<T> psi[12], h[6], u[9];
+    load_spinor<S>(a.in, ((int64_t)sin << a.bshift) + r, vstride, psi);
+    project<3, SGN>(psi, h);
+    load_link<S>(a.U, ((int64_t)(6 + 1 - a.out_parity) * a.Vh + sin) * NV, u);
+    mul_link<true>(u, h, wb);
+#pragma unroll
+    for (int i = 0; i < 6; i++) wb[i] = ph * wb[i];
+}
+
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT>
+__device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, int y, int z, int r, int V3, int yf,
+                               int yb, int zf, int zb, Cx<typename Store<S>::acc>* wb, Cx<double>& d0,
+                               Cx<double>& d1) {
+    typedef typename Store<S>::acc T;
+    constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
+    constexpr int SF = DAG ? -1 : 1;
+    const int p = a.out_parity;
+    const int64_t vstride = (int64_t)a.Vh << a.bshift;
+    int s = t * V3 + s3;
+    // opaque to the optimiser: otherwise it keeps one strength-reduced 64-bit
+    // pointer per direction and vector live across the t loop
+    asm volatile("" : "+v"(s));
+    const int x = 2 * xh + ((p + y + z + t) & 1);
+    const int row = s - xh;
+    const int xf = x + 1 == a.Lx ? 0 : x + 1, xb = x == 0 ? a.Lx - 1 : x - 1;
+    Cx<T> acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; i++) acc[i] = cmake<T>(0, 0);
+    const int sx = row + (xb >> 1), sy = s + yb, sz = s + zb;
+    hop_dir<S, 0, DAG>(a, row + (xf >> 1), sx, r, false, false, a.U, ((int64_t)p * a.Vh + s) * NV, a.U,
+                       ((int64_t)(1 - p) * a.Vh + sx) * NV, acc);
+    hop_dir<S, 1, DAG>(a, s + yf, sy, r, false, false, a.U, ((int64_t)(2 + p) * a.Vh + s) * NV, a.U,
+                       ((int64_t)(3 - p) * a.Vh + sy) * NV, acc);
+    hop_dir<S, 2, DAG>(a, s + zf, sz, r, false, false, a.U, ((int64_t)(4 + p) * a.Vh + s) * NV, a.U,
+                       ((int64_t)(5 - p) * a.Vh + sz) * NV, acc);
+    reconstruct<3, -SF>(acc, wb, T(1));
+    {
+        const int sn = (t + 1 == a.Lt ? 0 : t + 1) * V3 + s3;
+        Cx<T> psi[12], h[6], u[9], w[6];
+        load_spinor<S>(a.in, ((int64_t)sn << a.bshift) + r, vstride, psi);
+        project<3, SF>(psi, h);
+        load_link<S>(a.U, ((int64_t)(6 + p) * a.Vh + s) * NV, u);
+        mul_link<false>(u, h, w);
+        reconstruct<3, SF>(acc, w, (a.antiperiodic && t == a.Lt - 1) ? T(-1) : T(1));
+        if (t + 2 < t1) {   // backward t-hop of step t + 2, from the same input spinor
+            fence_acc(acc);
+            project<3, -SF>(psi, h);
+            load_link<S>(a.U, ((int64_t)(6 + 1 - p) * a.Vh + sn) * NV, u);
+            mul_link<true>(u, h, wb);
+        }
+    }
+    hop_epilogue<S, G5OUT, XPAY, DOT>(a, s, r, acc, d0, d1);
+    fence_n<6>(wb);   // the next step's loads stay below this step's arithmetic
+}
+
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT>
+__global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
+    typedef typename Store<S>::acc T;
+    constexpr int NP = DOT == HOPDOT_A_OUT ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
+    constexpr int SF = DAG ? -1 : 1;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int gid = blk * HOP_THREADS + threadIdx.x;
+    const int B = 1 << a.bshift;
+    const int col = gid >> a.bshift;   // chunk * V3 + column
+    const int r = gid & (B - 1);
+    const int V3 = a.Vh / a.Lt;
+    const int chunk = col / V3;
+    Cx<double> d0 = cmake(0.0, 0.0), d1 = cmake(0.0, 0.0);
+    if (chunk < a.nchunk) {
+        const int s3 = col - chunk * V3;
+        const int xh = s3 % a.Lxh;
+        const int y = (s3 / a.Lxh) % a.Ly;
+        const int z = s3 / (a.Lxh * a.Ly);
+        const int sy = a.Lxh, sz = a.Lxh * a.Ly;
+        const int yf = y == a.Ly - 1 ? -(a.Ly - 1) * sy : sy, yb = y == 0 ? (a.Ly - 1) * sy : -sy;
+        const int zf = z == a.Lz - 1 ? -(a.Lz - 1) * sz : sz, zb = z == 0 ? (a.Lz - 1) * sz : -sz;
+        const int64_t vstride = (int64_t)a.Vh << a.bshift;
+        const int t0 = chunk * a.tc, t1 = t0 + a.tc;
+        Cx<T> wb0[6], wb1[6];   // pending backward t-hops of the even / odd steps of the chunk
+        t_back<S, -SF>(a, (t0 == 0 ? a.Lt - 1 : t0 - 1) * V3 + s3, r, vstride,
+                       (a.antiperiodic && t0 == 0) ? T(-1) : T(1), wb0);
+        t_back<S, -SF>(a, t0 * V3 + s3, r, vstride, T(1), wb1);
+#pragma nounroll
+        for (int t = t0; t < t1; t += 2) {
+            tm_step<S, DAG, G5OUT, XPAY, DOT>(a, t, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb0, d0, d1);
+            tm_step<S, DAG, G5OUT, XPAY, DOT>(a, t + 1, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb1, d0, d1);
+        }
+    }
+    hop_block_reduce<NP>(a, blk, B, d0, d1);
+}
+
+template <typename S> constexpr int prec_of() {
+    return std::is_same<S, double>::value ? DHT_FP64 : (std::is_same<S, float>::value ? DHT_FP32 : DHT_BF16);
+}
+
+static int log2_batch(int nrhs) {
+    for (int b = 0; b < 9; b++)
+        if ((1 << b) == nrhs) return b;
+    return -1;
+}
+
+static int auto_chunk(const dht_ctx* c, int nrhs) {
+    const int Lt = c->g.L[3];
+    const int64_t cols = c->g.Vh / Lt * (int64_t)nrhs;
+    int tc = Lt;
+    while (tc % 4 == 0 && cols * (Lt / tc) < HOP_MIN_LANES) tc /= 2;
+    return tc;
+}
+
+int hop_config_check(const dht_ctx* c, int nrhs, const HopConfig& h) {
+    if (log2_batch(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
+    if (h.form < DHT_HOP_SITE || h.form > DHT_HOP_TMARCH || (h.nt != 0 && h.nt != 1))
+        return set_error(DHT_ERR_INVALID_ARG, "bad hop form");
+    if (h.form == DHT_HOP_SITE_LDS && (HOP_THREADS / nrhs) > 32)
+        return set_error(DHT_ERR_INVALID_ARG, "LDS-link form needs at least 8 right-hand sides");
+    if (h.form == DHT_HOP_TMARCH && h.tc != 0 && (h.tc < 2 || (h.tc & 1) || c->g.L[3] % h.tc))
+        return set_error(DHT_ERR_INVALID_ARG, "t chunk must be even and divide Lt");
+    return DHT_OK;
+}
+
+// Default shape: links from LDS for FP32 / FP64 batches of >= 8, otherwise one
+// lane per site; streaming stores.  (Measured on the 32^3x64 lattice at 16
+// RHS: the LDS copy pays in FP32 and FP64 and not in BF16, whose links take
+// only three 16-byte loads.)
+HopConfig hop_default_config(const dht_ctx* c, int prec, int nrhs) {
+    HopConfig h;
+    h.form = (prec != DHT_BF16 && HOP_THREADS / nrhs <= 32) ? DHT_HOP_SITE_LDS : DHT_HOP_SITE;
+    h.nt = 1;
+    h.tc = auto_chunk(c, nrhs);
+    return h;
+}
+
+HopConfig hop_config(const dht_ctx* c, int prec, int nrhs) {
+    HopConfig h;
+    const int b = log2_batch(nrhs);
+    if (c->hop_force) h = c->hop_forced;
+    else if (b >= 0 && prec >= 0 && prec < 3 && c->hop_cfg[prec][b].form >= 0) h = c->hop_cfg[prec][b];
+    else h = hop_default_config(c, prec, nrhs);
+    if (h.tc == 0) h.tc = auto_chunk(c, nrhs);
+    return h;
 }
 
 int hop_blocks(const dht_ctx* c, int nrhs) {
@@ -286,14 +527,28 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     a.da = dot ? dot->a : nullptr;
     a.partial = dot ? dot->partial : nullptr;
     if (kind == HOPDOT_OUT_X && !x) return set_error(DHT_ERR_INVALID_ARG, "fused (out, x) needs an xpay source");
-    const int nb = hop_blocks(c, nrhs);
+    const HopConfig cfg = hop_config(c, prec_of<S>(), nrhs);
+    a.tc = cfg.tc;
+    a.nchunk = a.Lt / cfg.tc;
+    a.nt = cfg.nt;
+    const int mode = cfg.form;
+    const int ns = HOP_THREADS >> a.bshift;   // sites per workgroup (site-parallel forms)
+    const int nb = mode == DHT_HOP_TMARCH
+                       ? (int)((c->g.Vh / a.Lt * (int64_t)a.nchunk * nrhs + HOP_THREADS - 1) / HOP_THREADS)
+                       : hop_blocks(c, nrhs);
+    const size_t lds = mode == DHT_HOP_SITE_LDS ? (size_t)8 * ns * ((9 + Store<S>::VW - 1) / Store<S>::VW) * 16 : 0;
     if (dot) dot->nblocks = nb;
     dim3 grid(nb), block(HOP_THREADS);
     bool xp = x != nullptr;
-#define DHT_HOP_CASE(D_, G_, X_, K_)                                                               \
-    if (dagger == D_ && g5out == G_ && xp == X_ && kind == K_) {                                   \
-        hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_>), grid, block, 0, c->stream, a);        \
-        goto launched;                                                                             \
+#define DHT_HOP_CASE(D_, G_, X_, K_)                                                                         \
+    if (dagger == D_ && g5out == G_ && xp == X_ && kind == K_) {                                             \
+        if (mode == DHT_HOP_TMARCH)                                                                          \
+            hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_>), grid, block, 0, c->stream, a);            \
+        else if (mode == DHT_HOP_SITE_LDS)                                                                   \
+            hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_, true>), grid, block, lds, c->stream, a);       \
+        else                                                                                                 \
+            hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_, false>), grid, block, 0, c->stream, a);        \
+        goto launched;                                                                                       \
     }
     DHT_HOP_CASE(false, false, false, HOPDOT_NONE)
     DHT_HOP_CASE(false, false, true, HOPDOT_NONE)

@@ -67,6 +67,12 @@ __host__ __device__ inline float bf16_bits_to_f32(uint32_t h) {
 
 // Storage traits: how a complex<T> element is loaded/stored, what it
 // accumulates in, and how VW of them pack into one 16-byte vector.
+// 16-byte vector types for streaming (non-temporal) accesses: data touched once
+// is marked so that it does not displace reused lines in L2.
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
 template <typename S> struct Store;
 template <> struct Store<double> {
     typedef double acc;
@@ -81,6 +87,14 @@ template <> struct Store<double> {
     }
     __device__ static inline void stv(void* base, int64_t v, const Cx<double>* i) {
         ((double2*)base)[v] = make_double2(i[0].re, i[0].im);
+    }
+    __device__ static inline void ldv_nt(const void* base, int64_t v, Cx<double>* o) {
+        f64x2_t d = __builtin_nontemporal_load((const f64x2_t*)base + v);
+        o[0] = cmake(d.x, d.y);
+    }
+    __device__ static inline void stv_nt(void* base, int64_t v, const Cx<double>* i) {
+        f64x2_t d = {i[0].re, i[0].im};
+        __builtin_nontemporal_store(d, (f64x2_t*)base + v);
     }
 };
 template <> struct Store<float> {
@@ -97,6 +111,15 @@ template <> struct Store<float> {
     }
     __device__ static inline void stv(void* base, int64_t v, const Cx<float>* i) {
         ((float4*)base)[v] = make_float4(i[0].re, i[0].im, i[1].re, i[1].im);
+    }
+    __device__ static inline void ldv_nt(const void* base, int64_t v, Cx<float>* o) {
+        f32x4_t d = __builtin_nontemporal_load((const f32x4_t*)base + v);
+        o[0] = cmake(d.x, d.y);
+        o[1] = cmake(d.z, d.w);
+    }
+    __device__ static inline void stv_nt(void* base, int64_t v, const Cx<float>* i) {
+        f32x4_t d = {i[0].re, i[0].im, i[1].re, i[1].im};
+        __builtin_nontemporal_store(d, (f32x4_t*)base + v);
     }
 };
 template <> struct Store<bf16x2> {
@@ -121,6 +144,17 @@ template <> struct Store<bf16x2> {
     }
     __device__ static inline void stv(void* base, int64_t v, const Cx<float>* i) {
         ((uint4*)base)[v] = make_uint4(pack(i[0]), pack(i[1]), pack(i[2]), pack(i[3]));
+    }
+    __device__ static inline void ldv_nt(const void* base, int64_t v, Cx<float>* o) {
+        u32x4_t d = __builtin_nontemporal_load((const u32x4_t*)base + v);
+        o[0] = unpack(d.x);
+        o[1] = unpack(d.y);
+        o[2] = unpack(d.z);
+        o[3] = unpack(d.w);
+    }
+    __device__ static inline void stv_nt(void* base, int64_t v, const Cx<float>* i) {
+        u32x4_t d = {pack(i[0]), pack(i[1]), pack(i[2]), pack(i[3])};
+        __builtin_nontemporal_store(d, (u32x4_t*)base + v);
     }
 };
 
@@ -175,6 +209,13 @@ struct ProfStat {
 };
 
 // learned preconditioner weights (device)
+// hopping-kernel launch shape (dht_hop_config); form < 0: unset
+struct HopConfig {
+    int form = -1;
+    int nt = 1;
+    int tc = 0;
+};
+
 struct NNState {
     bool ready = false;
     void* mem = nullptr;
@@ -227,6 +268,11 @@ struct dht_ctx {
     dht::Welford est_q, est_qd;
     // learned preconditioner
     dht::NNState nn;
+    // hopping-kernel shape per (precision, log2 batch); hop_force overrides
+    // every entry while the autotuner times a candidate
+    dht::HopConfig hop_cfg[3][9];
+    bool hop_force = false;
+    dht::HopConfig hop_forced;
     // workspace slots (grow-only)
     std::vector<dht::Buf> ws;
     // timings of the last call (ms)
@@ -259,6 +305,7 @@ enum Slot {
     WS_PARTIAL = WS_KLO + 9, WS_SCAL, WS_SCAL2, WS_FLAGS, WS_HOSTPIN,
     WS_Z, WS_XF, WS_QW, WS_PROJ, WS_COEF, WS_PROJ2, WS_ZCODE,
     WS_NN_PART, WS_NN_ACT, WS_NN_SCAL, WS_FG_V, WS_FG_Z, WS_FG_W, WS_FG_COEF, WS_FG_R, WS_FG_E, WS_XSTAR,
+    WS_TUNE_REF, WS_TUNE_RED,
     WS_NSLOTS
 };
 int ws_get(dht_ctx* c, int slot, size_t bytes, void** out);
@@ -300,6 +347,12 @@ struct HopDot {
 int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
         int nrhs, bool dagger, bool g5out, HopDot* dot = nullptr);
 int hop_blocks(const dht_ctx* c, int nrhs);   // workgroups of one hop launch
+constexpr int HOP_LANES = 256;   // lanes per hop workgroup
+// the shape a hop launch for (prec, nrhs) uses (t chunk resolved), and a check
+// that a shape fits the lattice and batch
+HopConfig hop_config(const dht_ctx* c, int prec, int nrhs);
+HopConfig hop_default_config(const dht_ctx* c, int prec, int nrhs);
+int hop_config_check(const dht_ctx* c, int nrhs, const HopConfig& h);
 int apply_full(dht_ctx* c, int op, int prec, const void* in, void* out, int nrhs);   // full-lattice D, D^H, g5, Q
 int g5_field(dht_ctx* c, int prec, const void* in, void* out, int nrhs);              // full-lattice g5
 

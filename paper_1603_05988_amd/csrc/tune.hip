@@ -1,0 +1,220 @@
+// Launch-shape autotuner for the even/odd hopping kernel.
+//
+// Every form of the kernel computes the same nearest-neighbour sums (the
+// stencil of Section 1) in a different order, so the candidates are checked
+// against the default form's output to rounding before they are timed; the
+// fastest accepted shape is installed on the context for its (precision,
+// batch) pair and used by every later hop launch.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace dht {
+
+static constexpr int TUNE_THREADS = 256;
+static constexpr int TUNE_BLOCKS = 1024;
+
+// per-block maxima of |a - b| and |b| over the real components of n 16-byte vectors
+template <typename S>
+__global__ __launch_bounds__(TUNE_THREADS) void maxdiff_kernel(const void* a, const void* b, size_t nvec,
+                                                               Cx<double>* part) {
+    constexpr int VW = Store<S>::VW;
+    double dm = 0.0, rm = 0.0;
+    for (size_t v = (size_t)blockIdx.x * TUNE_THREADS + threadIdx.x; v < nvec; v += (size_t)gridDim.x * TUNE_THREADS) {
+        Cx<typename Store<S>::acc> x[VW], y[VW];
+        Store<S>::ldv(a, (int64_t)v, x);
+        Store<S>::ldv(b, (int64_t)v, y);
+#pragma unroll
+        for (int j = 0; j < VW; j++) {
+            dm = fmax(dm, fmax(fabs((double)x[j].re - (double)y[j].re), fabs((double)x[j].im - (double)y[j].im)));
+            rm = fmax(rm, fmax(fabs((double)y[j].re), fabs((double)y[j].im)));
+        }
+    }
+    __shared__ double sd[TUNE_THREADS], sr[TUNE_THREADS];
+    sd[threadIdx.x] = dm;
+    sr[threadIdx.x] = rm;
+    __syncthreads();
+    for (int w = TUNE_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + w]);
+            sr[threadIdx.x] = fmax(sr[threadIdx.x], sr[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = cmake(sd[0], sr[0]);
+}
+
+// max|a - b| / max|b| over one half field of nrhs RHS
+static int rel_maxdiff(dht_ctx* c, int prec, const void* a, const void* b, int nrhs, Cx<double>* part, double* out) {
+    const size_t nvec = half_elems(c, nrhs) / vec_width(prec);
+    const int nb = (int)std::min<size_t>(TUNE_BLOCKS, (nvec + TUNE_THREADS - 1) / TUNE_THREADS);
+    switch (prec) {
+        case DHT_FP64: hipLaunchKernelGGL(maxdiff_kernel<double>, dim3(nb), dim3(TUNE_THREADS), 0, c->stream, a, b, nvec, part); break;
+        case DHT_FP32: hipLaunchKernelGGL(maxdiff_kernel<float>, dim3(nb), dim3(TUNE_THREADS), 0, c->stream, a, b, nvec, part); break;
+        default: hipLaunchKernelGGL(maxdiff_kernel<bf16x2>, dim3(nb), dim3(TUNE_THREADS), 0, c->stream, a, b, nvec, part); break;
+    }
+    DHT_HIP(hipGetLastError());
+    std::vector<Cx<double>> h(nb);
+    DHT_HIP(hipMemcpyAsync(h.data(), part, sizeof(Cx<double>) * nb, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    double dm = 0.0, rm = 0.0;
+    for (const auto& e : h) {
+        dm = std::max(dm, e.re);
+        rm = std::max(rm, e.im);
+    }
+    *out = rm > 0.0 ? dm / rm : dm;
+    return DHT_OK;
+}
+
+// mean time of `reps` hop applications (out parity 0) in the shape in effect
+static int time_hop(dht_ctx* c, int prec, const void* in, void* out, int nrhs, int reps, hipEvent_t e0, hipEvent_t e1,
+                    double* ms) {
+    for (int i = 0; i < 2; i++) DHT_TRY(hop(c, prec, 0, in, out, nullptr, 0.0, 1.0, nrhs, false, false));
+    DHT_HIP(hipEventRecord(e0, c->stream));
+    for (int i = 0; i < reps; i++) DHT_TRY(hop(c, prec, 0, in, out, nullptr, 0.0, 1.0, nrhs, false, false));
+    DHT_HIP(hipEventRecord(e1, c->stream));
+    DHT_HIP(hipEventSynchronize(e1));
+    float f = 0.f;
+    DHT_HIP(hipEventElapsedTime(&f, e0, e1));
+    *ms = (double)f / reps;
+    return DHT_OK;
+}
+
+static double tune_tolerance(int prec) { return prec == DHT_FP64 ? 1e-12 : (prec == DHT_FP32 ? 1e-5 : 1.6e-2); }
+
+static int log2_pow2(int n) {
+    for (int b = 0; b < 9; b++)
+        if ((1 << b) == n) return b;
+    return -1;
+}
+
+static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* res, hipEvent_t e0, hipEvent_t e1) {
+    const int b = log2_pow2(nrhs);
+    const size_t full = full_elems(c, nrhs) * elem_bytes(prec), half = full / 2;
+    void *fi, *fo, *fr, *pp;
+    DHT_TRY(ws_get(c, WS_PACK_IN, full, &fi));
+    DHT_TRY(ws_get(c, WS_PACK_OUT, half, &fo));
+    DHT_TRY(ws_get(c, WS_TUNE_REF, half, &fr));
+    DHT_TRY(ws_get(c, WS_TUNE_RED, sizeof(Cx<double>) * TUNE_BLOCKS, &pp));
+    Cx<double>* part = (Cx<double>*)pp;
+    dht_probe_spec sp = {2718281u, 0u, 0};
+    DHT_TRY(probes_gen(c, &sp, 0, nrhs, nrhs, fi, prec, nullptr, nullptr));
+    const void* in = (const char*)fi + half;
+
+    // reference: the built-in default shape
+    c->hop_force = true;
+    c->hop_forced = hop_default_config(c, prec, nrhs);
+    const HopConfig def = c->hop_forced;
+    DHT_TRY(hop(c, prec, 0, in, fr, nullptr, 0.0, 1.0, nrhs, false, false));
+    double def_ms = 0.0;
+    DHT_TRY(time_hop(c, prec, in, fo, nrhs, reps, e0, e1, &def_ms));
+
+    std::vector<HopConfig> cand;
+    for (int nt = 0; nt < 2; nt++) {
+        HopConfig h;
+        h.nt = nt;
+        h.form = DHT_HOP_SITE;
+        cand.push_back(h);
+        if (HOP_LANES / nrhs <= 32) {
+            h.form = DHT_HOP_SITE_LDS;
+            cand.push_back(h);
+        }
+        h.form = DHT_HOP_TMARCH;
+        for (int tc = 2; tc <= c->g.L[3]; tc += 2)
+            if (c->g.L[3] % tc == 0) {
+                h.tc = tc;
+                cand.push_back(h);
+            }
+    }
+    HopConfig best = def;
+    double best_ms = def_ms, worst_ok = 0.0;
+    int rejected = 0;
+    for (const HopConfig& h : cand) {
+        c->hop_forced = h;
+        DHT_TRY(hop(c, prec, 0, in, fo, nullptr, 0.0, 1.0, nrhs, false, false));
+        double rd = 0.0;
+        DHT_TRY(rel_maxdiff(c, prec, fo, fr, nrhs, part, &rd));
+        if (!(rd <= tune_tolerance(prec))) {
+            rejected++;
+            continue;
+        }
+        worst_ok = std::max(worst_ok, rd);
+        double ms = 0.0;
+        DHT_TRY(time_hop(c, prec, in, fo, nrhs, reps, e0, e1, &ms));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = h;
+        }
+    }
+    c->hop_force = false;
+    if (best.form == DHT_HOP_TMARCH && best.tc == 0) best.tc = hop_config(c, prec, nrhs).tc;
+    c->hop_cfg[prec][b] = best;
+    res->best.form = best.form;
+    res->best.streaming_stores = best.nt;
+    res->best.t_chunk = best.form == DHT_HOP_TMARCH ? best.tc : 0;
+    res->best_ms = best_ms;
+    res->default_ms = def_ms;
+    res->candidates = (int)cand.size();
+    res->rejected = rejected;
+    res->max_rel_diff = worst_ok;
+    return DHT_OK;
+}
+
+}  // namespace dht
+
+using namespace dht;
+
+extern "C" {
+
+int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, const dht_hop_config* cfg) {
+    if (!c) return set_error(DHT_ERR_INVALID_ARG, "null context");
+    if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    const int b = log2_pow2(nrhs);
+    if (b < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
+    if (!cfg) {
+        c->hop_cfg[prec][b] = HopConfig();
+        return DHT_OK;
+    }
+    HopConfig h;
+    h.form = cfg->form;
+    h.nt = cfg->streaming_stores;
+    h.tc = cfg->form == DHT_HOP_TMARCH ? cfg->t_chunk : 0;
+    DHT_TRY(hop_config_check(c, nrhs, h));
+    c->hop_cfg[prec][b] = h;
+    return DHT_OK;
+}
+
+int dht_hop_config_get(dht_ctx* c, int prec, int nrhs, dht_hop_config* out) {
+    if (!c || !out) return set_error(DHT_ERR_INVALID_ARG, "null argument");
+    if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    if (log2_pow2(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
+    HopConfig h = hop_config(c, prec, nrhs);
+    out->form = h.form;
+    out->streaming_stores = h.nt;
+    out->t_chunk = h.form == DHT_HOP_TMARCH ? h.tc : 0;
+    return DHT_OK;
+}
+
+int dht_autotune_hop(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* out) {
+    if (!c || !out) return set_error(DHT_ERR_INVALID_ARG, "null argument");
+    if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    if (log2_pow2(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
+    if (reps <= 0) return set_error(DHT_ERR_INVALID_ARG, "reps must be positive");
+    if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    DHT_HIP(hipSetDevice(c->device));
+    hipEvent_t e0, e1;
+    DHT_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_error(DHT_ERR_HIP, "hipEventCreate failed");
+    }
+    int rc = autotune(c, prec, nrhs, reps, out, e0, e1);
+    c->hop_force = false;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+}  // extern "C"
