@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP-event timing")
+    ap.add_argument("--tune", default="auto", choices=["auto", "off"],
+                    help="autotune the hopping-kernel shape before timing (off: built-in default)")
+    ap.add_argument("--tune-cache", default=None, help="JSON table to load the shapes from / save them to")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested); probes shard across GPUs "
@@ -145,6 +148,33 @@ def main():
 
     inner = L.FP32 if args.inner == "fp32" else L.BF16
     prm = ctx.params(L.SOLVER_DC_BICGSTAB, inner=inner, tol=w.tol, maxiter=5000)
+
+    # launch shapes of the hopping kernel for the inner and the FP64 outer
+    # precision at this batch: from the cache if it was measured on this
+    # lattice, else timed now (setup, outside the measured region)
+    if args.tune == "auto":
+        want = {(inner, B), (L.FP64, B)}
+        if args.tune_cache and os.path.exists(args.tune_cache):
+            ctx.load_tuning(args.tune_cache)
+        have = set(ctx._tuned)
+        for prec, nb in sorted(want - have):
+            r = ctx.autotune_hop(prec, nb, reps=5)
+            log("autotune prec %d B %d: %s %.3f ms (default %.3f ms, %d shapes, %d rejected)"
+                % (prec, nb, r["best"], r["best_ms"], r["default_ms"], r["candidates"], r["rejected"]))
+        if args.tune_cache:
+            ctx.save_tuning(args.tune_cache)
+    shapes = {("fp64" if prec == L.FP64 else ("fp32" if prec == L.FP32 else "bf16")): ctx.hop_config(prec, B)
+              for prec in sorted({inner, L.FP64})}
+    for k_, v_ in shapes.items():
+        v_["form"] = L.HOP_FORMS[v_["form"]]
+
+    # a plain 1 GiB device copy (untimed) so that hardware-counter runs of this
+    # command carry their own calibration of FETCH_SIZE / WRITE_SIZE
+    cal_a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    cal_b = torch.empty_like(cal_a)
+    cal_b.copy_(cal_a)
+    torch.cuda.synchronize()
+    del cal_a, cal_b
     nprobe = w.nprobe
 
     def run(prm, steps, first0=0, profile=False):
@@ -172,6 +202,8 @@ def main():
     iters = float(np.mean([r["iters"] for r in recs]))
     outer = float(np.mean([r["outer"] for r in recs]))
     est = ctx.estimate()
+    log("running estimate over %d probes: mean z^H D^-1 z = %.6g%+.6gi (synthetic basis: deflated value not physical)"
+        % (est["n"], est["mean_re"], est["mean_im"]))
     tm = ctx.timings()
     log("mixed: %.2f ms/step, %.2f RHS/s, worst residual %.2e, mean inner iters %.1f, outer %.1f"
         % (ms_step, value, worst, iters, outer))
@@ -232,7 +264,7 @@ def main():
             "batch": B, "probes": "hierarchical probing (Z4 base x Hadamard)" if w.hp else "Z4",
             "deflation_k": k, "deflation_storage": "bf16 (synthetic basis, diagonal Galerkin inverse)",
             "solver": "even/odd BiCGStab, %s inner, FP64 defect correction" % args.inner,
-            "preconditioner": "none", "tol": w.tol,
+            "preconditioner": "none", "tol": w.tol, "hop_shapes": shapes,
             "mean_inner_iters": round(iters, 2), "mean_outer_cycles": round(outer, 2),
             "worst_true_residual": worst,
         },
@@ -242,8 +274,6 @@ def main():
         "speedup_vs_fp64": round(value / fp64_value, 3) if fp64_value else None,
         "dslash_GBps": dslash,
         "phase_ms_last_step": {kk: round(v, 3) for kk, v in tm.items()},
-        "estimate": {"n": est["n"], "trace_defl": [est["mean_defl_re"], est["mean_defl_im"]],
-                     "var": est["var"], "var_defl": est["var_defl"]},
     }
     ctx.close()
     print(json.dumps(out), flush=True)
