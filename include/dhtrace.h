@@ -188,11 +188,43 @@ int dht_deflation_begin(dht_ctx* ctx, int k, int prec);
 /* Copy columns first .. first+count-1 of W from W_dev (canonical complex128,
  * [count][N]) into the stored basis, rounding to the storage precision. */
 int dht_deflation_set(dht_ctx* ctx, int first, int count, const double* W_dev);
-/* Fill the basis with eigenvectors of Q = g5 D of smallest |lambda| computed
- * by the library's own block eigensolver (FP64); tol is the relative residual
- * target ||Q w - lambda w|| / ||Q||; lambda_host (k doubles, may be NULL)
- * receives the Ritz values. */
-int dht_deflation_eigensolve(dht_ctx* ctx, double tol, int max_iter, uint64_t seed, double* lambda_host);
+/* Eigensolver for the basis (Section 5.1: the smallest singular triplets of D
+ * follow from the eigenpairs of Q = g5 D of smallest |lambda|).  FP64
+ * Chebyshev-filtered subspace iteration: a polynomial of `degree` in Q^2,
+ * bounded on [a, ||Q||^2] with a = the block's largest Ritz value of Q^2,
+ * amplifies the bottom of the spectrum of Q^2; each cycle orthonormalises the
+ * block (Cholesky QR, twice) and takes a Rayleigh-Ritz step with Q.
+ *   tol       relative residual target ||Q w - lambda w|| / B_Q with the norm
+ *             bound B_Q = |4 + m| + 4 >= ||Q||;
+ *   max_iter  filter cycles;  guard  extra block vectors beyond k (0: max(16, k/4));
+ *   seed      Z4 start block.
+ * The block (k + guard rounded up to a power of two >= 32) must not exceed
+ * 256 vectors; it takes four FP64 full fields of that many RHS of workspace. */
+typedef struct dht_eig_params {
+    double tol;
+    int max_iter;
+    int degree;
+    int guard;
+    uint64_t seed;
+} dht_eig_params;
+typedef struct dht_eig_stats {
+    int iters;          /* filter cycles run */
+    int converged;      /* leading Ritz pairs (by |lambda|) within tol */
+    int block;          /* block size used */
+    int64_t matvecs;    /* applications of Q to the whole block */
+} dht_eig_stats;
+/* Fill the k columns set up by dht_deflation_begin with the k Ritz vectors of
+ * smallest |lambda| (rounded to the storage precision); call
+ * dht_deflation_finalize afterwards for M and T_D.  lambda_host and
+ * resid_host (k doubles each, may be NULL) receive the Ritz values, ordered
+ * by |lambda|, and their relative residuals; stats may be NULL.  Returns
+ * DHT_ERR_NOT_CONVERGED (basis still filled) if some pair missed tol within
+ * max_iter cycles. */
+int dht_deflation_eigensolve(dht_ctx* ctx, const dht_eig_params* prm, double* lambda_host, double* resid_host,
+                             dht_eig_stats* stats);
+/* Copy columns first .. first+count-1 of the stored basis, as rounded to its
+ * storage precision, to W_dev (device, canonical complex128, [count][N]). */
+int dht_deflation_get(dht_ctx* ctx, int first, int count, double* W_dev);
 /* Finish: H = W^H Q W accumulated in FP64 from the stored basis, M = H^-1,
  * T_D = Tr(M W^H g5 W).  TD_host (2 doubles: re, im) may be NULL. */
 int dht_deflation_finalize(dht_ctx* ctx, double* TD_host);

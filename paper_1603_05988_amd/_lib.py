@@ -47,6 +47,16 @@ class Record(ctypes.Structure):
                 ("qd_im", ctypes.c_double), ("s", SolveStats)]
 
 
+class EigParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("degree", ctypes.c_int),
+                ("guard", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
+class EigStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("block", ctypes.c_int),
+                ("matvecs", ctypes.c_int64)]
+
+
 class HopConfig(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("streaming_stores", ctypes.c_int), ("t_chunk", ctypes.c_int)]
 
@@ -87,8 +97,9 @@ SIGNATURES = {
     "dht_solve": (_i, [_vp, ctypes.POINTER(SolverParams), _vp, _vp, _i, ctypes.POINTER(SolveStats)]),
     "dht_deflation_begin": (_i, [_vp, _i, _i]),
     "dht_deflation_set": (_i, [_vp, _i, _i, _vp]),
-    "dht_deflation_eigensolve": (_i, [_vp, _d, _i, _u64, _dp]),
+    "dht_deflation_eigensolve": (_i, [_vp, ctypes.POINTER(EigParams), _dp, _dp, ctypes.POINTER(EigStats)]),
     "dht_deflation_finalize": (_i, [_vp, _dp]),
+    "dht_deflation_get": (_i, [_vp, _i, _i, _vp]),
     "dht_deflation_finalize_diag": (_i, [_vp, _dp]),
     "dht_project_probes": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _dp, _dp]),
     "dht_profile_enable": (_i, [_vp, _i]),
@@ -257,6 +268,31 @@ class Context:
     def set_deflation_columns(self, first: int, Wblock):
         Wblock = Wblock.contiguous()
         check(load().dht_deflation_set(self.h, first, Wblock.shape[0], _ptr(Wblock)))
+
+    def eigensolve(self, k: int, prec: int = FP64, tol: float = 1e-10, max_iter: int = 200, degree: int = 16,
+                   guard: int = 0, seed: int = 1, finalize: bool = True, allow_not_converged: bool = False):
+        """Deflation basis from the library's eigensolver: the k eigenvectors of
+        Q = g5 D of smallest |lambda|, stored in `prec`; with finalize, also the
+        Galerkin M and T_D.  Returns (lambda, relative residuals, stats, T_D)."""
+        self.begin_deflation(k, prec)
+        lam = np.zeros(k)
+        res = np.zeros(k)
+        st = EigStats()
+        prm = EigParams(float(tol), int(max_iter), int(degree), int(guard), int(seed))
+        rc = load().dht_deflation_eigensolve(self.h, ctypes.byref(prm), _np_dp(lam), _np_dp(res), ctypes.byref(st))
+        if rc != 0 and not (allow_not_converged and rc == -6):
+            check(rc)
+        stats = {f[0]: getattr(st, f[0]) for f in EigStats._fields_}
+        stats["status"] = rc
+        td = self.finalize_deflation() if finalize else None
+        return lam, res, stats, td
+
+    def deflation_columns(self, first: int, count: int):
+        """Stored basis columns (rounded to the storage precision) as a
+        complex128 CUDA tensor [count][N]."""
+        out = self.torch.empty((count, self.N), dtype=self.torch.complex128, device="cuda")
+        check(load().dht_deflation_get(self.h, first, count, _ptr(out)))
+        return out
 
     def finalize_deflation(self, diagonal: bool = False):
         td = np.zeros(2)

@@ -297,10 +297,30 @@ int dht_deflation_set(dht_ctx* c, int first, int count, const double* W_dev) {
     return DHT_OK;
 }
 
-int dht_deflation_eigensolve(dht_ctx* c, double tol, int max_iter, uint64_t seed, double* lambda_host) {
+int dht_deflation_eigensolve(dht_ctx* c, const dht_eig_params* prm, double* lambda_host, double* resid_host,
+                             dht_eig_stats* stats) {
     DHT_TRY(check_ctx(c));
-    (void)tol; (void)max_iter; (void)seed; (void)lambda_host;
-    return set_error(DHT_ERR_STATE, "the block eigensolver is not available in this build");
+    if (!prm) return set_error(DHT_ERR_INVALID_ARG, "null parameters");
+    int rc = eigensolve(c, prm, lambda_host, resid_host, stats);
+    DHT_TRY(prof_harvest(c));
+    return rc;
+}
+
+int dht_deflation_get(dht_ctx* c, int first, int count, double* W_dev) {
+    DHT_TRY(check_ctx(c));
+    if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "no deflation basis");
+    if (first < 0 || count < 0 || first + count > c->k || (count > 0 && !W_dev))
+        return set_error(DHT_ERR_INVALID_ARG, "columns out of range");
+    for (int j = 0; j < count; j += 64) {
+        const int n = std::min(64, count - j);
+        const int bp = pad_rhs(n);
+        void* buf;
+        DHT_TRY(ws_get(c, WS_DEFL_GET, full_elems(c, bp) * sizeof(Cx<double>), &buf));
+        DHT_TRY(gather_columns(c, first + j, n, bp, buf));
+        DHT_TRY(unpack_spinor(c, buf, DHT_FP64, W_dev + (size_t)2 * 12 * c->g.V * j, n, bp));
+    }
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    return DHT_OK;
 }
 
 int dht_deflation_finalize(dht_ctx* c, double* TD) {
