@@ -279,6 +279,10 @@ int64_t dht_nn_num_weights(void);
 /* He-normal initial weights (std sqrt(2 / (81 Cin)), the last layer scaled
  * by 0.1) from a seeded SplitMix64/Box-Muller generator; resets the optimiser. */
 int dht_nn_init(dht_ctx* ctx, uint64_t seed);
+/* Skip coefficient s of the preconditioner M(r) = net(r) + s r (default 0).
+ * s = 1 / (4 + m) makes M the point-Jacobi inverse of D plus the learned
+ * correction; it enters forward, loss, training and the FGMRES application. */
+int dht_nn_set_skip(dht_ctx* ctx, double s);
 int dht_nn_set_weights(dht_ctx* ctx, const float* w_host);
 int dht_nn_get_weights(dht_ctx* ctx, float* w_host);
 /* E = M(R) for n spinors. */

@@ -74,22 +74,26 @@ def init_weights(seed: int, scale: float = 1.0):
     return Ws
 
 
-def forward(x: np.ndarray, Ws, L):
-    """Network output and the activations needed by the backward pass.
+def forward(x: np.ndarray, Ws, L, skip: float = 0.0):
+    """Preconditioner output M(x) = net(x) + skip * x and the activations
+    needed by the backward pass.
 
     x: [batch][V][24].  Returns (y, cache) with cache = (x, h1, a1, h2, a2).
+    skip = 1 / (4 + m), the inverse of the Wilson matrix's diagonal, makes M
+    the point-Jacobi inverse plus a learned correction.
     """
     h1 = conv(x, Ws[0], L)
     a1 = np.maximum(h1, 0.0)
     h2 = conv(a1, Ws[1], L)
     a2 = np.maximum(h2, 0.0)
-    y = conv(a2, Ws[2], L)
+    y = conv(a2, Ws[2], L) + skip * x
     return y, (x, h1, a1, h2, a2)
 
 
-def loss_and_grad(x: np.ndarray, e: np.ndarray, Ws, L):
-    """Relative squared error and its gradient with respect to the weights."""
-    y, (x0, h1, a1, h2, a2) = forward(x, Ws, L)
+def loss_and_grad(x: np.ndarray, e: np.ndarray, Ws, L, skip: float = 0.0):
+    """Relative squared error of M(x) against e and its gradient with respect
+    to the weights (the skip term has no weights)."""
+    y, (x0, h1, a1, h2, a2) = forward(x, Ws, L, skip)
     diff = y - e
     en = np.sum(e * e, axis=(1, 2))
     nb = x.shape[0]

@@ -116,6 +116,7 @@ SIGNATURES = {
     "dht_bench_hop": (_i, [_vp, _i, _i, _i, _i, _dp]),
     "dht_nn_num_weights": (_i64, []),
     "dht_nn_init": (_i, [_vp, _u64]),
+    "dht_nn_set_skip": (_i, [_vp, _d]),
     "dht_nn_set_weights": (_i, [_vp, ctypes.POINTER(ctypes.c_float)]),
     "dht_nn_get_weights": (_i, [_vp, ctypes.POINTER(ctypes.c_float)]),
     "dht_nn_forward": (_i, [_vp, _vp, _vp, _i]),
@@ -387,6 +388,10 @@ class Context:
 
     def nn_init(self, seed: int):
         check(load().dht_nn_init(self.h, seed))
+
+    def nn_set_skip(self, s: float):
+        """M(r) = net(r) + s r; s = 1 / (4 + m) for the Jacobi-plus-correction form."""
+        check(load().dht_nn_set_skip(self.h, float(s)))
 
     def nn_set_weights(self, Ws):
         flat = self._flat_weights(Ws)

@@ -577,6 +577,13 @@ int dht_nn_init(dht_ctx* c, uint64_t seed) {
     return nn_set_weights(c, w.data());
 }
 
+int dht_nn_set_skip(dht_ctx* c, double sk) {
+    DHT_TRY(check_ctx(c));
+    if (!isfinite(sk)) return set_error(DHT_ERR_INVALID_ARG, "skip coefficient must be finite");
+    c->nn.skip = (float)sk;
+    return DHT_OK;
+}
+
 int dht_nn_set_weights(dht_ctx* c, const float* w) {
     DHT_TRY(check_ctx(c));
     if (!w) return set_error(DHT_ERR_INVALID_ARG, "null weights");

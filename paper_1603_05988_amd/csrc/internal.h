@@ -226,6 +226,7 @@ struct NNState {
     uint16_t* wf[3] = {nullptr, nullptr, nullptr}; // BF16 forward copy
     uint16_t* wb[3] = {nullptr, nullptr, nullptr}; // BF16 reflected/transposed copy
     int64_t step = 0;
+    float skip = 0.f;                              // M(r) = net(r) + skip r
 };
 
 struct Welford {   // running mean / second moments of complex samples (Chan et al. update)

@@ -263,12 +263,15 @@ __global__ void wgrad_sum_kernel(const float* partial, int nchunk, int64_t n, fl
 // ---------------------------------------------------------------------------
 // loss (relative squared error per sample), its gradient, Adam, conversions
 // ---------------------------------------------------------------------------
-__global__ void loss_partial_kernel(const float* y, const float* e, int64_t per_sample, double* s1, double* s2) {
+// y: network output, rs: skip term s r (or null), e: target
+__global__ void loss_partial_kernel(const float* y, const float* rs, const float* e, int64_t per_sample, double* s1,
+                                    double* s2) {
     __shared__ double r1[256], r2[256];
     const int b = blockIdx.x;
     double a1 = 0.0, a2 = 0.0;
     for (int64_t i = threadIdx.x; i < per_sample; i += 256) {
         double yy = y[b * per_sample + i], ee = e[b * per_sample + i];
+        if (rs) yy += rs[b * per_sample + i];
         a1 += (yy - ee) * (yy - ee);
         a2 += ee * ee;
     }
@@ -288,13 +291,14 @@ __global__ void loss_partial_kernel(const float* y, const float* e, int64_t per_
     }
 }
 
-__global__ void loss_grad_kernel(const float* y, const float* e, const double* s2, int64_t per_sample, int64_t n,
-                                 double scale, uint16_t* gy) {
+__global__ void loss_grad_kernel(const float* y, const float* rs, const float* e, const double* s2, int64_t per_sample,
+                                 int64_t n, double scale, uint16_t* gy) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t b = i / per_sample;
     double den = s2[b] > 0 ? s2[b] : 1.0;
-    gy[i] = f2bf((float)(2.0 * (y[i] - e[i]) / den * scale));
+    double yy = (double)y[i] + (rs ? (double)rs[i] : 0.0);
+    gy[i] = f2bf((float)(2.0 * (yy - e[i]) / den * scale));
 }
 
 __global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
@@ -331,6 +335,14 @@ __global__ void canon_to_bf16_kernel(const double* in, uint16_t* out, int64_t n)
 __global__ void canon_to_f32_kernel(const double* in, float* out, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (float)in[i];
+}
+__global__ void canon_scaled_to_f32_kernel(const double* in, float s, float* out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = s * (float)in[i];
+}
+__global__ void f32_skip_to_canon_kernel(const float* in, const double* r, float s, double* out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)in[i] + (double)(s * (float)r[i]);
 }
 __global__ void f32_to_canon_kernel(const float* in, double* out, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -496,14 +508,14 @@ static int wgrad(dht_ctx* c, int l, const uint16_t* g, const uint16_t* in, int n
 // activation workspace for nb samples
 struct NNBufs {
     uint16_t *x, *h1, *a1, *h2, *a2, *gy, *g2, *g1;
-    float *y, *e;
+    float *y, *e, *rs;   // output, target, skip term s r (FP32, from the unrounded input)
 };
 
 static int nn_bufs(dht_ctx* c, int nb, NNBufs* b) {
     const int64_t V = c->g.V;
     const size_t s24 = (size_t)nb * V * 24, s48 = (size_t)nb * V * 48;
     void* p;
-    size_t bytes = sizeof(uint16_t) * (s24 * 2 + s48 * 6) + sizeof(float) * s24 * 2 + 1024;
+    size_t bytes = sizeof(uint16_t) * (s24 * 2 + s48 * 6) + sizeof(float) * s24 * 3 + 1536;
     DHT_TRY(ws_get(c, WS_NN_ACT, bytes, &p));
     char* q = (char*)p;
     auto take = [&](size_t nbytes) {
@@ -521,6 +533,7 @@ static int nn_bufs(dht_ctx* c, int nb, NNBufs* b) {
     b->g1 = (uint16_t*)take(2 * s48);
     b->y = (float*)take(4 * s24);
     b->e = (float*)take(4 * s24);
+    b->rs = (float*)take(4 * s24);
     (void)bytes;
     return DHT_OK;
 }
@@ -540,9 +553,10 @@ static int nn_loss_backward(dht_ctx* c, NNBufs& b, int nb, double* loss) {
     DHT_TRY(ws_get(c, WS_NN_SCAL, sizeof(double) * 2 * nb, &s));
     double* s1 = (double*)s;
     double* s2 = s1 + nb;
-    hipLaunchKernelGGL(loss_partial_kernel, dim3(nb), dim3(256), 0, c->stream, b.y, b.e, per, s1, s2);
+    const float* rs = c->nn.skip != 0.f ? b.rs : nullptr;
+    hipLaunchKernelGGL(loss_partial_kernel, dim3(nb), dim3(256), 0, c->stream, b.y, rs, b.e, per, s1, s2);
     DHT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(loss_grad_kernel, g256(per * nb), dim3(256), 0, c->stream, b.y, b.e, s2, per, per * nb,
+    hipLaunchKernelGGL(loss_grad_kernel, g256(per * nb), dim3(256), 0, c->stream, b.y, rs, b.e, s2, per, per * nb,
                        1.0 / nb, b.gy);
     DHT_HIP(hipGetLastError());
     // layer 3: weight gradient from a2; data gradient through layer 3, masked by h2 > 0
@@ -582,6 +596,10 @@ static int nn_load(dht_ctx* c, NNBufs& b, const double* R, const double* E, int 
     if (E) {
         hipLaunchKernelGGL(canon_to_f32_kernel, g256(n), dim3(256), 0, c->stream, E, b.e, n);
         DHT_HIP(hipGetLastError());
+        if (c->nn.skip != 0.f) {
+            hipLaunchKernelGGL(canon_scaled_to_f32_kernel, g256(n), dim3(256), 0, c->stream, R, c->nn.skip, b.rs, n);
+            DHT_HIP(hipGetLastError());
+        }
     }
     return DHT_OK;
 }
@@ -596,7 +614,8 @@ int nn_forward_canon(dht_ctx* c, const double* R, double* E, int n) {
         DHT_TRY(nn_load(c, b, R + off, nullptr, nb));
         DHT_TRY(nn_forward_bufs(c, b, nb));
         const int64_t m = (int64_t)nb * c->g.V * 24;
-        hipLaunchKernelGGL(f32_to_canon_kernel, g256(m), dim3(256), 0, c->stream, b.y, E + off, m);
+        hipLaunchKernelGGL(f32_skip_to_canon_kernel, g256(m), dim3(256), 0, c->stream, b.y, R + off, c->nn.skip,
+                           E + off, m);
         DHT_HIP(hipGetLastError());
     }
     DHT_HIP(hipStreamSynchronize(c->stream));
@@ -646,7 +665,8 @@ int nn_train_canon(dht_ctx* c, const double* R, const double* E, int npairs, int
 // Apply the network to a full internal FP32 field (nrhs slots) in place of
 // the preconditioner: out = M(in).  in/out: [2][6][Vh][B][2] complex FP32.
 template <bool TO_NN>
-__global__ void field_nn_kernel(float* field, uint16_t* xin, const float* yout, Geom g, int B, int n) {
+__global__ void field_nn_kernel(float* field, uint16_t* xin, const float* yout, const float* fin, float skip, Geom g,
+                                int B, int n) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (p, s, r)
     if (gid >= g.V * (int64_t)B) return;
     int64_t ps = gid / B;
@@ -673,7 +693,8 @@ __global__ void field_nn_kernel(float* field, uint16_t* xin, const float* yout, 
             float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
             if (r < n) {
                 const float* y = yout + ((int64_t)r * g.V + site) * 24 + 4 * j;
-                d = make_float4(y[0], y[1], y[2], y[3]);
+                const float4 x = ((const float4*)fin)[vbase + j * SB];
+                d = make_float4(y[0] + skip * x.x, y[1] + skip * x.y, y[2] + skip * x.z, y[3] + skip * x.w);
             }
             *v = d;
         }
@@ -687,11 +708,11 @@ int nn_apply_field(dht_ctx* c, const void* in, void* out, int nrhs) {
     DHT_TRY(nn_bufs(c, nrhs, &b));
     int64_t tot = c->g.V * (int64_t)nrhs;
     hipLaunchKernelGGL(field_nn_kernel<true>, g256(tot), dim3(256), 0, c->stream, (float*)in, b.x, (const float*)nullptr,
-                       c->g, nrhs, nrhs);
+                       (const float*)nullptr, 0.f, c->g, nrhs, nrhs);
     DHT_HIP(hipGetLastError());
     DHT_TRY(nn_forward_bufs(c, b, nrhs));
     hipLaunchKernelGGL(field_nn_kernel<false>, g256(tot), dim3(256), 0, c->stream, (float*)out, (uint16_t*)nullptr,
-                       (const float*)b.y, c->g, nrhs, nrhs);
+                       (const float*)b.y, (const float*)in, c->nn.skip, c->g, nrhs, nrhs);
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }

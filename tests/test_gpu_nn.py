@@ -1,6 +1,7 @@
 """GPU parity of the learned preconditioner and of FGMRES, against the CPU oracle.
 
-Tolerances: the network runs on BF16 matrix cores (8-bit mantissas on
+The preconditioner is M(r) = net(r) + s r (s = 0, or 1 / (4 + m) for the
+point-Jacobi-plus-correction form).  Tolerances: the network runs on BF16 matrix cores (8-bit mantissas on
 weights and activations, FP32 accumulation), so outputs and the loss are
 compared to the FP64 oracle at 2e-2 relative (Frobenius), gradients at 5e-2;
 training pairs satisfy D e = r to the accuracy of the 1e-12 reference solve;
@@ -53,27 +54,36 @@ def test_weights_roundtrip_and_init(c1):
         assert abs(W.std() / sd - 1) < 0.05 and abs(W.mean()) < 0.05 * sd
 
 
-def test_forward_matches_oracle(c1):
+SKIPS = [0.0, 1.0 / (4.0 + WORKLOADS["c1"].mass)]
+
+
+@pytest.mark.parametrize("skip", SKIPS)
+def test_forward_matches_oracle(c1, skip):
     w, U, ctx = c1
     Ws = nn.init_weights(11)
     ctx.nn_set_weights(Ws)
+    ctx.nn_set_skip(skip)
     X = random_spinors(w.L, 3, 5)
     Y = ctx.nn_forward(cuda(X)).cpu().numpy().reshape(3, -1)
+    ctx.nn_set_skip(0.0)
     x = nn.spinor_to_channels(X.reshape(3, -1))
-    y, _ = nn.forward(x, Ws, w.L)
+    y, _ = nn.forward(x, Ws, w.L, skip)
     ref = nn.channels_to_spinor(y)
     assert rel(Y, ref) <= 2e-2, rel(Y, ref)
 
 
-def test_gradient_matches_oracle(c1):
+@pytest.mark.parametrize("skip", SKIPS)
+def test_gradient_matches_oracle(c1, skip):
     w, U, ctx = c1
     Ws = nn.init_weights(13)
     ctx.nn_set_weights(Ws)
+    ctx.nn_set_skip(skip)
     R = random_spinors(w.L, 4, 8)
     E = random_spinors(w.L, 4, 9)
     loss, grads = ctx.nn_grad(cuda(R), cuda(E))
+    ctx.nn_set_skip(0.0)
     lref, gref = nn.loss_and_grad(nn.spinor_to_channels(R.reshape(4, -1)), nn.spinor_to_channels(E.reshape(4, -1)),
-                                  Ws, w.L)
+                                  Ws, w.L, skip)
     assert abs(loss - lref) <= 2e-2 * lref
     for l in range(3):
         assert rel(grads[l], gref[l]) <= 5e-2, (l, rel(grads[l], gref[l]))
@@ -114,12 +124,14 @@ def test_fgmres_solves_c1(c1, use_nn):
     L = _lib()
     if use_nn:
         ctx.nn_init(2)
+        ctx.nn_set_skip(1.0 / (4.0 + w.mass))
     D = lattice.dense_wilson(U, w.L, w.mass)
     Dinv = estimator.exact_inverse(D)
     Z = rng.probes(w.L, w.seed, 7, False, 0, 5)
     method = L.SOLVER_DC_FGMRES_NN if use_nn else L.SOLVER_DC_FGMRES
     prm = ctx.params(method, tol=1e-10, restart=16, maxiter=4000)
     X, stats, rc = ctx.solve(cuda(Z.reshape((5,) + ctx._spinor_shape())), prm)
+    ctx.nn_set_skip(0.0)
     X = X.cpu().numpy().reshape(5, -1)
     ref = (Dinv @ Z.T).T
     assert all(s["true_resid"] <= 1e-10 for s in stats), stats

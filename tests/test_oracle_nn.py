@@ -5,7 +5,10 @@
   fixing the tap convention out[x] = sum_d W[d] in[x + d];
 - translation equivariance on the torus and linearity of a layer;
 - positive homogeneity of the bias-free ReLU network;
-- backward pass against central finite differences of the loss;
+- backward pass against central finite differences of the loss (with and
+  without the skip term s x of M(x) = net(x) + s x);
+- with all weights zero, M is exactly the scaled identity s x, and the loss
+  of the target e = s x is zero;
 - Adam's first step equals the closed form lr * g / (|g| + eps).
 """
 import numpy as np
@@ -52,24 +55,35 @@ def test_network_positive_homogeneity():
     assert np.allclose(y2, 3.5 * y1, rtol=1e-12, atol=1e-12)
 
 
-def test_backward_matches_finite_differences():
+@pytest.mark.parametrize("skip", [0.0, 0.3])
+def test_backward_matches_finite_differences(skip):
     rs = np.random.default_rng(4)
     Ws = nn.init_weights(5)
     x = rs.standard_normal((2, V, 24))
     e = rs.standard_normal((2, V, 24))
-    loss, grads = nn.loss_and_grad(x, e, Ws, L)
+    loss, grads = nn.loss_and_grad(x, e, Ws, L, skip)
     h = 1e-6
     for l in range(3):
         for _ in range(6):
             idx = tuple(rs.integers(0, s) for s in Ws[l].shape)
             W0 = Ws[l][idx]
             Ws[l][idx] = W0 + h
-            lp, _ = nn.loss_and_grad(x, e, Ws, L)
+            lp, _ = nn.loss_and_grad(x, e, Ws, L, skip)
             Ws[l][idx] = W0 - h
-            lm, _ = nn.loss_and_grad(x, e, Ws, L)
+            lm, _ = nn.loss_and_grad(x, e, Ws, L, skip)
             Ws[l][idx] = W0
             fd = (lp - lm) / (2 * h)
             assert abs(fd - grads[l][idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (l, idx, fd, grads[l][idx])
+
+
+def test_zero_network_is_scaled_identity():
+    rs = np.random.default_rng(9)
+    Ws = [np.zeros_like(W) for W in nn.init_weights(1)]
+    x = rs.standard_normal((3, V, 24))
+    y, _ = nn.forward(x, Ws, L, skip=0.25)
+    assert np.array_equal(y, 0.25 * x)
+    loss, grads = nn.loss_and_grad(x, 0.25 * x, Ws, L, skip=0.25)
+    assert loss == 0.0 and all(not g.any() for g in grads)
 
 
 def test_adam_first_step_closed_form():
