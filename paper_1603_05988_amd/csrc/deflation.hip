@@ -206,9 +206,16 @@ struct MfmaProjArgs {
 
 __device__ inline uint32_t bf16_unit(int v) { return v > 0 ? 0x3F80u : (v < 0 ? 0xBF80u : 0u); }
 
+// Each workgroup takes a contiguous run of chunks of one group; the probe
+// fragments of MP_FILL chunks are expanded into LDS at a time, and inside a
+// chunk every wave issues all of its A-fragment loads (RT tiles x the chunk's
+// K-steps) before the MFMAs, so that RT * kc / 8 16-byte loads per lane are in
+// flight; the FP32 accumulators are flushed to FP64 after every chunk.
+static constexpr int MP_FILL = 4;
+
 template <int RT, int NT>
 __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
-    extern __shared__ uint4 bfr[];   // [kc/8][NT][64] B fragments
+    extern __shared__ uint4 bfr[];   // [MP_FILL][kc/8][NT][64] B fragments
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -216,6 +223,9 @@ __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
     const int wslot = blockIdx.x - g * a.wg_per_group;
     const int tile0 = (blockIdx.y * MP_WAVES + wave) * RT;
     const int nks = a.kc >> 3;
+    const int64_t per = (a.chunks_per_group + a.wg_per_group - 1) / a.wg_per_group;
+    const int64_t c_begin = wslot * per;
+    const int64_t c_end = c_begin + per < a.chunks_per_group ? c_begin + per : a.chunks_per_group;
 
     f32x16_t acc[RT][NT];
     double facc[RT][NT][16];
@@ -230,14 +240,15 @@ __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
             }
         }
 
-    for (int64_t ch = wslot; ch < a.chunks_per_group; ch += a.wg_per_group) {
-        const int64_t K0 = (int64_t)g * a.group_len + ch * a.kc;
+    for (int64_t cf = c_begin; cf < c_end; cf += MP_FILL) {
+        const int nfill = (int)(c_end - cf < MP_FILL ? c_end - cf : MP_FILL);
+        const int64_t K0 = (int64_t)g * a.group_len + cf * a.kc;
         __syncthreads();
-        // expand the chunk's probe codes into B fragments in LDS
-        for (int f = tid; f < nks * NT * 64; f += MP_THREADS) {
+        // expand the probe codes of nfill chunks into B fragments in LDS
+        for (int f = tid; f < nfill * nks * NT * 64; f += MP_THREADS) {
             int l = f & 63;
             int nt = (f >> 6) % NT;
-            int ks = (f >> 6) / NT;
+            int ks = (f >> 6) / NT;                       // K-step within the fill
             int col = nt * 32 + (l & 31);
             int r = col >> 1, part = col & 1;
             uint32_t w[4];
@@ -256,36 +267,44 @@ __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
             bfr[f] = make_uint4(w[0], w[1], w[2], w[3]);
         }
         __syncthreads();
-        for (int ks = 0; ks < nks; ks++) {
-            bf16x8_t bf[NT];
+        for (int cc = 0; cc < nfill; cc++) {
+            const int64_t step0 = (K0 >> 3) + (int64_t)cc * nks;
+            for (int kb = 0; kb < nks; kb += 8) {   // the chunk in blocks of 8 K-steps
+                uint4 av[RT][8];
 #pragma unroll
-            for (int nt = 0; nt < NT; nt++) {
-                uint4 v = bfr[(ks * NT + nt) * 64 + lane];
-                bf[nt] = __builtin_bit_cast(bf16x8_t, v);
-            }
-            const int64_t step = (K0 >> 3) + ks;
+                for (int rt = 0; rt < RT; rt++) {
+                    const int t = tile0 + rt < a.ntiles ? tile0 + rt : a.ntiles - 1;
 #pragma unroll
-            for (int rt = 0; rt < RT; rt++) {
-                const int t = tile0 + rt;
-                if (t < a.ntiles) {
-                    uint4 v = a.W[((int64_t)t * a.nsteps + step) * 64 + lane];
-                    bf16x8_t af = __builtin_bit_cast(bf16x8_t, v);
+                    for (int u = 0; u < 8; u++)
+                        if (kb + u < nks) av[rt][u] = a.W[((int64_t)t * a.nsteps + step0 + kb + u) * 64 + lane];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    if (kb + u >= nks) break;
+                    bf16x8_t bf[NT];
 #pragma unroll
                     for (int nt = 0; nt < NT; nt++)
-                        acc[rt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf[nt], acc[rt][nt], 0, 0, 0);
+                        bf[nt] = __builtin_bit_cast(bf16x8_t, bfr[((cc * nks + kb + u) * NT + nt) * 64 + lane]);
+#pragma unroll
+                    for (int rt = 0; rt < RT; rt++) {
+                        bf16x8_t af = __builtin_bit_cast(bf16x8_t, av[rt][u]);
+#pragma unroll
+                        for (int nt = 0; nt < NT; nt++)
+                            acc[rt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf[nt], acc[rt][nt], 0, 0, 0);
+                    }
                 }
             }
+            // flush the chunk sums into FP64
+#pragma unroll
+            for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+                    for (int q = 0; q < 16; q++) {
+                        facc[rt][nt][q] += (double)acc[rt][nt][q];
+                        acc[rt][nt][q] = 0.f;
+                    }
         }
-        // flush the chunk sums into FP64
-#pragma unroll
-        for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-            for (int nt = 0; nt < NT; nt++)
-#pragma unroll
-                for (int q = 0; q < 16; q++) {
-                    facc[rt][nt][q] += (double)acc[rt][nt][q];
-                    acc[rt][nt][q] = 0.f;
-                }
     }
     // this workgroup's partial sums; C layout: row = 8 (q/4) + 4 (lane/32) + q%4, col = lane % 32
     const int ncol = NT * 32;
@@ -344,7 +363,7 @@ int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<do
     a.ntiles = wl.kp / 32;
     int NT = (2 * nrhs + 31) / 32;
     if (NT == 3) NT = 4;
-    const int RT = NT == 1 ? 4 : (NT == 2 ? 2 : 1);
+    const int RT = NT == 1 ? 2 : 1;
     const int rows_per_wg = MP_WAVES * RT * 32;
     const int rowgroups = (wl.kp + rows_per_wg - 1) / rows_per_wg;
     int wpg = (int)std::min<int64_t>(a.chunks_per_group, std::max(1, 512 / (4 * rowgroups)));
@@ -355,11 +374,11 @@ int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<do
     a.partial = (double*)part;
     DHT_TRY(zero(c, part, (size_t)nwg * wl.kp * NT * 32 * sizeof(double)));
     dim3 grid(nwg, rowgroups), block(MP_THREADS);
-    size_t lds = (size_t)(a.kc / 8) * NT * 64 * sizeof(uint4);
+    size_t lds = (size_t)MP_FILL * (a.kc / 8) * NT * 64 * sizeof(uint4);
     int tok;
     DHT_TRY(prof_begin(c, &tok));
-    if (NT == 1) hipLaunchKernelGGL((proj_mfma_kernel<4, 1>), grid, block, lds, c->stream, a);
-    else if (NT == 2) hipLaunchKernelGGL((proj_mfma_kernel<2, 2>), grid, block, lds, c->stream, a);
+    if (NT == 1) hipLaunchKernelGGL((proj_mfma_kernel<2, 1>), grid, block, lds, c->stream, a);
+    else if (NT == 2) hipLaunchKernelGGL((proj_mfma_kernel<1, 2>), grid, block, lds, c->stream, a);
     else hipLaunchKernelGGL((proj_mfma_kernel<1, 4>), grid, block, lds, c->stream, a);
     DHT_HIP(hipGetLastError());
     // algorithmic bytes: the stored basis once, the probe codes once per row group, the partials
