@@ -31,6 +31,7 @@ struct HopArgs {
     void* out;
     const void* in;
     const void* x;       // xpay source (same parity as out) or null
+    const void* z;       // second axpy source (same parity as out) or null
     const void* U;
     const void* da;      // dot operand a (HOPDOT_A_OUT)
     Cx<double>* partial;
@@ -41,7 +42,7 @@ struct HopArgs {
     int bshift;          // log2(B)
     int tc, nchunk;      // t-marching: slices per chunk (even, divides Lt) and chunks
     int nt;              // non-temporal (streaming) output stores
-    double ca, cb;       // out = ca * x + cb * Hop(in)
+    double ca, cb, cz;   // out = ca * x + cb * Hop(in) + cz * z
 };
 
 static constexpr int HOP_THREADS = HOP_LANES;
@@ -232,9 +233,18 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
     for (int i = 0; i < 12; i++) {
         Cx<T> v = cb * acc[i];
         if (XPAY) v = v + ca * xv[i];
-        if (G5OUT && i >= 6) v = neg(v);
         acc[i] = v;
     }
+    if (XPAY && a.z) {   // out += cz * z (residuals z - D x in one pass)
+        const T cz = (T)a.cz;
+        Cx<T> zv[12];
+        load_spinor<S>(a.z, v0, vstride, zv);
+#pragma unroll
+        for (int i = 0; i < 12; i++) acc[i] = acc[i] + cz * zv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 12; i++)
+        if (G5OUT && i >= 6) acc[i] = neg(acc[i]);
 #pragma unroll
     for (int j = 0; j < 12 / VW; j++) {
         if (a.nt) Store<S>::stv_nt(a.out, v0 + j * vstride, acc + j * VW);
@@ -250,6 +260,9 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
 #pragma unroll
             for (int i = 0; i < 12; i++)
                 d0 = d0 + conjmul(cmake<double>(av[i].re, av[i].im), cmake<double>(ov[i].re, ov[i].im));
+        } else if (DOT == HOPDOT_NORM) {
+#pragma unroll
+            for (int i = 0; i < 12; i++) d0.re += (double)ov[i].re * ov[i].re + (double)ov[i].im * ov[i].im;
         } else {
 #pragma unroll
             for (int i = 0; i < 12; i++) {
@@ -289,7 +302,7 @@ template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, bool LDSL>
 __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
     constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
-    constexpr int NP = DOT == HOPDOT_A_OUT ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
+    constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
     extern __shared__ uint4 hop_lds[];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int B = 1 << a.bshift;
@@ -412,7 +425,7 @@ __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, 
 template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT>
 __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
-    constexpr int NP = DOT == HOPDOT_A_OUT ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
+    constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
     constexpr int SF = DAG ? -1 : 1;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int gid = blk * HOP_THREADS + threadIdx.x;
@@ -503,11 +516,14 @@ int hop_blocks(const dht_ctx* c, int nrhs) {
 
 template <typename S>
 static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, const void* x, double ca, double cb,
-                      int nrhs, bool dagger, bool g5out, HopDot* dot) {
+                      int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz) {
     HopArgs a;
     a.out = out;
     a.in = in;
     a.x = x;
+    a.z = z;
+    a.cz = cz;
+    if (z && !x) return set_error(DHT_ERR_INVALID_ARG, "second axpy source needs an xpay source");
     a.U = c->U[std::is_same<S, double>::value ? 0 : (std::is_same<S, float>::value ? 1 : 2)];
     a.Lx = c->g.L[0];
     a.Ly = c->g.L[1];
@@ -560,6 +576,7 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     DHT_HOP_CASE(true, true, true, HOPDOT_NONE)
     DHT_HOP_CASE(false, false, true, HOPDOT_A_OUT)
     DHT_HOP_CASE(false, false, true, HOPDOT_OUT_X)
+    DHT_HOP_CASE(false, false, true, HOPDOT_NORM)
 #undef DHT_HOP_CASE
     return set_error(DHT_ERR_INVALID_ARG, "unsupported hop variant");
 launched:
@@ -568,22 +585,22 @@ launched:
 }
 
 int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
-        int nrhs, bool dagger, bool g5out, HopDot* dot) {
+        int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz) {
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
     int tok;
     DHT_TRY(prof_begin(c, &tok));
     int rc = DHT_OK;
     switch (prec) {
-        case DHT_FP64: rc = launch_hop<double>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot); break;
-        case DHT_FP32: rc = launch_hop<float>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot); break;
-        case DHT_BF16: rc = launch_hop<bf16x2>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot); break;
+        case DHT_FP64: rc = launch_hop<double>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz); break;
+        case DHT_FP32: rc = launch_hop<float>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz); break;
+        case DHT_BF16: rc = launch_hop<bf16x2>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz); break;
     }
     if (rc != DHT_OK) return rc;
     // algorithmic bytes: read the input half field (and the xpay / dot operand),
     // write the output, read each of the 8 Vh link matrices of this parity once
     const double eb = (double)elem_bytes(prec);
-    double nfield = 2.0 + (x ? 1.0 : 0.0) + ((dot && dot->kind == HOPDOT_A_OUT) ? 1.0 : 0.0);
+    double nfield = 2.0 + (x ? 1.0 : 0.0) + (z ? 1.0 : 0.0) + ((dot && dot->kind == HOPDOT_A_OUT) ? 1.0 : 0.0);
     const double bytes = nfield * 12.0 * c->g.Vh * nrhs * eb + 72.0 * c->g.Vh * eb;
     return prof_end(c, tok, PROF_HOP64 + prec, bytes);
 }

@@ -307,6 +307,7 @@ enum Slot {
     WS_Z, WS_XF, WS_QW, WS_PROJ, WS_COEF, WS_PROJ2, WS_ZCODE,
     WS_NN_PART, WS_NN_ACT, WS_NN_SCAL, WS_FG_V, WS_FG_Z, WS_FG_W, WS_FG_COEF, WS_FG_R, WS_FG_E, WS_XSTAR,
     WS_TUNE_REF, WS_TUNE_RED,
+    WS_NORMS,
     WS_EIG_V, WS_EIG_W, WS_EIG_T, WS_EIG_U, WS_EIG_PART, WS_EIG_SMALL, WS_EIG_RPART, WS_EIG_LAM, WS_EIG_CANON, WS_DEFL_GET,
     WS_NSLOTS
 };
@@ -335,11 +336,13 @@ int pack_gauge(dht_ctx* c, const double* U_dev);
 int pack_spinor(dht_ctx* c, const double* canon, void* field, int prec, int n, int bp);
 int unpack_spinor(dht_ctx* c, const void* field, int prec, double* canon, int n, int bp);
 
-// dslash.hip: out_p = a * x_p + b * Hop_{p <- 1-p}(in), optionally g5 on the result and/or dagger hop.
-// A per-RHS FP64 reduction can be fused into the epilogue: HOPDOT_A_OUT gives
-// (a, out) = sum conj(a) out; HOPDOT_OUT_X gives (out, x) and (out, out).
-// Partial sums go to partial[block][pair][nrhs]; *nblocks receives the count.
-enum { HOPDOT_NONE = 0, HOPDOT_A_OUT = 1, HOPDOT_OUT_X = 2 };
+// dslash.hip: out_p = a * x_p + b * Hop_{p <- 1-p}(in) (+ cz * z_p when z is
+// given), optionally g5 on the result and/or dagger hop.  A per-RHS FP64
+// reduction can be fused into the epilogue: HOPDOT_A_OUT gives (a, out) =
+// sum conj(a) out; HOPDOT_OUT_X gives (out, x) and (out, out); HOPDOT_NORM
+// gives (out, out).  Partial sums go to partial[block][pair][nrhs]; nblocks
+// receives the count.
+enum { HOPDOT_NONE = 0, HOPDOT_A_OUT = 1, HOPDOT_OUT_X = 2, HOPDOT_NORM = 3 };
 struct HopDot {
     int kind = HOPDOT_NONE;
     const void* a = nullptr;
@@ -347,7 +350,7 @@ struct HopDot {
     int nblocks = 0;
 };
 int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
-        int nrhs, bool dagger, bool g5out, HopDot* dot = nullptr);
+        int nrhs, bool dagger, bool g5out, HopDot* dot = nullptr, const void* z = nullptr, double cz = 0.0);
 int hop_blocks(const dht_ctx* c, int nrhs);   // workgroups of one hop launch
 constexpr int HOP_LANES = 256;   // lanes per hop workgroup
 // the shape a hop launch for (prec, nrhs) uses (t chunk resolved), and a check

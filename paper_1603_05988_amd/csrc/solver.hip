@@ -111,6 +111,28 @@ int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::
 }
 
 // per-RHS FP64 norms^2 of an FP64 field of nvec vectors (host result)
+// residual of a parity, out = z + ca x + cb Hop(in), with its per-RHS squared
+// norms reduced from the hop's fused epilogue sums; `slot` selects where the
+// sums are kept so that two residuals can be summed on the host
+static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const void* x, double ca, double cb,
+                        const void* z, int nrhs, int slot, std::vector<double>& n2) {
+    void *part, *sums;
+    DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
+    DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 2 * nrhs, &sums));
+    HopDot d;
+    d.kind = HOPDOT_NORM;
+    d.partial = (Cx<double>*)part;
+    DHT_TRY(hop(c, DHT_FP64, parity, in, out, x, ca, cb, nrhs, false, false, &d, z, 1.0));
+    Cx<double>* s = (Cx<double>*)sums + (size_t)slot * nrhs;
+    DHT_TRY(finalize(c, d.partial, d.nblocks, 1, nrhs, nullptr, FIN_SUM, 0.0, s));
+    std::vector<Cx<double>> h(nrhs);
+    DHT_HIP(hipMemcpyAsync(h.data(), s, sizeof(Cx<double>) * nrhs, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    n2.resize(nrhs);
+    for (int i = 0; i < nrhs; i++) n2[i] = h[i].re;
+    return DHT_OK;
+}
+
 static int norms2(dht_ctx* c, const void* f, size_t nvec, int nrhs, std::vector<double>& out) {
     void* d;
     DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 3 * nrhs, &d));
@@ -187,8 +209,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     bool last_bad = false;
     void* e;
     void* rlo;
+    DHT_TRY(norms2(c, r_e, nh, nrhs, rn2));
     for (; outer < max_outer; outer++) {
-        DHT_TRY(norms2(c, r_e, nh, nrhs, rn2));
         bool any = false, stalled = false;
         std::vector<double> sdown(nrhs), sup(nrhs), itarget(nrhs);
         for (int i = 0; i < nrhs; i++) {
@@ -235,9 +257,10 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         total_iters += std::max(maxit, 1);
         DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
         DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nrhs));
-        // FP64 true residual of the Schur system
-        DHT_TRY(apply_schur(c, DHT_FP64, X_e, tmpf, tmp_o, nrhs));
-        DHT_TRY(sub(c, bhat, tmpf, r_e, nh));
+        // FP64 true residual of the Schur system, r = bhat - (a x - Hop_eo Hop_oe x / (4a)),
+        // and its norms, in the second hop's epilogue
+        DHT_TRY(hop(c, DHT_FP64, 1, X_e, tmp_o, nullptr, 0.0, 1.0, nrhs, false, false));
+        DHT_TRY(residual_hop(c, 0, tmp_o, r_e, X_e, -a, 1.0 / (4.0 * a), bhat, nrhs, 0, rn2));
         if (bad && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
         last_bad = bad;
         for (int i = 0; i < nrhs; i++)
@@ -246,12 +269,13 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     }
     // odd sites and the FP64 full-lattice true residual
     DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false));
+    // r_p = z_p - (a x_p - Hop_{p <- 1-p} x / 2) per parity, norms fused
     void* full;
     DHT_TRY(ws_get(c, WS_XF, 2 * bh, &full));
-    DHT_TRY(apply_full(c, DHT_OP_D, DHT_FP64, X, full, nrhs));
-    DHT_TRY(sub(c, Z, full, full, 2 * nh));
-    std::vector<double> fr2;
-    DHT_TRY(norms2(c, full, 2 * nh, nrhs, fr2));
+    std::vector<double> fr2, fr2o;
+    DHT_TRY(residual_hop(c, 0, X_o, full, X_e, -a, 0.5, Z_e, nrhs, 0, fr2));
+    DHT_TRY(residual_hop(c, 1, X_e, (char*)full + bh, X_o, -a, 0.5, Z_o, nrhs, 1, fr2o));
+    for (int i = 0; i < nrhs; i++) fr2[i] += fr2o[i];
     bool all_ok = true;
     for (int i = 0; i < nrhs; i++) {
         double rr = zn2[i] > 0 ? sqrt(fr2[i] / zn2[i]) : 0.0;
