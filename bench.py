@@ -99,7 +99,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c5")
-    ap.add_argument("--inner", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--inner", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--inner-tol", type=float, default=0.0, help="inner relative residual per outer cycle (0: library default)")
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
@@ -147,7 +148,7 @@ def main():
     log("deflation basis k=%d set up in %.1f s, T_D = %.6g" % (k, t_setup, TD.real))
 
     inner = L.FP32 if args.inner == "fp32" else L.BF16
-    prm = ctx.params(L.SOLVER_DC_BICGSTAB, inner=inner, tol=w.tol, maxiter=5000)
+    prm = ctx.params(L.SOLVER_DC_BICGSTAB, inner=inner, tol=w.tol, maxiter=5000, inner_tol=args.inner_tol)
 
     # launch shapes of the hopping kernel for the inner and the FP64 outer
     # precision at this batch: from the cache if it was measured on this

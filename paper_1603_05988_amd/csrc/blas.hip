@@ -19,7 +19,7 @@
 namespace dht {
 
 static constexpr int RED_THREADS = 256;
-static constexpr int RED_MAX_BLOCKS = 1024;
+static constexpr int RED_MAX_BLOCKS = 4096;
 
 static int red_blocks(size_t nvec) {
     size_t nb = (nvec + RED_THREADS - 1) / RED_THREADS;
@@ -171,8 +171,39 @@ __global__ __launch_bounds__(RED_THREADS) void finalize_kernel(const Cx<double>*
     }
 }
 
+// First stage for long partial lists (one row per hop workgroup): workgroup f
+// sums a contiguous slice of rows [b][np * B]; the rows are read coalesced.
+static constexpr int FOLD_ROWS = 256;
+__global__ __launch_bounds__(RED_THREADS) void fold_partials_kernel(const Cx<double>* partial, int nblocks, int w,
+                                                                    Cx<double>* out) {
+    __shared__ Cx<double> red[RED_THREADS];
+    const int per = (nblocks + gridDim.x - 1) / gridDim.x;
+    const int b0 = blockIdx.x * per, b1 = min(nblocks, b0 + per);
+    const int rows = RED_THREADS / w;   // rows summed side by side (w <= RED_THREADS)
+    const int col = threadIdx.x % w, slot = threadIdx.x / w;
+    Cx<double> s = cmake(0.0, 0.0);
+    if (slot < rows)
+        for (int b = b0 + slot; b < b1; b += rows) s = s + partial[(int64_t)b * w + col];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (slot == 0) {
+        for (int q = 1; q < rows; q++) s = s + red[q * w + col];
+        out[(int64_t)blockIdx.x * w + col] = s;
+    }
+}
+
 int finalize(dht_ctx* c, const Cx<double>* partial, int nblocks, int np, int nrhs, RhsState* st, int op, double bd_eps,
              Cx<double>* sums) {
+    const int w = np * nrhs;
+    if (nblocks > 4 * FOLD_ROWS && w <= RED_THREADS) {
+        void* fold;
+        DHT_TRY(ws_get(c, WS_FOLD, sizeof(Cx<double>) * FOLD_ROWS * RED_THREADS, &fold));
+        hipLaunchKernelGGL(fold_partials_kernel, dim3(FOLD_ROWS), dim3(RED_THREADS), 0, c->stream, partial, nblocks, w,
+                           (Cx<double>*)fold);
+        DHT_HIP(hipGetLastError());
+        partial = (const Cx<double>*)fold;
+        nblocks = FOLD_ROWS;
+    }
     hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(RED_THREADS), 0, c->stream, partial, nblocks, np, nrhs, st,
                        op, bd_eps, sums);
     DHT_HIP(hipGetLastError());

@@ -434,7 +434,7 @@ __global__ void pack_w_kernel(const Cx<double>* canon, typename Store<SW>::elem*
     int64_t n = lex_index(g, cc);
     Cx<double> v = canon[((int64_t)j * g.V + n) * 12 + comp];
     typedef typename Store<SW>::acc T;
-    Store<SW>::st(W + w_index(wl, first + j, K), cmake<T>((T)v.re, (T)v.im));
+    Store<SW>::st_rne(W + w_index(wl, first + j, K), cmake<T>((T)v.re, (T)v.im));
 }
 
 int deflation_set(dht_ctx* c, int first, int count, const double* W_dev) {

@@ -58,6 +58,14 @@ __host__ __device__ inline uint32_t f32_to_bf16_bits(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return u >> 16;
 }
+// Hardware conversion of two values in one instruction (v_cvt_pk_bf16_f32 on
+// gfx950): round to nearest, but exact ties do not go to even, so it is used
+// only for values the kernels compute, not where RNE is part of the contract.
+typedef __bf16 bf16x2_vec_t __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t f32x2_to_bf16x2_bits(float lo, float hi) {
+    bf16x2_vec_t b = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, b);
+}
 __host__ __device__ inline float bf16_bits_to_f32(uint32_t h) {
     uint32_t u = h << 16;
     float f;
@@ -88,6 +96,8 @@ template <> struct Store<double> {
     __device__ static inline void stv(void* base, int64_t v, const Cx<double>* i) {
         ((double2*)base)[v] = make_double2(i[0].re, i[0].im);
     }
+    __device__ static inline void stv_rne(void* base, int64_t v, const Cx<double>* i) { stv(base, v, i); }
+    __device__ static inline void st_rne(elem* p, Cx<double> v) { *p = v; }
     __device__ static inline void ldv_nt(const void* base, int64_t v, Cx<double>* o) {
         f64x2_t d = __builtin_nontemporal_load((const f64x2_t*)base + v);
         o[0] = cmake(d.x, d.y);
@@ -112,6 +122,8 @@ template <> struct Store<float> {
     __device__ static inline void stv(void* base, int64_t v, const Cx<float>* i) {
         ((float4*)base)[v] = make_float4(i[0].re, i[0].im, i[1].re, i[1].im);
     }
+    __device__ static inline void stv_rne(void* base, int64_t v, const Cx<float>* i) { stv(base, v, i); }
+    __device__ static inline void st_rne(elem* p, Cx<float> v) { *p = v; }
     __device__ static inline void ldv_nt(const void* base, int64_t v, Cx<float>* o) {
         f32x4_t d = __builtin_nontemporal_load((const f32x4_t*)base + v);
         o[0] = cmake(d.x, d.y);
@@ -129,8 +141,18 @@ template <> struct Store<bf16x2> {
     __device__ static inline Cx<float> unpack(uint32_t b) {
         return cmake(bf16_bits_to_f32(b & 0xffffu), bf16_bits_to_f32(b >> 16));
     }
+    // values the kernels compute: the hardware conversion (round to nearest;
+    // its tie rule is not ties-to-even)
     __device__ static inline uint32_t pack(Cx<float> v) {
+        return f32x2_to_bf16x2_bits(v.re, v.im);
+    }
+    // stored inputs (links, basis, packed spinors): IEEE round-to-nearest-even
+    __device__ static inline uint32_t pack_rne(Cx<float> v) {
         return f32_to_bf16_bits(v.re) | (f32_to_bf16_bits(v.im) << 16);
+    }
+    __device__ static inline void st_rne(elem* p, Cx<float> v) { p->bits = pack_rne(v); }
+    __device__ static inline void stv_rne(void* base, int64_t v, const Cx<float>* i) {
+        ((uint4*)base)[v] = make_uint4(pack_rne(i[0]), pack_rne(i[1]), pack_rne(i[2]), pack_rne(i[3]));
     }
     __device__ static inline Cx<float> round(Cx<float> v) { return unpack(pack(v)); }
     __device__ static inline Cx<float> ld(const elem* p) { return unpack(p->bits); }
@@ -307,7 +329,7 @@ enum Slot {
     WS_Z, WS_XF, WS_QW, WS_PROJ, WS_COEF, WS_PROJ2, WS_ZCODE,
     WS_NN_PART, WS_NN_ACT, WS_NN_SCAL, WS_FG_V, WS_FG_Z, WS_FG_W, WS_FG_COEF, WS_FG_R, WS_FG_E, WS_XSTAR,
     WS_TUNE_REF, WS_TUNE_RED,
-    WS_NORMS,
+    WS_NORMS, WS_FOLD,
     WS_EIG_V, WS_EIG_W, WS_EIG_T, WS_EIG_U, WS_EIG_PART, WS_EIG_SMALL, WS_EIG_RPART, WS_EIG_LAM, WS_EIG_CANON, WS_DEFL_GET,
     WS_NSLOTS
 };

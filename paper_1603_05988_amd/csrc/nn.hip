@@ -35,7 +35,7 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 static const int NN_CH[4] = {24, 48, 48, 24};
 
-__device__ inline uint16_t f2bf(float f) { return (uint16_t)f32_to_bf16_bits(f); }
+__device__ inline uint16_t f2bf(float f) { return (uint16_t)(f32x2_to_bf16x2_bits(f, 0.f) & 0xffffu); }
 __device__ inline float bf2f(uint16_t h) { return bf16_bits_to_f32(h); }
 
 struct ConvArgs {

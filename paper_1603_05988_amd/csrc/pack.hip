@@ -22,7 +22,7 @@ __device__ inline void store_link(void* U, int mu, int p, int64_t s, int64_t Vh,
 #pragma unroll
     for (int i = 0; i < NV * VW; i++) e[i] = i < 9 ? from_double<S>(m[i]) : from_double<S>(cmake(0.0, 0.0));
 #pragma unroll
-    for (int j = 0; j < NV; j++) Store<S>::stv(U, ((int64_t)(mu * 2 + p) * Vh + s) * NV + j, e + j * VW);
+    for (int j = 0; j < NV; j++) Store<S>::stv_rne(U, ((int64_t)(mu * 2 + p) * Vh + s) * NV + j, e + j * VW);
 }
 
 __global__ void pack_gauge_kernel(const Cx<double>* __restrict__ Uc, void* U64, void* U32, void* U16, Geom g) {
@@ -74,7 +74,7 @@ __global__ void spinor_pack_kernel(Cx<double>* canon, void* field, Geom g, int n
         for (int comp = 0; comp < 12; comp++)
             e[comp] = r < n ? from_double<S>(canon[((int64_t)r * g.V + nsite) * 12 + comp]) : cmake<T>(0, 0);
 #pragma unroll
-        for (int j = 0; j < 12 / VW; j++) Store<S>::stv(field, vbase + j * SB, e + j * VW);
+        for (int j = 0; j < 12 / VW; j++) Store<S>::stv_rne(field, vbase + j * SB, e + j * VW);
     } else {
 #pragma unroll
         for (int j = 0; j < 12 / VW; j++) Store<S>::ldv(field, vbase + j * SB, e + j * VW);

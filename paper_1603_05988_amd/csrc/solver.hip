@@ -226,7 +226,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         if (total_iters >= prm->maxiter) break;
         for (int i = 0; i < nrhs; i++) {
             double itol = prm->inner_tol > 0 ? prm->inner_tol
-                                             : (inner == DHT_BF16 ? 3e-2 : (inner == DHT_FP32 ? 1e-5 : 0.0));
+                                             : (inner == DHT_BF16 ? 1e-2 : (inner == DHT_FP32 ? 1e-5 : 0.0));
             double need = sup[i] > 0 ? 0.25 * target2[i] / rn2[i] : 1.0;
             itarget[i] = std::max(itol * itol, need);
         }
