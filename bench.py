@@ -160,14 +160,17 @@ def main():
         have = set(ctx._tuned)
         for prec, nb in sorted(want - have):
             r = ctx.autotune_hop(prec, nb, reps=5)
-            log("autotune prec %d B %d: %s %.3f ms (default %.3f ms, %d shapes, %d rejected)"
+            log("autotune prec %d B %d: %s %s ms (default %s ms, %d shapes per class, %d rejected)"
                 % (prec, nb, r["best"], r["best_ms"], r["default_ms"], r["candidates"], r["rejected"]))
         if args.tune_cache:
             ctx.save_tuning(args.tune_cache)
-    shapes = {("fp64" if prec == L.FP64 else ("fp32" if prec == L.FP32 else "bf16")): ctx.hop_config(prec, B)
-              for prec in sorted({inner, L.FP64})}
-    for k_, v_ in shapes.items():
-        v_["form"] = L.HOP_FORMS[v_["form"]]
+    shapes = {}
+    for prec in sorted({inner, L.FP64}):
+        name = "fp64" if prec == L.FP64 else ("fp32" if prec == L.FP32 else "bf16")
+        for cls, cname in L.HOP_CLASSES.items():
+            v_ = ctx.hop_config(prec, B, cls)
+            v_["form"] = L.HOP_FORMS[v_["form"]]
+            shapes[name + "_" + cname] = v_
 
     # a plain 1 GiB device copy (untimed) so that hardware-counter runs of this
     # command carry their own calibration of FETCH_SIZE / WRITE_SIZE

@@ -305,9 +305,10 @@ int dht_nn_make_pairs(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, i
 
 /* ---- instrumentation ------------------------------------------------------ */
 
-/* Timing of the last dht_trace_batch / dht_solve, from HIP events on the
- * context stream, in milliseconds: [0] probes, [1] solve, [2] projection,
- * [3] quadratic forms, [4] whole call.  n must be >= 5. */
+/* Timing of the last dht_trace_batch / dht_solve, from HIP events, in
+ * milliseconds: [0] probes, [1] solve, [2] projection (on a second stream of
+ * the library's own, concurrent with the solve), [3] quadratic forms, [4]
+ * whole call.  n must be >= 5. */
 int dht_last_timings(dht_ctx* ctx, double* ms_host, int n);
 
 /* Per-kernel-class timing: when enabled, every launch of an instrumented
@@ -345,29 +346,36 @@ typedef struct dht_hop_config {
     int t_chunk;
 } dht_hop_config;
 
-/* Set the hopping-kernel shape used for (prec, nrhs) on this context; cfg =
- * NULL restores the built-in default.  Errors: DHT_ERR_INVALID_ARG for a shape
- * that does not fit the lattice or batch (nrhs: power of two <= 256). */
-int dht_hop_config_set(dht_ctx* ctx, int prec, int nrhs, const dht_hop_config* cfg);
-/* The shape in effect for (prec, nrhs) (t_chunk resolved). */
-int dht_hop_config_get(dht_ctx* ctx, int prec, int nrhs, dht_hop_config* out);
+/* Epilogue classes, tuned separately: DHT_HOP_PLAIN launches compute
+ * out = b Hop(in); DHT_HOP_FUSED launches also read an x-pay operand (and a
+ * second axpy operand or fused dot products), as in the Krylov solvers. */
+enum { DHT_HOP_PLAIN = 0, DHT_HOP_FUSED = 1 };
+
+/* Set the hopping-kernel shape used for (prec, nrhs, epilogue class) on this
+ * context; cfg = NULL restores the built-in default.  Errors:
+ * DHT_ERR_INVALID_ARG for a shape that does not fit the lattice or batch
+ * (nrhs: power of two <= 256) or a bad class. */
+int dht_hop_config_set(dht_ctx* ctx, int prec, int nrhs, int epilogue, const dht_hop_config* cfg);
+/* The shape in effect for (prec, nrhs, epilogue class) (t_chunk resolved). */
+int dht_hop_config_get(dht_ctx* ctx, int prec, int nrhs, int epilogue, dht_hop_config* out);
 
 typedef struct dht_tune_result {
-    dht_hop_config best;     /* fastest candidate that passed the parity check */
-    double best_ms;          /* its mean time per hop application */
-    double default_ms;       /* the built-in default's time */
-    int candidates;          /* shapes timed */
+    dht_hop_config best[2];  /* per epilogue class: fastest candidate that passed the parity check */
+    double best_ms[2];       /* its mean time per hop application */
+    double default_ms[2];    /* the built-in default's time */
+    int candidates;          /* shapes timed per class */
     int rejected;            /* shapes whose output differed from the default's beyond rounding */
     double max_rel_diff;     /* largest max|out - out_default| / max|out_default| among accepted shapes */
 } dht_tune_result;
 
-/* Autotuner: time every hopping-kernel shape valid for (prec, nrhs) on this
- * lattice (reps applications each, HIP events on the context stream, after
- * warm-up), check each output against the default shape's (relative max-norm
- * difference <= 1e-12 FP64, 1e-5 FP32, 1.6e-2 BF16, i.e. a few units in the last place of
- * the storage format), and install the fastest accepted shape for
- * (prec, nrhs) on the context.  Needs the gauge field; uses the context
- * workspace (three half fields of nrhs RHS). */
+/* Autotuner: for each epilogue class, time every hopping-kernel shape valid
+ * for (prec, nrhs) on this lattice (reps applications each, HIP events on the
+ * context stream, after warm-up; the fused class with an x-pay operand and the
+ * fused (out, x), (out, out) sums), check each output against the default
+ * shape's (relative max-norm difference <= 1e-12 FP64, 1e-5 FP32, 1.6e-2 BF16,
+ * i.e. a few units in the last place of the storage format), and install the
+ * fastest accepted shape per class on the context.  Needs the gauge field;
+ * uses the context workspace (four half fields of nrhs RHS). */
 int dht_autotune_hop(dht_ctx* ctx, int prec, int nrhs, int reps, dht_tune_result* out);
 
 #ifdef __cplusplus

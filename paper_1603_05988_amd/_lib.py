@@ -62,11 +62,13 @@ class HopConfig(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("best", HopConfig), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+    _fields_ = [("best", HopConfig * 2), ("best_ms", ctypes.c_double * 2), ("default_ms", ctypes.c_double * 2),
                 ("candidates", ctypes.c_int), ("rejected", ctypes.c_int), ("max_rel_diff", ctypes.c_double)]
 
 
 HOP_SITE, HOP_SITE_LDS, HOP_TMARCH = 0, 1, 2
+HOP_PLAIN, HOP_FUSED = 0, 1
+HOP_CLASSES = {HOP_PLAIN: "plain", HOP_FUSED: "fused"}
 HOP_FORMS = {HOP_SITE: "site", HOP_SITE_LDS: "site_lds", HOP_TMARCH: "tmarch"}
 
 
@@ -123,8 +125,8 @@ SIGNATURES = {
     "dht_nn_grad": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(ctypes.c_float), _dp]),
     "dht_nn_train": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _dp]),
     "dht_nn_make_pairs": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _i, _vp, _vp, _i, ctypes.POINTER(_i)]),
-    "dht_hop_config_set": (_i, [_vp, _i, _i, ctypes.POINTER(HopConfig)]),
-    "dht_hop_config_get": (_i, [_vp, _i, _i, ctypes.POINTER(HopConfig)]),
+    "dht_hop_config_set": (_i, [_vp, _i, _i, _i, ctypes.POINTER(HopConfig)]),
+    "dht_hop_config_get": (_i, [_vp, _i, _i, _i, ctypes.POINTER(HopConfig)]),
     "dht_autotune_hop": (_i, [_vp, _i, _i, _i, ctypes.POINTER(TuneResult)]),
 }
 
@@ -431,28 +433,34 @@ class Context:
         return R[:cnt.value], E[:cnt.value]
 
     # ---- launch-shape autotuning -------------------------------------------
-    def hop_config(self, prec: int, nrhs: int) -> dict:
+    def hop_config(self, prec: int, nrhs: int, epilogue: int = HOP_PLAIN) -> dict:
         h = HopConfig()
-        check(load().dht_hop_config_get(self.h, prec, nrhs, ctypes.byref(h)))
+        check(load().dht_hop_config_get(self.h, prec, nrhs, epilogue, ctypes.byref(h)))
         return {"form": h.form, "streaming_stores": h.streaming_stores, "t_chunk": h.t_chunk}
 
-    def set_hop_config(self, prec: int, nrhs: int, cfg: dict | None):
-        """Install a hopping-kernel shape for (prec, nrhs); None restores the default."""
-        if cfg is None:
-            check(load().dht_hop_config_set(self.h, prec, nrhs, None))
-            return
-        h = HopConfig(int(cfg["form"]), int(cfg.get("streaming_stores", 1)), int(cfg.get("t_chunk", 0)))
-        check(load().dht_hop_config_set(self.h, prec, nrhs, ctypes.byref(h)))
+    def set_hop_config(self, prec: int, nrhs: int, cfg: dict | None, epilogue: int | None = None):
+        """Install a hopping-kernel shape for (prec, nrhs) and one epilogue
+        class (both when epilogue is None); None restores the default."""
+        for cls in ((HOP_PLAIN, HOP_FUSED) if epilogue is None else (epilogue,)):
+            if cfg is None:
+                check(load().dht_hop_config_set(self.h, prec, nrhs, cls, None))
+                continue
+            h = HopConfig(int(cfg["form"]), int(cfg.get("streaming_stores", 1)), int(cfg.get("t_chunk", 0)))
+            check(load().dht_hop_config_set(self.h, prec, nrhs, cls, ctypes.byref(h)))
 
     def autotune_hop(self, prec: int, nrhs: int, reps: int = 10) -> dict:
-        """Time every valid hopping-kernel shape for (prec, nrhs), keep the
-        fastest one whose output matches the default's to rounding."""
+        """Time every valid hopping-kernel shape for (prec, nrhs), per epilogue
+        class, and keep the fastest one whose output matches the default's to
+        rounding."""
         r = TuneResult()
         check(load().dht_autotune_hop(self.h, prec, nrhs, reps, ctypes.byref(r)))
-        best = {"form": r.best.form, "streaming_stores": r.best.streaming_stores, "t_chunk": r.best.t_chunk}
-        out = {"prec": prec, "nrhs": nrhs, "best": best, "best_form": HOP_FORMS[r.best.form],
-               "best_ms": r.best_ms, "default_ms": r.default_ms, "candidates": r.candidates,
-               "rejected": r.rejected, "max_rel_diff": r.max_rel_diff}
+        best = {HOP_CLASSES[k]: {"form": r.best[k].form, "streaming_stores": r.best[k].streaming_stores,
+                                 "t_chunk": r.best[k].t_chunk} for k in (HOP_PLAIN, HOP_FUSED)}
+        out = {"prec": prec, "nrhs": nrhs, "best": best,
+               "best_form": {c: HOP_FORMS[b["form"]] for c, b in best.items()},
+               "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in (HOP_PLAIN, HOP_FUSED)},
+               "default_ms": {HOP_CLASSES[k]: r.default_ms[k] for k in (HOP_PLAIN, HOP_FUSED)},
+               "candidates": r.candidates, "rejected": r.rejected, "max_rel_diff": r.max_rel_diff}
         self._tuned[(prec, nrhs)] = out
         return out
 
@@ -475,7 +483,8 @@ class Context:
         n = 0
         for key, ent in tab.get("entries", {}).items():
             prec, nrhs = (int(v) for v in key.split(":"))
-            self.set_hop_config(prec, nrhs, ent["best"])
+            for cls, name in HOP_CLASSES.items():
+                self.set_hop_config(prec, nrhs, ent["best"][name], cls)
             self._tuned[(prec, nrhs)] = ent
             n += 1
         return n

@@ -227,6 +227,7 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
     const int64_t vstride = (int64_t)a.Vh << a.bshift;
     const int64_t v0 = ((int64_t)s << a.bshift) + r;
     const T cb = (T)a.cb, ca = (T)a.ca;
+    fence_acc(acc);   // the epilogue's operand loads stay below the stencil arithmetic
     Cx<T> xv[12];
     if (XPAY) load_spinor<S>(a.x, v0, vstride, xv);
 #pragma unroll
@@ -362,23 +363,38 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
 // t direction, and the x, y, z neighbours of a step all lie in one slice that
 // the step before has just brought into the caches.
 // ---------------------------------------------------------------------------
+// The pending backward t-hops live in LDS, [slot][6][lanes] per workgroup
+// (one lane's entries are HOP_THREADS apart: conflict-free), which keeps the
+// kernel's registers at the level of the site-parallel form.
+template <typename T>
+__device__ inline void wb_store(Cx<T>* wbs, const Cx<T>* w) {
+#pragma unroll
+    for (int i = 0; i < 6; i++) wbs[i * HOP_THREADS + threadIdx.x] = w[i];
+}
+template <typename T>
+__device__ inline void wb_load(const Cx<T>* wbs, Cx<T>* w) {
+#pragma unroll
+    for (int i = 0; i < 6; i++) w[i] = wbs[i * HOP_THREADS + threadIdx.x];
+}
+
 template <typename S, int SGN>
 __device__ inline void t_back(const HopArgs& a, int sin, int r, int64_t vstride, typename Store<S>::acc ph,
-                              Cx<typename Store<S>::acc>* wb) {
+                              Cx<typename Store<S>::acc>* wbs) {
     typedef typename Store<S>::acc T;
     constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
-    Cx<T> psi[12], h[6], u[9];
+    Cx<T> psi[12], h[6], u[9], wb[6];
     load_spinor<S>(a.in, ((int64_t)sin << a.bshift) + r, vstride, psi);
     project<3, SGN>(psi, h);
     load_link<S>(a.U, ((int64_t)(6 + 1 - a.out_parity) * a.Vh + sin) * NV, u);
     mul_link<true>(u, h, wb);
 #pragma unroll
     for (int i = 0; i < 6; i++) wb[i] = ph * wb[i];
+    wb_store(wbs, wb);
 }
 
 template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT>
 __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, int y, int z, int r, int V3, int yf,
-                               int yb, int zf, int zb, Cx<typename Store<S>::acc>* wb, Cx<double>& d0,
+                               int yb, int zf, int zb, Cx<typename Store<S>::acc>* wbs, Cx<double>& d0,
                                Cx<double>& d1) {
     typedef typename Store<S>::acc T;
     constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
@@ -402,7 +418,11 @@ __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, 
                        ((int64_t)(3 - p) * a.Vh + sy) * NV, acc);
     hop_dir<S, 2, DAG>(a, s + zf, sz, r, false, false, a.U, ((int64_t)(4 + p) * a.Vh + s) * NV, a.U,
                        ((int64_t)(5 - p) * a.Vh + sz) * NV, acc);
-    reconstruct<3, -SF>(acc, wb, T(1));
+    {
+        Cx<T> wb[6];
+        wb_load(wbs, wb);
+        reconstruct<3, -SF>(acc, wb, T(1));
+    }
     {
         const int sn = (t + 1 == a.Lt ? 0 : t + 1) * V3 + s3;
         Cx<T> psi[12], h[6], u[9], w[6];
@@ -415,16 +435,18 @@ __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, 
             fence_acc(acc);
             project<3, -SF>(psi, h);
             load_link<S>(a.U, ((int64_t)(6 + 1 - p) * a.Vh + sn) * NV, u);
-            mul_link<true>(u, h, wb);
+            mul_link<true>(u, h, w);
+            wb_store(wbs, w);
         }
     }
     hop_epilogue<S, G5OUT, XPAY, DOT>(a, s, r, acc, d0, d1);
-    fence_n<6>(wb);   // the next step's loads stay below this step's arithmetic
+    fence_acc(acc);   // the next step's loads stay below this step's arithmetic
 }
 
 template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT>
 __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
+    extern __shared__ uint4 hop_lds[];   // [2][6][HOP_THREADS] Cx<T>
     constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
     constexpr int SF = DAG ? -1 : 1;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -445,7 +467,9 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
         const int zf = z == a.Lz - 1 ? -(a.Lz - 1) * sz : sz, zb = z == 0 ? (a.Lz - 1) * sz : -sz;
         const int64_t vstride = (int64_t)a.Vh << a.bshift;
         const int t0 = chunk * a.tc, t1 = t0 + a.tc;
-        Cx<T> wb0[6], wb1[6];   // pending backward t-hops of the even / odd steps of the chunk
+        // pending backward t-hops of the even / odd steps of the chunk
+        Cx<T>* wb0 = (Cx<T>*)hop_lds;
+        Cx<T>* wb1 = wb0 + 6 * HOP_THREADS;
         t_back<S, -SF>(a, (t0 == 0 ? a.Lt - 1 : t0 - 1) * V3 + s3, r, vstride,
                        (a.antiperiodic && t0 == 0) ? T(-1) : T(1), wb0);
         t_back<S, -SF>(a, t0 * V3 + s3, r, vstride, T(1), wb1);
@@ -499,11 +523,11 @@ HopConfig hop_default_config(const dht_ctx* c, int prec, int nrhs) {
     return h;
 }
 
-HopConfig hop_config(const dht_ctx* c, int prec, int nrhs) {
+HopConfig hop_config(const dht_ctx* c, int prec, int nrhs, int cls) {
     HopConfig h;
     const int b = log2_batch(nrhs);
     if (c->hop_force) h = c->hop_forced;
-    else if (b >= 0 && prec >= 0 && prec < 3 && c->hop_cfg[prec][b].form >= 0) h = c->hop_cfg[prec][b];
+    else if (b >= 0 && prec >= 0 && prec < 3 && c->hop_cfg[prec][b][cls].form >= 0) h = c->hop_cfg[prec][b][cls];
     else h = hop_default_config(c, prec, nrhs);
     if (h.tc == 0) h.tc = auto_chunk(c, nrhs);
     return h;
@@ -543,7 +567,8 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     a.da = dot ? dot->a : nullptr;
     a.partial = dot ? dot->partial : nullptr;
     if (kind == HOPDOT_OUT_X && !x) return set_error(DHT_ERR_INVALID_ARG, "fused (out, x) needs an xpay source");
-    const HopConfig cfg = hop_config(c, prec_of<S>(), nrhs);
+    const int cls = (x || dot) ? HOP_FUSED : HOP_PLAIN;
+    const HopConfig cfg = hop_config(c, prec_of<S>(), nrhs, cls);
     a.tc = cfg.tc;
     a.nchunk = a.Lt / cfg.tc;
     a.nt = cfg.nt;
@@ -553,13 +578,14 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
                        ? (int)((c->g.Vh / a.Lt * (int64_t)a.nchunk * nrhs + HOP_THREADS - 1) / HOP_THREADS)
                        : hop_blocks(c, nrhs);
     const size_t lds = mode == DHT_HOP_SITE_LDS ? (size_t)8 * ns * ((9 + Store<S>::VW - 1) / Store<S>::VW) * 16 : 0;
+    const size_t tm_lds = (size_t)2 * 6 * HOP_THREADS * sizeof(Cx<typename Store<S>::acc>);
     if (dot) dot->nblocks = nb;
     dim3 grid(nb), block(HOP_THREADS);
     bool xp = x != nullptr;
 #define DHT_HOP_CASE(D_, G_, X_, K_)                                                                         \
     if (dagger == D_ && g5out == G_ && xp == X_ && kind == K_) {                                             \
         if (mode == DHT_HOP_TMARCH)                                                                          \
-            hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_>), grid, block, 0, c->stream, a);            \
+            hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_>), grid, block, tm_lds, c->stream, a);       \
         else if (mode == DHT_HOP_SITE_LDS)                                                                   \
             hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_, true>), grid, block, lds, c->stream, a);       \
         else                                                                                                 \

@@ -293,7 +293,7 @@ struct dht_ctx {
     dht::NNState nn;
     // hopping-kernel shape per (precision, log2 batch); hop_force overrides
     // every entry while the autotuner times a candidate
-    dht::HopConfig hop_cfg[3][9];
+    dht::HopConfig hop_cfg[3][9][2];   // [precision][log2 batch][epilogue class]
     bool hop_force = false;
     dht::HopConfig hop_forced;
     // workspace slots (grow-only)
@@ -302,6 +302,10 @@ struct dht_ctx {
     double timings[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[6];
     bool events = false;
+    // second stream (default priority) on which the deflation projection of
+    // a batch runs concurrently with its solve; created on first use
+    hipStream_t side = nullptr;
+    hipEvent_t side_ev[4];
 };
 
 namespace dht {
@@ -377,7 +381,9 @@ int hop_blocks(const dht_ctx* c, int nrhs);   // workgroups of one hop launch
 constexpr int HOP_LANES = 256;   // lanes per hop workgroup
 // the shape a hop launch for (prec, nrhs) uses (t chunk resolved), and a check
 // that a shape fits the lattice and batch
-HopConfig hop_config(const dht_ctx* c, int prec, int nrhs);
+// epilogue classes: plain (out = b Hop(in)) and fused (x-pay, second operand or a fused dot)
+enum { HOP_PLAIN = 0, HOP_FUSED = 1 };
+HopConfig hop_config(const dht_ctx* c, int prec, int nrhs, int cls);
 HopConfig hop_default_config(const dht_ctx* c, int prec, int nrhs);
 int hop_config_check(const dht_ctx* c, int nrhs, const HopConfig& h);
 int apply_full(dht_ctx* c, int op, int prec, const void* in, void* out, int nrhs);   // full-lattice D, D^H, g5, Q

@@ -4,12 +4,13 @@
 // stencil of Section 1) in a different order, so the candidates are checked
 // against the default form's output to rounding before they are timed; the
 // fastest accepted shape is installed on the context for its (precision,
-// batch) pair and used by every later hop launch.
+// batch, epilogue class) and used by every later hop launch of that kind.
 #include <algorithm>
 #include <cmath>
 #include <vector>
 
 #include "internal.h"
+#include "solver.h"
 
 namespace dht {
 
@@ -68,12 +69,30 @@ static int rel_maxdiff(dht_ctx* c, int prec, const void* a, const void* b, int n
     return DHT_OK;
 }
 
-// mean time of `reps` hop applications (out parity 0) in the shape in effect
-static int time_hop(dht_ctx* c, int prec, const void* in, void* out, int nrhs, int reps, hipEvent_t e0, hipEvent_t e1,
+// one hop of the class being tuned: plain out = Hop(in); fused out = 0.5 x +
+// Hop(in) with the (out, x), (out, out) sums of BiCGStab's second product
+struct TuneLaunch {
+    int cls;
+    const void* in;
+    void* out;
+    const void* x;
+    Cx<double>* partial;
+};
+
+static int tune_hop(dht_ctx* c, int prec, int nrhs, const TuneLaunch& L) {
+    if (L.cls == HOP_PLAIN) return hop(c, prec, 0, L.in, L.out, nullptr, 0.0, 1.0, nrhs, false, false);
+    HopDot d;
+    d.kind = HOPDOT_OUT_X;
+    d.partial = L.partial;
+    return hop(c, prec, 0, L.in, L.out, L.x, 0.5, 1.0, nrhs, false, false, &d);
+}
+
+// mean time of `reps` launches in the shape in effect
+static int time_hop(dht_ctx* c, int prec, int nrhs, const TuneLaunch& L, int reps, hipEvent_t e0, hipEvent_t e1,
                     double* ms) {
-    for (int i = 0; i < 2; i++) DHT_TRY(hop(c, prec, 0, in, out, nullptr, 0.0, 1.0, nrhs, false, false));
+    for (int i = 0; i < 2; i++) DHT_TRY(tune_hop(c, prec, nrhs, L));
     DHT_HIP(hipEventRecord(e0, c->stream));
-    for (int i = 0; i < reps; i++) DHT_TRY(hop(c, prec, 0, in, out, nullptr, 0.0, 1.0, nrhs, false, false));
+    for (int i = 0; i < reps; i++) DHT_TRY(tune_hop(c, prec, nrhs, L));
     DHT_HIP(hipEventRecord(e1, c->stream));
     DHT_HIP(hipEventSynchronize(e1));
     float f = 0.f;
@@ -93,23 +112,17 @@ static int log2_pow2(int n) {
 static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* res, hipEvent_t e0, hipEvent_t e1) {
     const int b = log2_pow2(nrhs);
     const size_t full = full_elems(c, nrhs) * elem_bytes(prec), half = full / 2;
-    void *fi, *fo, *fr, *pp;
+    void *fi, *fo, *fr, *pp, *part;
     DHT_TRY(ws_get(c, WS_PACK_IN, full, &fi));
     DHT_TRY(ws_get(c, WS_PACK_OUT, half, &fo));
     DHT_TRY(ws_get(c, WS_TUNE_REF, half, &fr));
     DHT_TRY(ws_get(c, WS_TUNE_RED, sizeof(Cx<double>) * TUNE_BLOCKS, &pp));
-    Cx<double>* part = (Cx<double>*)pp;
+    DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
+    Cx<double>* red = (Cx<double>*)pp;
     dht_probe_spec sp = {2718281u, 0u, 0};
     DHT_TRY(probes_gen(c, &sp, 0, nrhs, nrhs, fi, prec, nullptr, nullptr));
-    const void* in = (const char*)fi + half;
-
-    // reference: the built-in default shape
-    c->hop_force = true;
-    c->hop_forced = hop_default_config(c, prec, nrhs);
-    const HopConfig def = c->hop_forced;
-    DHT_TRY(hop(c, prec, 0, in, fr, nullptr, 0.0, 1.0, nrhs, false, false));
-    double def_ms = 0.0;
-    DHT_TRY(time_hop(c, prec, in, fo, nrhs, reps, e0, e1, &def_ms));
+    // in = the odd half of the probe field, x = its even half
+    TuneLaunch L{HOP_PLAIN, (const char*)fi + half, fo, fi, (Cx<double>*)part};
 
     std::vector<HopConfig> cand;
     for (int nt = 0; nt < 2; nt++) {
@@ -128,34 +141,47 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
                 cand.push_back(h);
             }
     }
-    HopConfig best = def;
-    double best_ms = def_ms, worst_ok = 0.0;
     int rejected = 0;
-    for (const HopConfig& h : cand) {
-        c->hop_forced = h;
-        DHT_TRY(hop(c, prec, 0, in, fo, nullptr, 0.0, 1.0, nrhs, false, false));
-        double rd = 0.0;
-        DHT_TRY(rel_maxdiff(c, prec, fo, fr, nrhs, part, &rd));
-        if (!(rd <= tune_tolerance(prec))) {
-            rejected++;
-            continue;
+    double worst_ok = 0.0;
+    for (int cls = 0; cls < 2; cls++) {
+        L.cls = cls;
+        // reference: the built-in default shape
+        c->hop_force = true;
+        c->hop_forced = hop_default_config(c, prec, nrhs);
+        const HopConfig def = c->hop_forced;
+        L.out = fr;
+        DHT_TRY(tune_hop(c, prec, nrhs, L));
+        L.out = fo;
+        double def_ms = 0.0;
+        DHT_TRY(time_hop(c, prec, nrhs, L, reps, e0, e1, &def_ms));
+        HopConfig best = def;
+        double best_ms = def_ms;
+        for (const HopConfig& h : cand) {
+            c->hop_forced = h;
+            DHT_TRY(tune_hop(c, prec, nrhs, L));
+            double rd = 0.0;
+            DHT_TRY(rel_maxdiff(c, prec, fo, fr, nrhs, red, &rd));
+            if (!(rd <= tune_tolerance(prec))) {
+                rejected++;
+                continue;
+            }
+            worst_ok = std::max(worst_ok, rd);
+            double ms = 0.0;
+            DHT_TRY(time_hop(c, prec, nrhs, L, reps, e0, e1, &ms));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = h;
+            }
         }
-        worst_ok = std::max(worst_ok, rd);
-        double ms = 0.0;
-        DHT_TRY(time_hop(c, prec, in, fo, nrhs, reps, e0, e1, &ms));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = h;
-        }
+        c->hop_force = false;
+        if (best.form == DHT_HOP_TMARCH && best.tc == 0) best.tc = hop_config(c, prec, nrhs, cls).tc;
+        c->hop_cfg[prec][b][cls] = best;
+        res->best[cls].form = best.form;
+        res->best[cls].streaming_stores = best.nt;
+        res->best[cls].t_chunk = best.form == DHT_HOP_TMARCH ? best.tc : 0;
+        res->best_ms[cls] = best_ms;
+        res->default_ms[cls] = def_ms;
     }
-    c->hop_force = false;
-    if (best.form == DHT_HOP_TMARCH && best.tc == 0) best.tc = hop_config(c, prec, nrhs).tc;
-    c->hop_cfg[prec][b] = best;
-    res->best.form = best.form;
-    res->best.streaming_stores = best.nt;
-    res->best.t_chunk = best.form == DHT_HOP_TMARCH ? best.tc : 0;
-    res->best_ms = best_ms;
-    res->default_ms = def_ms;
     res->candidates = (int)cand.size();
     res->rejected = rejected;
     res->max_rel_diff = worst_ok;
@@ -168,13 +194,14 @@ using namespace dht;
 
 extern "C" {
 
-int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, const dht_hop_config* cfg) {
+int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, int epilogue, const dht_hop_config* cfg) {
     if (!c) return set_error(DHT_ERR_INVALID_ARG, "null context");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    if (epilogue != DHT_HOP_PLAIN && epilogue != DHT_HOP_FUSED) return set_error(DHT_ERR_INVALID_ARG, "bad epilogue class");
     const int b = log2_pow2(nrhs);
     if (b < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
     if (!cfg) {
-        c->hop_cfg[prec][b] = HopConfig();
+        c->hop_cfg[prec][b][epilogue] = HopConfig();
         return DHT_OK;
     }
     HopConfig h;
@@ -182,15 +209,16 @@ int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, const dht_hop_config* cfg
     h.nt = cfg->streaming_stores;
     h.tc = cfg->form == DHT_HOP_TMARCH ? cfg->t_chunk : 0;
     DHT_TRY(hop_config_check(c, nrhs, h));
-    c->hop_cfg[prec][b] = h;
+    c->hop_cfg[prec][b][epilogue] = h;
     return DHT_OK;
 }
 
-int dht_hop_config_get(dht_ctx* c, int prec, int nrhs, dht_hop_config* out) {
+int dht_hop_config_get(dht_ctx* c, int prec, int nrhs, int epilogue, dht_hop_config* out) {
     if (!c || !out) return set_error(DHT_ERR_INVALID_ARG, "null argument");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    if (epilogue != DHT_HOP_PLAIN && epilogue != DHT_HOP_FUSED) return set_error(DHT_ERR_INVALID_ARG, "bad epilogue class");
     if (log2_pow2(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
-    HopConfig h = hop_config(c, prec, nrhs);
+    HopConfig h = hop_config(c, prec, nrhs, epilogue);
     out->form = h.form;
     out->streaming_stores = h.nt;
     out->t_chunk = h.form == DHT_HOP_TMARCH ? h.tc : 0;

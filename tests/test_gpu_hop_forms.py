@@ -64,11 +64,12 @@ def test_every_form_matches_dense(L, nrhs):
     refs = {Lb.OP_D: (D @ Xv.T).T, Lb.OP_DDAG: (D.conj().T @ Xv.T).T, Lb.OP_Q: (g5[:, None] * D @ Xv.T).T}
     for prec in (0, 1, 2):
         for cfg in forms(L, nrhs):
-            ctx.set_hop_config(prec, nrhs, cfg)
-            got = ctx.hop_config(prec, nrhs)
-            assert got["form"] == cfg["form"] and got["streaming_stores"] == cfg["streaming_stores"]
-            if cfg["form"] == 2:
-                assert got["t_chunk"] == cfg["t_chunk"]
+            ctx.set_hop_config(prec, nrhs, cfg)     # both epilogue classes
+            for cls in (Lb.HOP_PLAIN, Lb.HOP_FUSED):
+                got = ctx.hop_config(prec, nrhs, cls)
+                assert got["form"] == cfg["form"] and got["streaming_stores"] == cfg["streaming_stores"]
+                if cfg["form"] == 2:
+                    assert got["t_chunk"] == cfg["t_chunk"]
             for op, ref in refs.items():
                 Y = ctx.apply(cuda(X), op, prec).cpu().numpy().reshape(nrhs, -1)
                 e = err_of(prec, Y, ref)
@@ -136,8 +137,9 @@ def test_autotune_c2(tmp_path):
         res[prec] = r
         assert r["rejected"] == 0 and r["candidates"] == len(forms(w.L, 16)), r
         assert r["max_rel_diff"] <= {0: 1e-12, 1: 1e-5, 2: 1.6e-2}[prec], r
-        assert 0 < r["best_ms"] <= r["default_ms"] * (1 + 1e-9), r
-        assert ctx.hop_config(prec, 16)["form"] == r["best"]["form"]
+        for cls, name in ((Lb.HOP_PLAIN, "plain"), (Lb.HOP_FUSED, "fused")):
+            assert 0 < r["best_ms"][name] <= r["default_ms"][name] * (1 + 1e-9), r
+            assert ctx.hop_config(prec, 16, cls) == r["best"][name]
     X = random_spinors(w.L, 16, 21)
     Y = ctx.apply(cuda(X), 0, 0).cpu().numpy()
     for rr in (0, 15):
@@ -150,7 +152,8 @@ def test_autotune_c2(tmp_path):
     ctx2 = Lb.Context(w.L, w.mass)
     assert ctx2.load_tuning(str(path)) == 3
     for prec in (0, 1, 2):
-        assert ctx2.hop_config(prec, 16) == res[prec]["best"]
+        assert ctx2.hop_config(prec, 16, Lb.HOP_PLAIN) == res[prec]["best"]["plain"]
+        assert ctx2.hop_config(prec, 16, Lb.HOP_FUSED) == res[prec]["best"]["fused"]
     other = Lb.Context((4, 4, 4, 4), -0.2)
     assert other.load_tuning(str(path)) == 0     # measured on another lattice: ignored
     other.close()
