@@ -207,6 +207,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     int outer = 0, total_iters = 0;
     const int start_inner = inner;
     bool last_bad = false;
+    bool have_full = false;        // the loop ended on a verified full-lattice residual
+    std::vector<double> full2;     // its squared norms
     void* e;
     void* rlo;
     DHT_TRY(norms2(c, r_e, nh, nrhs, rn2));
@@ -257,25 +259,56 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         total_iters += std::max(maxit, 1);
         DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
         DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nrhs));
-        // FP64 true residual of the Schur system, r = bhat - (a x - Hop_eo Hop_oe x / (4a)),
-        // and its norms, in the second hop's epilogue
-        DHT_TRY(hop(c, DHT_FP64, 1, X_e, tmp_o, nullptr, 0.0, 1.0, nrhs, false, false));
-        DHT_TRY(residual_hop(c, 0, tmp_o, r_e, X_e, -a, 1.0 / (4.0 * a), bhat, nrhs, 0, rn2));
+        // When the inner solver's own residual says this correction finishes
+        // every RHS, go straight to the full-lattice check: its even residual
+        // z_e - a x_e + Hop_eo x_o / 2 is the Schur residual (x_o reconstructed
+        // from x_e), so a wrong guess costs one hop (x_o) and the loop continues
+        // from it, while a right one saves the two hops of the Schur residual.
+        bool predict = true;
+        for (int i = 0; i < nrhs; i++)
+            if (sup[i] > 0 && !(rn2[i] * br.rnorm2[i] <= target2[i])) predict = false;
+        if (predict) {
+            DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false));
+            std::vector<double> ro2;
+            DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2));
+            DHT_TRY(residual_hop(c, 1, X_e, tmp_o, X_o, -a, 0.5, Z_o, nrhs, 1, ro2));
+            bool done = true;
+            full2.assign(nrhs, 0.0);
+            for (int i = 0; i < nrhs; i++) {
+                full2[i] = rn2[i] + ro2[i];
+                if (zn2[i] > 0 && !(full2[i] <= prm->tol * prm->tol * zn2[i])) done = false;
+            }
+            if (done) {
+                have_full = true;
+                outer++;
+                break;
+            }
+        } else {
+            // FP64 true residual of the Schur system, r = bhat - (a x - Hop_eo Hop_oe x / (4a)),
+            // and its norms, in the second hop's epilogue
+            DHT_TRY(hop(c, DHT_FP64, 1, X_e, tmp_o, nullptr, 0.0, 1.0, nrhs, false, false));
+            DHT_TRY(residual_hop(c, 0, tmp_o, r_e, X_e, -a, 1.0 / (4.0 * a), bhat, nrhs, 0, rn2));
+        }
         if (bad && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
         last_bad = bad;
         for (int i = 0; i < nrhs; i++)
             if (inner != start_inner && rn2[i] > target2[i])
                 escalated[i] = inner == DHT_FP32 ? DHT_STATUS_FALLBACK_FP32 : DHT_STATUS_FALLBACK_FP64;
     }
-    // odd sites and the FP64 full-lattice true residual
-    DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false));
-    // r_p = z_p - (a x_p - Hop_{p <- 1-p} x / 2) per parity, norms fused
-    void* full;
-    DHT_TRY(ws_get(c, WS_XF, 2 * bh, &full));
-    std::vector<double> fr2, fr2o;
-    DHT_TRY(residual_hop(c, 0, X_o, full, X_e, -a, 0.5, Z_e, nrhs, 0, fr2));
-    DHT_TRY(residual_hop(c, 1, X_e, (char*)full + bh, X_o, -a, 0.5, Z_o, nrhs, 1, fr2o));
-    for (int i = 0; i < nrhs; i++) fr2[i] += fr2o[i];
+    std::vector<double> fr2;
+    if (have_full) {
+        fr2 = full2;
+    } else {
+        // odd sites and the FP64 full-lattice true residual
+        DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false));
+        // r_p = z_p - (a x_p - Hop_{p <- 1-p} x / 2) per parity, norms fused
+        void* full;
+        DHT_TRY(ws_get(c, WS_XF, 2 * bh, &full));
+        std::vector<double> fr2o;
+        DHT_TRY(residual_hop(c, 0, X_o, full, X_e, -a, 0.5, Z_e, nrhs, 0, fr2));
+        DHT_TRY(residual_hop(c, 1, X_e, (char*)full + bh, X_o, -a, 0.5, Z_o, nrhs, 1, fr2o));
+        for (int i = 0; i < nrhs; i++) fr2[i] += fr2o[i];
+    }
     bool all_ok = true;
     for (int i = 0; i < nrhs; i++) {
         double rr = zn2[i] > 0 ? sqrt(fr2[i] / zn2[i]) : 0.0;
