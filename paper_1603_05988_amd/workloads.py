@@ -96,3 +96,40 @@ def random_gauge_transform(L, seed: int) -> np.ndarray:
     d = np.diagonal(r, axis1=-2, axis2=-1)
     q = q * (d / np.abs(d))[:, None, :]
     return q.reshape(Lt, Lz, Ly, Lx, 3, 3)
+
+
+def _mix32(x, xp):
+    """A 32-bit integer mixer (xor-shift / multiply; Wellons' "lowbias32"
+    constants) on non-negative int64 arrays of numpy or torch, kept to 32 bits."""
+    m = 0xFFFFFFFF
+    x = x & m
+    x = x ^ (x >> 16)
+    x = (x * 0x7FEB352D) & m
+    x = x ^ (x >> 15)
+    x = (x * 0x846CA68B) & m
+    x = x ^ (x >> 16)
+    return x
+
+
+def hashed_basis(cols, N: int, seed: int, xp=np, device=None):
+    """Synthetic deflation-basis columns with entries (+-1 +- i) * 2^-13, the
+    signs hashed from (seed, column, index): exact in BF16 and in every FP32
+    partial sum of their products with Z4 probes, so sampled projection
+    coefficients can be checked exactly.  cols: column indices; returns a
+    complex128 array [len(cols)][N] (numpy, or torch on `device`)."""
+    out = []
+    for c in cols:
+        if xp is np:
+            n = np.arange(N, dtype=np.int64)
+            key = int(_mix32(np.int64(seed * 1000003 + int(c)), np))
+        else:
+            n = xp.arange(N, dtype=xp.int64, device=device)
+            key = int(_mix32(np.int64(seed * 1000003 + int(c)), np))
+        h = _mix32(n ^ key, xp)
+        re = 1.0 - 2.0 * (h & 1)
+        im = 1.0 - 2.0 * ((h >> 1) & 1)
+        if xp is np:
+            out.append((re + 1j * im) * 2.0 ** -13)
+        else:
+            out.append(xp.complex(re.double(), im.double()) * 2.0 ** -13)
+    return np.stack(out) if xp is np else xp.stack(out)

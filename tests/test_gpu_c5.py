@@ -1,0 +1,98 @@
+"""Parity at the full 32^3x64 size (N = 25,165,824), in the launch configuration
+bench.py times (autotuned hop shapes, batches of 16 hierarchical probes, BF16
+inner storage with FP64 defect correction, k = 1000 BF16 deflation basis),
+on outputs the oracle can compute one by one or on properties that hold at
+any size:
+
+- gamma5-hermiticity of the FP64 operator, <phi, D psi> = <D^H phi, psi>,
+  on two random fields (relative 1e-12);
+- the true relative residual ||z - D x|| / ||z|| of two sampled solutions of
+  a 16-probe batch, recomputed by the oracle's C stencil from the oracle's own
+  probes (<= 1e-8, the solve tolerance);
+- bit-exact projection coefficients W^H z and W^H g5 z for sampled
+  (column, probe) pairs: the basis entries are (+-1 +- i) 2^-13, exact in BF16,
+  and every partial sum of their products with Z4 probes is exact in FP32 and
+  FP64, so the MFMA path must reproduce the oracle's sums exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import lattice, rng, stencil
+from paper_1603_05988_amd.workloads import WORKLOADS, gauge_links, hashed_basis, random_spinors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W5 = WORKLOADS["c5"]
+
+
+def _lib():
+    from paper_1603_05988_amd import _lib as L
+    return L
+
+
+@pytest.fixture(scope="module")
+def c5():
+    Lb = _lib()
+    U = gauge_links(W5.L, W5.eps, W5.seed)
+    ctx = Lb.Context(W5.L, W5.mass)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    for prec in (Lb.FP64, Lb.BF16):   # the shapes bench.py times
+        ctx.autotune_hop(prec, W5.batch, reps=3)
+    yield U, ctx
+    ctx.close()
+
+
+def test_c5_gamma5_hermiticity(c5):
+    U, ctx = c5
+    Lb = _lib()
+    X = random_spinors(W5.L, 2, 17)
+    phi = torch.from_numpy(X[0:1]).cuda()
+    psi = torch.from_numpy(X[1:2]).cuda()
+    Dpsi = ctx.apply(psi, Lb.OP_D, Lb.FP64)
+    Dhphi = ctx.apply(phi, Lb.OP_DDAG, Lb.FP64)
+    a = torch.vdot(phi.flatten(), Dpsi.flatten()).item()
+    b = torch.vdot(Dhphi.flatten(), psi.flatten()).item()
+    assert abs(a - b) <= 1e-12 * abs(a), (a, b)
+
+
+def test_c5_mixed_solve_true_residual_by_oracle(c5):
+    U, ctx = c5
+    Lb = _lib()
+    B = W5.batch
+    Z = ctx.make_probes(W5.seed, 0, W5.hp, 0, B)
+    prm = ctx.params(Lb.SOLVER_DC_BICGSTAB, inner=Lb.BF16, tol=W5.tol, maxiter=5000)
+    X, stats, rc = ctx.solve(Z, prm)
+    assert all(s["true_resid"] <= W5.tol for s in stats), stats
+    del Z
+    for r in (0, B - 1):
+        z = rng.probe(W5.L, W5.seed, 0, W5.hp, r)
+        x = X[r].cpu().numpy().ravel()
+        res = z - stencil.apply_D(U, W5.L, W5.mass, x)
+        rel = np.linalg.norm(res) / np.linalg.norm(z)
+        assert rel <= W5.tol, (r, rel, stats[r])
+        assert abs(rel - stats[r]["true_resid"]) <= 1e-3 * W5.tol + 1e-3 * rel
+
+
+def test_c5_projection_sampled_exact(c5):
+    U, ctx = c5
+    Lb = _lib()
+    k, B, N = W5.k, W5.batch, W5.N
+    ctx.begin_deflation(k, Lb.BF16)
+    for j in range(0, k, 32):
+        cols = list(range(j, min(k, j + 32)))
+        Wb = hashed_basis(cols, N, 11, xp=torch, device="cuda")
+        ctx.set_deflation_columns(j, Wb)
+        del Wb
+    torch.cuda.empty_cache()
+    ctx.finalize_deflation(diagonal=True)
+    c1, c2 = ctx.project_probes(W5.seed, 0, W5.hp, 0, B)
+    g5 = lattice.gamma5_full(W5.V)
+    for r in (0, 7, B - 1):
+        z = rng.probe(W5.L, W5.seed, 0, W5.hp, r)
+        for i in (0, 517, k - 1):
+            w = hashed_basis([i], N, 11)[0]
+            e1 = np.vdot(w, z)
+            e2 = np.vdot(w, g5 * z)
+            assert c1[i, r] == e1 and c2[i, r] == e2, (i, r, c1[i, r], e1, c2[i, r], e2)
+    ctx.clear_deflation()
