@@ -263,6 +263,14 @@ int dht_trace_batch(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int
                     const dht_solver_params* prm, dht_record* records, double* coef_host);
 int dht_estimate_get(dht_ctx* ctx, dht_estimate* est);
 int dht_estimate_reset(dht_ctx* ctx);
+/* Checkpoint / resume of the running estimates (Algorithm 1 accumulates over
+ * probes; a long run can be split across processes).  save writes a small text
+ * file at `path` (exact round trip of the moments); load restores them into a
+ * context of the same lattice and mass, and of the same deflation space when
+ * one is set (T_D must agree to 1e-12 relative).  Errors: DHT_ERR_INVALID_ARG
+ * for an unreadable or foreign file, DHT_ERR_STATE for a mismatched context. */
+int dht_state_save(dht_ctx* ctx, const char* path);
+int dht_state_load(dht_ctx* ctx, const char* path);
 
 /* ---- learned preconditioner ----------------------------------------------- */
 /* A 3-layer 4D convolutional network (3^4 taps, 24 -> 48 -> 48 -> 24 real
@@ -377,6 +385,11 @@ typedef struct dht_tune_result {
  * fastest accepted shape per class on the context.  Needs the gauge field;
  * uses the context workspace (four half fields of nrhs RHS). */
 int dht_autotune_hop(dht_ctx* ctx, int prec, int nrhs, int reps, dht_tune_result* out);
+/* The autotuner with a cache file: if `cache_path` (may be NULL) holds shapes
+ * for this lattice, prec and nrhs they are installed without timing
+ * (out->candidates = 0); otherwise dht_autotune_hop runs and its shapes are
+ * appended to the file (one text line per epilogue class). */
+int dht_autotune(dht_ctx* ctx, int prec, int nrhs, int reps, const char* cache_path, dht_tune_result* out);
 
 #ifdef __cplusplus
 }

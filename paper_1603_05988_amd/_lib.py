@@ -128,6 +128,9 @@ SIGNATURES = {
     "dht_hop_config_set": (_i, [_vp, _i, _i, _i, ctypes.POINTER(HopConfig)]),
     "dht_hop_config_get": (_i, [_vp, _i, _i, _i, ctypes.POINTER(HopConfig)]),
     "dht_autotune_hop": (_i, [_vp, _i, _i, _i, ctypes.POINTER(TuneResult)]),
+    "dht_autotune": (_i, [_vp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(TuneResult)]),
+    "dht_state_save": (_i, [_vp, ctypes.c_char_p]),
+    "dht_state_load": (_i, [_vp, ctypes.c_char_p]),
 }
 
 SOLVER_DC_FGMRES = 3
@@ -463,6 +466,26 @@ class Context:
                "candidates": r.candidates, "rejected": r.rejected, "max_rel_diff": r.max_rel_diff}
         self._tuned[(prec, nrhs)] = out
         return out
+
+    def autotune(self, prec: int, nrhs: int, reps: int = 10, cache_path: str | None = None) -> dict:
+        """The library's autotuner with its text cache file (shapes reused when
+        the file holds this lattice, prec and nrhs)."""
+        r = TuneResult()
+        cp = cache_path.encode() if cache_path else None
+        check(load().dht_autotune(self.h, prec, nrhs, reps, cp, ctypes.byref(r)))
+        return {"best": {HOP_CLASSES[k]: {"form": r.best[k].form, "streaming_stores": r.best[k].streaming_stores,
+                                          "t_chunk": r.best[k].t_chunk} for k in (HOP_PLAIN, HOP_FUSED)},
+                "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in (HOP_PLAIN, HOP_FUSED)},
+                "candidates": r.candidates, "rejected": r.rejected}
+
+    def save_state(self, path: str):
+        """Checkpoint the running estimates."""
+        check(load().dht_state_save(self.h, path.encode()))
+
+    def load_state(self, path: str):
+        """Resume the running estimates from a checkpoint of the same lattice,
+        operator and deflation space."""
+        check(load().dht_state_load(self.h, path.encode()))
 
     def tuning_table(self) -> dict:
         """The shapes installed by autotune_hop / load_tuning, keyed

@@ -5,9 +5,11 @@
 // negative return codes with a thread-local message; no C++ exception leaves
 // this file.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 
 #include "solver.h"
@@ -581,6 +583,59 @@ int dht_estimate_reset(dht_ctx* c) {
     if (!c) return set_error(DHT_ERR_INVALID_ARG, "null context");
     c->est_q = Welford();
     c->est_qd = Welford();
+    return DHT_OK;
+}
+
+int dht_state_save(dht_ctx* c, const char* path) {
+    if (!c || !path) return set_error(DHT_ERR_INVALID_ARG, "null argument");
+    FILE* f = fopen(path, "w");
+    if (!f) return set_error(DHT_ERR_INVALID_ARG, std::string("cannot write ") + path);
+    fprintf(f, "dhtrace-estimate 1\n");
+    fprintf(f, "lattice %d %d %d %d %d\n", c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3], c->g.antiperiodic);
+    fprintf(f, "mass %.17g\n", c->mass);
+    fprintf(f, "deflation %d %.17g %.17g\n", c->defl_ready ? c->k : 0, c->TD[0], c->TD[1]);
+    const Welford* w[2] = {&c->est_q, &c->est_qd};
+    for (int i = 0; i < 2; i++)
+        fprintf(f, "moments %lld %.17g %.17g %.17g %.17g\n", (long long)w[i]->n, w[i]->mre, w[i]->mim, w[i]->m2re,
+                w[i]->m2im);
+    const bool ok = fclose(f) == 0;
+    return ok ? DHT_OK : set_error(DHT_ERR_INVALID_ARG, std::string("cannot write ") + path);
+}
+
+int dht_state_load(dht_ctx* c, const char* path) {
+    if (!c || !path) return set_error(DHT_ERR_INVALID_ARG, "null argument");
+    FILE* f = fopen(path, "r");
+    if (!f) return set_error(DHT_ERR_INVALID_ARG, std::string("cannot read ") + path);
+    int ver = 0, L[4], ap, k;
+    double mass, td[2];
+    long long n[2];
+    double m[2][4];
+    bool ok = fscanf(f, "dhtrace-estimate %d", &ver) == 1 && ver == 1 &&
+              fscanf(f, " lattice %d %d %d %d %d", &L[0], &L[1], &L[2], &L[3], &ap) == 5 &&
+              fscanf(f, " mass %lf", &mass) == 1 && fscanf(f, " deflation %d %lf %lf", &k, &td[0], &td[1]) == 3;
+    for (int i = 0; ok && i < 2; i++)
+        ok = fscanf(f, " moments %lld %lf %lf %lf %lf", &n[i], &m[i][0], &m[i][1], &m[i][2], &m[i][3]) == 5 &&
+             n[i] >= 0;
+    fclose(f);
+    if (!ok) return set_error(DHT_ERR_INVALID_ARG, std::string("not an estimate file: ") + path);
+    for (int d = 0; d < 4; d++)
+        if (L[d] != c->g.L[d]) return set_error(DHT_ERR_STATE, "estimate file belongs to another lattice");
+    if (ap != c->g.antiperiodic || mass != c->mass) return set_error(DHT_ERR_STATE, "estimate file belongs to another operator");
+    const int kc = c->defl_ready ? c->k : 0;
+    if (k != kc) return set_error(DHT_ERR_STATE, "estimate file belongs to another deflation space");
+    if (kc > 0) {
+        const double sc = std::max(std::hypot(c->TD[0], c->TD[1]), 1e-300);
+        if (std::hypot(td[0] - c->TD[0], td[1] - c->TD[1]) > 1e-12 * sc)
+            return set_error(DHT_ERR_STATE, "estimate file belongs to another deflation space (T_D differs)");
+    }
+    Welford* w[2] = {&c->est_q, &c->est_qd};
+    for (int i = 0; i < 2; i++) {
+        w[i]->n = n[i];
+        w[i]->mre = m[i][0];
+        w[i]->mim = m[i][1];
+        w[i]->m2re = m[i][2];
+        w[i]->m2im = m[i][3];
+    }
     return DHT_OK;
 }
 

@@ -5,8 +5,12 @@
 // against the default form's output to rounding before they are timed; the
 // fastest accepted shape is installed on the context for its (precision,
 // batch, epilogue class) and used by every later hop launch of that kind.
+#include <stdio.h>
+#include <string.h>
+
 #include <algorithm>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -243,6 +247,56 @@ int dht_autotune_hop(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int dht_autotune(dht_ctx* c, int prec, int nrhs, int reps, const char* cache_path, dht_tune_result* out) {
+    if (!c || !out) return set_error(DHT_ERR_INVALID_ARG, "null argument");
+    if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    if (log2_pow2(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
+    // cache lines: "hop Lx Ly Lz Lt prec nrhs class form streaming_stores t_chunk ms"
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "r");
+        if (f) {
+            dht_hop_config found[2];
+            double ms[2] = {0, 0};
+            bool have[2] = {false, false};
+            char tag[8];
+            int L[4], p, n, cls, form, nt, tc;
+            double t;
+            while (fscanf(f, "%7s %d %d %d %d %d %d %d %d %d %d %lf", tag, &L[0], &L[1], &L[2], &L[3], &p, &n, &cls,
+                          &form, &nt, &tc, &t) == 12) {
+                if (strcmp(tag, "hop") != 0 || p != prec || n != nrhs || cls < 0 || cls > 1) continue;
+                if (L[0] != c->g.L[0] || L[1] != c->g.L[1] || L[2] != c->g.L[2] || L[3] != c->g.L[3]) continue;
+                found[cls] = dht_hop_config{form, nt, tc};
+                ms[cls] = t;
+                have[cls] = true;
+            }
+            fclose(f);
+            if (have[0] && have[1]) {
+                for (int cls2 = 0; cls2 < 2; cls2++) {
+                    DHT_TRY(dht_hop_config_set(c, prec, nrhs, cls2, &found[cls2]));
+                    out->best[cls2] = found[cls2];
+                    out->best_ms[cls2] = ms[cls2];
+                    out->default_ms[cls2] = 0.0;
+                }
+                out->candidates = 0;
+                out->rejected = 0;
+                out->max_rel_diff = 0.0;
+                return DHT_OK;
+            }
+        }
+    }
+    DHT_TRY(dht_autotune_hop(c, prec, nrhs, reps, out));
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (!f) return set_error(DHT_ERR_INVALID_ARG, std::string("cannot write ") + cache_path);
+        for (int cls = 0; cls < 2; cls++)
+            fprintf(f, "hop %d %d %d %d %d %d %d %d %d %d %.6g\n", c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3], prec,
+                    nrhs, cls, out->best[cls].form, out->best[cls].streaming_stores, out->best[cls].t_chunk,
+                    out->best_ms[cls]);
+        if (fclose(f) != 0) return set_error(DHT_ERR_INVALID_ARG, std::string("cannot write ") + cache_path);
+    }
+    return DHT_OK;
 }
 
 }  // extern "C"
