@@ -488,7 +488,11 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
         DHT_TRY(prc);
     }
     std::vector<dht_solve_stats> st(bp);
-    int rc = solve_fields(c, prm, fz, fx, bp, st.data());
+    // every component of a Z4 / hierarchical probe has modulus 1: ||z||^2 = N
+    // exactly for the nrhs probes, 0 for the padding columns
+    std::vector<double> zn2(bp, 0.0);
+    for (int r = 0; r < nrhs; r++) zn2[r] = (double)(12 * c->g.V);
+    int rc = solve_fields(c, prm, fz, fx, bp, st.data(), zn2.data());
     if (k > 0 && rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) {
         (void)hipStreamSynchronize(c->side);   // the next batch rewrites the probes
         return rc;

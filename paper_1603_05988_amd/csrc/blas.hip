@@ -116,7 +116,7 @@ __device__ void state_update(RhsState& x, const Cx<double>* v, int op, double bd
     if (op == FIN_INIT) {   // v0 = (r, r) with rhat = r = b
         x.rnorm2 = v[0].re;
         x.rhat2 = v[0].re;
-        x.rho = cmake(1.0, 0.0);
+        x.rho = cmake(v[0].re, 0.0);   // (rhat, r) with rhat = r
         x.alpha = cmake(1.0, 0.0);
         x.omega = cmake(1.0, 0.0);
         x.beta = cmake(0.0, 0.0);
@@ -269,7 +269,7 @@ __global__ void s_update_kernel(void* s, const void* r_, const void* v, const Rh
 template <typename S>
 __global__ __launch_bounds__(RED_THREADS) void xr_update_kernel(void* x_, void* r_, const void* p, const void* s,
                                                                 const void* t, const void* rh, const RhsState* st,
-                                                                size_t nvec, int B, Cx<double>* partial) {
+                                                                size_t nvec, int B, Cx<double>* partial, int x_zero) {
     typedef typename Store<S>::acc T;
     constexpr int VW = Store<S>::VW;
     __shared__ Cx<double> red[2][RED_THREADS];
@@ -280,7 +280,12 @@ __global__ __launch_bounds__(RED_THREADS) void xr_update_kernel(void* x_, void* 
         Cx<T> al = cscal<T>(x.alpha), om = cscal<T>(x.omega);
         for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nvec; i += stride) {
             Cx<T> xv[VW], pv[VW], sv[VW], tv[VW], hv[VW];
-            Store<S>::ldv(x_, i, xv);
+            if (x_zero) {   // first iteration from x = 0: x is written, not read
+#pragma unroll
+                for (int j = 0; j < VW; j++) xv[j] = cmake<T>(0, 0);
+            } else {
+                Store<S>::ldv(x_, i, xv);
+            }
             Store<S>::ldv(p, i, pv);
             Store<S>::ldv(s, i, sv);
             Store<S>::ldv(t, i, tv);
@@ -296,6 +301,9 @@ __global__ __launch_bounds__(RED_THREADS) void xr_update_kernel(void* x_, void* 
             Store<S>::stv(x_, i, xv);
             Store<S>::stv(r_, i, sv);
         }
+    } else if (x_zero) {   // an RHS that stopped before its first x update keeps x = 0
+        const Cx<T> zv[VW] = {};
+        for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nvec; i += stride) Store<S>::stv(x_, i, zv);
     }
     red[0][threadIdx.x] = d0;
     red[1][threadIdx.x] = d1;
@@ -327,11 +335,11 @@ int s_update(dht_ctx* c, int prec, void* s, const void* r, const void* v, const 
     return DHT_OK;
 }
 int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const void* s, const void* t, const void* rh,
-                   const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks) {
+                   const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks, bool x_zero) {
     int nb = red_blocks(nvec);
     *nblocks = nb;
     DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(xr_update_kernel<T_>, dim3(nb), dim3(RED_THREADS), 0, c->stream, x, r, p, s,
-                                             t, rh, st, nvec, B, partial))
+                                             t, rh, st, nvec, B, partial, (int)x_zero))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
@@ -357,6 +365,47 @@ __global__ void scale_down_kernel(const Cx<double>* in, void* out, const double*
     }
     Store<SO>::stv(out, v, e);
 }
+// Start of an inner solve from x = 0: r = rhat = p = round(scale_r * in) in the
+// inner precision (in: FP64 half field), with the per-RHS partials of (r, r).
+template <typename SO>
+__global__ __launch_bounds__(RED_THREADS) void solve_init_kernel(const Cx<double>* in, const double* scale, void* r,
+                                                                 void* rh, void* p, size_t nlo, int64_t SB, int B,
+                                                                 Cx<double>* partial) {
+    typedef typename Store<SO>::acc T;
+    constexpr int VW = Store<SO>::VW;
+    __shared__ Cx<double> red[1][RED_THREADS];
+    Cx<double> d0 = cmake(0.0, 0.0);
+    const double sc = scale[threadIdx.x & (B - 1)];   // the stride keeps each lane on one RHS
+    for (size_t v = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; v < nlo; v += (size_t)gridDim.x * RED_THREADS) {
+        int64_t cv = (int64_t)(v / SB), sr = (int64_t)v - cv * SB;
+        Cx<T> e[VW];
+#pragma unroll
+        for (int j = 0; j < VW; j++) {
+            Cx<double> d = in[(cv * VW + j) * SB + sr];
+            e[j] = Store<SO>::round(cmake<T>((T)(sc * d.re), (T)(sc * d.im)));
+            d0.re += (double)e[j].re * e[j].re + (double)e[j].im * e[j].im;
+        }
+        Store<SO>::stv(r, v, e);
+        Store<SO>::stv(rh, v, e);
+        Store<SO>::stv(p, v, e);
+    }
+    red[0][threadIdx.x] = d0;
+    block_reduce_rhs<1>(red, B);
+    if ((int)threadIdx.x < B) partial[(int64_t)blockIdx.x * B + threadIdx.x] = red[0][threadIdx.x];
+}
+
+int solve_init(dht_ctx* c, const void* in, int pout, const double* scale, void* r, void* rh, void* p, int nrhs,
+               Cx<double>* partial, int* nblocks) {
+    const int64_t SB = c->g.Vh * (int64_t)nrhs;
+    size_t nlo = half_elems(c, nrhs) / vec_width(pout);
+    const int nb = red_blocks(nlo);
+    *nblocks = nb;
+    DHT_PREC_SWITCH(pout, hipLaunchKernelGGL(solve_init_kernel<T_>, dim3(nb), dim3(RED_THREADS), 0, c->stream,
+                                             (const Cx<double>*)in, scale, r, rh, p, nlo, SB, nrhs, partial))
+    DHT_HIP(hipGetLastError());
+    return DHT_OK;
+}
+
 template <typename SI>
 __global__ void accum_up_kernel(Cx<double>* x, const void* e_, const double* scale, size_t nlo, int64_t SB, int B) {
     typedef typename Store<SI>::acc T;

@@ -46,7 +46,8 @@ int dots(dht_ctx* c, int prec, int np, const void* const* a, const void* const* 
 int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const RhsState* st, size_t nvec, int B);
 int s_update(dht_ctx* c, int prec, void* s, const void* r, const void* v, const RhsState* st, size_t nvec, int B);
 int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const void* s, const void* t, const void* rh,
-                   const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks);
+                   const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks,
+                   bool x_zero = false);
 // half fields: out_low = scale[r] * in_fp64 ; x_fp64 += scale[r] * e_low
 int scale_down(dht_ctx* c, const void* in, void* out, int pout, const double* scale, int nrhs);
 int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, int nrhs);
@@ -68,12 +69,19 @@ struct BicgResult {
     std::vector<int> iters, status;
     std::vector<double> rnorm2;
 };
-int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::vector<double>& target2, int maxiter,
-             BicgResult* res);
+// r = rhat = p = round(scale * in) (in: FP64 half field), partials of (r, r)
+int solve_init(dht_ctx* c, const void* in, int pout, const double* scale, void* r, void* rh, void* p, int nrhs,
+               Cx<double>* partial, int* nblocks);
+// BiCGStab on the Schur system from x = 0 for the right-hand side scale * src
+// (src: FP64 half field, scale: device, per RHS), in storage precision prec
+int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
+             const std::vector<double>& target2, int maxiter, BicgResult* res);
 
 // Top-level solve of D X = Z on internal full FP64 fields (Z, X: [2][12][Vh][B]);
 // stats has nrhs entries (the padded batch).
-int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats);
+// zn2_known (host, nrhs, may be null): ||Z||^2 per RHS when the caller knows it exactly
+int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats,
+                 const double* zn2_known = nullptr);
 
 // fgmres.hip: FP64 defect correction around FGMRES(m) cycles (FP32) on the
 // full lattice with the network (use_nn) or the identity as right

@@ -34,8 +34,8 @@ int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o
 
 static int slot_base(int prec) { return prec == DHT_FP64 ? WS_K64 : WS_KLO; }
 
-int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::vector<double>& target2, int maxiter,
-             BicgResult* res) {
+int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
+             const std::vector<double>& target2, int maxiter, BicgResult* res) {
     const size_t nvec = half_vecs(c, nrhs, prec);
     const size_t bytes = nvec * 16;
     const int base = slot_base(prec);
@@ -59,21 +59,15 @@ int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::
         hs[i].target2 = target2[i];
     }
     DHT_HIP(hipMemcpyAsync(st, hs, sizeof(RhsState) * nrhs, hipMemcpyHostToDevice, c->stream));
-    DHT_TRY(zero(c, x, bytes));
-    DHT_TRY(zero(c, p, bytes));
-    DHT_TRY(zero(c, v, bytes));
-    DHT_HIP(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, c->stream));
-    DHT_HIP(hipMemcpyAsync(rh, b, bytes, hipMemcpyDeviceToDevice, c->stream));
+    // x = 0 is never materialised: the first x update writes x; r, rhat and
+    // p = r come out of one pass over the FP64 source with the (r, r) sums
     const double bd_eps = prec == DHT_FP64 ? 1e-14 : 1e-6;
     int nb;
-    {
-        const void* aa[1] = {r};
-        DHT_TRY(launch_dot_partials(c, prec, 1, aa, aa, nvec, nrhs, partial, &nb));
-        DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_INIT, bd_eps));
-    }
+    DHT_TRY(solve_init(c, src, prec, scale, r, rh, p, nrhs, partial, &nb));
+    DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_INIT, bd_eps));
     const int check_every = 2;
     for (int it = 0; it < maxiter; it++) {
-        DHT_TRY(p_update(c, prec, p, r, v, st, nvec, nrhs));
+        if (it > 0) DHT_TRY(p_update(c, prec, p, r, v, st, nvec, nrhs));
         HopDot d1;
         d1.kind = HOPDOT_A_OUT;   // (rhat, v)
         d1.a = rh;
@@ -86,7 +80,7 @@ int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::
         d2.partial = partial;
         DHT_TRY(apply_schur(c, prec, s, t, tmp, nrhs, &d2));
         DHT_TRY(finalize(c, partial, d2.nblocks, 2, nrhs, st, FIN_OMEGA, bd_eps));
-        DHT_TRY(xr_update_dots(c, prec, x, r, p, s, t, rh, st, nvec, nrhs, partial, &nb));   // (rhat, r), (r, r)
+        DHT_TRY(xr_update_dots(c, prec, x, r, p, s, t, rh, st, nvec, nrhs, partial, &nb, it == 0));   // (rhat, r), (r, r)
         DHT_TRY(finalize(c, partial, nb, 2, nrhs, st, FIN_RHO, bd_eps));
         if ((it + 1) % check_every == 0 || it + 1 == maxiter) {
             DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
@@ -110,7 +104,6 @@ int bicgstab(dht_ctx* c, int prec, const void* b, void* x, int nrhs, const std::
     return DHT_OK;
 }
 
-// per-RHS FP64 norms^2 of an FP64 field of nvec vectors (host result)
 // residual of a parity, out = z + ca x + cb Hop(in), with its per-RHS squared
 // norms reduced from the hop's fused epilogue sums; `slot` selects where the
 // sums are kept so that two residuals can be summed on the host
@@ -122,7 +115,7 @@ static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const
     HopDot d;
     d.kind = HOPDOT_NORM;
     d.partial = (Cx<double>*)part;
-    DHT_TRY(hop(c, DHT_FP64, parity, in, out, x, ca, cb, nrhs, false, false, &d, z, 1.0));
+    DHT_TRY(hop(c, DHT_FP64, parity, in, out, x, ca, cb, nrhs, false, false, &d, z, z ? 1.0 : 0.0));
     Cx<double>* s = (Cx<double>*)sums + (size_t)slot * nrhs;
     DHT_TRY(finalize(c, d.partial, d.nblocks, 1, nrhs, nullptr, FIN_SUM, 0.0, s));
     std::vector<Cx<double>> h(nrhs);
@@ -133,6 +126,7 @@ static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const
     return DHT_OK;
 }
 
+// per-RHS FP64 norms^2 of an FP64 field of nvec vectors (host result)
 static int norms2(dht_ctx* c, const void* f, size_t nvec, int nrhs, std::vector<double>& out) {
     void* d;
     DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 3 * nrhs, &d));
@@ -146,7 +140,8 @@ static int norms2(dht_ctx* c, const void* f, size_t nvec, int nrhs, std::vector<
     return DHT_OK;
 }
 
-int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats) {
+int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats,
+                 const double* zn2_known) {
     const double a = 4.0 + c->mass;
     const size_t nh = half_elems(c, nrhs);   // complex entries (= FP64 vectors) per half field
     const size_t bh = nh * 16;
@@ -174,7 +169,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         p2.inner = DHT_FP32;
         std::vector<dht_solve_stats> st2(nrhs);
         std::vector<dht_solve_stats> st1(stats ? stats : st2.data(), (stats ? stats : st2.data()) + nrhs);
-        rc = solve_fields(c, &p2, Z, X, nrhs, st2.data());
+        rc = solve_fields(c, &p2, Z, X, nrhs, st2.data(), zn2_known);
         if (stats)
             for (int i = 0; i < nrhs; i++) {
                 stats[i] = st2[i];
@@ -191,17 +186,17 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     if (inner < DHT_FP64 || inner > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad inner precision");
     const int max_outer = prm->max_outer > 0 ? prm->max_outer : 50;
 
-    // right-hand side of the Schur system and ||Z||^2
-    DHT_TRY(hop(c, DHT_FP64, 0, Z_o, bhat, Z_e, 1.0, 1.0 / (2.0 * a), nrhs, false, false));
+    // right-hand side of the Schur system with its norms, and ||Z||^2
     std::vector<double> zn2, rn2;
-    DHT_TRY(norms2(c, Z, 2 * nh, nrhs, zn2));
+    DHT_TRY(residual_hop(c, 0, Z_o, bhat, Z_e, 1.0, 1.0 / (2.0 * a), nullptr, nrhs, 0, rn2));
+    if (zn2_known) zn2.assign(zn2_known, zn2_known + nrhs);
+    else DHT_TRY(norms2(c, Z, 2 * nh, nrhs, zn2));
     std::vector<double> target2(nrhs);
     // the Schur loop aims 10% below the tolerance so that the reconstructed
     // full-lattice residual, checked last, is not lost to rounding
     for (int i = 0; i < nrhs; i++) target2[i] = 0.81 * prm->tol * prm->tol * zn2[i];
 
     DHT_TRY(zero(c, X_e, bh));
-    DHT_HIP(hipMemcpyAsync(r_e, bhat, bh, hipMemcpyDeviceToDevice, c->stream));
     std::vector<int> iters(nrhs, 0), escalated(nrhs, DHT_STATUS_CONVERGED);
     std::vector<double> last_rn2(nrhs, INFINITY);
     int outer = 0, total_iters = 0;
@@ -210,8 +205,6 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     bool have_full = false;        // the loop ended on a verified full-lattice residual
     std::vector<double> full2;     // its squared norms
     void* e;
-    void* rlo;
-    DHT_TRY(norms2(c, r_e, nh, nrhs, rn2));
     for (; outer < max_outer; outer++) {
         bool any = false, stalled = false;
         std::vector<double> sdown(nrhs), sup(nrhs), itarget(nrhs);
@@ -234,18 +227,17 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         }
         const size_t lbytes = nh * elem_bytes(inner);
         const int base = slot_base(inner);
-        DHT_TRY(ws_get(c, base + 7, lbytes, &rlo));   // inner right-hand side
         DHT_TRY(ws_get(c, base + 8, lbytes, &e));     // inner solution
-        DHT_HIP(hipMemcpyAsync(scl, sdown.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-        DHT_TRY(scale_down(c, r_e, rlo, inner, (const double*)scl, nrhs));
         if ((prm->fault_inject & 1u) && outer == 0 && inner != DHT_FP64) {
             // testing hook: poison the first inner right-hand side to exercise the fallback
-            std::vector<double> nanv(nrhs, NAN);
-            DHT_HIP(hipMemcpyAsync(scl, nanv.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-            DHT_TRY(scale_down(c, r_e, rlo, inner, (const double*)scl, nrhs));
+            for (int i = 0; i < nrhs; i++) sdown[i] = NAN;
         }
+        DHT_HIP(hipMemcpyAsync(scl, sdown.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+        // the inner right-hand side is the normalised Schur residual; in the
+        // first cycle that is bhat itself
         BicgResult br;
-        DHT_TRY(bicgstab(c, inner, rlo, e, nrhs, itarget, prm->maxiter - total_iters, &br));
+        DHT_TRY(bicgstab(c, inner, outer == 0 ? bhat : r_e, (const double*)scl, e, nrhs, itarget,
+                         prm->maxiter - total_iters, &br));
         int maxit = 0;
         bool bad = false;
         for (int i = 0; i < nrhs; i++) {
