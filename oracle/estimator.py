@@ -66,7 +66,7 @@ def masked_offdiag_frobenius2(A: np.ndarray, colours: np.ndarray, nbits: int) ->
 
 
 # --------------------------------------------------------------------------
-# deflation (Section 5.2, Algorithm 1 line 2)
+# deflation (Section 5.2; the T_D step of Algorithm 1)
 # --------------------------------------------------------------------------
 def q_eigenpairs(D: np.ndarray, g5diag: np.ndarray, k: int):
     """k eigenpairs of Q = g5 D with smallest |lambda| (dense eigh)."""

@@ -1,4 +1,5 @@
-// Probe vectors on the device (Algorithm 1, lines 3, 5 and 6).
+// Probe vectors on the device (Algorithm 1: the Z4 base vector, the
+// hierarchical-probing Hadamard vectors and their elementwise product).
 //
 // z_j(n) = i^k(n) * h_j(site(n)):  k(n) in {0,1,2,3} is the Z4 noise index
 // (Section 1: entries uniform in {1, i, -1, -i}) from the counter-based
