@@ -96,13 +96,15 @@ def cpu_baseline(U, w, k: int, hp: bool):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", default="c5")
     ap.add_argument("--inner", default="bf16", choices=["fp32", "bf16"])
     ap.add_argument("--inner-tol", type=float, default=0.0, help="inner relative residual per outer cycle (0: library default)")
     ap.add_argument("--k", type=int, default=None)
-    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--proj-window", type=int, default=64,
+                    help="probes per pass over the deflation basis (0: each batch on its own)")
+    ap.add_argument("--fp64-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP-event timing")
     ap.add_argument("--tune", default="auto", choices=["auto", "off"],
@@ -183,6 +185,11 @@ def main():
 
     def run(prm, steps, first0=0, profile=False):
         recs = []
+        # a fresh window: every projection the timed batches use is computed
+        # inside the timed region (a last window that reaches past it is
+        # computed in full, so a step count that is not a multiple of the
+        # window counts extra projection work, never less)
+        ctx.set_projection_window(args.proj_window)
         if profile:
             ctx.profile(True)
             ctx.profile_reset()
@@ -267,6 +274,7 @@ def main():
             "workload": w.name, "lattice": list(w.L), "N": w.N, "mass": w.mass, "link_eps": w.eps,
             "batch": B, "probes": "hierarchical probing (Z4 base x Hadamard)" if w.hp else "Z4",
             "deflation_k": k, "deflation_storage": "bf16 (synthetic basis, diagonal Galerkin inverse)",
+            "projection_window": args.proj_window,
             "solver": "even/odd BiCGStab, %s inner, FP64 defect correction" % args.inner,
             "preconditioner": "none", "tol": w.tol, "hop_shapes": shapes,
             "mean_inner_iters": round(iters, 2), "mean_outer_cycles": round(outer, 2),

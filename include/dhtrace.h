@@ -73,7 +73,7 @@ typedef struct {
     int t_antiperiodic;  /* 1: -1 phase on hops across the t boundary         */
 } dht_lattice;
 
-/* Probe vectors (Algorithm 1, lines 3, 5, 6).
+/* Probe vectors (Algorithm 1: Z4 base vector, Hadamard vector, product).
  * hp = 0: plain Z4 noise, a fresh vector per probe index j.
  * hp = 1: one Z4 base vector z0 per (seed, run), times the hierarchical-
  *         probing Hadamard vector h_j; probe indices j < 2^63.
@@ -134,7 +134,7 @@ typedef struct {
     dht_solve_stats s;
 } dht_record;
 
-/* Running estimates (Algorithm 1, line 9): mean = T_R / n, mean_defl =
+/* Running estimates (Algorithm 1, the trace update): mean = T_R / n, mean_defl =
  * T_D + (mean of q_defl).  Variances are unbiased sample variances
  * (1/(n-1)): var = mean |q - qbar|^2 (the Z4 variance of Section 1),
  * var_re / var_im of the real / imaginary parts. */
@@ -181,7 +181,7 @@ int dht_probe_indices(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, i
 int dht_solve(dht_ctx* ctx, const dht_solver_params* prm, const double* Z_dev, double* X_dev,
               int nrhs, dht_solve_stats* stats);
 
-/* ---- deflation (Section 5.2; Algorithm 1, lines 1-2) ----------------------- */
+/* ---- deflation (Section 5.2; Algorithm 1, the deflation space and T_D) ---- */
 
 /* Start a deflation basis of k vectors stored in precision `prec`. */
 int dht_deflation_begin(dht_ctx* ctx, int k, int prec);
@@ -253,7 +253,7 @@ int dht_project_probes(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, 
 
 /* ---- Algorithm 1 ---------------------------------------------------------- */
 
-/* Algorithm 1 lines 5-9 for probes j = first .. first+nrhs-1: generate the
+/* The loop body of Algorithm 1 for probes j = first .. first+nrhs-1: generate the
  * probes on the device, solve, form q = z^H x in FP64, project on the
  * deflation basis (when set) and accumulate the running estimates.  records
  * (host, nrhs entries, may be NULL) receives per-probe results; coef_host
@@ -261,6 +261,21 @@ int dht_project_probes(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, 
  * [2][k][nrhs] for playback with other k (Section 6.4). */
 int dht_trace_batch(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int nrhs,
                     const dht_solver_params* prm, dht_record* records, double* coef_host);
+
+/* Projection window for dht_trace_batch (Section 5.2: the coefficients
+ * V^H z and V^H g5 z of each probe).  nprobes = 0 (the default) projects each
+ * batch on its own.  With 0 < nrhs < nprobes <= 64 and a BF16 basis, a batch
+ * whose probes are not covered by the last window starts a new window
+ * j = first .. first+nprobes-1: the coefficients of all its probes come out
+ * of one pass over the basis (the basis read is shared by up to 64 probes)
+ * and later batches inside the window reuse them.  Each coefficient has the
+ * same FP32 partial sums over 64-entry chunks as in a per-batch projection;
+ * only the FP64 order in which the chunk sums are added may differ (the split
+ * of the basis over workgroups depends on the column count).  Changing the
+ * basis, or calling this function, drops the window.  The window's 2-bit
+ * probe codes (N x pad(nprobes) bytes) and coefficients stay allocated in
+ * the context.  Errors: DHT_ERR_INVALID_ARG outside 0..64. */
+int dht_set_projection_window(dht_ctx* ctx, int nprobes);
 int dht_estimate_get(dht_ctx* ctx, dht_estimate* est);
 int dht_estimate_reset(dht_ctx* ctx);
 /* Checkpoint / resume of the running estimates (Algorithm 1 accumulates over

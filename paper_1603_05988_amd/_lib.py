@@ -104,6 +104,7 @@ SIGNATURES = {
     "dht_deflation_get": (_i, [_vp, _i, _i, _vp]),
     "dht_deflation_finalize_diag": (_i, [_vp, _dp]),
     "dht_project_probes": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _dp, _dp]),
+    "dht_set_projection_window": (_i, [_vp, _i]),
     "dht_profile_enable": (_i, [_vp, _i]),
     "dht_profile_reset": (_i, [_vp]),
     "dht_profile_get": (_i, [_vp, _i, ctypes.POINTER(_i64), _dp, _dp]),
@@ -312,6 +313,11 @@ class Context:
         c2 = np.zeros(2 * self.k * nrhs)
         check(load().dht_project_probes(self.h, ctypes.byref(sp), first, nrhs, _np_dp(c1), _np_dp(c2)))
         return (c1.view(np.complex128).reshape(self.k, nrhs), c2.view(np.complex128).reshape(self.k, nrhs))
+
+    def set_projection_window(self, nprobes: int):
+        """Project up to 64 probes per pass over a BF16 basis inside
+        trace_batch (0: each batch on its own); also drops the current window."""
+        check(load().dht_set_projection_window(self.h, int(nprobes)))
 
     # -- instrumentation --------------------------------------------------
     PROF_CLASSES = {"hop_fp64": 0, "hop_fp32": 1, "hop_bf16": 2, "proj_mfma": 3, "proj_generic": 4}

@@ -48,12 +48,14 @@ int ws_get(dht_ctx* c, int slot, size_t bytes, void** out) {
 }
 
 static int prof_event(dht_ctx* c, int* idx) {
-    if (c->prof_next >= (int)c->prof_events.size()) {
+    if (c->prof_free.empty()) {
         hipEvent_t e;
         DHT_HIP(hipEventCreate(&e));
         c->prof_events.push_back(e);
+        c->prof_free.push_back((int)c->prof_events.size() - 1);
     }
-    *idx = c->prof_next++;
+    *idx = c->prof_free.back();
+    c->prof_free.pop_back();
     return DHT_OK;
 }
 
@@ -79,22 +81,30 @@ int prof_end(dht_ctx* c, int token, int cls, double bytes) {
     return DHT_OK;
 }
 
+// Accumulates every timed launch that has completed; launches still running
+// (on the side stream) stay pending with their events held.
 int prof_harvest(dht_ctx* c) {
-    if (c->prof_pending.empty()) {
-        c->prof_next = 0;
-        return DHT_OK;
-    }
+    if (c->prof_pending.empty()) return DHT_OK;
     DHT_HIP(hipStreamSynchronize(c->stream));
-    for (const ProfPending& p : c->prof_pending) {
+    size_t keep = 0;
+    for (size_t i = 0; i < c->prof_pending.size(); i++) {
+        const ProfPending p = c->prof_pending[i];
+        hipError_t q = hipEventQuery(c->prof_events[p.ev1]);
+        if (q == hipErrorNotReady) {
+            c->prof_pending[keep++] = p;
+            continue;
+        }
+        DHT_HIP(q);
         float ms = 0.f;
         DHT_HIP(hipEventElapsedTime(&ms, c->prof_events[p.ev0], c->prof_events[p.ev1]));
         ProfStat& s = c->prof_stat[p.cls];
         s.count++;
         s.ms += ms;
         s.bytes += p.bytes;
+        c->prof_free.push_back(p.ev0);
+        c->prof_free.push_back(p.ev1);
     }
-    c->prof_pending.clear();
-    c->prof_next = 0;
+    c->prof_pending.resize(keep);
     return DHT_OK;
 }
 
@@ -361,6 +371,7 @@ int dht_profile_enable(dht_ctx* c, int on) {
 
 int dht_profile_reset(dht_ctx* c) {
     DHT_TRY(check_ctx(c));
+    if (c->side) DHT_HIP(hipStreamSynchronize(c->side));
     DHT_TRY(prof_harvest(c));
     for (int i = 0; i < PROF_NCLASS; i++) c->prof_stat[i] = ProfStat();
     return DHT_OK;
@@ -370,6 +381,7 @@ int dht_profile_get(dht_ctx* c, int cls, int64_t* count, double* total_ms, doubl
     DHT_TRY(check_ctx(c));
     if (cls < 0 || cls >= PROF_NCLASS || !count || !total_ms || !total_bytes)
         return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (c->side) DHT_HIP(hipStreamSynchronize(c->side));
     DHT_TRY(prof_harvest(c));
     *count = c->prof_stat[cls].count;
     *total_ms = c->prof_stat[cls].ms;
@@ -391,7 +403,7 @@ int dht_deflation_clear(dht_ctx* c) {
     if (c->W) DHT_HIP(hipFree(c->W));
     c->W = nullptr;
     c->k = 0;
-    c->defl_ready = false;
+    c->defl_ready = false; c->defl_gen++;
     c->TD[0] = c->TD[1] = 0;
     c->M.clear();
     return DHT_OK;
@@ -448,6 +460,15 @@ static int side_stream(dht_ctx* c) {
     return DHT_OK;
 }
 
+int dht_set_projection_window(dht_ctx* c, int nprobes) {
+    DHT_TRY(check_ctx(c));
+    if (nprobes < 0 || nprobes > 64) return set_error(DHT_ERR_INVALID_ARG, "projection window must be 0..64 probes");
+    if (c->side) DHT_HIP(hipStreamSynchronize(c->side));
+    c->proj_window = nprobes;
+    c->pw_valid = false;
+    return DHT_OK;
+}
+
 int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, const dht_solver_params* prm,
                     dht_record* records, double* coef_host) {
     DHT_TRY(check_ctx(c));
@@ -461,31 +482,54 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     DHT_TRY(ws_get(c, WS_PACK_OUT, fb, &fx));
     const int k = c->defl_ready ? c->k : 0;
     const bool mfma = k > 0 && c->wprec == DHT_BF16 && bp <= 64;
-    if (mfma) DHT_TRY(ws_get(c, WS_ZCODE, full_elems(c, bp), &zc));
+    // With a projection window the basis pass covers the probes of several
+    // batches at once (one read of W for up to 64 probes); later batches of
+    // the window take their coefficients from that pass.
+    const int win = mfma && c->proj_window > nrhs ? c->proj_window : 0;
+    const bool hit = win && c->pw_valid && c->pw_gen == c->defl_gen && c->pw_spec.seed == spec->seed &&
+                     c->pw_spec.run == spec->run && (c->pw_spec.hp != 0) == (spec->hp != 0) && first >= c->pw_first &&
+                     first + nrhs <= c->pw_first + c->pw_count;
+    const bool launch = k > 0 && !hit;
+    const int wpad = win ? pad_rhs(win) : bp;
+    void* pwc = nullptr;
+    if (mfma) DHT_TRY(ws_get(c, win ? WS_PW_CODE : WS_ZCODE, full_elems(c, wpad), &zc));
+    if (win) DHT_TRY(ws_get(c, WS_PW_COEF, sizeof(Cx<double>) * 2 * (size_t)k * wpad, &pwc));
     DHT_TRY(ws_get(c, WS_COEF, sizeof(Cx<double>) * (2 * (size_t)k * bp + bp) + 64, &cc));
-    Cx<double>* d1 = (Cx<double>*)cc;
-    Cx<double>* d2 = d1 + (size_t)k * bp;
-    Cx<double>* dq = d2 + (size_t)k * bp;
+    Cx<double>* d1 = win ? (Cx<double>*)pwc : (Cx<double>*)cc;
+    Cx<double>* d2 = d1 + (size_t)k * wpad;
+    Cx<double>* dq = (Cx<double>*)cc + 2 * (size_t)k * bp;
 
     DHT_TRY(record(c, 0));
-    DHT_TRY(probes_gen(c, spec, first, nrhs, bp, fz, DHT_FP64, nullptr, nullptr, (uint8_t*)zc));
+    DHT_TRY(probes_gen(c, spec, first, nrhs, bp, fz, DHT_FP64, nullptr, nullptr, win ? nullptr : (uint8_t*)zc));
     DHT_TRY(record(c, 1));
     // the projection needs only the probes: it runs on the side stream while
     // the main stream solves (both read fz; neither writes it)
-    if (k > 0) {
+    if (launch) {
+        if (win) c->pw_valid = false;
         DHT_TRY(side_stream(c));
         DHT_HIP(hipEventRecord(c->side_ev[0], c->stream));
         DHT_HIP(hipStreamWaitEvent(c->side, c->side_ev[0], 0));
         hipStream_t main_stream = c->stream;
         c->stream = c->side;
         int prc = hipEventRecord(c->side_ev[1], c->side) == hipSuccess ? DHT_OK : set_error(DHT_ERR_HIP, "event");
+        if (prc == DHT_OK && win)   // the window's probes as 2-bit codes, generated on the side stream
+            prc = probes_gen(c, spec, first, win, wpad, nullptr, DHT_FP64, nullptr, nullptr, (uint8_t*)zc);
         if (prc == DHT_OK) {
-            if (mfma) prc = project_codes(c, (const uint8_t*)zc, bp, d1, d2);
+            if (mfma) prc = project_codes(c, (const uint8_t*)zc, wpad, d1, d2);
             else prc = project_field(c, fz, DHT_FP64, bp, d1, d2);
         }
         if (prc == DHT_OK && hipEventRecord(c->side_ev[2], c->side) != hipSuccess) prc = set_error(DHT_ERR_HIP, "event");
         c->stream = main_stream;
+        if (prc != DHT_OK) (void)hipStreamSynchronize(c->side);
         DHT_TRY(prc);
+        if (win) {
+            c->pw_valid = true;
+            c->pw_first = first;
+            c->pw_count = win;
+            c->pw_pad = wpad;
+            c->pw_spec = *spec;
+            c->pw_gen = c->defl_gen;
+        }
     }
     std::vector<dht_solve_stats> st(bp);
     // every component of a Z4 / hierarchical probe has modulus 1: ||z||^2 = N
@@ -493,14 +537,14 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     std::vector<double> zn2(bp, 0.0);
     for (int r = 0; r < nrhs; r++) zn2[r] = (double)(12 * c->g.V);
     int rc = solve_fields(c, prm, fz, fx, bp, st.data(), zn2.data());
-    if (k > 0 && rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) {
+    if (launch && rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) {
         (void)hipStreamSynchronize(c->side);   // the next batch rewrites the probes
         return rc;
     }
     if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) return rc;
     std::string msg = g_err;
     DHT_TRY(record(c, 2));
-    if (k > 0) DHT_HIP(hipStreamWaitEvent(c->stream, c->side_ev[2], 0));
+    if (launch) DHT_HIP(hipStreamWaitEvent(c->stream, c->side_ev[2], 0));
     DHT_TRY(record(c, 3));
     {
         const void* aa[1] = {fz};
@@ -509,13 +553,16 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     }
     DHT_TRY(record(c, 4));
     std::vector<Cx<double>> hc((size_t)2 * k * bp + bp);
+    if (win && k > 0)   // this batch's columns of the window's [2k][wpad] coefficients, next to q
+        DHT_HIP(hipMemcpy2DAsync(cc, sizeof(Cx<double>) * bp, d1 + (first - c->pw_first), sizeof(Cx<double>) * wpad,
+                                 sizeof(Cx<double>) * nrhs, 2 * (size_t)k, hipMemcpyDeviceToDevice, c->stream));
     DHT_HIP(hipMemcpyAsync(hc.data(), cc, sizeof(Cx<double>) * hc.size(), hipMemcpyDeviceToHost, c->stream));
     DHT_TRY(record(c, 5));
     DHT_HIP(hipStreamSynchronize(c->stream));
     c->timings[0] = elapsed(c, 0, 1);
     c->timings[1] = elapsed(c, 1, 2);
     c->timings[2] = 0.0;   // the projection's own duration (it overlaps the solve)
-    if (k > 0) {
+    if (launch) {
         float pm = 0.f;
         if (hipEventElapsedTime(&pm, c->side_ev[1], c->side_ev[2]) == hipSuccess) c->timings[2] = pm;
     }

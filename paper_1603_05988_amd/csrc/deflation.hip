@@ -1,4 +1,5 @@
-// Deflation of the trace estimator (Section 5.2; Algorithm 1, lines 1-2 and 8).
+// Deflation of the trace estimator (Section 5.2; Algorithm 1: the deflation space, T_D, and the
+// deflation correction of each probe's quadratic form).
 //
 // With k eigenvectors W of the Hermitian Q = g5 D (stored rounded to FP64,
 // FP32 or BF16), the deflated part of D^-1 = Q^-1 g5 is P = W M W^H g5 with
@@ -206,16 +207,22 @@ struct MfmaProjArgs {
 
 __device__ inline uint32_t bf16_unit(int v) { return v > 0 ? 0x3F80u : (v < 0 ? 0xBF80u : 0u); }
 
-// Each workgroup takes a contiguous run of chunks of one group; the probe
-// fragments of MP_FILL chunks are expanded into LDS at a time, and inside a
-// chunk every wave issues all of its A-fragment loads (RT tiles x the chunk's
-// K-steps) before the MFMAs, so that RT * kc / 8 16-byte loads per lane are in
-// flight; the FP32 accumulators are flushed to FP64 after every chunk.
+// Each workgroup takes a contiguous run of chunks of one group.  The probe
+// codes of MP_FILL chunks (a contiguous run of bytes) are fetched with 8-byte
+// loads one fill ahead, so their latency hides behind the previous fill's
+// MFMAs; each fill stages them in LDS and expands them there into B
+// fragments.  Inside a chunk every wave issues all of its A-fragment loads
+// (RT tiles x the chunk's K-steps) before the MFMAs, so that RT * kc / 8
+// 16-byte loads per lane are in flight; the FP32 accumulators are flushed
+// to FP64 after every chunk.
 static constexpr int MP_FILL = 4;
+static constexpr int MP_KC_MAX = 64;   // largest chunk (complex entries)
 
 template <int RT, int NT>
 __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
-    extern __shared__ uint4 bfr[];   // [MP_FILL][kc/8][NT][64] B fragments
+    extern __shared__ uint4 bfr[];   // [MP_FILL][kc/8][NT][64] B fragments, then the raw codes
+    // raw codes of one fill: MP_FILL * kc * B bytes <= MP_FILL * 64 * NT * 16
+    constexpr int RAW_PER_THREAD = (MP_FILL * MP_KC_MAX * NT * 16 / 8 + MP_THREADS - 1) / MP_THREADS;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -226,6 +233,7 @@ __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
     const int64_t per = (a.chunks_per_group + a.wg_per_group - 1) / a.wg_per_group;
     const int64_t c_begin = wslot * per;
     const int64_t c_end = c_begin + per < a.chunks_per_group ? c_begin + per : a.chunks_per_group;
+    uint8_t* raw = (uint8_t*)(bfr + (size_t)MP_FILL * nks * NT * 64);
 
     f32x16_t acc[RT][NT];
     double facc[RT][NT][16];
@@ -240,31 +248,60 @@ __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
             }
         }
 
+    // 8-byte words of the codes of the fill starting at chunk cf
+    uint2 rv[RAW_PER_THREAD];
+    auto fetch = [&](int64_t cf) {
+        const int nfill = (int)(c_end - cf < MP_FILL ? c_end - cf : MP_FILL);
+        const int nwords = (nfill * a.kc * a.B) >> 3;
+        const uint2* src = (const uint2*)(a.zc + ((int64_t)g * a.group_len + cf * a.kc) * a.B);
+#pragma unroll
+        for (int j = 0; j < RAW_PER_THREAD; j++) {
+            const int w = tid + j * MP_THREADS;
+            if (w < nwords) rv[j] = src[w];
+        }
+    };
+    if (c_begin < c_end) fetch(c_begin);
+
     for (int64_t cf = c_begin; cf < c_end; cf += MP_FILL) {
         const int nfill = (int)(c_end - cf < MP_FILL ? c_end - cf : MP_FILL);
         const int64_t K0 = (int64_t)g * a.group_len + cf * a.kc;
-        __syncthreads();
-        // expand the probe codes of nfill chunks into B fragments in LDS
-        for (int f = tid; f < nfill * nks * NT * 64; f += MP_THREADS) {
-            int l = f & 63;
-            int nt = (f >> 6) % NT;
-            int ks = (f >> 6) / NT;                       // K-step within the fill
-            int col = nt * 32 + (l & 31);
-            int r = col >> 1, part = col & 1;
-            uint32_t w[4];
+        __syncthreads();   // the previous fill's fragments and codes are no longer read
+        {
+            const int nwords = (nfill * a.kc * a.B) >> 3;
 #pragma unroll
-            for (int e = 0; e < 4; e++) {   // complex entry K = 8 ks + 4 (l / 32) + e
-                uint32_t lo = 0, hi = 0;
-                if (r < a.B) {
-                    int code = a.zc[(K0 + 8 * ks + 4 * (l >> 5) + e) * a.B + r] & 3;
-                    int zr = code == 0 ? 1 : (code == 2 ? -1 : 0);
-                    int zi = code == 1 ? 1 : (code == 3 ? -1 : 0);
-                    lo = bf16_unit(part ? zi : zr);
-                    hi = bf16_unit(part ? -zr : zi);
-                }
-                w[e] = lo | (hi << 16);
+            for (int j = 0; j < RAW_PER_THREAD; j++) {
+                const int w = tid + j * MP_THREADS;
+                if (w < nwords) ((uint2*)raw)[w] = rv[j];
             }
-            bfr[f] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        __syncthreads();
+        if (cf + MP_FILL < c_end) fetch(cf + MP_FILL);   // in flight during this fill
+        // expand: item (K-step, half, probe) -> the fragments of columns 2r
+        // (real part: zr, zi) and 2r + 1 (imaginary part: zi, -zr) for the
+        // complex entries K = 8 ks + 4 half + e, e = 0..3
+        constexpr int RCOLS = NT * 16;
+        for (int f = tid; f < nfill * nks * 2 * RCOLS; f += MP_THREADS) {
+            const int r = f % RCOLS;
+            const int rest = f / RCOLS;
+            const int hh = rest & 1, ks = rest >> 1;
+            uint32_t w0[4], w1[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                uint32_t z0 = 0, z1 = 0;
+                if (r < a.B) {
+                    const int code = raw[(8 * ks + 4 * hh + e) * a.B + r] & 3;
+                    const int zr = code == 0 ? 1 : (code == 2 ? -1 : 0);
+                    const int zi = code == 1 ? 1 : (code == 3 ? -1 : 0);
+                    z0 = bf16_unit(zr) | (bf16_unit(zi) << 16);
+                    z1 = bf16_unit(zi) | (bf16_unit(-zr) << 16);
+                }
+                w0[e] = z0;
+                w1[e] = z1;
+            }
+            const int col = 2 * r;
+            const int nt = col >> 5, l = (col & 31) + 32 * hh;
+            bfr[(ks * NT + nt) * 64 + l] = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+            bfr[(ks * NT + nt) * 64 + l + 1] = make_uint4(w1[0], w1[1], w1[2], w1[3]);
         }
         __syncthreads();
         for (int cc = 0; cc < nfill; cc++) {
@@ -374,7 +411,9 @@ int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<do
     a.partial = (double*)part;
     DHT_TRY(zero(c, part, (size_t)nwg * wl.kp * NT * 32 * sizeof(double)));
     dim3 grid(nwg, rowgroups), block(MP_THREADS);
-    size_t lds = (size_t)MP_FILL * (a.kc / 8) * NT * 64 * sizeof(uint4);
+    if (a.group_len % 8 != 0 || a.kc > MP_KC_MAX) return set_error(DHT_ERR_INVALID_ARG, "lattice volume not a multiple of 8");
+    // B fragments of one fill, then its raw codes
+    size_t lds = (size_t)MP_FILL * (a.kc / 8) * NT * 64 * sizeof(uint4) + (size_t)MP_FILL * a.kc * nrhs;
     int tok;
     DHT_TRY(prof_begin(c, &tok));
     if (NT == 1) hipLaunchKernelGGL((proj_mfma_kernel<2, 1>), grid, block, lds, c->stream, a);
@@ -403,7 +442,7 @@ int deflation_begin(dht_ctx* c, int k, int prec) {
         c->W = nullptr;
     }
     c->k = 0;
-    c->defl_ready = false;
+    c->defl_ready = false; c->defl_gen++;
     c->TD[0] = c->TD[1] = 0;
     size_t bytes = w_bytes(c, k, prec);
     if (hipMalloc(&c->W, bytes) != hipSuccess) {
@@ -450,7 +489,7 @@ int deflation_set(dht_ctx* c, int first, int count, const double* W_dev) {
         case DHT_BF16: hipLaunchKernelGGL(pack_w_kernel<bf16x2>, grid, block, 0, c->stream, (const Cx<double>*)W_dev, (bf16x2*)c->W, wl, c->g, first, count); break;
     }
     DHT_HIP(hipGetLastError());
-    c->defl_ready = false;
+    c->defl_ready = false; c->defl_gen++;
     return DHT_OK;
 }
 
@@ -532,7 +571,7 @@ static int store_M(dht_ctx* c, const std::vector<std::complex<double>>& M, std::
     c->M_diag = diagonal;
     c->TD[0] = td.real();
     c->TD[1] = td.imag();
-    c->defl_ready = true;
+    c->defl_ready = true; c->defl_gen++;
     return DHT_OK;
 }
 

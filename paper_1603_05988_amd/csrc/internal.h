@@ -284,7 +284,7 @@ struct dht_ctx {
     // per-kernel-class timing with HIP events (off unless enabled)
     bool prof = false;
     std::vector<hipEvent_t> prof_events;           // pool
-    int prof_next = 0;                             // next free event of the pool
+    std::vector<int> prof_free;                    // pool events not in use
     std::vector<dht::ProfPending> prof_pending;    // launches not yet harvested
     dht::ProfStat prof_stat[dht::PROF_NCLASS];
     // estimator
@@ -306,6 +306,15 @@ struct dht_ctx {
     // a batch runs concurrently with its solve; created on first use
     hipStream_t side = nullptr;
     hipEvent_t side_ev[4];
+    // projection window (BF16 basis): the coefficients of probes
+    // [pw_first, pw_first + pw_count) of pw_spec, computed in one pass over
+    // the basis for basis generation pw_gen; defl_gen changes with the basis
+    int proj_window = 0;
+    bool pw_valid = false;
+    int64_t pw_first = 0;
+    int pw_count = 0, pw_pad = 0;
+    dht_probe_spec pw_spec = {0u, 0u, 0};
+    uint64_t pw_gen = 0, defl_gen = 0;
 };
 
 namespace dht {
@@ -335,6 +344,7 @@ enum Slot {
     WS_TUNE_REF, WS_TUNE_RED,
     WS_NORMS, WS_FOLD,
     WS_EIG_V, WS_EIG_W, WS_EIG_T, WS_EIG_U, WS_EIG_PART, WS_EIG_SMALL, WS_EIG_RPART, WS_EIG_LAM, WS_EIG_CANON, WS_DEFL_GET,
+    WS_PW_CODE, WS_PW_COEF,
     WS_NSLOTS
 };
 int ws_get(dht_ctx* c, int slot, size_t bytes, void** out);

@@ -121,10 +121,10 @@ def hashed_basis(cols, N: int, seed: int, xp=np, device=None):
     for c in cols:
         if xp is np:
             n = np.arange(N, dtype=np.int64)
-            key = int(_mix32(np.int64(seed * 1000003 + int(c)), np))
+            key = int(_mix32(seed * 1000003 + int(c), np))
         else:
             n = xp.arange(N, dtype=xp.int64, device=device)
-            key = int(_mix32(np.int64(seed * 1000003 + int(c)), np))
+            key = int(_mix32(seed * 1000003 + int(c), np))
         h = _mix32(n ^ key, xp)
         re = 1.0 - 2.0 * (h & 1)
         im = 1.0 - 2.0 * ((h >> 1) & 1)

@@ -74,10 +74,11 @@ def test_c5_mixed_solve_true_residual_by_oracle(c5):
         assert abs(rel - stats[r]["true_resid"]) <= 1e-3 * W5.tol + 1e-3 * rel
 
 
-def test_c5_projection_sampled_exact(c5):
+@pytest.fixture(scope="module")
+def c5_basis(c5):
     U, ctx = c5
     Lb = _lib()
-    k, B, N = W5.k, W5.batch, W5.N
+    k, N = W5.k, W5.N
     ctx.begin_deflation(k, Lb.BF16)
     for j in range(0, k, 32):
         cols = list(range(j, min(k, j + 32)))
@@ -86,13 +87,38 @@ def test_c5_projection_sampled_exact(c5):
         del Wb
     torch.cuda.empty_cache()
     ctx.finalize_deflation(diagonal=True)
-    c1, c2 = ctx.project_probes(W5.seed, 0, W5.hp, 0, B)
+    yield U, ctx
+    ctx.set_projection_window(0)
+    ctx.clear_deflation()
+
+
+def _check_exact(c1, c2, first, rows):
     g5 = lattice.gamma5_full(W5.V)
-    for r in (0, 7, B - 1):
-        z = rng.probe(W5.L, W5.seed, 0, W5.hp, r)
-        for i in (0, 517, k - 1):
-            w = hashed_basis([i], N, 11)[0]
+    for r in rows:
+        z = rng.probe(W5.L, W5.seed, 0, W5.hp, first + r)
+        for i in (0, 517, W5.k - 1):
+            w = hashed_basis([i], W5.N, 11)[0]
             e1 = np.vdot(w, z)
             e2 = np.vdot(w, g5 * z)
-            assert c1[i, r] == e1 and c2[i, r] == e2, (i, r, c1[i, r], e1, c2[i, r], e2)
-    ctx.clear_deflation()
+            assert c1[i, r] == e1 and c2[i, r] == e2, (i, first + r, c1[i, r], e1, c2[i, r], e2)
+
+
+def test_c5_projection_sampled_exact(c5_basis):
+    U, ctx = c5_basis
+    c1, c2 = ctx.project_probes(W5.seed, 0, W5.hp, 0, W5.batch)
+    _check_exact(c1, c2, 0, (0, 7, W5.batch - 1))
+
+
+def test_c5_projection_window_exact(c5_basis):
+    """The 64-probe projection window bench.py times: the batch that opens the
+    window and one that reuses it get the exact coefficients of their probes."""
+    U, ctx = c5_basis
+    Lb = _lib()
+    B = W5.batch
+    prm = ctx.params(Lb.SOLVER_DC_BICGSTAB, inner=Lb.BF16, tol=W5.tol, maxiter=5000)
+    ctx.set_projection_window(4 * B)
+    for first in (0, 2 * B):
+        recs, c1, c2 = ctx.trace_batch(W5.seed, 0, W5.hp, first, B, prm, want_coef=True)
+        assert all(r["true_resid"] <= W5.tol for r in recs)
+        _check_exact(c1, c2, first, (0, B - 1))
+    ctx.set_projection_window(0)

@@ -136,3 +136,44 @@ def test_trace_batch_bf16_basis_c2():
     dM = np.abs(M).sum()
     assert np.abs((q - qd) - d_ref).max() <= 4 * bound.max() * dM * max(np.abs(r1).max(), np.abs(r2).max())
     ctx.close()
+
+
+@pytest.mark.parametrize("window,firsts", [(32, (0, 8, 16, 24, 32, 4)), (20, (0, 8, 16, 24))])
+def test_trace_batch_projection_window_c2(window, firsts):
+    """A projection window shares one pass over the BF16 basis between the
+    batches it covers: every batch gets the coefficients of its own probes
+    (oracle bound as above; against a per-batch projection only the FP64
+    order of the chunk sums may differ), and the quadratic forms do not
+    depend on the window."""
+    w = WORKLOADS["c2"]
+    L_ = _lib()
+    U = gauge_links(w.L, w.eps, w.seed)
+    ctx = L_.Context(w.L, w.mass)
+    ctx.set_gauge(cuda(U))
+    k, nrhs = 48, 8
+    W = random_basis(w.N, k, 11)
+    ctx.set_deflation(cuda(W.T), L_.BF16)
+    Wr = round_bf16(W)
+    g5 = lattice.gamma5_full(w.V)
+    prm = ctx.params(L_.SOLVER_DC_BICGSTAB, inner=L_.FP32, tol=1e-10)
+    bound = 32 * 2.0 ** -24 * np.abs(Wr).sum(axis=0)[:, None] + 1e-12
+    reorder = 1e-12 * np.abs(Wr).sum(axis=0)[:, None]
+    M = ctx.deflation_M()
+    with pytest.raises(L_.DhtError):
+        ctx.set_projection_window(65)
+    ctx.set_projection_window(window)
+    for first in firsts:
+        recs, c1, c2 = ctx.trace_batch(w.seed, 0, True, first, nrhs, prm, want_coef=True)
+        p1, p2 = ctx.project_probes(w.seed, 0, True, first, nrhs)
+        assert np.all(np.abs(c1 - p1) <= reorder) and np.all(np.abs(c2 - p2) <= reorder), first
+        Z = rng.probes(w.L, w.seed, 0, True, first, nrhs)
+        r1, r2 = estimator.projection_coefficients(Wr, Z, g5)
+        assert np.all(np.abs(c1 - r1) <= bound) and np.all(np.abs(c2 - r2) <= bound), first
+        q = np.array([r["q"] for r in recs])
+        qd = np.array([r["q_defl"] for r in recs])
+        assert np.abs((q - qd) - estimator.deflation_corrections(c1, c2, M)).max() <= 1e-10 * np.abs(q).max()
+    # without the window: the same solves, so the same quadratic forms
+    ctx.set_projection_window(0)
+    recs0 = ctx.trace_batch(w.seed, 0, True, firsts[-1], nrhs, prm)
+    assert [r["q"] for r in recs0] == [r["q"] for r in recs]
+    ctx.close()
