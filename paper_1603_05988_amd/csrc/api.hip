@@ -536,7 +536,10 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     // exactly for the nrhs probes, 0 for the padding columns
     std::vector<double> zn2(bp, 0.0);
     for (int r = 0; r < nrhs; r++) zn2[r] = (double)(12 * c->g.V);
-    int rc = solve_fields(c, prm, fz, fx, bp, st.data(), zn2.data());
+    // the BiCGStab paths sum q = z^H x in the epilogues of their final residual
+    const bool fused_q = prm->method == DHT_SOLVER_DC_BICGSTAB || prm->method == DHT_SOLVER_BICGSTAB_FP64;
+    std::vector<Cx<double>> zxq(bp);
+    int rc = solve_fields(c, prm, fz, fx, bp, st.data(), zn2.data(), fused_q ? zxq.data() : nullptr);
     if (launch && rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) {
         (void)hipStreamSynchronize(c->side);   // the next batch rewrites the probes
         return rc;
@@ -546,7 +549,7 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     DHT_TRY(record(c, 2));
     if (launch) DHT_HIP(hipStreamWaitEvent(c->stream, c->side_ev[2], 0));
     DHT_TRY(record(c, 3));
-    {
+    if (!fused_q) {
         const void* aa[1] = {fz};
         const void* bb[1] = {fx};
         DHT_TRY(dots(c, DHT_FP64, 1, aa, bb, full_elems(c, bp), bp, dq));
@@ -571,7 +574,7 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     DHT_TRY(prof_harvest(c));
     std::vector<double> dre(bp, 0.0), dim(bp, 0.0);
     if (k > 0) deflation_corrections(c, hc.data(), hc.data() + (size_t)k * bp, bp, nrhs, dre.data(), dim.data());
-    const Cx<double>* q = hc.data() + (size_t)2 * k * bp;
+    const Cx<double>* q = fused_q ? zxq.data() : hc.data() + (size_t)2 * k * bp;
     // a padding slot that failed cannot fail the batch: only real probes count
     if (rc == DHT_ERR_NOT_CONVERGED) {
         bool any = false;

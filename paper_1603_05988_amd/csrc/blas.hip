@@ -406,21 +406,29 @@ int solve_init(dht_ctx* c, const void* in, int pout, const double* scale, void* 
     return DHT_OK;
 }
 
+// x += scale_r * e (assign: x = scale_r * e, x not read)
 template <typename SI>
-__global__ void accum_up_kernel(Cx<double>* x, const void* e_, const double* scale, size_t nlo, int64_t SB, int B) {
+__global__ void accum_up_kernel(Cx<double>* x, const void* e_, const double* scale, size_t nlo, int64_t SB, int B,
+                                int assign) {
     typedef typename Store<SI>::acc T;
     constexpr int VW = Store<SI>::VW;
     size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nlo) return;
     int64_t cv = v / SB, sr = v - cv * SB;
     double sc = scale[sr & (B - 1)];
-    if (sc == 0.0) return;
+    if (sc == 0.0) {
+        if (assign)
+#pragma unroll
+            for (int j = 0; j < VW; j++) x[(cv * VW + j) * SB + sr] = cmake(0.0, 0.0);
+        return;
+    }
     Cx<T> e[VW];
     Store<SI>::ldv(e_, v, e);
 #pragma unroll
     for (int j = 0; j < VW; j++) {
         Cx<double>& xd = x[(cv * VW + j) * SB + sr];
-        xd = cmake(xd.re + sc * (double)e[j].re, xd.im + sc * (double)e[j].im);
+        const Cx<double> x0 = assign ? cmake(0.0, 0.0) : xd;
+        xd = cmake(x0.re + sc * (double)e[j].re, x0.im + sc * (double)e[j].im);
     }
 }
 
@@ -432,11 +440,11 @@ int scale_down(dht_ctx* c, const void* in, void* out, int pout, const double* sc
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
-int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, int nrhs) {
+int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, int nrhs, bool assign) {
     const int64_t SB = c->g.Vh * (int64_t)nrhs;
     size_t nlo = half_elems(c, nrhs) / vec_width(pin);
     DHT_PREC_SWITCH(pin, hipLaunchKernelGGL(accum_up_kernel<T_>, egrid(nlo), dim3(256), 0, c->stream,
-                                            (Cx<double>*)x, e, scale, nlo, SB, nrhs))
+                                            (Cx<double>*)x, e, scale, nlo, SB, nrhs, (int)assign))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }

@@ -236,9 +236,9 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
         if (XPAY) v = v + ca * xv[i];
         acc[i] = v;
     }
+    Cx<T> zv[12];
     if (XPAY && a.z) {   // out += cz * z (residuals z - D x in one pass)
         const T cz = (T)a.cz;
-        Cx<T> zv[12];
         load_spinor<S>(a.z, v0, vstride, zv);
 #pragma unroll
         for (int i = 0; i < 12; i++) acc[i] = acc[i] + cz * zv[i];
@@ -264,6 +264,12 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
         } else if (DOT == HOPDOT_NORM) {
 #pragma unroll
             for (int i = 0; i < 12; i++) d0.re += (double)ov[i].re * ov[i].re + (double)ov[i].im * ov[i].im;
+        } else if (DOT == HOPDOT_NORM_ZX) {
+#pragma unroll
+            for (int i = 0; i < 12; i++) {
+                d0.re += (double)ov[i].re * ov[i].re + (double)ov[i].im * ov[i].im;
+                d1 = d1 + conjmul(cmake<double>(zv[i].re, zv[i].im), cmake<double>(xv[i].re, xv[i].im));
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < 12; i++) {
@@ -303,7 +309,7 @@ template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, bool LDSL>
 __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
     constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
-    constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
+    constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : ((DOT == HOPDOT_OUT_X || DOT == HOPDOT_NORM_ZX) ? 2 : 0);
     extern __shared__ uint4 hop_lds[];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int B = 1 << a.bshift;
@@ -447,7 +453,7 @@ template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT>
 __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
     extern __shared__ uint4 hop_lds[];   // [2][6][HOP_THREADS] Cx<T>
-    constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : (DOT == HOPDOT_OUT_X ? 2 : 0);
+    constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : ((DOT == HOPDOT_OUT_X || DOT == HOPDOT_NORM_ZX) ? 2 : 0);
     constexpr int SF = DAG ? -1 : 1;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int gid = blk * HOP_THREADS + threadIdx.x;
@@ -567,6 +573,7 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     a.da = dot ? dot->a : nullptr;
     a.partial = dot ? dot->partial : nullptr;
     if (kind == HOPDOT_OUT_X && !x) return set_error(DHT_ERR_INVALID_ARG, "fused (out, x) needs an xpay source");
+    if (kind == HOPDOT_NORM_ZX && !z) return set_error(DHT_ERR_INVALID_ARG, "fused (z, x) needs both axpy sources");
     const int cls = (x || dot) ? HOP_FUSED : HOP_PLAIN;
     const HopConfig cfg = hop_config(c, prec_of<S>(), nrhs, cls);
     a.tc = cfg.tc;
@@ -603,6 +610,7 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     DHT_HOP_CASE(false, false, true, HOPDOT_A_OUT)
     DHT_HOP_CASE(false, false, true, HOPDOT_OUT_X)
     DHT_HOP_CASE(false, false, true, HOPDOT_NORM)
+    DHT_HOP_CASE(false, false, true, HOPDOT_NORM_ZX)
 #undef DHT_HOP_CASE
     return set_error(DHT_ERR_INVALID_ARG, "unsupported hop variant");
 launched:

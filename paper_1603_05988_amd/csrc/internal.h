@@ -376,9 +376,10 @@ int unpack_spinor(dht_ctx* c, const void* field, int prec, double* canon, int n,
 // given), optionally g5 on the result and/or dagger hop.  A per-RHS FP64
 // reduction can be fused into the epilogue: HOPDOT_A_OUT gives (a, out) =
 // sum conj(a) out; HOPDOT_OUT_X gives (out, x) and (out, out); HOPDOT_NORM
-// gives (out, out).  Partial sums go to partial[block][pair][nrhs]; nblocks
-// receives the count.
-enum { HOPDOT_NONE = 0, HOPDOT_A_OUT = 1, HOPDOT_OUT_X = 2, HOPDOT_NORM = 3 };
+// gives (out, out); HOPDOT_NORM_ZX gives (out, out) and (z, x) (a residual
+// z - D x with its norm and the quadratic form z^H x of the same operands).
+// Partial sums go to partial[block][pair][nrhs]; nblocks receives the count.
+enum { HOPDOT_NONE = 0, HOPDOT_A_OUT = 1, HOPDOT_OUT_X = 2, HOPDOT_NORM = 3, HOPDOT_NORM_ZX = 4 };
 struct HopDot {
     int kind = HOPDOT_NONE;
     const void* a = nullptr;

@@ -50,7 +50,7 @@ int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const 
                    bool x_zero = false);
 // half fields: out_low = scale[r] * in_fp64 ; x_fp64 += scale[r] * e_low
 int scale_down(dht_ctx* c, const void* in, void* out, int pout, const double* scale, int nrhs);
-int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, int nrhs);
+int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, int nrhs, bool assign = false);
 int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t ncomplex);
 int zero(dht_ctx* c, void* p, size_t bytes);
 
@@ -79,9 +79,11 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
 
 // Top-level solve of D X = Z on internal full FP64 fields (Z, X: [2][12][Vh][B]);
 // stats has nrhs entries (the padded batch).
-// zn2_known (host, nrhs, may be null): ||Z||^2 per RHS when the caller knows it exactly
+// zn2_known (host, nrhs, may be null): ||Z||^2 per RHS when the caller knows it exactly;
+// zx_out (host, nrhs, may be null; BiCGStab methods only): z^H x per RHS, summed in
+// the epilogues of the final full-lattice residual
 int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats,
-                 const double* zn2_known = nullptr);
+                 const double* zn2_known = nullptr, Cx<double>* zx_out = nullptr);
 
 // fgmres.hip: FP64 defect correction around FGMRES(m) cycles (FP32) on the
 // full lattice with the network (use_nn) or the identity as right

@@ -106,23 +106,28 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
 
 // residual of a parity, out = z + ca x + cb Hop(in), with its per-RHS squared
 // norms reduced from the hop's fused epilogue sums; `slot` selects where the
-// sums are kept so that two residuals can be summed on the host
+// sums are kept so that two residuals can be summed on the host.  With zx
+// non-null the same epilogue also sums z^H x per RHS (z and x are the
+// epilogue's operands) into *zx.
 static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const void* x, double ca, double cb,
-                        const void* z, int nrhs, int slot, std::vector<double>& n2) {
+                        const void* z, int nrhs, int slot, std::vector<double>& n2,
+                        std::vector<Cx<double>>* zx = nullptr) {
     void *part, *sums;
     DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
-    DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 2 * nrhs, &sums));
+    DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 4 * nrhs, &sums));
+    const int np = zx ? 2 : 1;
     HopDot d;
-    d.kind = HOPDOT_NORM;
+    d.kind = zx ? HOPDOT_NORM_ZX : HOPDOT_NORM;
     d.partial = (Cx<double>*)part;
     DHT_TRY(hop(c, DHT_FP64, parity, in, out, x, ca, cb, nrhs, false, false, &d, z, z ? 1.0 : 0.0));
-    Cx<double>* s = (Cx<double>*)sums + (size_t)slot * nrhs;
-    DHT_TRY(finalize(c, d.partial, d.nblocks, 1, nrhs, nullptr, FIN_SUM, 0.0, s));
-    std::vector<Cx<double>> h(nrhs);
-    DHT_HIP(hipMemcpyAsync(h.data(), s, sizeof(Cx<double>) * nrhs, hipMemcpyDeviceToHost, c->stream));
+    Cx<double>* s = (Cx<double>*)sums + (size_t)slot * 2 * nrhs;
+    DHT_TRY(finalize(c, d.partial, d.nblocks, np, nrhs, nullptr, FIN_SUM, 0.0, s));
+    std::vector<Cx<double>> h((size_t)np * nrhs);
+    DHT_HIP(hipMemcpyAsync(h.data(), s, sizeof(Cx<double>) * h.size(), hipMemcpyDeviceToHost, c->stream));
     DHT_HIP(hipStreamSynchronize(c->stream));
     n2.resize(nrhs);
     for (int i = 0; i < nrhs; i++) n2[i] = h[i].re;
+    if (zx) zx->assign(h.begin() + nrhs, h.end());
     return DHT_OK;
 }
 
@@ -141,7 +146,7 @@ static int norms2(dht_ctx* c, const void* f, size_t nvec, int nrhs, std::vector<
 }
 
 int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats,
-                 const double* zn2_known) {
+                 const double* zn2_known, Cx<double>* zx_out) {
     const double a = 4.0 + c->mass;
     const size_t nh = half_elems(c, nrhs);   // complex entries (= FP64 vectors) per half field
     const size_t bh = nh * 16;
@@ -161,6 +166,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     if (prm->tol <= 0.0 || prm->maxiter <= 0) return set_error(DHT_ERR_INVALID_ARG, "tol and maxiter must be positive");
     if (prm->method == DHT_SOLVER_DC_FGMRES_NN || prm->method == DHT_SOLVER_DC_FGMRES) {
         const bool use_nn = prm->method == DHT_SOLVER_DC_FGMRES_NN;
+        if (zx_out) return set_error(DHT_ERR_INVALID_ARG, "z^H x is fused only into the BiCGStab paths");
         int rc = solve_fgmres(c, prm, Z, X, nrhs, stats, use_nn, nullptr);
         if (rc != DHT_ERR_NOT_CONVERGED) return rc;
         // fallback: plain BiCGStab (FP32 inner, FP64 defect correction) for the whole batch
@@ -169,7 +175,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         p2.inner = DHT_FP32;
         std::vector<dht_solve_stats> st2(nrhs);
         std::vector<dht_solve_stats> st1(stats ? stats : st2.data(), (stats ? stats : st2.data()) + nrhs);
-        rc = solve_fields(c, &p2, Z, X, nrhs, st2.data(), zn2_known);
+        rc = solve_fields(c, &p2, Z, X, nrhs, st2.data(), zn2_known, nullptr);
         if (stats)
             for (int i = 0; i < nrhs; i++) {
                 stats[i] = st2[i];
@@ -196,7 +202,6 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     // full-lattice residual, checked last, is not lost to rounding
     for (int i = 0; i < nrhs; i++) target2[i] = 0.81 * prm->tol * prm->tol * zn2[i];
 
-    DHT_TRY(zero(c, X_e, bh));
     std::vector<int> iters(nrhs, 0), escalated(nrhs, DHT_STATUS_CONVERGED);
     std::vector<double> last_rn2(nrhs, INFINITY);
     int outer = 0, total_iters = 0;
@@ -204,6 +209,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     bool last_bad = false;
     bool have_full = false;        // the loop ended on a verified full-lattice residual
     std::vector<double> full2;     // its squared norms
+    std::vector<Cx<double>> zx_e, zx_o;   // z^H x per parity from the same epilogues
+    bool x_written = false;        // X_e holds the solution so far (else it is 0)
     void* e;
     for (; outer < max_outer; outer++) {
         bool any = false, stalled = false;
@@ -250,7 +257,9 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         }
         total_iters += std::max(maxit, 1);
         DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-        DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nrhs));
+        // the first correction is x itself: X_e = 0 is never materialised
+        DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nrhs, !x_written));
+        x_written = true;
         // When the inner solver's own residual says this correction finishes
         // every RHS, go straight to the full-lattice check: its even residual
         // z_e - a x_e + Hop_eo x_o / 2 is the Schur residual (x_o reconstructed
@@ -262,8 +271,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         if (predict) {
             DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false));
             std::vector<double> ro2;
-            DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2));
-            DHT_TRY(residual_hop(c, 1, X_e, tmp_o, X_o, -a, 0.5, Z_o, nrhs, 1, ro2));
+            DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, zx_out ? &zx_e : nullptr));
+            DHT_TRY(residual_hop(c, 1, X_e, tmp_o, X_o, -a, 0.5, Z_o, nrhs, 1, ro2, zx_out ? &zx_o : nullptr));
             bool done = true;
             full2.assign(nrhs, 0.0);
             for (int i = 0; i < nrhs; i++) {
@@ -287,6 +296,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             if (inner != start_inner && rn2[i] > target2[i])
                 escalated[i] = inner == DHT_FP32 ? DHT_STATUS_FALLBACK_FP32 : DHT_STATUS_FALLBACK_FP64;
     }
+    if (!x_written) DHT_TRY(zero(c, X_e, bh));
     std::vector<double> fr2;
     if (have_full) {
         fr2 = full2;
@@ -297,10 +307,12 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         void* full;
         DHT_TRY(ws_get(c, WS_XF, 2 * bh, &full));
         std::vector<double> fr2o;
-        DHT_TRY(residual_hop(c, 0, X_o, full, X_e, -a, 0.5, Z_e, nrhs, 0, fr2));
-        DHT_TRY(residual_hop(c, 1, X_e, (char*)full + bh, X_o, -a, 0.5, Z_o, nrhs, 1, fr2o));
+        DHT_TRY(residual_hop(c, 0, X_o, full, X_e, -a, 0.5, Z_e, nrhs, 0, fr2, zx_out ? &zx_e : nullptr));
+        DHT_TRY(residual_hop(c, 1, X_e, (char*)full + bh, X_o, -a, 0.5, Z_o, nrhs, 1, fr2o, zx_out ? &zx_o : nullptr));
         for (int i = 0; i < nrhs; i++) fr2[i] += fr2o[i];
     }
+    if (zx_out)
+        for (int i = 0; i < nrhs; i++) zx_out[i] = zx_e[i] + zx_o[i];
     bool all_ok = true;
     for (int i = 0; i < nrhs; i++) {
         double rr = zn2[i] > 0 ? sqrt(fr2[i] / zn2[i]) : 0.0;

@@ -242,6 +242,30 @@ def test_trace_batch_c1_mc_and_deflated(c1, c1_inv):
     ctx.clear_deflation()
 
 
+@pytest.mark.parametrize("method", ["fp64", "dc_bf16"])
+def test_solve_zero_right_hand_sides(c1, c1_inv, method):
+    """A zero right-hand side has the solution 0 (the solver writes it although
+    no correction is ever applied), alone or next to a non-zero one, and the
+    non-zero one is solved as usual."""
+    w, U, D, ctx = c1
+    L = _lib()
+    prm = (ctx.params(L.SOLVER_BICGSTAB_FP64, tol=1e-10) if method == "fp64"
+           else ctx.params(L.SOLVER_DC_BICGSTAB, inner=L.BF16, tol=1e-10))
+    shape = (2,) + ctx._spinor_shape()
+    # the workspace first holds a non-zero solution, so stale values would show
+    Z = cuda(random_spinors(w.L, 2, 5))
+    ctx.solve(Z, prm)
+    X, st, rc = ctx.solve(torch.zeros(shape, dtype=torch.complex128, device="cuda"), prm)
+    assert torch.count_nonzero(X).item() == 0
+    assert all(s["true_resid"] == 0.0 for s in st)
+    Z[1] = 0
+    X, st, rc = ctx.solve(Z, prm)
+    assert torch.count_nonzero(X[1]).item() == 0
+    x0 = X[0].cpu().numpy().ravel()
+    z0 = Z[0].cpu().numpy().ravel()
+    assert np.linalg.norm(x0 - c1_inv @ z0) <= 1e-8 * np.linalg.norm(c1_inv @ z0)
+
+
 def test_invalid_arguments(c1):
     w, U, D, ctx = c1
     L = _lib()
