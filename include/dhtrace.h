@@ -361,12 +361,17 @@ int dht_bench_hop(dht_ctx* ctx, int prec, int nrhs, int warmup, int reps, double
  *   DHT_HOP_TMARCH    one lane per (x, y, z column, RHS) walking t_chunk
  *                     slices in t, the backward t-neighbour kept in registers
  *                     (t_chunk even, divides Lt; 0 = automatic).
- * streaming_stores = 1 writes the output with non-temporal stores. */
+ * streaming_stores = 1 writes the output with non-temporal stores.
+ * rhs_group = G (a power of two dividing nrhs; 0 = nrhs): the lattice is swept
+ * once per group of G right-hand sides, the groups side by side on the chip,
+ * so fewer bytes per site share the caches while the links are read once per
+ * group (the LDS form needs G >= 8). */
 enum { DHT_HOP_SITE = 0, DHT_HOP_SITE_LDS = 1, DHT_HOP_TMARCH = 2 };
 typedef struct dht_hop_config {
     int form;
     int streaming_stores;
     int t_chunk;
+    int rhs_group;
 } dht_hop_config;
 
 /* Epilogue classes, tuned separately: DHT_HOP_PLAIN launches compute

@@ -58,7 +58,8 @@ class EigStats(ctypes.Structure):
 
 
 class HopConfig(ctypes.Structure):
-    _fields_ = [("form", ctypes.c_int), ("streaming_stores", ctypes.c_int), ("t_chunk", ctypes.c_int)]
+    _fields_ = [("form", ctypes.c_int), ("streaming_stores", ctypes.c_int), ("t_chunk", ctypes.c_int),
+                ("rhs_group", ctypes.c_int)]
 
 
 class TuneResult(ctypes.Structure):
@@ -445,7 +446,8 @@ class Context:
     def hop_config(self, prec: int, nrhs: int, epilogue: int = HOP_PLAIN) -> dict:
         h = HopConfig()
         check(load().dht_hop_config_get(self.h, prec, nrhs, epilogue, ctypes.byref(h)))
-        return {"form": h.form, "streaming_stores": h.streaming_stores, "t_chunk": h.t_chunk}
+        return {"form": h.form, "streaming_stores": h.streaming_stores, "t_chunk": h.t_chunk,
+                "rhs_group": h.rhs_group}
 
     def set_hop_config(self, prec: int, nrhs: int, cfg: dict | None, epilogue: int | None = None):
         """Install a hopping-kernel shape for (prec, nrhs) and one epilogue
@@ -454,7 +456,8 @@ class Context:
             if cfg is None:
                 check(load().dht_hop_config_set(self.h, prec, nrhs, cls, None))
                 continue
-            h = HopConfig(int(cfg["form"]), int(cfg.get("streaming_stores", 1)), int(cfg.get("t_chunk", 0)))
+            h = HopConfig(int(cfg["form"]), int(cfg.get("streaming_stores", 1)), int(cfg.get("t_chunk", 0)),
+                          int(cfg.get("rhs_group", 0)))
             check(load().dht_hop_config_set(self.h, prec, nrhs, cls, ctypes.byref(h)))
 
     def autotune_hop(self, prec: int, nrhs: int, reps: int = 10) -> dict:
@@ -464,7 +467,8 @@ class Context:
         r = TuneResult()
         check(load().dht_autotune_hop(self.h, prec, nrhs, reps, ctypes.byref(r)))
         best = {HOP_CLASSES[k]: {"form": r.best[k].form, "streaming_stores": r.best[k].streaming_stores,
-                                 "t_chunk": r.best[k].t_chunk} for k in (HOP_PLAIN, HOP_FUSED)}
+                                 "t_chunk": r.best[k].t_chunk, "rhs_group": r.best[k].rhs_group}
+                for k in (HOP_PLAIN, HOP_FUSED)}
         out = {"prec": prec, "nrhs": nrhs, "best": best,
                "best_form": {c: HOP_FORMS[b["form"]] for c, b in best.items()},
                "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in (HOP_PLAIN, HOP_FUSED)},
@@ -480,7 +484,8 @@ class Context:
         cp = cache_path.encode() if cache_path else None
         check(load().dht_autotune(self.h, prec, nrhs, reps, cp, ctypes.byref(r)))
         return {"best": {HOP_CLASSES[k]: {"form": r.best[k].form, "streaming_stores": r.best[k].streaming_stores,
-                                          "t_chunk": r.best[k].t_chunk} for k in (HOP_PLAIN, HOP_FUSED)},
+                                          "t_chunk": r.best[k].t_chunk, "rhs_group": r.best[k].rhs_group}
+                         for k in (HOP_PLAIN, HOP_FUSED)},
                 "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in (HOP_PLAIN, HOP_FUSED)},
                 "candidates": r.candidates, "rejected": r.rejected}
 

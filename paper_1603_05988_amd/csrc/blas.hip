@@ -220,8 +220,9 @@ int dots(dht_ctx* c, int prec, int np, const void* const* a, const void* const* 
 }
 
 size_t partial_bytes(const dht_ctx* c, int nrhs) {
-    // enough for a fused hop epilogue (one partial per hop workgroup) with 3 pairs
-    size_t nb = std::max<size_t>(RED_MAX_BLOCKS, (size_t)hop_blocks(c, nrhs));
+    // enough for a fused hop epilogue (one partial per hop workgroup, at most
+    // hop_blocks + nrhs of them with RHS groups) with 3 pairs
+    size_t nb = std::max<size_t>(RED_MAX_BLOCKS, (size_t)hop_blocks(c, nrhs) + nrhs);
     return nb * 3 * nrhs * sizeof(Cx<double>);
 }
 

@@ -39,7 +39,9 @@ struct HopArgs {
     int Vh;
     int antiperiodic;
     int out_parity;
-    int bshift;          // log2(B)
+    int bshift;          // log2(B): the layout's RHS count
+    int gshift;          // log2(G): RHS handled per sweep of the lattice (G divides B)
+    int bpg;             // workgroups per RHS group; logical workgroup = group * bpg + index
     int tc, nchunk;      // t-marching: slices per chunk (even, divides Lt) and chunks
     int nt;              // non-temporal (streaming) output stores
     double ca, cb, cz;   // out = ca * x + cb * Hop(in) + cz * z
@@ -281,15 +283,17 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
     }
 }
 
-// workgroup tree over the lanes of equal RHS, partial[blk][q][B]
+// workgroup tree over the lanes of equal RHS, partial[blk][q][B]; a workgroup
+// of RHS group g (G RHS from g * G) writes zeros for the other RHS
 template <int NP>
-__device__ inline void hop_block_reduce(const HopArgs& a, int blk, int B, Cx<double> d0, Cx<double> d1) {
+__device__ inline void hop_block_reduce(const HopArgs& a, int blk, int g, Cx<double> d0, Cx<double> d1) {
     if (NP > 0) {
+        const int B = 1 << a.bshift, G = 1 << a.gshift;
         __shared__ Cx<double> red[NP > 0 ? NP : 1][HOP_THREADS];
         red[0][threadIdx.x] = d0;
         if (NP > 1) red[NP - 1][threadIdx.x] = d1;
         __syncthreads();
-        for (int w = HOP_THREADS / 2; w >= B; w >>= 1) {
+        for (int w = HOP_THREADS / 2; w >= G; w >>= 1) {
             if ((int)threadIdx.x < w) {
 #pragma unroll
                 for (int q = 0; q < NP; q++) red[q][threadIdx.x] = red[q][threadIdx.x] + red[q][threadIdx.x + w];
@@ -297,8 +301,11 @@ __device__ inline void hop_block_reduce(const HopArgs& a, int blk, int B, Cx<dou
             __syncthreads();
         }
         if ((int)threadIdx.x < B) {
+            const int lr = (int)threadIdx.x - g * G;
+            const bool mine = lr >= 0 && lr < G;
 #pragma unroll
-            for (int q = 0; q < NP; q++) a.partial[((int64_t)blk * NP + q) * B + threadIdx.x] = red[q][threadIdx.x];
+            for (int q = 0; q < NP; q++)
+                a.partial[((int64_t)blk * NP + q) * B + threadIdx.x] = mine ? red[q][lr] : cmake(0.0, 0.0);
         }
     }
 }
@@ -312,14 +319,16 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
     constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : ((DOT == HOPDOT_OUT_X || DOT == HOPDOT_NORM_ZX) ? 2 : 0);
     extern __shared__ uint4 hop_lds[];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int B = 1 << a.bshift;
-    const int ns = HOP_THREADS >> a.bshift;
-    const int sl = threadIdx.x >> a.bshift;
-    const int s = blk * ns + sl;
-    const int r = threadIdx.x & (B - 1);
+    const int g = blk / a.bpg;                 // RHS group
+    const int bl = blk - g * a.bpg;            // workgroup within the group's sweep
+    const int G = 1 << a.gshift;
+    const int ns = HOP_THREADS >> a.gshift;
+    const int sl = threadIdx.x >> a.gshift;
+    const int s = bl * ns + sl;
+    const int r = g * G + (threadIdx.x & (G - 1));
     const int p = a.out_parity;
     if (LDSL) {
-        const int s0 = blk * ns;
+        const int s0 = bl * ns;
         stage_links<S>(a, hop_lds, ns, [&](int k) { return s0 + k < a.Vh ? s0 + k : -1; });
         __syncthreads();
     }
@@ -357,7 +366,7 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
 #undef DHT_DIR
         hop_epilogue<S, G5OUT, XPAY, DOT>(a, s, r, acc, d0, d1);
     }
-    hop_block_reduce<NP>(a, blk, B, d0, d1);
+    hop_block_reduce<NP>(a, blk, g, d0, d1);
 }
 
 // ---------------------------------------------------------------------------
@@ -456,10 +465,11 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
     constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : ((DOT == HOPDOT_OUT_X || DOT == HOPDOT_NORM_ZX) ? 2 : 0);
     constexpr int SF = DAG ? -1 : 1;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int gid = blk * HOP_THREADS + threadIdx.x;
-    const int B = 1 << a.bshift;
-    const int col = gid >> a.bshift;   // chunk * V3 + column
-    const int r = gid & (B - 1);
+    const int g = blk / a.bpg;                 // RHS group
+    const int gid = (blk - g * a.bpg) * HOP_THREADS + threadIdx.x;
+    const int G = 1 << a.gshift;
+    const int col = gid >> a.gshift;   // chunk * V3 + column
+    const int r = g * G + (gid & (G - 1));
     const int V3 = a.Vh / a.Lt;
     const int chunk = col / V3;
     Cx<double> d0 = cmake(0.0, 0.0), d1 = cmake(0.0, 0.0);
@@ -485,7 +495,7 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
             tm_step<S, DAG, G5OUT, XPAY, DOT>(a, t + 1, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb1, d0, d1);
         }
     }
-    hop_block_reduce<NP>(a, blk, B, d0, d1);
+    hop_block_reduce<NP>(a, blk, g, d0, d1);
 }
 
 template <typename S> constexpr int prec_of() {
@@ -510,8 +520,10 @@ int hop_config_check(const dht_ctx* c, int nrhs, const HopConfig& h) {
     if (log2_batch(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
     if (h.form < DHT_HOP_SITE || h.form > DHT_HOP_TMARCH || (h.nt != 0 && h.nt != 1))
         return set_error(DHT_ERR_INVALID_ARG, "bad hop form");
-    if (h.form == DHT_HOP_SITE_LDS && (HOP_THREADS / nrhs) > 32)
-        return set_error(DHT_ERR_INVALID_ARG, "LDS-link form needs at least 8 right-hand sides");
+    const int G = h.rg > 0 ? h.rg : nrhs;
+    if (log2_batch(G) < 0 || G > nrhs) return set_error(DHT_ERR_INVALID_ARG, "RHS group must be a power of two <= nrhs");
+    if (h.form == DHT_HOP_SITE_LDS && (HOP_THREADS / G) > 32)
+        return set_error(DHT_ERR_INVALID_ARG, "LDS-link form needs at least 8 right-hand sides per sweep");
     if (h.form == DHT_HOP_TMARCH && h.tc != 0 && (h.tc < 2 || (h.tc & 1) || c->g.L[3] % h.tc))
         return set_error(DHT_ERR_INVALID_ARG, "t chunk must be even and divide Lt");
     return DHT_OK;
@@ -539,6 +551,8 @@ HopConfig hop_config(const dht_ctx* c, int prec, int nrhs, int cls) {
     return h;
 }
 
+// workgroups of the site-parallel forms with one sweep over all RHS; the
+// other shapes use at most this many plus one per RHS group
 int hop_blocks(const dht_ctx* c, int nrhs) {
     int64_t n = c->g.Vh * (int64_t)nrhs;
     return (int)((n + HOP_THREADS - 1) / HOP_THREADS);
@@ -580,10 +594,14 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     a.nchunk = a.Lt / cfg.tc;
     a.nt = cfg.nt;
     const int mode = cfg.form;
-    const int ns = HOP_THREADS >> a.bshift;   // sites per workgroup (site-parallel forms)
-    const int nb = mode == DHT_HOP_TMARCH
-                       ? (int)((c->g.Vh / a.Lt * (int64_t)a.nchunk * nrhs + HOP_THREADS - 1) / HOP_THREADS)
-                       : hop_blocks(c, nrhs);
+    const int G = cfg.rg > 0 ? cfg.rg : nrhs;   // RHS per sweep
+    a.gshift = log2_batch(G);
+    if (a.gshift < 0 || G > nrhs) return set_error(DHT_ERR_INVALID_ARG, "bad RHS group");
+    const int ns = HOP_THREADS >> a.gshift;   // sites per workgroup (site-parallel forms)
+    a.bpg = mode == DHT_HOP_TMARCH
+                ? (int)((c->g.Vh / a.Lt * (int64_t)a.nchunk * G + HOP_THREADS - 1) / HOP_THREADS)
+                : (int)((c->g.Vh + ns - 1) / ns);
+    const int nb = a.bpg * (nrhs / G);
     const size_t lds = mode == DHT_HOP_SITE_LDS ? (size_t)8 * ns * ((9 + Store<S>::VW - 1) / Store<S>::VW) * 16 : 0;
     const size_t tm_lds = (size_t)2 * 6 * HOP_THREADS * sizeof(Cx<typename Store<S>::acc>);
     if (dot) dot->nblocks = nb;

@@ -236,6 +236,7 @@ struct HopConfig {
     int form = -1;
     int nt = 1;
     int tc = 0;
+    int rg = 0;   // RHS per sweep of the lattice (0: all)
 };
 
 struct NNState {

@@ -128,23 +128,28 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
     // in = the odd half of the probe field, x = its even half
     TuneLaunch L{HOP_PLAIN, (const char*)fi + half, fo, fi, (Cx<double>*)part};
 
+    // every form and t chunk, with streaming stores on and off, sweeping the
+    // lattice once for all RHS or once per group of nrhs / 2 or nrhs / 4
     std::vector<HopConfig> cand;
-    for (int nt = 0; nt < 2; nt++) {
-        HopConfig h;
-        h.nt = nt;
-        h.form = DHT_HOP_SITE;
-        cand.push_back(h);
-        if (HOP_LANES / nrhs <= 32) {
-            h.form = DHT_HOP_SITE_LDS;
+    for (int gdiv = 1; gdiv <= 4 && gdiv <= nrhs; gdiv *= 2)
+        for (int nt = 0; nt < 2; nt++) {
+            HopConfig h;
+            h.rg = gdiv == 1 ? 0 : nrhs / gdiv;
+            const int G = nrhs / gdiv;
+            h.nt = nt;
+            h.form = DHT_HOP_SITE;
             cand.push_back(h);
-        }
-        h.form = DHT_HOP_TMARCH;
-        for (int tc = 2; tc <= c->g.L[3]; tc += 2)
-            if (c->g.L[3] % tc == 0) {
-                h.tc = tc;
+            if (HOP_LANES / G <= 32) {
+                h.form = DHT_HOP_SITE_LDS;
                 cand.push_back(h);
             }
-    }
+            h.form = DHT_HOP_TMARCH;
+            for (int tc = 2; tc <= c->g.L[3]; tc += 2)
+                if (c->g.L[3] % tc == 0) {
+                    h.tc = tc;
+                    cand.push_back(h);
+                }
+        }
     int rejected = 0;
     double worst_ok = 0.0;
     for (int cls = 0; cls < 2; cls++) {
@@ -183,6 +188,7 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
         res->best[cls].form = best.form;
         res->best[cls].streaming_stores = best.nt;
         res->best[cls].t_chunk = best.form == DHT_HOP_TMARCH ? best.tc : 0;
+        res->best[cls].rhs_group = best.rg > 0 ? best.rg : nrhs;
         res->best_ms[cls] = best_ms;
         res->default_ms[cls] = def_ms;
     }
@@ -212,6 +218,7 @@ int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, int epilogue, const dht_h
     h.form = cfg->form;
     h.nt = cfg->streaming_stores;
     h.tc = cfg->form == DHT_HOP_TMARCH ? cfg->t_chunk : 0;
+    h.rg = cfg->rhs_group == nrhs ? 0 : cfg->rhs_group;
     DHT_TRY(hop_config_check(c, nrhs, h));
     c->hop_cfg[prec][b][epilogue] = h;
     return DHT_OK;
@@ -226,6 +233,7 @@ int dht_hop_config_get(dht_ctx* c, int prec, int nrhs, int epilogue, dht_hop_con
     out->form = h.form;
     out->streaming_stores = h.nt;
     out->t_chunk = h.form == DHT_HOP_TMARCH ? h.tc : 0;
+    out->rhs_group = h.rg > 0 ? h.rg : nrhs;
     return DHT_OK;
 }
 
@@ -253,7 +261,7 @@ int dht_autotune(dht_ctx* c, int prec, int nrhs, int reps, const char* cache_pat
     if (!c || !out) return set_error(DHT_ERR_INVALID_ARG, "null argument");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
     if (log2_pow2(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
-    // cache lines: "hop Lx Ly Lz Lt prec nrhs class form streaming_stores t_chunk ms"
+    // cache lines: "hop Lx Ly Lz Lt prec nrhs class form streaming_stores t_chunk rhs_group ms"
     if (cache_path) {
         FILE* f = fopen(cache_path, "r");
         if (f) {
@@ -261,13 +269,13 @@ int dht_autotune(dht_ctx* c, int prec, int nrhs, int reps, const char* cache_pat
             double ms[2] = {0, 0};
             bool have[2] = {false, false};
             char tag[8];
-            int L[4], p, n, cls, form, nt, tc;
+            int L[4], p, n, cls, form, nt, tc, rg;
             double t;
-            while (fscanf(f, "%7s %d %d %d %d %d %d %d %d %d %d %lf", tag, &L[0], &L[1], &L[2], &L[3], &p, &n, &cls,
-                          &form, &nt, &tc, &t) == 12) {
+            while (fscanf(f, "%7s %d %d %d %d %d %d %d %d %d %d %d %lf", tag, &L[0], &L[1], &L[2], &L[3], &p, &n, &cls,
+                          &form, &nt, &tc, &rg, &t) == 13) {
                 if (strcmp(tag, "hop") != 0 || p != prec || n != nrhs || cls < 0 || cls > 1) continue;
                 if (L[0] != c->g.L[0] || L[1] != c->g.L[1] || L[2] != c->g.L[2] || L[3] != c->g.L[3]) continue;
-                found[cls] = dht_hop_config{form, nt, tc};
+                found[cls] = dht_hop_config{form, nt, tc, rg};
                 ms[cls] = t;
                 have[cls] = true;
             }
@@ -291,9 +299,9 @@ int dht_autotune(dht_ctx* c, int prec, int nrhs, int reps, const char* cache_pat
         FILE* f = fopen(cache_path, "a");
         if (!f) return set_error(DHT_ERR_INVALID_ARG, std::string("cannot write ") + cache_path);
         for (int cls = 0; cls < 2; cls++)
-            fprintf(f, "hop %d %d %d %d %d %d %d %d %d %d %.6g\n", c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3], prec,
-                    nrhs, cls, out->best[cls].form, out->best[cls].streaming_stores, out->best[cls].t_chunk,
-                    out->best_ms[cls]);
+            fprintf(f, "hop %d %d %d %d %d %d %d %d %d %d %d %.6g\n", c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3],
+                    prec, nrhs, cls, out->best[cls].form, out->best[cls].streaming_stores, out->best[cls].t_chunk,
+                    out->best[cls].rhs_group, out->best_ms[cls]);
         if (fclose(f) != 0) return set_error(DHT_ERR_INVALID_ARG, std::string("cannot write ") + cache_path);
     }
     return DHT_OK;

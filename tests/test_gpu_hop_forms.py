@@ -2,7 +2,8 @@
 autotuner that chooses among them.
 
 The forms (one lane per site with links per lane or staged in LDS; one lane
-per (x, y, z) column walking t in chunks, with or without streaming stores)
+per (x, y, z) column walking t in chunks, with or without streaming stores,
+sweeping the lattice once for all right-hand sides or once per group of them)
 accumulate the same 8 neighbour terms in different orders, so each must match
 the dense Wilson matrix to the storage precision: FP64 1e-13 relative
 (max-norm), FP32 1e-6, BF16 2e-2 (Frobenius).  The fused-dot variants used
@@ -31,13 +32,14 @@ def cuda(a):
 
 def forms(L, nrhs):
     out = []
-    for nt in (0, 1):
-        out.append({"form": 0, "streaming_stores": nt, "t_chunk": 0})
-        if nrhs >= 8:
-            out.append({"form": 1, "streaming_stores": nt, "t_chunk": 0})
-        for tc in range(2, L[3] + 1, 2):
-            if L[3] % tc == 0:
-                out.append({"form": 2, "streaming_stores": nt, "t_chunk": tc})
+    for G in sorted({nrhs, max(1, nrhs // 2), max(1, nrhs // 4)}, reverse=True):
+        for nt in (0, 1):
+            out.append({"form": 0, "streaming_stores": nt, "t_chunk": 0, "rhs_group": G})
+            if G >= 8:
+                out.append({"form": 1, "streaming_stores": nt, "t_chunk": 0, "rhs_group": G})
+            for tc in range(2, L[3] + 1, 2):
+                if L[3] % tc == 0:
+                    out.append({"form": 2, "streaming_stores": nt, "t_chunk": tc, "rhs_group": G})
     return out
 
 
@@ -68,6 +70,7 @@ def test_every_form_matches_dense(L, nrhs):
             for cls in (Lb.HOP_PLAIN, Lb.HOP_FUSED):
                 got = ctx.hop_config(prec, nrhs, cls)
                 assert got["form"] == cfg["form"] and got["streaming_stores"] == cfg["streaming_stores"]
+                assert got["rhs_group"] == cfg["rhs_group"]
                 if cfg["form"] == 2:
                     assert got["t_chunk"] == cfg["t_chunk"]
             for op, ref in refs.items():
@@ -81,7 +84,9 @@ def test_every_form_matches_dense(L, nrhs):
 @pytest.mark.parametrize("cfg", [{"form": 0, "streaming_stores": 0, "t_chunk": 0},
                                  {"form": 1, "streaming_stores": 1, "t_chunk": 0},
                                  {"form": 2, "streaming_stores": 1, "t_chunk": 2},
-                                 {"form": 2, "streaming_stores": 0, "t_chunk": 4}])
+                                 {"form": 2, "streaming_stores": 0, "t_chunk": 4},
+                                 {"form": 0, "streaming_stores": 1, "t_chunk": 0, "rhs_group": 2},
+                                 {"form": 2, "streaming_stores": 1, "t_chunk": 2, "rhs_group": 4}])
 def test_solves_in_every_form(cfg):
     """BiCGStab (FP64, and FP32 inside FP64 defect correction) with the fused
     hop+dot kernels in one forced shape, against the LU inverse."""
@@ -117,6 +122,12 @@ def test_invalid_shapes_rejected():
         ctx.set_hop_config(1, 12, {"form": 0})                         # batch not a power of two
     with pytest.raises(Lb.DhtError):
         ctx.set_hop_config(1, 16, {"form": 7})
+    with pytest.raises(Lb.DhtError):
+        ctx.set_hop_config(1, 16, {"form": 0, "rhs_group": 3})         # group not a power of two
+    with pytest.raises(Lb.DhtError):
+        ctx.set_hop_config(1, 16, {"form": 0, "rhs_group": 32})        # group larger than the batch
+    with pytest.raises(Lb.DhtError):
+        ctx.set_hop_config(1, 16, {"form": 1, "rhs_group": 4})         # LDS links need >= 8 RHS per sweep
     with pytest.raises(Lb.DhtError):
         ctx.autotune_hop(1, 16, 2)                                       # no gauge field yet
     ctx.close()
