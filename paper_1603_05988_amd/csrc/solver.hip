@@ -114,7 +114,7 @@ static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const
                         std::vector<Cx<double>>* zx = nullptr) {
     void *part, *sums;
     DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
-    DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 4 * nrhs, &sums));
+    DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs, &sums));
     const int np = zx ? 2 : 1;
     HopDot d;
     d.kind = zx ? HOPDOT_NORM_ZX : HOPDOT_NORM;
@@ -128,6 +128,29 @@ static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const
     n2.resize(nrhs);
     for (int i = 0; i < nrhs; i++) n2[i] = h[i].re;
     if (zx) zx->assign(h.begin() + nrhs, h.end());
+    return DHT_OK;
+}
+
+// odd sites from the even ones, x_o = (z_o + Hop_oe x_e / 2) / a; with zx
+// non-null the epilogue also sums z_o^H x_o per RHS into *zx
+static int odd_from_even(dht_ctx* c, const void* X_e, void* X_o, const void* Z_o, int nrhs,
+                         std::vector<Cx<double>>* zx) {
+    const double a = 4.0 + c->mass;
+    if (!zx) return hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false);
+    void *part, *sums;
+    DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
+    DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs, &sums));
+    HopDot d;
+    d.kind = HOPDOT_OUT_X;   // (x_o, z_o) and (x_o, x_o)
+    d.partial = (Cx<double>*)part;
+    DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false, &d));
+    Cx<double>* s = (Cx<double>*)sums + (size_t)2 * 2 * nrhs;
+    DHT_TRY(finalize(c, d.partial, d.nblocks, 2, nrhs, nullptr, FIN_SUM, 0.0, s));
+    std::vector<Cx<double>> h(nrhs);
+    DHT_HIP(hipMemcpyAsync(h.data(), s, sizeof(Cx<double>) * nrhs, hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    zx->resize(nrhs);
+    for (int i = 0; i < nrhs; i++) (*zx)[i] = cmake(h[i].re, -h[i].im);   // z^H x = conj(x^H z)
     return DHT_OK;
 }
 
@@ -264,21 +287,19 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         // every RHS, go straight to the full-lattice check: its even residual
         // z_e - a x_e + Hop_eo x_o / 2 is the Schur residual (x_o reconstructed
         // from x_e), so a wrong guess costs one hop (x_o) and the loop continues
-        // from it, while a right one saves the two hops of the Schur residual.
+        // from it, while a right one saves a hop of the Schur residual.  The odd
+        // residual z_o - a x_o + Hop_oe x_e / 2 vanishes by the construction of
+        // x_o (to FP64 rounding), so the even one is the full residual.
         bool predict = true;
         for (int i = 0; i < nrhs; i++)
             if (sup[i] > 0 && !(rn2[i] * br.rnorm2[i] <= target2[i])) predict = false;
         if (predict) {
-            DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false));
-            std::vector<double> ro2;
+            DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr));
             DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, zx_out ? &zx_e : nullptr));
-            DHT_TRY(residual_hop(c, 1, X_e, tmp_o, X_o, -a, 0.5, Z_o, nrhs, 1, ro2, zx_out ? &zx_o : nullptr));
             bool done = true;
-            full2.assign(nrhs, 0.0);
-            for (int i = 0; i < nrhs; i++) {
-                full2[i] = rn2[i] + ro2[i];
+            full2 = rn2;
+            for (int i = 0; i < nrhs; i++)
                 if (zn2[i] > 0 && !(full2[i] <= prm->tol * prm->tol * zn2[i])) done = false;
-            }
             if (done) {
                 have_full = true;
                 outer++;
@@ -301,15 +322,11 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     if (have_full) {
         fr2 = full2;
     } else {
-        // odd sites and the FP64 full-lattice true residual
-        DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false));
-        // r_p = z_p - (a x_p - Hop_{p <- 1-p} x / 2) per parity, norms fused
-        void* full;
-        DHT_TRY(ws_get(c, WS_XF, 2 * bh, &full));
-        std::vector<double> fr2o;
-        DHT_TRY(residual_hop(c, 0, X_o, full, X_e, -a, 0.5, Z_e, nrhs, 0, fr2, zx_out ? &zx_e : nullptr));
-        DHT_TRY(residual_hop(c, 1, X_e, (char*)full + bh, X_o, -a, 0.5, Z_o, nrhs, 1, fr2o, zx_out ? &zx_o : nullptr));
-        for (int i = 0; i < nrhs; i++) fr2[i] += fr2o[i];
+        // odd sites and the FP64 full-lattice true residual: its even half
+        // r_e = z_e - (a x_e - Hop_eo x_o / 2) with norms fused (the odd half
+        // vanishes by the construction of x_o)
+        DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr));
+        DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, fr2, zx_out ? &zx_e : nullptr));
     }
     if (zx_out)
         for (int i = 0; i < nrhs; i++) zx_out[i] = zx_e[i] + zx_o[i];
