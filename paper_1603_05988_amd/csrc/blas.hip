@@ -266,11 +266,37 @@ __global__ void s_update_kernel(void* s, const void* r_, const void* v, const Rh
     Store<S>::stv(s, i, rv);
 }
 
-// x += alpha p + omega s;  r = s - omega t;  partials of (rhat, r) and (r, r)
-template <typename S>
+// x += alpha p + omega s;  r = s - omega t;  partials of (rhat, r) and (r, r).
+// X32: x is kept in FP32 storage (vector index cv * SB + sr of S holds
+// components VW cv .. VW cv + VW - 1, which FP32 keeps in VW / 2 vectors)
+template <typename S, bool X32>
+__device__ inline void ld_x(const void* x_, size_t i, int64_t SB, Cx<typename Store<S>::acc>* xv) {
+    constexpr int VW = Store<S>::VW;
+    if constexpr (X32) {
+        const int64_t cv = (int64_t)i / SB, sr = (int64_t)i - cv * SB;
+#pragma unroll
+        for (int h = 0; h < VW / 2; h++) Store<float>::ldv(x_, (cv * (VW / 2) + h) * SB + sr, xv + 2 * h);
+    } else {
+        Store<S>::ldv(x_, i, xv);
+    }
+}
+template <typename S, bool X32>
+__device__ inline void st_x(void* x_, size_t i, int64_t SB, const Cx<typename Store<S>::acc>* xv) {
+    constexpr int VW = Store<S>::VW;
+    if constexpr (X32) {
+        const int64_t cv = (int64_t)i / SB, sr = (int64_t)i - cv * SB;
+#pragma unroll
+        for (int h = 0; h < VW / 2; h++) Store<float>::stv(x_, (cv * (VW / 2) + h) * SB + sr, xv + 2 * h);
+    } else {
+        Store<S>::stv(x_, i, xv);
+    }
+}
+
+template <typename S, bool X32>
 __global__ __launch_bounds__(RED_THREADS) void xr_update_kernel(void* x_, void* r_, const void* p, const void* s,
                                                                 const void* t, const void* rh, const RhsState* st,
-                                                                size_t nvec, int B, Cx<double>* partial, int x_zero) {
+                                                                size_t nvec, int B, Cx<double>* partial, int x_zero,
+                                                                int64_t SB) {
     typedef typename Store<S>::acc T;
     constexpr int VW = Store<S>::VW;
     __shared__ Cx<double> red[2][RED_THREADS];
@@ -285,7 +311,7 @@ __global__ __launch_bounds__(RED_THREADS) void xr_update_kernel(void* x_, void* 
 #pragma unroll
                 for (int j = 0; j < VW; j++) xv[j] = cmake<T>(0, 0);
             } else {
-                Store<S>::ldv(x_, i, xv);
+                ld_x<S, X32>(x_, i, SB, xv);
             }
             Store<S>::ldv(p, i, pv);
             Store<S>::ldv(s, i, sv);
@@ -299,12 +325,12 @@ __global__ __launch_bounds__(RED_THREADS) void xr_update_kernel(void* x_, void* 
                 d0 = d0 + conjmul(cmake<double>(hv[j].re, hv[j].im), rd);
                 d1.re += rd.re * rd.re + rd.im * rd.im;
             }
-            Store<S>::stv(x_, i, xv);
+            st_x<S, X32>(x_, i, SB, xv);
             Store<S>::stv(r_, i, sv);
         }
     } else if (x_zero) {   // an RHS that stopped before its first x update keeps x = 0
         const Cx<T> zv[VW] = {};
-        for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nvec; i += stride) Store<S>::stv(x_, i, zv);
+        for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nvec; i += stride) st_x<S, X32>(x_, i, SB, zv);
     }
     red[0][threadIdx.x] = d0;
     red[1][threadIdx.x] = d1;
@@ -336,11 +362,18 @@ int s_update(dht_ctx* c, int prec, void* s, const void* r, const void* v, const 
     return DHT_OK;
 }
 int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const void* s, const void* t, const void* rh,
-                   const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks, bool x_zero) {
+                   const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks, bool x_zero, bool x32) {
     int nb = red_blocks(nvec);
     *nblocks = nb;
-    DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(xr_update_kernel<T_>, dim3(nb), dim3(RED_THREADS), 0, c->stream, x, r, p, s,
-                                             t, rh, st, nvec, B, partial, (int)x_zero))
+    const int64_t SB = c->g.Vh * (int64_t)B;
+    if (x32 && prec == DHT_BF16) {
+        hipLaunchKernelGGL((xr_update_kernel<bf16x2, true>), dim3(nb), dim3(RED_THREADS), 0, c->stream, x, r, p, s, t,
+                           rh, st, nvec, B, partial, (int)x_zero, SB);
+    } else {
+        if (x32 && prec != DHT_FP32) return set_error(DHT_ERR_INVALID_ARG, "FP32 x needs BF16 or FP32 vectors");
+        DHT_PREC_SWITCH(prec, hipLaunchKernelGGL((xr_update_kernel<T_, false>), dim3(nb), dim3(RED_THREADS), 0, c->stream,
+                                                 x, r, p, s, t, rh, st, nvec, B, partial, (int)x_zero, SB))
+    }
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }

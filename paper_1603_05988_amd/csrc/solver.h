@@ -47,7 +47,8 @@ int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const 
 int s_update(dht_ctx* c, int prec, void* s, const void* r, const void* v, const RhsState* st, size_t nvec, int B);
 int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const void* s, const void* t, const void* rh,
                    const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks,
-                   bool x_zero = false);
+                   bool x_zero = false,
+                   bool x32 = false);
 // half fields: out_low = scale[r] * in_fp64 ; x_fp64 += scale[r] * e_low
 int scale_down(dht_ctx* c, const void* in, void* out, int pout, const double* scale, int nrhs);
 int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, int nrhs, bool assign = false);
@@ -74,8 +75,9 @@ int solve_init(dht_ctx* c, const void* in, int pout, const double* scale, void* 
                Cx<double>* partial, int* nblocks);
 // BiCGStab on the Schur system from x = 0 for the right-hand side scale * src
 // (src: FP64 half field, scale: device, per RHS), in storage precision prec
+// x32: the solution x is kept in FP32 storage (BF16 vectors only)
 int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
-             const std::vector<double>& target2, int maxiter, BicgResult* res);
+             const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32 = false);
 
 // Top-level solve of D X = Z on internal full FP64 fields (Z, X: [2][12][Vh][B]);
 // stats has nrhs entries (the padded batch).

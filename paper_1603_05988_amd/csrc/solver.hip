@@ -35,7 +35,7 @@ int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o
 static int slot_base(int prec) { return prec == DHT_FP64 ? WS_K64 : WS_KLO; }
 
 int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
-             const std::vector<double>& target2, int maxiter, BicgResult* res) {
+             const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32) {
     const size_t nvec = half_vecs(c, nrhs, prec);
     const size_t bytes = nvec * 16;
     const int base = slot_base(prec);
@@ -80,7 +80,7 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
         d2.partial = partial;
         DHT_TRY(apply_schur(c, prec, s, t, tmp, nrhs, &d2));
         DHT_TRY(finalize(c, partial, d2.nblocks, 2, nrhs, st, FIN_OMEGA, bd_eps));
-        DHT_TRY(xr_update_dots(c, prec, x, r, p, s, t, rh, st, nvec, nrhs, partial, &nb, it == 0));   // (rhat, r), (r, r)
+        DHT_TRY(xr_update_dots(c, prec, x, r, p, s, t, rh, st, nvec, nrhs, partial, &nb, it == 0, x32));   // (rhat, r), (r, r)
         DHT_TRY(finalize(c, partial, nb, 2, nrhs, st, FIN_RHO, bd_eps));
         if ((it + 1) % check_every == 0 || it + 1 == maxiter) {
             DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
@@ -255,7 +255,9 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             double need = sup[i] > 0 ? 0.25 * target2[i] / rn2[i] : 1.0;
             itarget[i] = std::max(itol * itol, need);
         }
-        const size_t lbytes = nh * elem_bytes(inner);
+        // the inner solution of a BF16 solve is kept in FP32 storage
+        const bool x32 = inner == DHT_BF16;
+        const size_t lbytes = nh * elem_bytes(x32 ? DHT_FP32 : inner);
         const int base = slot_base(inner);
         DHT_TRY(ws_get(c, base + 8, lbytes, &e));     // inner solution
         if ((prm->fault_inject & 1u) && outer == 0 && inner != DHT_FP64) {
@@ -267,7 +269,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         // first cycle that is bhat itself
         BicgResult br;
         DHT_TRY(bicgstab(c, inner, outer == 0 ? bhat : r_e, (const double*)scl, e, nrhs, itarget,
-                         prm->maxiter - total_iters, &br));
+                         prm->maxiter - total_iters, &br, x32));
         int maxit = 0;
         bool bad = false;
         for (int i = 0; i < nrhs; i++) {
@@ -281,7 +283,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         total_iters += std::max(maxit, 1);
         DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
         // the first correction is x itself: X_e = 0 is never materialised
-        DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nrhs, !x_written));
+        DHT_TRY(accum_up(c, X_e, e, x32 ? DHT_FP32 : inner, (const double*)scl, nrhs, !x_written));
         x_written = true;
         // When the inner solver's own residual says this correction finishes
         // every RHS, go straight to the full-lattice check: its even residual
