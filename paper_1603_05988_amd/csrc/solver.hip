@@ -65,7 +65,10 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     int nb;
     DHT_TRY(solve_init(c, src, prec, scale, r, rh, p, nrhs, partial, &nb));
     DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_INIT, bd_eps));
-    const int check_every = 2;
+    // the host reads the per-RHS states after every iteration: a batch that
+    // converges stops at once (a skipped check costs a whole iteration of 4
+    // hops, a check only a short stream synchronisation)
+    const int check_every = 1;
     for (int it = 0; it < maxiter; it++) {
         if (it > 0) DHT_TRY(p_update(c, prec, p, r, v, st, nvec, nrhs));
         HopDot d1;
