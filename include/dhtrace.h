@@ -376,8 +376,10 @@ typedef struct dht_hop_config {
 
 /* Epilogue classes, tuned separately: DHT_HOP_PLAIN launches compute
  * out = b Hop(in); DHT_HOP_FUSED launches also read an x-pay operand (and a
- * second axpy operand or fused dot products), as in the Krylov solvers. */
-enum { DHT_HOP_PLAIN = 0, DHT_HOP_FUSED = 1 };
+ * second axpy operand or fused sums of the output with its own operands);
+ * DHT_HOP_FUSED_A launches read an x-pay operand and sum (a, out) with a
+ * third operand a (BiCGStab's (rhat, v)). */
+enum { DHT_HOP_PLAIN = 0, DHT_HOP_FUSED = 1, DHT_HOP_FUSED_A = 2 };
 
 /* Set the hopping-kernel shape used for (prec, nrhs, epilogue class) on this
  * context; cfg = NULL restores the built-in default.  Errors:
@@ -388,9 +390,9 @@ int dht_hop_config_set(dht_ctx* ctx, int prec, int nrhs, int epilogue, const dht
 int dht_hop_config_get(dht_ctx* ctx, int prec, int nrhs, int epilogue, dht_hop_config* out);
 
 typedef struct dht_tune_result {
-    dht_hop_config best[2];  /* per epilogue class: fastest candidate that passed the parity check */
-    double best_ms[2];       /* its mean time per hop application */
-    double default_ms[2];    /* the built-in default's time */
+    dht_hop_config best[3];  /* per epilogue class: fastest candidate that passed the parity check */
+    double best_ms[3];       /* its mean time per hop application */
+    double default_ms[3];    /* the built-in default's time */
     int candidates;          /* shapes timed per class */
     int rejected;            /* shapes whose output differed from the default's beyond rounding */
     double max_rel_diff;     /* largest max|out - out_default| / max|out_default| among accepted shapes */

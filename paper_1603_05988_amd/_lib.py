@@ -63,13 +63,13 @@ class HopConfig(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("best", HopConfig * 2), ("best_ms", ctypes.c_double * 2), ("default_ms", ctypes.c_double * 2),
+    _fields_ = [("best", HopConfig * 3), ("best_ms", ctypes.c_double * 3), ("default_ms", ctypes.c_double * 3),
                 ("candidates", ctypes.c_int), ("rejected", ctypes.c_int), ("max_rel_diff", ctypes.c_double)]
 
 
 HOP_SITE, HOP_SITE_LDS, HOP_TMARCH = 0, 1, 2
-HOP_PLAIN, HOP_FUSED = 0, 1
-HOP_CLASSES = {HOP_PLAIN: "plain", HOP_FUSED: "fused"}
+HOP_PLAIN, HOP_FUSED, HOP_FUSED_A = 0, 1, 2
+HOP_CLASSES = {HOP_PLAIN: "plain", HOP_FUSED: "fused", HOP_FUSED_A: "fused_a"}
 HOP_FORMS = {HOP_SITE: "site", HOP_SITE_LDS: "site_lds", HOP_TMARCH: "tmarch"}
 
 
@@ -452,7 +452,7 @@ class Context:
     def set_hop_config(self, prec: int, nrhs: int, cfg: dict | None, epilogue: int | None = None):
         """Install a hopping-kernel shape for (prec, nrhs) and one epilogue
         class (both when epilogue is None); None restores the default."""
-        for cls in ((HOP_PLAIN, HOP_FUSED) if epilogue is None else (epilogue,)):
+        for cls in (tuple(HOP_CLASSES) if epilogue is None else (epilogue,)):
             if cfg is None:
                 check(load().dht_hop_config_set(self.h, prec, nrhs, cls, None))
                 continue
@@ -468,11 +468,11 @@ class Context:
         check(load().dht_autotune_hop(self.h, prec, nrhs, reps, ctypes.byref(r)))
         best = {HOP_CLASSES[k]: {"form": r.best[k].form, "streaming_stores": r.best[k].streaming_stores,
                                  "t_chunk": r.best[k].t_chunk, "rhs_group": r.best[k].rhs_group}
-                for k in (HOP_PLAIN, HOP_FUSED)}
+                for k in HOP_CLASSES}
         out = {"prec": prec, "nrhs": nrhs, "best": best,
                "best_form": {c: HOP_FORMS[b["form"]] for c, b in best.items()},
-               "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in (HOP_PLAIN, HOP_FUSED)},
-               "default_ms": {HOP_CLASSES[k]: r.default_ms[k] for k in (HOP_PLAIN, HOP_FUSED)},
+               "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in HOP_CLASSES},
+               "default_ms": {HOP_CLASSES[k]: r.default_ms[k] for k in HOP_CLASSES},
                "candidates": r.candidates, "rejected": r.rejected, "max_rel_diff": r.max_rel_diff}
         self._tuned[(prec, nrhs)] = out
         return out
@@ -485,8 +485,8 @@ class Context:
         check(load().dht_autotune(self.h, prec, nrhs, reps, cp, ctypes.byref(r)))
         return {"best": {HOP_CLASSES[k]: {"form": r.best[k].form, "streaming_stores": r.best[k].streaming_stores,
                                           "t_chunk": r.best[k].t_chunk, "rhs_group": r.best[k].rhs_group}
-                         for k in (HOP_PLAIN, HOP_FUSED)},
-                "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in (HOP_PLAIN, HOP_FUSED)},
+                         for k in HOP_CLASSES},
+                "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in HOP_CLASSES},
                 "candidates": r.candidates, "rejected": r.rejected}
 
     def save_state(self, path: str):
@@ -517,6 +517,8 @@ class Context:
         n = 0
         for key, ent in tab.get("entries", {}).items():
             prec, nrhs = (int(v) for v in key.split(":"))
+            if any(name not in ent.get("best", {}) for name in HOP_CLASSES.values()):
+                continue   # a table from before an epilogue class existed: tune again
             for cls, name in HOP_CLASSES.items():
                 self.set_hop_config(prec, nrhs, ent["best"][name], cls)
             self._tuned[(prec, nrhs)] = ent

@@ -588,7 +588,7 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     a.partial = dot ? dot->partial : nullptr;
     if (kind == HOPDOT_OUT_X && !x) return set_error(DHT_ERR_INVALID_ARG, "fused (out, x) needs an xpay source");
     if (kind == HOPDOT_NORM_ZX && !z) return set_error(DHT_ERR_INVALID_ARG, "fused (z, x) needs both axpy sources");
-    const int cls = (x || dot) ? HOP_FUSED : HOP_PLAIN;
+    const int cls = (dot && kind == HOPDOT_A_OUT) ? HOP_FUSED_A : ((x || dot) ? HOP_FUSED : HOP_PLAIN);
     const HopConfig cfg = hop_config(c, prec_of<S>(), nrhs, cls);
     a.tc = cfg.tc;
     a.nchunk = a.Lt / cfg.tc;

@@ -294,7 +294,7 @@ struct dht_ctx {
     dht::NNState nn;
     // hopping-kernel shape per (precision, log2 batch); hop_force overrides
     // every entry while the autotuner times a candidate
-    dht::HopConfig hop_cfg[3][9][2];   // [precision][log2 batch][epilogue class]
+    dht::HopConfig hop_cfg[3][9][3];   // [precision][log2 batch][epilogue class]
     bool hop_force = false;
     dht::HopConfig hop_forced;
     // workspace slots (grow-only)
@@ -394,7 +394,7 @@ constexpr int HOP_LANES = 256;   // lanes per hop workgroup
 // the shape a hop launch for (prec, nrhs) uses (t chunk resolved), and a check
 // that a shape fits the lattice and batch
 // epilogue classes: plain (out = b Hop(in)) and fused (x-pay, second operand or a fused dot)
-enum { HOP_PLAIN = 0, HOP_FUSED = 1 };
+enum { HOP_PLAIN = 0, HOP_FUSED = 1, HOP_FUSED_A = 2, HOP_NCLASS = 3 };
 HopConfig hop_config(const dht_ctx* c, int prec, int nrhs, int cls);
 HopConfig hop_default_config(const dht_ctx* c, int prec, int nrhs);
 int hop_config_check(const dht_ctx* c, int nrhs, const HopConfig& h);

@@ -83,10 +83,13 @@ struct TuneLaunch {
     Cx<double>* partial;
 };
 
+// one launch of the class's representative: plain; x-pay with (out, x) and
+// (out, out); x-pay with (a, out), a = the input field's other half
 static int tune_hop(dht_ctx* c, int prec, int nrhs, const TuneLaunch& L) {
     if (L.cls == HOP_PLAIN) return hop(c, prec, 0, L.in, L.out, nullptr, 0.0, 1.0, nrhs, false, false);
     HopDot d;
-    d.kind = HOPDOT_OUT_X;
+    d.kind = L.cls == HOP_FUSED_A ? HOPDOT_A_OUT : HOPDOT_OUT_X;
+    d.a = L.cls == HOP_FUSED_A ? L.in : nullptr;
     d.partial = L.partial;
     return hop(c, prec, 0, L.in, L.out, L.x, 0.5, 1.0, nrhs, false, false, &d);
 }
@@ -152,7 +155,7 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
         }
     int rejected = 0;
     double worst_ok = 0.0;
-    for (int cls = 0; cls < 2; cls++) {
+    for (int cls = 0; cls < HOP_NCLASS; cls++) {
         L.cls = cls;
         // reference: the built-in default shape
         c->hop_force = true;
@@ -207,7 +210,7 @@ extern "C" {
 int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, int epilogue, const dht_hop_config* cfg) {
     if (!c) return set_error(DHT_ERR_INVALID_ARG, "null context");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
-    if (epilogue != DHT_HOP_PLAIN && epilogue != DHT_HOP_FUSED) return set_error(DHT_ERR_INVALID_ARG, "bad epilogue class");
+    if (epilogue < 0 || epilogue >= HOP_NCLASS) return set_error(DHT_ERR_INVALID_ARG, "bad epilogue class");
     const int b = log2_pow2(nrhs);
     if (b < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
     if (!cfg) {
@@ -227,7 +230,7 @@ int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, int epilogue, const dht_h
 int dht_hop_config_get(dht_ctx* c, int prec, int nrhs, int epilogue, dht_hop_config* out) {
     if (!c || !out) return set_error(DHT_ERR_INVALID_ARG, "null argument");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
-    if (epilogue != DHT_HOP_PLAIN && epilogue != DHT_HOP_FUSED) return set_error(DHT_ERR_INVALID_ARG, "bad epilogue class");
+    if (epilogue < 0 || epilogue >= HOP_NCLASS) return set_error(DHT_ERR_INVALID_ARG, "bad epilogue class");
     if (log2_pow2(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
     HopConfig h = hop_config(c, prec, nrhs, epilogue);
     out->form = h.form;
@@ -265,23 +268,23 @@ int dht_autotune(dht_ctx* c, int prec, int nrhs, int reps, const char* cache_pat
     if (cache_path) {
         FILE* f = fopen(cache_path, "r");
         if (f) {
-            dht_hop_config found[2];
-            double ms[2] = {0, 0};
-            bool have[2] = {false, false};
+            dht_hop_config found[HOP_NCLASS];
+            double ms[HOP_NCLASS] = {0, 0, 0};
+            bool have[HOP_NCLASS] = {false, false, false};
             char tag[8];
             int L[4], p, n, cls, form, nt, tc, rg;
             double t;
             while (fscanf(f, "%7s %d %d %d %d %d %d %d %d %d %d %d %lf", tag, &L[0], &L[1], &L[2], &L[3], &p, &n, &cls,
                           &form, &nt, &tc, &rg, &t) == 13) {
-                if (strcmp(tag, "hop") != 0 || p != prec || n != nrhs || cls < 0 || cls > 1) continue;
+                if (strcmp(tag, "hop") != 0 || p != prec || n != nrhs || cls < 0 || cls >= HOP_NCLASS) continue;
                 if (L[0] != c->g.L[0] || L[1] != c->g.L[1] || L[2] != c->g.L[2] || L[3] != c->g.L[3]) continue;
                 found[cls] = dht_hop_config{form, nt, tc, rg};
                 ms[cls] = t;
                 have[cls] = true;
             }
             fclose(f);
-            if (have[0] && have[1]) {
-                for (int cls2 = 0; cls2 < 2; cls2++) {
+            if (have[0] && have[1] && have[2]) {
+                for (int cls2 = 0; cls2 < HOP_NCLASS; cls2++) {
                     DHT_TRY(dht_hop_config_set(c, prec, nrhs, cls2, &found[cls2]));
                     out->best[cls2] = found[cls2];
                     out->best_ms[cls2] = ms[cls2];
@@ -298,7 +301,7 @@ int dht_autotune(dht_ctx* c, int prec, int nrhs, int reps, const char* cache_pat
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (!f) return set_error(DHT_ERR_INVALID_ARG, std::string("cannot write ") + cache_path);
-        for (int cls = 0; cls < 2; cls++)
+        for (int cls = 0; cls < HOP_NCLASS; cls++)
             fprintf(f, "hop %d %d %d %d %d %d %d %d %d %d %d %.6g\n", c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3],
                     prec, nrhs, cls, out->best[cls].form, out->best[cls].streaming_stores, out->best[cls].t_chunk,
                     out->best[cls].rhs_group, out->best_ms[cls]);

@@ -67,7 +67,7 @@ def test_every_form_matches_dense(L, nrhs):
     for prec in (0, 1, 2):
         for cfg in forms(L, nrhs):
             ctx.set_hop_config(prec, nrhs, cfg)     # both epilogue classes
-            for cls in (Lb.HOP_PLAIN, Lb.HOP_FUSED):
+            for cls in Lb.HOP_CLASSES:
                 got = ctx.hop_config(prec, nrhs, cls)
                 assert got["form"] == cfg["form"] and got["streaming_stores"] == cfg["streaming_stores"]
                 assert got["rhs_group"] == cfg["rhs_group"]
@@ -148,7 +148,7 @@ def test_autotune_c2(tmp_path):
         res[prec] = r
         assert r["rejected"] == 0 and r["candidates"] == len(forms(w.L, 16)), r
         assert r["max_rel_diff"] <= {0: 1e-12, 1: 1e-5, 2: 1.6e-2}[prec], r
-        for cls, name in ((Lb.HOP_PLAIN, "plain"), (Lb.HOP_FUSED, "fused")):
+        for cls, name in Lb.HOP_CLASSES.items():
             assert 0 < r["best_ms"][name] <= r["default_ms"][name] * (1 + 1e-9), r
             assert ctx.hop_config(prec, 16, cls) == r["best"][name]
     X = random_spinors(w.L, 16, 21)
@@ -163,8 +163,8 @@ def test_autotune_c2(tmp_path):
     ctx2 = Lb.Context(w.L, w.mass)
     assert ctx2.load_tuning(str(path)) == 3
     for prec in (0, 1, 2):
-        assert ctx2.hop_config(prec, 16, Lb.HOP_PLAIN) == res[prec]["best"]["plain"]
-        assert ctx2.hop_config(prec, 16, Lb.HOP_FUSED) == res[prec]["best"]["fused"]
+        for cls, name in Lb.HOP_CLASSES.items():
+            assert ctx2.hop_config(prec, 16, cls) == res[prec]["best"][name]
     other = Lb.Context((4, 4, 4, 4), -0.2)
     assert other.load_tuning(str(path)) == 0     # measured on another lattice: ignored
     other.close()

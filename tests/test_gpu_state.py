@@ -79,13 +79,13 @@ def test_autotune_cache_file(tmp_path):
     assert r1["candidates"] > 0
     a.close()
     lines = open(cache).read().split("\n")
-    assert sum(1 for x in lines if x.startswith("hop ")) == 2
+    assert sum(1 for x in lines if x.startswith("hop ")) == len(Lb.HOP_CLASSES)
     b = _ctx(w, U)
     r2 = b.autotune(Lb.BF16, 16, reps=2, cache_path=cache)
     assert r2["candidates"] == 0 and r2["best"] == r1["best"]
-    assert b.hop_config(Lb.BF16, 16, Lb.HOP_PLAIN) == r1["best"]["plain"]
-    assert b.hop_config(Lb.BF16, 16, Lb.HOP_FUSED) == r1["best"]["fused"]
+    for cls, name in Lb.HOP_CLASSES.items():
+        assert b.hop_config(Lb.BF16, 16, cls) == r1["best"][name]
     r3 = b.autotune(Lb.FP32, 16, reps=2, cache_path=cache)     # not cached yet: tuned and appended
     assert r3["candidates"] > 0
-    assert sum(1 for x in open(cache).read().split("\n") if x.startswith("hop ")) == 4
+    assert sum(1 for x in open(cache).read().split("\n") if x.startswith("hop ")) == 2 * len(Lb.HOP_CLASSES)
     b.close()
