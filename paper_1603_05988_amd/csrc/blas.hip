@@ -232,7 +232,8 @@ size_t partial_bytes(const dht_ctx* c, int nrhs) {
 template <typename T> __device__ inline Cx<T> cscal(Cx<double> a) { return cmake<T>((T)a.re, (T)a.im); }
 
 template <typename S>
-__global__ void p_update_kernel(void* p, const void* r_, const void* v, const RhsState* st, size_t nvec, int B) {
+__global__ void p_update_kernel(void* p, const void* p_in, const void* r_, const void* v, const RhsState* st,
+                                size_t nvec, int B) {
     typedef typename Store<S>::acc T;
     constexpr int VW = Store<S>::VW;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,7 +242,7 @@ __global__ void p_update_kernel(void* p, const void* r_, const void* v, const Rh
     if (!x.active) return;
     Cx<T> beta = cscal<T>(x.beta), om = cscal<T>(x.omega);
     Cx<T> pv[VW], rv[VW], vv[VW];
-    Store<S>::ldv(p, i, pv);
+    Store<S>::ldv(p_in, i, pv);
     Store<S>::ldv(r_, i, rv);
     Store<S>::ldv(v, i, vv);
 #pragma unroll
@@ -351,8 +352,10 @@ static dim3 egrid(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
         default: return set_error(DHT_ERR_INVALID_ARG, "bad precision"); \
     }
 
-int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const RhsState* st, size_t nvec, int B) {
-    DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(p_update_kernel<T_>, egrid(nvec), dim3(256), 0, c->stream, p, r, v, st, nvec, B))
+int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const RhsState* st, size_t nvec, int B,
+             const void* p_in) {
+    DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(p_update_kernel<T_>, egrid(nvec), dim3(256), 0, c->stream, p,
+                                             p_in ? p_in : p, r, v, st, nvec, B))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
@@ -374,6 +377,111 @@ int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const 
         DHT_PREC_SWITCH(prec, hipLaunchKernelGGL((xr_update_kernel<T_, false>), dim3(nb), dim3(RED_THREADS), 0, c->stream,
                                                  x, r, p, s, t, rh, st, nvec, B, partial, (int)x_zero, SB))
     }
+    DHT_HIP(hipGetLastError());
+    return DHT_OK;
+}
+
+// r = s - omega t with the partials of (rhat, r) and (r, r), x left alone: the
+// iteration's (alpha, omega) go to hist[B] (zero for an RHS that is not
+// active) and x is rebuilt later from the stored p and s (accum_hist)
+template <typename S>
+__global__ __launch_bounds__(RED_THREADS) void r_update_kernel(void* r_, const void* s, const void* t, const void* rh,
+                                                               const RhsState* st, size_t nvec, int B,
+                                                               Cx<double>* partial, Cx<double>* hist) {
+    typedef typename Store<S>::acc T;
+    constexpr int VW = Store<S>::VW;
+    __shared__ Cx<double> red[2][RED_THREADS];
+    Cx<double> d0 = cmake(0.0, 0.0), d1 = cmake(0.0, 0.0);
+    const size_t stride = (size_t)gridDim.x * RED_THREADS;
+    const RhsState& x = st[threadIdx.x & (B - 1)];   // the stride keeps each lane on one RHS
+    if (blockIdx.x == 0 && (int)threadIdx.x < B) {
+        hist[threadIdx.x] = x.active ? x.alpha : cmake(0.0, 0.0);
+        hist[B + threadIdx.x] = x.active ? x.omega : cmake(0.0, 0.0);
+    }
+    if (x.active) {
+        Cx<T> om = cscal<T>(x.omega);
+        for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nvec; i += stride) {
+            Cx<T> sv[VW], tv[VW], hv[VW];
+            Store<S>::ldv(s, i, sv);
+            Store<S>::ldv(t, i, tv);
+            Store<S>::ldv(rh, i, hv);
+#pragma unroll
+            for (int j = 0; j < VW; j++) {
+                sv[j] = Store<S>::round(sv[j] - om * tv[j]);   // the new r, as stored
+                Cx<double> rd = cmake<double>(sv[j].re, sv[j].im);
+                d0 = d0 + conjmul(cmake<double>(hv[j].re, hv[j].im), rd);
+                d1.re += rd.re * rd.re + rd.im * rd.im;
+            }
+            Store<S>::stv(r_, i, sv);
+        }
+    }
+    red[0][threadIdx.x] = d0;
+    red[1][threadIdx.x] = d1;
+    block_reduce_rhs<2>(red, B);
+    if ((int)threadIdx.x < B) {
+        partial[((int64_t)blockIdx.x * 2 + 0) * B + threadIdx.x] = red[0][threadIdx.x];
+        partial[((int64_t)blockIdx.x * 2 + 1) * B + threadIdx.x] = red[1][threadIdx.x];
+    }
+}
+
+// X (FP64 half field) = [X +] scale_r * sum_j (alpha_j p_j + omega_j s_j) over
+// the n stored iterations (p_j, s_j: slot j of the rings, storage S; hist:
+// [n][2][B]); a zero coefficient skips its vector (its slot may hold another
+// RHS's stale values)
+template <typename S>
+__global__ void accum_hist_kernel(Cx<double>* X, const void* P, const void* Sv, const Cx<double>* hist, int n,
+                                  size_t nvec, int64_t SB, int B, const double* scale, int assign) {
+    typedef typename Store<S>::acc T;
+    constexpr int VW = Store<S>::VW;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nvec) return;
+    const int rr = (int)(i & (B - 1));
+    const int64_t cv = (int64_t)i / SB, sr = (int64_t)i - cv * SB;
+    const double sc = scale[rr];
+    Cx<double> acc[VW];
+#pragma unroll
+    for (int q = 0; q < VW; q++) acc[q] = cmake(0.0, 0.0);
+    if (sc != 0.0) {
+        for (int j = 0; j < n; j++) {
+            const Cx<double> al = hist[(int64_t)j * 2 * B + rr], om = hist[((int64_t)j * 2 + 1) * B + rr];
+            Cx<T> v[VW];
+            if (al.re != 0.0 || al.im != 0.0) {
+                Store<S>::ldv((const char*)P + (size_t)j * nvec * 16, i, v);
+#pragma unroll
+                for (int q = 0; q < VW; q++) acc[q] = acc[q] + al * cmake<double>(v[q].re, v[q].im);
+            }
+            if (om.re != 0.0 || om.im != 0.0) {
+                Store<S>::ldv((const char*)Sv + (size_t)j * nvec * 16, i, v);
+#pragma unroll
+                for (int q = 0; q < VW; q++) acc[q] = acc[q] + om * cmake<double>(v[q].re, v[q].im);
+            }
+        }
+    }
+    if (sc == 0.0 && !assign) return;
+#pragma unroll
+    for (int q = 0; q < VW; q++) {
+        Cx<double>& xd = X[(cv * VW + q) * SB + sr];
+        const Cx<double> x0 = assign ? cmake(0.0, 0.0) : xd;
+        xd = cmake(x0.re + sc * acc[q].re, x0.im + sc * acc[q].im);
+    }
+}
+
+int r_update_dots(dht_ctx* c, int prec, void* r, const void* s, const void* t, const void* rh, const RhsState* st,
+                  size_t nvec, int B, Cx<double>* partial, int* nblocks, Cx<double>* hist) {
+    int nb = red_blocks(nvec);
+    *nblocks = nb;
+    DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(r_update_kernel<T_>, dim3(nb), dim3(RED_THREADS), 0, c->stream, r, s, t, rh,
+                                             st, nvec, B, partial, hist))
+    DHT_HIP(hipGetLastError());
+    return DHT_OK;
+}
+
+int accum_hist(dht_ctx* c, int prec, void* X, const void* P, const void* Sv, const Cx<double>* hist, int n, int nrhs,
+               const double* scale, bool assign) {
+    const int64_t SB = c->g.Vh * (int64_t)nrhs;
+    const size_t nvec = half_vecs(c, nrhs, prec);
+    DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(accum_hist_kernel<T_>, egrid(nvec), dim3(256), 0, c->stream, (Cx<double>*)X,
+                                             P, Sv, hist, n, nvec, SB, nrhs, scale, (int)assign))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }

@@ -43,7 +43,9 @@ int finalize(dht_ctx* c, const Cx<double>* partial, int nblocks, int np, int nrh
 // out_dev[pair][r] = sum conj(a_pair) b_pair over nvec vectors
 int dots(dht_ctx* c, int prec, int np, const void* const* a, const void* const* b, size_t nvec, int nrhs,
          Cx<double>* out_dev);
-int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const RhsState* st, size_t nvec, int B);
+// p = r + beta (p_in - omega v) (p_in = null: in place)
+int p_update(dht_ctx* c, int prec, void* p, const void* r, const void* v, const RhsState* st, size_t nvec, int B,
+             const void* p_in = nullptr);
 int s_update(dht_ctx* c, int prec, void* s, const void* r, const void* v, const RhsState* st, size_t nvec, int B);
 int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const void* s, const void* t, const void* rh,
                    const RhsState* st, size_t nvec, int B, Cx<double>* partial, int* nblocks,
@@ -52,6 +54,12 @@ int xr_update_dots(dht_ctx* c, int prec, void* x, void* r, const void* p, const 
 // half fields: out_low = scale[r] * in_fp64 ; x_fp64 += scale[r] * e_low
 int scale_down(dht_ctx* c, const void* in, void* out, int pout, const double* scale, int nrhs);
 int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, int nrhs, bool assign = false);
+// r = s - omega t, (rhat, r), (r, r); (alpha, omega) of the iteration to hist [2][B]
+int r_update_dots(dht_ctx* c, int prec, void* r, const void* s, const void* t, const void* rh, const RhsState* st,
+                  size_t nvec, int B, Cx<double>* partial, int* nblocks, Cx<double>* hist);
+// X (FP64) = [X +] scale * sum over n stored iterations of (alpha_j p_j + omega_j s_j)
+int accum_hist(dht_ctx* c, int prec, void* X, const void* P, const void* Sv, const Cx<double>* hist, int n, int nrhs,
+               const double* scale, bool assign);
 int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t ncomplex);
 int zero(dht_ctx* c, void* p, size_t bytes);
 
@@ -75,9 +83,19 @@ int solve_init(dht_ctx* c, const void* in, int pout, const double* scale, void* 
                Cx<double>* partial, int* nblocks);
 // BiCGStab on the Schur system from x = 0 for the right-hand side scale * src
 // (src: FP64 half field, scale: device, per RHS), in storage precision prec
-// x32: the solution x is kept in FP32 storage (BF16 vectors only)
+// Solution by history: instead of updating x every iteration, keep the
+// iterations' p and s (rings of up to 16) with their (alpha, omega) and add
+// scale_r * x to the FP64 field X when a ring is full and at the end (an RHS
+// whose solve ended in NaN contributes nothing from then on).
+struct XAccum {
+    void* X = nullptr;             // FP64 half field
+    std::vector<double> scale;     // per RHS (0: leave the RHS alone)
+    bool assign = false;           // the first contribution assigns X
+};
+// x32: the solution x is kept in FP32 storage (BF16 vectors only); xa: see XAccum (x unused)
 int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
-             const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32 = false);
+             const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32 = false,
+             XAccum* xa = nullptr);
 
 // Top-level solve of D X = Z on internal full FP64 fields (Z, X: [2][12][Vh][B]);
 // stats has nrhs entries (the padded batch).

@@ -35,18 +35,39 @@ int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o
 static int slot_base(int prec) { return prec == DHT_FP64 ? WS_K64 : WS_KLO; }
 
 int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
-             const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32) {
+             const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32, XAccum* xa) {
     const size_t nvec = half_vecs(c, nrhs, prec);
     const size_t bytes = nvec * 16;
     const int base = slot_base(prec);
     void *r, *rh, *p, *v, *s, *t, *tmp, *stv, *part, *hostv;
     DHT_TRY(ws_get(c, base + 0, bytes, &r));
     DHT_TRY(ws_get(c, base + 1, bytes, &rh));
-    DHT_TRY(ws_get(c, base + 2, bytes, &p));
     DHT_TRY(ws_get(c, base + 3, bytes, &v));
-    DHT_TRY(ws_get(c, base + 4, bytes, &s));
     DHT_TRY(ws_get(c, base + 5, bytes, &t));
     DHT_TRY(ws_get(c, base + 6, bytes, &tmp));
+    // p and s: one vector each, or with XAccum rings of K slots
+    int K = 1;
+    char *ringP, *ringS;
+    Cx<double>* hist = nullptr;
+    double* hscale = nullptr;
+    if (xa) {
+        const size_t budget = (size_t)12 << 30;   // bytes for both rings
+        K = (int)std::min<size_t>(16, std::max<size_t>(2, budget / (2 * bytes)));
+        void *pp, *ss, *hh, *sc;
+        DHT_TRY(ws_get(c, WS_RING_P, (size_t)K * bytes, &pp));
+        DHT_TRY(ws_get(c, WS_RING_S, (size_t)K * bytes, &ss));
+        DHT_TRY(ws_get(c, WS_HIST, sizeof(Cx<double>) * 2 * (size_t)K * nrhs, &hh));
+        DHT_TRY(ws_get(c, WS_HIST_SCALE, sizeof(double) * nrhs, &sc));
+        ringP = (char*)pp;
+        ringS = (char*)ss;
+        hist = (Cx<double>*)hh;
+        hscale = (double*)sc;
+    } else {
+        DHT_TRY(ws_get(c, base + 2, bytes, &p));
+        DHT_TRY(ws_get(c, base + 4, bytes, &s));
+        ringP = (char*)p;
+        ringS = (char*)s;
+    }
     DHT_TRY(ws_get(c, WS_SCAL, sizeof(RhsState) * nrhs, &stv));
     DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
     DHT_TRY(ws_get(c, WS_HOSTPIN, sizeof(RhsState) * nrhs, &hostv));   // pinned host buffer
@@ -63,37 +84,59 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     // p = r come out of one pass over the FP64 source with the (r, r) sums
     const double bd_eps = prec == DHT_FP64 ? 1e-14 : 1e-6;
     int nb;
-    DHT_TRY(solve_init(c, src, prec, scale, r, rh, p, nrhs, partial, &nb));
+    DHT_TRY(solve_init(c, src, prec, scale, r, rh, ringP, nrhs, partial, &nb));
     DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_INIT, bd_eps));
+    // add the stored iterations [0, n) to X (after a synchronisation, so hs
+    // holds the current states)
+    bool first_flush = true;
+    std::vector<double> fs(nrhs);
+    auto flush = [&](int n) -> int {
+        for (int i = 0; i < nrhs; i++) fs[i] = hs[i].status == RS_NAN ? 0.0 : xa->scale[i];
+        DHT_HIP(hipMemcpyAsync(hscale, fs.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+        DHT_TRY(accum_hist(c, prec, xa->X, ringP, ringS, hist, n, nrhs, hscale, xa->assign && first_flush));
+        first_flush = false;
+        return DHT_OK;
+    };
     // the host reads the per-RHS states after every iteration: a batch that
     // converges stops at once (a skipped check costs a whole iteration of 4
     // hops, a check only a short stream synchronisation)
-    const int check_every = 1;
+    int stored = 0;
     for (int it = 0; it < maxiter; it++) {
-        if (it > 0) DHT_TRY(p_update(c, prec, p, r, v, st, nvec, nrhs));
+        const int slot = xa ? it % K : 0;
+        char* pc = ringP + (size_t)slot * bytes;
+        char* sc = ringS + (size_t)slot * bytes;
+        if (it > 0) DHT_TRY(p_update(c, prec, pc, r, v, st, nvec, nrhs, xa ? ringP + (size_t)((it - 1) % K) * bytes : nullptr));
         HopDot d1;
         d1.kind = HOPDOT_A_OUT;   // (rhat, v)
         d1.a = rh;
         d1.partial = partial;
-        DHT_TRY(apply_schur(c, prec, p, v, tmp, nrhs, &d1));
+        DHT_TRY(apply_schur(c, prec, pc, v, tmp, nrhs, &d1));
         DHT_TRY(finalize(c, partial, d1.nblocks, 1, nrhs, st, FIN_ALPHA, bd_eps));
-        DHT_TRY(s_update(c, prec, s, r, v, st, nvec, nrhs));
+        DHT_TRY(s_update(c, prec, sc, r, v, st, nvec, nrhs));
         HopDot d2;
         d2.kind = HOPDOT_OUT_X;   // (t, s), (t, t)
         d2.partial = partial;
-        DHT_TRY(apply_schur(c, prec, s, t, tmp, nrhs, &d2));
+        DHT_TRY(apply_schur(c, prec, sc, t, tmp, nrhs, &d2));
         DHT_TRY(finalize(c, partial, d2.nblocks, 2, nrhs, st, FIN_OMEGA, bd_eps));
-        DHT_TRY(xr_update_dots(c, prec, x, r, p, s, t, rh, st, nvec, nrhs, partial, &nb, it == 0, x32));   // (rhat, r), (r, r)
+        if (xa) {
+            DHT_TRY(r_update_dots(c, prec, r, sc, t, rh, st, nvec, nrhs, partial, &nb, hist + (size_t)slot * 2 * nrhs));
+        } else {
+            DHT_TRY(xr_update_dots(c, prec, x, r, pc, sc, t, rh, st, nvec, nrhs, partial, &nb, it == 0, x32));
+        }
         DHT_TRY(finalize(c, partial, nb, 2, nrhs, st, FIN_RHO, bd_eps));
-        if ((it + 1) % check_every == 0 || it + 1 == maxiter) {
-            DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
-            DHT_HIP(hipStreamSynchronize(c->stream));
-            DHT_TRY(prof_harvest(c));
-            bool any = false;
-            for (int i = 0; i < nrhs; i++) any |= hs[i].active != 0;
-            if (!any) break;
+        stored++;
+        DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
+        DHT_HIP(hipStreamSynchronize(c->stream));
+        DHT_TRY(prof_harvest(c));
+        bool any = false;
+        for (int i = 0; i < nrhs; i++) any |= hs[i].active != 0;
+        if (!any) break;
+        if (xa && stored == K) {   // the rings are full
+            DHT_TRY(flush(K));
+            stored = 0;
         }
     }
+    if (xa && (stored > 0 || first_flush)) DHT_TRY(flush(stored));
     DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
     DHT_HIP(hipStreamSynchronize(c->stream));
     res->iters.assign(nrhs, 0);
@@ -258,11 +301,13 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             double need = sup[i] > 0 ? 0.25 * target2[i] / rn2[i] : 1.0;
             itarget[i] = std::max(itol * itol, need);
         }
-        // the inner solution of a BF16 solve is kept in FP32 storage
-        const bool x32 = inner == DHT_BF16;
-        const size_t lbytes = nh * elem_bytes(x32 ? DHT_FP32 : inner);
+        // a BF16 solve adds its solution to X_e itself, rebuilt in FP64 from its
+        // stored iterations; the others return it in their storage precision
+        const bool hist = inner == DHT_BF16;
+        const size_t lbytes = nh * elem_bytes(inner);
         const int base = slot_base(inner);
-        DHT_TRY(ws_get(c, base + 8, lbytes, &e));     // inner solution
+        e = nullptr;
+        if (!hist) DHT_TRY(ws_get(c, base + 8, lbytes, &e));     // inner solution
         if ((prm->fault_inject & 1u) && outer == 0 && inner != DHT_FP64) {
             // testing hook: poison the first inner right-hand side to exercise the fallback
             for (int i = 0; i < nrhs; i++) sdown[i] = NAN;
@@ -271,8 +316,14 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         // the inner right-hand side is the normalised Schur residual; in the
         // first cycle that is bhat itself
         BicgResult br;
+        XAccum xa;
+        if (hist) {
+            xa.X = X_e;
+            xa.scale = sup;
+            xa.assign = !x_written;
+        }
         DHT_TRY(bicgstab(c, inner, outer == 0 ? bhat : r_e, (const double*)scl, e, nrhs, itarget,
-                         prm->maxiter - total_iters, &br, x32));
+                         prm->maxiter - total_iters, &br, false, hist ? &xa : nullptr));
         int maxit = 0;
         bool bad = false;
         for (int i = 0; i < nrhs; i++) {
@@ -284,9 +335,11 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             }
         }
         total_iters += std::max(maxit, 1);
-        DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-        // the first correction is x itself: X_e = 0 is never materialised
-        DHT_TRY(accum_up(c, X_e, e, x32 ? DHT_FP32 : inner, (const double*)scl, nrhs, !x_written));
+        if (!hist) {
+            DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+            // the first correction is x itself: X_e = 0 is never materialised
+            DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nrhs, !x_written));
+        }
         x_written = true;
         // When the inner solver's own residual says this correction finishes
         // every RHS, go straight to the full-lattice check: its even residual
