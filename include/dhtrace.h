@@ -27,8 +27,11 @@
  *    after the call returns.  The library owns its internal copies (links in
  *    three precisions, the deflation basis, solver workspace), allocated with
  *    hipMalloc on first use and released by dht_destroy.
- *  - Streams: all device work is enqueued on the stream given to dht_create.
- *    Calls that return host values synchronise that stream before returning.
+ *  - Streams: all device work is enqueued on the stream given to dht_create,
+ *    except dht_trace_batch's per-batch projection, which runs on a second
+ *    stream of the library's own (default priority) after the probes are made
+ *    and is joined before the call returns.  Calls that return host values
+ *    synchronise the context stream before returning.
  *  - Errors: every int-returning call returns DHT_OK (0) or a negative code;
  *    dht_last_error() gives a message for the calling thread.  No C++
  *    exception crosses the interface.
@@ -117,6 +120,9 @@ typedef struct {
     double inner_tol;  /* relative reduction per inner solve (0: 1e-2 BF16, 1e-5 FP32) */
     int max_outer;     /* cap on defect-correction cycles (0: default 50)       */
     uint32_t fault_inject; /* testing only: bit 0 forces an inner NaN           */
+    int history;       /* BF16 inner solves: iterations whose p and s are kept
+                          before x is rebuilt from them (0: automatic, up to 16
+                          within a 12 GB budget; else 2..16)                   */
 } dht_solver_params;
 
 typedef struct {
@@ -329,9 +335,10 @@ int dht_nn_make_pairs(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, i
 /* ---- instrumentation ------------------------------------------------------ */
 
 /* Timing of the last dht_trace_batch / dht_solve, from HIP events, in
- * milliseconds: [0] probes, [1] solve, [2] projection (on a second stream of
- * the library's own, concurrent with the solve), [3] quadratic forms, [4]
- * whole call.  n must be >= 5. */
+ * milliseconds: [0] probes, [1] solve, [2] projection (a batch's own pass
+ * runs on a second stream concurrently with the solve; a projection window's
+ * pass runs on the context stream before it; 0 when the batch reused a
+ * window), [3] quadratic forms, [4] whole call.  n must be >= 5. */
 int dht_last_timings(dht_ctx* ctx, double* ms_host, int n);
 
 /* Per-kernel-class timing: when enabled, every launch of an instrumented

@@ -34,7 +34,7 @@ class ProbeSpec(ctypes.Structure):
 class SolverParams(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("inner", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxiter", ctypes.c_int), ("restart", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("max_outer", ctypes.c_int), ("fault_inject", ctypes.c_uint32)]
+                ("max_outer", ctypes.c_int), ("fault_inject", ctypes.c_uint32), ("history", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -248,8 +248,8 @@ class Context:
     # -- solver -----------------------------------------------------------
     @staticmethod
     def params(method=SOLVER_BICGSTAB_FP64, inner=FP32, tol=1e-10, maxiter=10000, restart=32,
-               inner_tol=0.0, max_outer=0, fault_inject=0):
-        return SolverParams(method, inner, tol, maxiter, restart, inner_tol, max_outer, fault_inject)
+               inner_tol=0.0, max_outer=0, fault_inject=0, history=0):
+        return SolverParams(method, inner, tol, maxiter, restart, inner_tol, max_outer, fault_inject, history)
 
     def solve(self, Z, prm: SolverParams, allow_not_converged: bool = False):
         X = self.torch.empty_like(Z)

@@ -502,25 +502,32 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     DHT_TRY(record(c, 0));
     DHT_TRY(probes_gen(c, spec, first, nrhs, bp, fz, DHT_FP64, nullptr, nullptr, win ? nullptr : (uint8_t*)zc));
     DHT_TRY(record(c, 1));
-    // the projection needs only the probes: it runs on the side stream while
-    // the main stream solves (both read fz; neither writes it)
+    // the projection needs only the probes: a batch's own pass runs on the
+    // side stream while the main stream solves (both read fz; neither writes
+    // it); a window's pass runs on the main stream before the solve (its
+    // workgroups hold most of the LDS of every compute unit, so next to the
+    // solve it would only delay the solve's kernels)
     if (launch) {
         if (win) c->pw_valid = false;
         DHT_TRY(side_stream(c));
-        DHT_HIP(hipEventRecord(c->side_ev[0], c->stream));
-        DHT_HIP(hipStreamWaitEvent(c->side, c->side_ev[0], 0));
         hipStream_t main_stream = c->stream;
-        c->stream = c->side;
-        int prc = hipEventRecord(c->side_ev[1], c->side) == hipSuccess ? DHT_OK : set_error(DHT_ERR_HIP, "event");
+        hipStream_t ps = main_stream;
+        if (!win) {
+            DHT_HIP(hipEventRecord(c->side_ev[0], c->stream));
+            DHT_HIP(hipStreamWaitEvent(c->side, c->side_ev[0], 0));
+            ps = c->side;
+        }
+        c->stream = ps;
+        int prc = hipEventRecord(c->side_ev[1], ps) == hipSuccess ? DHT_OK : set_error(DHT_ERR_HIP, "event");
         if (prc == DHT_OK && win)   // the window's probes as 2-bit codes, generated on the side stream
             prc = probes_gen(c, spec, first, win, wpad, nullptr, DHT_FP64, nullptr, nullptr, (uint8_t*)zc);
         if (prc == DHT_OK) {
             if (mfma) prc = project_codes(c, (const uint8_t*)zc, wpad, d1, d2);
             else prc = project_field(c, fz, DHT_FP64, bp, d1, d2);
         }
-        if (prc == DHT_OK && hipEventRecord(c->side_ev[2], c->side) != hipSuccess) prc = set_error(DHT_ERR_HIP, "event");
+        if (prc == DHT_OK && hipEventRecord(c->side_ev[2], ps) != hipSuccess) prc = set_error(DHT_ERR_HIP, "event");
         c->stream = main_stream;
-        if (prc != DHT_OK) (void)hipStreamSynchronize(c->side);
+        if (prc != DHT_OK) (void)hipStreamSynchronize(ps);
         DHT_TRY(prc);
         if (win) {
             c->pw_valid = true;

@@ -342,7 +342,7 @@ enum Slot {
     WS_PARTIAL = WS_KLO + 9, WS_SCAL, WS_SCAL2, WS_FLAGS, WS_HOSTPIN,
     WS_Z, WS_XF, WS_QW, WS_PROJ, WS_COEF, WS_PROJ2, WS_ZCODE,
     WS_NN_PART, WS_NN_ACT, WS_NN_SCAL, WS_FG_V, WS_FG_Z, WS_FG_W, WS_FG_COEF, WS_FG_R, WS_FG_E, WS_XSTAR,
-    WS_TUNE_REF, WS_TUNE_RED,
+    WS_TUNE_REF, WS_TUNE_RED, WS_TUNE_A,
     WS_NORMS, WS_FOLD,
     WS_EIG_V, WS_EIG_W, WS_EIG_T, WS_EIG_U, WS_EIG_PART, WS_EIG_SMALL, WS_EIG_RPART, WS_EIG_LAM, WS_EIG_CANON, WS_DEFL_GET,
     WS_PW_CODE, WS_PW_COEF,

@@ -88,6 +88,7 @@ int solve_init(dht_ctx* c, const void* in, int pout, const double* scale, void* 
 // scale_r * x to the FP64 field X when a ring is full and at the end (an RHS
 // whose solve ended in NaN contributes nothing from then on).
 struct XAccum {
+    int ring = 0;                  // iterations kept before a rebuild (0: automatic)
     void* X = nullptr;             // FP64 half field
     std::vector<double> scale;     // per RHS (0: leave the RHS alone)
     bool assign = false;           // the first contribution assigns X

@@ -52,7 +52,7 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     double* hscale = nullptr;
     if (xa) {
         const size_t budget = (size_t)12 << 30;   // bytes for both rings
-        K = (int)std::min<size_t>(16, std::max<size_t>(2, budget / (2 * bytes)));
+        K = xa->ring > 0 ? xa->ring : (int)std::min<size_t>(16, std::max<size_t>(2, budget / (2 * bytes)));
         void *pp, *ss, *hh, *sc;
         DHT_TRY(ws_get(c, WS_RING_P, (size_t)K * bytes, &pp));
         DHT_TRY(ws_get(c, WS_RING_S, (size_t)K * bytes, &ss));
@@ -233,6 +233,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     DHT_TRY(ws_get(c, WS_FLAGS, sizeof(double) * nrhs, &scl));
 
     if (prm->tol <= 0.0 || prm->maxiter <= 0) return set_error(DHT_ERR_INVALID_ARG, "tol and maxiter must be positive");
+    if (prm->history != 0 && (prm->history < 2 || prm->history > 16))
+        return set_error(DHT_ERR_INVALID_ARG, "history must be 0 or 2..16");
     if (prm->method == DHT_SOLVER_DC_FGMRES_NN || prm->method == DHT_SOLVER_DC_FGMRES) {
         const bool use_nn = prm->method == DHT_SOLVER_DC_FGMRES_NN;
         if (zx_out) return set_error(DHT_ERR_INVALID_ARG, "z^H x is fused only into the BiCGStab paths");
@@ -318,6 +320,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         BicgResult br;
         XAccum xa;
         if (hist) {
+            xa.ring = prm->history;
             xa.X = X_e;
             xa.scale = sup;
             xa.assign = !x_written;

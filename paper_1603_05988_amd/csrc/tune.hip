@@ -81,15 +81,16 @@ struct TuneLaunch {
     void* out;
     const void* x;
     Cx<double>* partial;
+    const void* a;   // third operand of the (a, out) class: a field of its own, as in the solver
 };
 
 // one launch of the class's representative: plain; x-pay with (out, x) and
-// (out, out); x-pay with (a, out), a = the input field's other half
+// (out, out); x-pay with (a, out)
 static int tune_hop(dht_ctx* c, int prec, int nrhs, const TuneLaunch& L) {
     if (L.cls == HOP_PLAIN) return hop(c, prec, 0, L.in, L.out, nullptr, 0.0, 1.0, nrhs, false, false);
     HopDot d;
     d.kind = L.cls == HOP_FUSED_A ? HOPDOT_A_OUT : HOPDOT_OUT_X;
-    d.a = L.cls == HOP_FUSED_A ? L.in : nullptr;
+    d.a = L.cls == HOP_FUSED_A ? L.a : nullptr;
     d.partial = L.partial;
     return hop(c, prec, 0, L.in, L.out, L.x, 0.5, 1.0, nrhs, false, false, &d);
 }
@@ -123,13 +124,16 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
     DHT_TRY(ws_get(c, WS_PACK_IN, full, &fi));
     DHT_TRY(ws_get(c, WS_PACK_OUT, half, &fo));
     DHT_TRY(ws_get(c, WS_TUNE_REF, half, &fr));
+    void* fa;
+    DHT_TRY(ws_get(c, WS_TUNE_A, half, &fa));
+    DHT_TRY(zero(c, fa, half));
     DHT_TRY(ws_get(c, WS_TUNE_RED, sizeof(Cx<double>) * TUNE_BLOCKS, &pp));
     DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
     Cx<double>* red = (Cx<double>*)pp;
     dht_probe_spec sp = {2718281u, 0u, 0};
     DHT_TRY(probes_gen(c, &sp, 0, nrhs, nrhs, fi, prec, nullptr, nullptr));
     // in = the odd half of the probe field, x = its even half
-    TuneLaunch L{HOP_PLAIN, (const char*)fi + half, fo, fi, (Cx<double>*)part};
+    TuneLaunch L{HOP_PLAIN, (const char*)fi + half, fo, fi, (Cx<double>*)part, fa};
 
     // every form and t chunk, with streaming stores on and off, sweeping the
     // lattice once for all RHS or once per group of nrhs / 2 or nrhs / 4

@@ -266,6 +266,34 @@ def test_solve_zero_right_hand_sides(c1, c1_inv, method):
     assert np.linalg.norm(x0 - c1_inv @ z0) <= 1e-8 * np.linalg.norm(c1_inv @ z0)
 
 
+def test_bf16_inner_solution_history_ring_wraps():
+    """A BF16 inner solve rebuilds its solution from the stored iterations in
+    rings (here of 3, forced): a cycle runs longer than that, so the rings
+    are flushed into x in the middle of the cycle.  The solution must still
+    meet the true-residual tolerance and match FP64."""
+    L = _lib()
+    w = WORKLOADS["c2"]
+    U = gauge_links(w.L, w.eps, w.seed)
+    ctx = L.Context(w.L, w.mass)
+    ctx.set_gauge(cuda(U))
+    Z = cuda(random_spinors(w.L, 4, 31))
+    prm = ctx.params(L.SOLVER_DC_BICGSTAB, inner=L.BF16, tol=1e-9, maxiter=4000, inner_tol=1e-5, history=3)
+    X, st, rc = ctx.solve(Z, prm)
+    assert all(s["true_resid"] <= 1e-9 for s in st), st
+    assert max(s["iters"] / max(1, s["outer"]) for s in st) > 3, st   # longer than a ring
+    with pytest.raises(L.DhtError):
+        ctx.solve(Z, ctx.params(L.SOLVER_DC_BICGSTAB, inner=L.BF16, tol=1e-9, history=17))
+    X64, st64, _ = ctx.solve(Z, ctx.params(L.SOLVER_BICGSTAB_FP64, tol=1e-11, maxiter=4000))
+    err = (X - X64).abs().max().item() / X64.abs().max().item()
+    assert err <= 1e-7, err
+    for r in (0, 3):
+        x = X[r].cpu().numpy().ravel()
+        z = Z[r].cpu().numpy().ravel()
+        res = np.linalg.norm(z - stencil.apply_D(U, w.L, w.mass, x)) / np.linalg.norm(z)
+        assert res <= 1e-9, (r, res)
+    ctx.close()
+
+
 def test_invalid_arguments(c1):
     w, U, D, ctx = c1
     L = _lib()
