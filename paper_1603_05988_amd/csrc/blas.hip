@@ -19,7 +19,7 @@
 namespace dht {
 
 static constexpr int RED_THREADS = 256;
-static constexpr int RED_MAX_BLOCKS = 4096;
+static constexpr int RED_MAX_BLOCKS = 16384;
 
 static int red_blocks(size_t nvec) {
     size_t nb = (nvec + RED_THREADS - 1) / RED_THREADS;
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(RED_THREADS) void r_update_kernel(void* r_, const v
 // RHS's stale values)
 template <typename S>
 __global__ void accum_hist_kernel(Cx<double>* X, const void* P, const void* Sv, const Cx<double>* hist, int n,
-                                  size_t nvec, int64_t SB, int B, const double* scale, int assign) {
+                                  size_t nvec, int64_t SB, int B, const double* scale, int assign, const void* P0) {
     typedef typename Store<S>::acc T;
     constexpr int VW = Store<S>::VW;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -446,7 +446,7 @@ __global__ void accum_hist_kernel(Cx<double>* X, const void* P, const void* Sv, 
             const Cx<double> al = hist[(int64_t)j * 2 * B + rr], om = hist[((int64_t)j * 2 + 1) * B + rr];
             Cx<T> v[VW];
             if (al.re != 0.0 || al.im != 0.0) {
-                Store<S>::ldv((const char*)P + (size_t)j * nvec * 16, i, v);
+                Store<S>::ldv((j == 0 && P0) ? P0 : (const void*)((const char*)P + (size_t)j * nvec * 16), i, v);
 #pragma unroll
                 for (int q = 0; q < VW; q++) acc[q] = acc[q] + al * cmake<double>(v[q].re, v[q].im);
             }
@@ -477,11 +477,11 @@ int r_update_dots(dht_ctx* c, int prec, void* r, const void* s, const void* t, c
 }
 
 int accum_hist(dht_ctx* c, int prec, void* X, const void* P, const void* Sv, const Cx<double>* hist, int n, int nrhs,
-               const double* scale, bool assign) {
+               const double* scale, bool assign, const void* P0) {
     const int64_t SB = c->g.Vh * (int64_t)nrhs;
     const size_t nvec = half_vecs(c, nrhs, prec);
     DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(accum_hist_kernel<T_>, egrid(nvec), dim3(256), 0, c->stream, (Cx<double>*)X,
-                                             P, Sv, hist, n, nvec, SB, nrhs, scale, (int)assign))
+                                             P, Sv, hist, n, nvec, SB, nrhs, scale, (int)assign, P0))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
@@ -508,7 +508,8 @@ __global__ void scale_down_kernel(const Cx<double>* in, void* out, const double*
     Store<SO>::stv(out, v, e);
 }
 // Start of an inner solve from x = 0: r = rhat = p = round(scale_r * in) in the
-// inner precision (in: FP64 half field), with the per-RHS partials of (r, r).
+// inner precision (in: FP64 half field; p = null: p is not written), with the
+// per-RHS partials of (r, r).
 template <typename SO>
 __global__ __launch_bounds__(RED_THREADS) void solve_init_kernel(const Cx<double>* in, const double* scale, void* r,
                                                                  void* rh, void* p, size_t nlo, int64_t SB, int B,
@@ -529,7 +530,7 @@ __global__ __launch_bounds__(RED_THREADS) void solve_init_kernel(const Cx<double
         }
         Store<SO>::stv(r, v, e);
         Store<SO>::stv(rh, v, e);
-        Store<SO>::stv(p, v, e);
+        if (p) Store<SO>::stv(p, v, e);
     }
     red[0][threadIdx.x] = d0;
     block_reduce_rhs<1>(red, B);

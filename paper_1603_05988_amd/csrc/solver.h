@@ -58,8 +58,9 @@ int accum_up(dht_ctx* c, void* x, const void* e, int pin, const double* scale, i
 int r_update_dots(dht_ctx* c, int prec, void* r, const void* s, const void* t, const void* rh, const RhsState* st,
                   size_t nvec, int B, Cx<double>* partial, int* nblocks, Cx<double>* hist);
 // X (FP64) = [X +] scale * sum over n stored iterations of (alpha_j p_j + omega_j s_j)
+// (P0 non-null: p_0 is read from P0 instead of slot 0)
 int accum_hist(dht_ctx* c, int prec, void* X, const void* P, const void* Sv, const Cx<double>* hist, int n, int nrhs,
-               const double* scale, bool assign);
+               const double* scale, bool assign, const void* P0 = nullptr);
 int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t ncomplex);
 int zero(dht_ctx* c, void* p, size_t bytes);
 

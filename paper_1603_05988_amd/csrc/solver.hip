@@ -84,7 +84,8 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     // p = r come out of one pass over the FP64 source with the (r, r) sums
     const double bd_eps = prec == DHT_FP64 ? 1e-14 : 1e-6;
     int nb;
-    DHT_TRY(solve_init(c, src, prec, scale, r, rh, ringP, nrhs, partial, &nb));
+    // with XAccum the first direction p_0 = r_0 is rhat itself (not copied)
+    DHT_TRY(solve_init(c, src, prec, scale, r, rh, xa ? nullptr : ringP, nrhs, partial, &nb));
     DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_INIT, bd_eps));
     // add the stored iterations [0, n) to X (after a synchronisation, so hs
     // holds the current states)
@@ -93,7 +94,8 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     auto flush = [&](int n) -> int {
         for (int i = 0; i < nrhs; i++) fs[i] = hs[i].status == RS_NAN ? 0.0 : xa->scale[i];
         DHT_HIP(hipMemcpyAsync(hscale, fs.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-        DHT_TRY(accum_hist(c, prec, xa->X, ringP, ringS, hist, n, nrhs, hscale, xa->assign && first_flush));
+        DHT_TRY(accum_hist(c, prec, xa->X, ringP, ringS, hist, n, nrhs, hscale, xa->assign && first_flush,
+                           first_flush ? rh : nullptr));
         first_flush = false;
         return DHT_OK;
     };
@@ -103,9 +105,13 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     int stored = 0;
     for (int it = 0; it < maxiter; it++) {
         const int slot = xa ? it % K : 0;
-        char* pc = ringP + (size_t)slot * bytes;
+        char* pc = (xa && it == 0) ? (char*)rh : ringP + (size_t)slot * bytes;
         char* sc = ringS + (size_t)slot * bytes;
-        if (it > 0) DHT_TRY(p_update(c, prec, pc, r, v, st, nvec, nrhs, xa ? ringP + (size_t)((it - 1) % K) * bytes : nullptr));
+        if (it > 0) {
+            const void* pin = nullptr;   // in place
+            if (xa) pin = it == 1 ? rh : (const void*)(ringP + (size_t)((it - 1) % K) * bytes);
+            DHT_TRY(p_update(c, prec, pc, r, v, st, nvec, nrhs, pin));
+        }
         HopDot d1;
         d1.kind = HOPDOT_A_OUT;   // (rhat, v)
         d1.a = rh;
