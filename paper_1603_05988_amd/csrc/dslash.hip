@@ -92,6 +92,15 @@ __device__ inline void load_spinor(const void* base, int64_t v0, int64_t vstride
 }
 
 
+// the same with non-temporal loads (operands read once: kept out of the way
+// of the stencil input's neighbour reuse in the caches)
+template <typename S>
+__device__ inline void load_spinor_nt(const void* base, int64_t v0, int64_t vstride, Cx<typename Store<S>::acc>* p) {
+    constexpr int VW = Store<S>::VW;
+#pragma unroll
+    for (int j = 0; j < 12 / VW; j++) Store<S>::ldv_nt(base, v0 + j * vstride, p + j * VW);
+}
+
 template <typename S>
 __device__ inline void load_link(const void* base, int64_t v0, Cx<typename Store<S>::acc>* u) {
     constexpr int VW = Store<S>::VW;
@@ -231,7 +240,7 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
     const T cb = (T)a.cb, ca = (T)a.ca;
     fence_acc(acc);   // the epilogue's operand loads stay below the stencil arithmetic
     Cx<T> xv[12];
-    if (XPAY) load_spinor<S>(a.x, v0, vstride, xv);
+    if (XPAY) load_spinor_nt<S>(a.x, v0, vstride, xv);
 #pragma unroll
     for (int i = 0; i < 12; i++) {
         Cx<T> v = cb * acc[i];
@@ -241,7 +250,7 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
     Cx<T> zv[12];
     if (XPAY && a.z) {   // out += cz * z (residuals z - D x in one pass)
         const T cz = (T)a.cz;
-        load_spinor<S>(a.z, v0, vstride, zv);
+        load_spinor_nt<S>(a.z, v0, vstride, zv);
 #pragma unroll
         for (int i = 0; i < 12; i++) acc[i] = acc[i] + cz * zv[i];
     }
@@ -259,7 +268,7 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
         for (int i = 0; i < 12; i++) ov[i] = Store<S>::round(acc[i]);
         if (DOT == HOPDOT_A_OUT) {
             Cx<T> av[12];
-            load_spinor<S>(a.da, v0, vstride, av);
+            load_spinor_nt<S>(a.da, v0, vstride, av);
 #pragma unroll
             for (int i = 0; i < 12; i++)
                 d0 = d0 + conjmul(cmake<double>(av[i].re, av[i].im), cmake<double>(ov[i].re, ov[i].im));
