@@ -153,10 +153,11 @@ def main():
     prm = ctx.params(L.SOLVER_DC_BICGSTAB, inner=inner, tol=w.tol, maxiter=5000, inner_tol=args.inner_tol)
 
     # launch shapes of the hopping kernel for the inner and the FP64 outer
-    # precision at this batch: from the cache if it was measured on this
-    # lattice, else timed now (setup, outside the measured region)
+    # precision (and FP32, which updates the late residuals of BF16 solves)
+    # at this batch: from the cache if it was measured on this lattice, else
+    # timed now (setup, outside the measured region)
     if args.tune == "auto":
-        want = {(inner, B), (L.FP64, B)}
+        want = {(inner, B), (L.FP64, B), (L.FP32, B)}
         if args.tune_cache and os.path.exists(args.tune_cache):
             ctx.load_tuning(args.tune_cache)
         have = set(ctx._tuned)
@@ -167,7 +168,7 @@ def main():
         if args.tune_cache:
             ctx.save_tuning(args.tune_cache)
     shapes = {}
-    for prec in sorted({inner, L.FP64}):
+    for prec in sorted({inner, L.FP64, L.FP32}):
         name = "fp64" if prec == L.FP64 else ("fp32" if prec == L.FP32 else "bf16")
         for cls, cname in L.HOP_CLASSES.items():
             v_ = ctx.hop_config(prec, B, cls)

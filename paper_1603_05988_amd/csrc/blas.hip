@@ -427,10 +427,13 @@ __global__ __launch_bounds__(RED_THREADS) void r_update_kernel(void* r_, const v
 // X (FP64 half field) = [X +] scale_r * sum_j (alpha_j p_j + omega_j s_j) over
 // the n stored iterations (p_j, s_j: slot j of the rings, storage S; hist:
 // [n][2][B]); a zero coefficient skips its vector (its slot may hold another
-// RHS's stale values)
+// RHS's stale values).  With E32 (FP32 half field) the sum is also kept there,
+// E = [E +] sum rounded to FP32, and X moves by scale_r times exactly what E
+// moved by, so that X - scale_r E stays what it was (exact to FP64 rounding).
 template <typename S>
 __global__ void accum_hist_kernel(Cx<double>* X, const void* P, const void* Sv, const Cx<double>* hist, int n,
-                                  size_t nvec, int64_t SB, int B, const double* scale, int assign, const void* P0) {
+                                  size_t nvec, int64_t SB, int B, const double* scale, int assign, const void* P0,
+                                  void* E32, int e_assign) {
     typedef typename Store<S>::acc T;
     constexpr int VW = Store<S>::VW;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -457,6 +460,24 @@ __global__ void accum_hist_kernel(Cx<double>* X, const void* P, const void* Sv, 
             }
         }
     }
+    if constexpr (VW >= 2) {
+        if (E32 && (sc != 0.0 || e_assign)) {
+#pragma unroll
+            for (int h = 0; h < VW / 2; h++) {
+                const int64_t ev = (cv * (VW / 2) + h) * SB + sr;
+                Cx<float> eo[2] = {cmake(0.f, 0.f), cmake(0.f, 0.f)};
+                if (!e_assign) Store<float>::ldv(E32, ev, eo);
+                Cx<float> en[2];
+#pragma unroll
+                for (int q2 = 0; q2 < 2; q2++) {
+                    Cx<double>& a = acc[2 * h + q2];
+                    en[q2] = cmake((float)((double)eo[q2].re + a.re), (float)((double)eo[q2].im + a.im));
+                    a = cmake((double)en[q2].re - (double)eo[q2].re, (double)en[q2].im - (double)eo[q2].im);
+                }
+                Store<float>::stv(E32, ev, en);
+            }
+        }
+    }
     if (sc == 0.0 && !assign) return;
 #pragma unroll
     for (int q = 0; q < VW; q++) {
@@ -464,6 +485,43 @@ __global__ void accum_hist_kernel(Cx<double>* X, const void* P, const void* Sv, 
         const Cx<double> x0 = assign ? cmake(0.0, 0.0) : xd;
         xd = cmake(x0.re + sc * acc[q].re, x0.im + sc * acc[q].im);
     }
+}
+
+// r (FP64 half field) -= scale_r * w (FP32 half field), with the per-RHS
+// partials of (r, r) for the new r
+__global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* r, const void* w, const double* scale,
+                                                                    size_t nvec32, int64_t SB, int B,
+                                                                    Cx<double>* partial) {
+    __shared__ Cx<double> red[1][RED_THREADS];
+    Cx<double> d0 = cmake(0.0, 0.0);
+    const double sc = scale[threadIdx.x & (B - 1)];   // the stride keeps each lane on one RHS
+    for (size_t v = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; v < nvec32; v += (size_t)gridDim.x * RED_THREADS) {
+        const int64_t cv = (int64_t)v / SB, sr = (int64_t)v - cv * SB;
+        Cx<float> wv[2];
+        Store<float>::ldv(w, v, wv);
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            Cx<double>& rd = r[(cv * 2 + q) * SB + sr];
+            const Cx<double> nr = cmake(rd.re - sc * (double)wv[q].re, rd.im - sc * (double)wv[q].im);
+            rd = nr;
+            d0.re += nr.re * nr.re + nr.im * nr.im;
+        }
+    }
+    red[0][threadIdx.x] = d0;
+    block_reduce_rhs<1>(red, B);
+    if ((int)threadIdx.x < B) partial[(int64_t)blockIdx.x * B + threadIdx.x] = red[0][threadIdx.x];
+}
+
+int residual_step(dht_ctx* c, void* r, const void* w32, const double* scale, int nrhs, Cx<double>* partial,
+                  int* nblocks) {
+    const int64_t SB = c->g.Vh * (int64_t)nrhs;
+    const size_t nvec32 = half_vecs(c, nrhs, DHT_FP32);
+    const int nb = red_blocks(nvec32);
+    *nblocks = nb;
+    hipLaunchKernelGGL(residual_step_kernel, dim3(nb), dim3(RED_THREADS), 0, c->stream, (Cx<double>*)r, w32, scale,
+                       nvec32, SB, nrhs, partial);
+    DHT_HIP(hipGetLastError());
+    return DHT_OK;
 }
 
 int r_update_dots(dht_ctx* c, int prec, void* r, const void* s, const void* t, const void* rh, const RhsState* st,
@@ -477,11 +535,12 @@ int r_update_dots(dht_ctx* c, int prec, void* r, const void* s, const void* t, c
 }
 
 int accum_hist(dht_ctx* c, int prec, void* X, const void* P, const void* Sv, const Cx<double>* hist, int n, int nrhs,
-               const double* scale, bool assign, const void* P0) {
+               const double* scale, bool assign, const void* P0, void* E32, bool e_assign) {
+    if (E32 && prec == DHT_FP64) return set_error(DHT_ERR_INVALID_ARG, "an FP32 copy of the sum needs 16- or 32-bit vectors");
     const int64_t SB = c->g.Vh * (int64_t)nrhs;
     const size_t nvec = half_vecs(c, nrhs, prec);
     DHT_PREC_SWITCH(prec, hipLaunchKernelGGL(accum_hist_kernel<T_>, egrid(nvec), dim3(256), 0, c->stream, (Cx<double>*)X,
-                                             P, Sv, hist, n, nvec, SB, nrhs, scale, (int)assign, P0))
+                                             P, Sv, hist, n, nvec, SB, nrhs, scale, (int)assign, P0, E32, (int)e_assign))
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }

@@ -59,8 +59,12 @@ int r_update_dots(dht_ctx* c, int prec, void* r, const void* s, const void* t, c
                   size_t nvec, int B, Cx<double>* partial, int* nblocks, Cx<double>* hist);
 // X (FP64) = [X +] scale * sum over n stored iterations of (alpha_j p_j + omega_j s_j)
 // (P0 non-null: p_0 is read from P0 instead of slot 0)
+// (E32 non-null: the sum is also accumulated into that FP32 field, assigned when e_assign)
 int accum_hist(dht_ctx* c, int prec, void* X, const void* P, const void* Sv, const Cx<double>* hist, int n, int nrhs,
-               const double* scale, bool assign, const void* P0 = nullptr);
+               const double* scale, bool assign, const void* P0 = nullptr, void* E32 = nullptr, bool e_assign = false);
+// r (FP64) -= scale * w (FP32), with the (r, r) partials of the new r
+int residual_step(dht_ctx* c, void* r, const void* w32, const double* scale, int nrhs, Cx<double>* partial,
+                  int* nblocks);
 int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t ncomplex);
 int zero(dht_ctx* c, void* p, size_t bytes);
 
@@ -93,6 +97,7 @@ struct XAccum {
     void* X = nullptr;             // FP64 half field
     std::vector<double> scale;     // per RHS (0: leave the RHS alone)
     bool assign = false;           // the first contribution assigns X
+    void* E32 = nullptr;           // optional FP32 half field that receives x itself
 };
 // x32: the solution x is kept in FP32 storage (BF16 vectors only); xa: see XAccum (x unused)
 int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
