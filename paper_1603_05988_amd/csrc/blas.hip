@@ -487,9 +487,10 @@ __global__ void accum_hist_kernel(Cx<double>* X, const void* P, const void* Sv, 
     }
 }
 
-// r (FP64 half field) -= scale_r * w (FP32 half field), with the per-RHS
-// partials of (r, r) for the new r
-__global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* r, const void* w, const double* scale,
+// r = r_in - scale_r * w (FP64 half fields r, r_in; FP32 w), with the
+// per-RHS partials of (r, r) for the new r
+__global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* r, const Cx<double>* r_in,
+                                                                    const void* w, const double* scale,
                                                                     size_t nvec32, int64_t SB, int B,
                                                                     Cx<double>* partial) {
     __shared__ Cx<double> red[1][RED_THREADS];
@@ -501,9 +502,10 @@ __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* 
         Store<float>::ldv(w, v, wv);
 #pragma unroll
         for (int q = 0; q < 2; q++) {
-            Cx<double>& rd = r[(cv * 2 + q) * SB + sr];
-            const Cx<double> nr = cmake(rd.re - sc * (double)wv[q].re, rd.im - sc * (double)wv[q].im);
-            rd = nr;
+            const int64_t e = (cv * 2 + q) * SB + sr;
+            const Cx<double> ri = r_in[e];
+            const Cx<double> nr = cmake(ri.re - sc * (double)wv[q].re, ri.im - sc * (double)wv[q].im);
+            r[e] = nr;
             d0.re += nr.re * nr.re + nr.im * nr.im;
         }
     }
@@ -512,14 +514,14 @@ __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* 
     if ((int)threadIdx.x < B) partial[(int64_t)blockIdx.x * B + threadIdx.x] = red[0][threadIdx.x];
 }
 
-int residual_step(dht_ctx* c, void* r, const void* w32, const double* scale, int nrhs, Cx<double>* partial,
-                  int* nblocks) {
+int residual_step(dht_ctx* c, void* r, const void* r_in, const void* w32, const double* scale, int nrhs,
+                  Cx<double>* partial, int* nblocks) {
     const int64_t SB = c->g.Vh * (int64_t)nrhs;
     const size_t nvec32 = half_vecs(c, nrhs, DHT_FP32);
     const int nb = red_blocks(nvec32);
     *nblocks = nb;
-    hipLaunchKernelGGL(residual_step_kernel, dim3(nb), dim3(RED_THREADS), 0, c->stream, (Cx<double>*)r, w32, scale,
-                       nvec32, SB, nrhs, partial);
+    hipLaunchKernelGGL(residual_step_kernel, dim3(nb), dim3(RED_THREADS), 0, c->stream, (Cx<double>*)r,
+                       (const Cx<double>*)r_in, w32, scale, nvec32, SB, nrhs, partial);
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }

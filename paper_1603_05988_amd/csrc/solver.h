@@ -62,9 +62,9 @@ int r_update_dots(dht_ctx* c, int prec, void* r, const void* s, const void* t, c
 // (E32 non-null: the sum is also accumulated into that FP32 field, assigned when e_assign)
 int accum_hist(dht_ctx* c, int prec, void* X, const void* P, const void* Sv, const Cx<double>* hist, int n, int nrhs,
                const double* scale, bool assign, const void* P0 = nullptr, void* E32 = nullptr, bool e_assign = false);
-// r (FP64) -= scale * w (FP32), with the (r, r) partials of the new r
-int residual_step(dht_ctx* c, void* r, const void* w32, const double* scale, int nrhs, Cx<double>* partial,
-                  int* nblocks);
+// r = r_in - scale * w (r, r_in FP64, may alias; w FP32), with the (r, r) partials of the new r
+int residual_step(dht_ctx* c, void* r, const void* r_in, const void* w32, const double* scale, int nrhs,
+                  Cx<double>* partial, int* nblocks);
 int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t ncomplex);
 int zero(dht_ctx* c, void* p, size_t bytes);
 
