@@ -569,8 +569,8 @@ __global__ void scale_down_kernel(const Cx<double>* in, void* out, const double*
     Store<SO>::stv(out, v, e);
 }
 // Start of an inner solve from x = 0: r = rhat = p = round(scale_r * in) in the
-// inner precision (in: FP64 half field; p = null: p is not written), with the
-// per-RHS partials of (r, r).
+// inner precision (in: FP64 half field; r or p = null: not written), with
+// the per-RHS partials of (r, r).
 template <typename SO>
 __global__ __launch_bounds__(RED_THREADS) void solve_init_kernel(const Cx<double>* in, const double* scale, void* r,
                                                                  void* rh, void* p, size_t nlo, int64_t SB, int B,
@@ -589,7 +589,7 @@ __global__ __launch_bounds__(RED_THREADS) void solve_init_kernel(const Cx<double
             e[j] = Store<SO>::round(cmake<T>((T)(sc * d.re), (T)(sc * d.im)));
             d0.re += (double)e[j].re * e[j].re + (double)e[j].im * e[j].im;
         }
-        Store<SO>::stv(r, v, e);
+        if (r) Store<SO>::stv(r, v, e);
         Store<SO>::stv(rh, v, e);
         if (p) Store<SO>::stv(p, v, e);
     }

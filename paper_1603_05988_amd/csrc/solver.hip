@@ -87,8 +87,10 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     // p = r come out of one pass over the FP64 source with the (r, r) sums
     const double bd_eps = prec == DHT_FP64 ? 1e-14 : 1e-6;
     int nb;
-    // with XAccum the first direction p_0 = r_0 is rhat itself (not copied)
-    DHT_TRY(solve_init(c, src, prec, scale, r, rh, xa ? nullptr : ringP, nrhs, partial, &nb));
+    // with XAccum, r_0 and the first direction p_0 = r_0 are rhat itself (not
+    // copied): iteration 0 reads rhat for both, and r is first written by its
+    // residual update
+    DHT_TRY(solve_init(c, src, prec, scale, xa ? nullptr : r, rh, xa ? nullptr : ringP, nrhs, partial, &nb));
     DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_INIT, bd_eps));
     // add the stored iterations [0, n) to X (after a synchronisation, so hs
     // holds the current states)
@@ -121,7 +123,7 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
         d1.partial = partial;
         DHT_TRY(apply_schur(c, prec, pc, v, tmp, nrhs, &d1));
         DHT_TRY(finalize(c, partial, d1.nblocks, 1, nrhs, st, FIN_ALPHA, bd_eps));
-        DHT_TRY(s_update(c, prec, sc, r, v, st, nvec, nrhs));
+        DHT_TRY(s_update(c, prec, sc, (xa && it == 0) ? rh : r, v, st, nvec, nrhs));
         HopDot d2;
         d2.kind = HOPDOT_OUT_X;   // (t, s), (t, t)
         d2.partial = partial;
