@@ -396,8 +396,10 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
                 outer++;
                 break;
             }
-        } else if (inc) {
+        } else if (inc && !bad) {
             // r -= sigma Dhat e: Dhat e in FP32, the update and its norms in FP64
+            // (after a NaN the discarded RHS's x may hold part of the
+            // correction: that cycle recomputes the residual from x instead)
             DHT_TRY(apply_schur(c, DHT_FP32, E32, W32, T32, nrhs, nullptr));
             DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
             void *part, *sums;
