@@ -236,10 +236,9 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     const void* Z_o = Zc + bh;
     void* X_e = Xc;
     void* X_o = Xc + bh;
-    void *bhat, *r_e, *tmpf, *scl, *tmp_o;
+    void *bhat, *r_e, *scl, *tmp_o;
     DHT_TRY(ws_get(c, WS_B, bh, &bhat));
     DHT_TRY(ws_get(c, WS_RE, bh, &r_e));
-    DHT_TRY(ws_get(c, WS_TMP_HALF, bh, &tmpf));
     DHT_TRY(ws_get(c, WS_TMPO, bh, &tmp_o));
     DHT_TRY(ws_get(c, WS_FLAGS, sizeof(double) * nrhs, &scl));
 
