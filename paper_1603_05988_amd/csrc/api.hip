@@ -499,8 +499,13 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     Cx<double>* d2 = d1 + (size_t)k * wpad;
     Cx<double>* dq = (Cx<double>*)cc + 2 * (size_t)k * bp;
 
+    // the BiCGStab paths sum q = z^H x in the epilogues of their final residual
+    const bool fused_q = prm->method == DHT_SOLVER_DC_BICGSTAB || prm->method == DHT_SOLVER_BICGSTAB_FP64;
+    // probe values are exact in BF16: the solve reads them from a BF16 field
+    // (the FP64 hops widen them exactly) unless a generic projection reads z
+    const int zprec = fused_q && (k == 0 || mfma) ? DHT_BF16 : DHT_FP64;
     DHT_TRY(record(c, 0));
-    DHT_TRY(probes_gen(c, spec, first, nrhs, bp, fz, DHT_FP64, nullptr, nullptr, win ? nullptr : (uint8_t*)zc));
+    DHT_TRY(probes_gen(c, spec, first, nrhs, bp, fz, zprec, nullptr, nullptr, win ? nullptr : (uint8_t*)zc));
     DHT_TRY(record(c, 1));
     // the projection needs only the probes: a batch's own pass runs on the
     // side stream while the main stream solves (both read fz; neither writes
@@ -543,10 +548,8 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     // exactly for the nrhs probes, 0 for the padding columns
     std::vector<double> zn2(bp, 0.0);
     for (int r = 0; r < nrhs; r++) zn2[r] = (double)(12 * c->g.V);
-    // the BiCGStab paths sum q = z^H x in the epilogues of their final residual
-    const bool fused_q = prm->method == DHT_SOLVER_DC_BICGSTAB || prm->method == DHT_SOLVER_BICGSTAB_FP64;
     std::vector<Cx<double>> zxq(bp);
-    int rc = solve_fields(c, prm, fz, fx, bp, st.data(), zn2.data(), fused_q ? zxq.data() : nullptr);
+    int rc = solve_fields(c, prm, fz, fx, bp, st.data(), zn2.data(), fused_q ? zxq.data() : nullptr, zprec);
     if (launch && rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) {
         (void)hipStreamSynchronize(c->side);   // the next batch rewrites the probes
         return rc;

@@ -101,6 +101,24 @@ __device__ inline void load_spinor_nt(const void* base, int64_t v0, int64_t vstr
     for (int j = 0; j < 12 / VW; j++) Store<S>::ldv_nt(base, v0 + j * vstride, p + j * VW);
 }
 
+// 12 components of an operand stored in S, or with B16 (an FP64 hop whose
+// operand holds values exact in BF16: probe fields) read from BF16 storage
+// and widened exactly; NT selects non-temporal loads
+template <typename S, bool B16, bool NT>
+__device__ inline void load_operand(const void* base, int64_t v0, int64_t vstride, Cx<typename Store<S>::acc>* p) {
+    typedef typename Store<S>::acc T;
+    if constexpr (B16 && !std::is_same<S, bf16x2>::value) {
+        Cx<float> q[12];
+        if (NT) load_spinor_nt<bf16x2>(base, v0, vstride, q);
+        else load_spinor<bf16x2>(base, v0, vstride, q);
+#pragma unroll
+        for (int i = 0; i < 12; i++) p[i] = cmake<T>((T)q[i].re, (T)q[i].im);
+    } else {
+        if (NT) load_spinor_nt<S>(base, v0, vstride, p);
+        else load_spinor<S>(base, v0, vstride, p);
+    }
+}
+
 template <typename S>
 __device__ inline void load_link(const void* base, int64_t v0, Cx<typename Store<S>::acc>* u) {
     constexpr int VW = Store<S>::VW;
@@ -144,7 +162,7 @@ __device__ inline void fence_acc(Cx<T>* acc) { fence_n<12>(acc); }
 // one direction: forward neighbour sf with its link at (lf, lfv), backward
 // neighbour sb with its link at (lb, lbv) (16-byte vector indices; the links
 // come from global memory or from the workgroup's LDS copy)
-template <typename S, int MU, bool DAG>
+template <typename S, int MU, bool DAG, int MIX>
 __device__ inline void hop_dir(const HopArgs& a, int sf, int sb, int r, bool phf, bool phb, const void* lf,
                                int64_t lfv, const void* lb, int64_t lbv, Cx<typename Store<S>::acc>* acc) {
     typedef typename Store<S>::acc T;
@@ -152,7 +170,7 @@ __device__ inline void hop_dir(const HopArgs& a, int sf, int sb, int r, bool phf
     constexpr int SF = DAG ? -1 : 1;   // sign of the forward projector (1 - SF g)
     {
         Cx<T> psi[12], h[6], u[9], w[6];
-        load_spinor<S>(a.in, ((int64_t)sf << a.bshift) + r, vstride, psi);
+        load_operand<S, (MIX & HOP_IN16) != 0, false>(a.in, ((int64_t)sf << a.bshift) + r, vstride, psi);
         project<MU, SF>(psi, h);
         load_link<S>(lf, lfv, u);
         mul_link<false>(u, h, w);
@@ -163,7 +181,7 @@ __device__ inline void hop_dir(const HopArgs& a, int sf, int sb, int r, bool phf
     fence_acc(acc);
     {
         Cx<T> psi[12], h[6], u[9], w[6];
-        load_spinor<S>(a.in, ((int64_t)sb << a.bshift) + r, vstride, psi);
+        load_operand<S, (MIX & HOP_IN16) != 0, false>(a.in, ((int64_t)sb << a.bshift) + r, vstride, psi);
         project<MU, -SF>(psi, h);
         load_link<S>(lb, lbv, u);
         mul_link<true>(u, h, w);
@@ -230,7 +248,7 @@ static constexpr int64_t HOP_MIN_LANES = 1 << 20;
 
 // out = cb * acc + ca * x (g5 applied on request), stored; the fused dot
 // products use the stored (rounded) values, so they match a separate pass
-template <typename S, bool G5OUT, bool XPAY, int DOT>
+template <typename S, bool G5OUT, bool XPAY, int DOT, int MIX>
 __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename Store<S>::acc>* acc, Cx<double>& d0,
                                     Cx<double>& d1) {
     typedef typename Store<S>::acc T;
@@ -240,7 +258,7 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
     const T cb = (T)a.cb, ca = (T)a.ca;
     fence_acc(acc);   // the epilogue's operand loads stay below the stencil arithmetic
     Cx<T> xv[12];
-    if (XPAY) load_spinor_nt<S>(a.x, v0, vstride, xv);
+    if (XPAY) load_operand<S, (MIX & HOP_X16) != 0, true>(a.x, v0, vstride, xv);
 #pragma unroll
     for (int i = 0; i < 12; i++) {
         Cx<T> v = cb * acc[i];
@@ -250,7 +268,7 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
     Cx<T> zv[12];
     if (XPAY && a.z) {   // out += cz * z (residuals z - D x in one pass)
         const T cz = (T)a.cz;
-        load_spinor_nt<S>(a.z, v0, vstride, zv);
+        load_operand<S, (MIX & HOP_Z16) != 0, true>(a.z, v0, vstride, zv);
 #pragma unroll
         for (int i = 0; i < 12; i++) acc[i] = acc[i] + cz * zv[i];
     }
@@ -321,7 +339,7 @@ __device__ inline void hop_block_reduce(const HopArgs& a, int blk, int g, Cx<dou
 
 // Site-parallel form: one lane per (site, RHS), RHS fastest.  With LDSL the
 // workgroup's ns = 256 / B sites take their links from LDS.
-template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, bool LDSL>
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, bool LDSL, int MIX>
 __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
     constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
@@ -362,10 +380,10 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
         for (int i = 0; i < 12; i++) acc[i] = cmake<T>(0, 0);
 #define DHT_DIR(MU, PHF, PHB)                                                                              \
     if (LDSL)                                                                                            \
-        hop_dir<S, MU, DAG>(a, sn[2 * MU], sn[2 * MU + 1], r, PHF, PHB, hop_lds,                         \
+        hop_dir<S, MU, DAG, MIX>(a, sn[2 * MU], sn[2 * MU + 1], r, PHF, PHB, hop_lds,                         \
                             (int64_t)((2 * MU) * ns + sl) * NV, hop_lds, (int64_t)((2 * MU + 1) * ns + sl) * NV, acc); \
     else                                                                                                 \
-        hop_dir<S, MU, DAG>(a, sn[2 * MU], sn[2 * MU + 1], r, PHF, PHB, a.U,                             \
+        hop_dir<S, MU, DAG, MIX>(a, sn[2 * MU], sn[2 * MU + 1], r, PHF, PHB, a.U,                             \
                             ((int64_t)(MU * 2 + p) * a.Vh + s) * NV, a.U,                                \
                             ((int64_t)(MU * 2 + 1 - p) * a.Vh + sn[2 * MU + 1]) * NV, acc);
         DHT_DIR(0, false, false)
@@ -373,7 +391,7 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
         DHT_DIR(2, false, false)
         DHT_DIR(3, a.antiperiodic && t == a.Lt - 1, a.antiperiodic && t == 0)
 #undef DHT_DIR
-        hop_epilogue<S, G5OUT, XPAY, DOT>(a, s, r, acc, d0, d1);
+        hop_epilogue<S, G5OUT, XPAY, DOT, MIX>(a, s, r, acc, d0, d1);
     }
     hop_block_reduce<NP>(a, blk, g, d0, d1);
 }
@@ -401,13 +419,13 @@ __device__ inline void wb_load(const Cx<T>* wbs, Cx<T>* w) {
     for (int i = 0; i < 6; i++) w[i] = wbs[i * HOP_THREADS + threadIdx.x];
 }
 
-template <typename S, int SGN>
+template <typename S, int SGN, int MIX>
 __device__ inline void t_back(const HopArgs& a, int sin, int r, int64_t vstride, typename Store<S>::acc ph,
                               Cx<typename Store<S>::acc>* wbs) {
     typedef typename Store<S>::acc T;
     constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
     Cx<T> psi[12], h[6], u[9], wb[6];
-    load_spinor<S>(a.in, ((int64_t)sin << a.bshift) + r, vstride, psi);
+    load_operand<S, (MIX & HOP_IN16) != 0, false>(a.in, ((int64_t)sin << a.bshift) + r, vstride, psi);
     project<3, SGN>(psi, h);
     load_link<S>(a.U, ((int64_t)(6 + 1 - a.out_parity) * a.Vh + sin) * NV, u);
     mul_link<true>(u, h, wb);
@@ -416,7 +434,7 @@ __device__ inline void t_back(const HopArgs& a, int sin, int r, int64_t vstride,
     wb_store(wbs, wb);
 }
 
-template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT>
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, int MIX>
 __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, int y, int z, int r, int V3, int yf,
                                int yb, int zf, int zb, Cx<typename Store<S>::acc>* wbs, Cx<double>& d0,
                                Cx<double>& d1) {
@@ -436,11 +454,11 @@ __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, 
 #pragma unroll
     for (int i = 0; i < 12; i++) acc[i] = cmake<T>(0, 0);
     const int sx = row + (xb >> 1), sy = s + yb, sz = s + zb;
-    hop_dir<S, 0, DAG>(a, row + (xf >> 1), sx, r, false, false, a.U, ((int64_t)p * a.Vh + s) * NV, a.U,
+    hop_dir<S, 0, DAG, MIX>(a, row + (xf >> 1), sx, r, false, false, a.U, ((int64_t)p * a.Vh + s) * NV, a.U,
                        ((int64_t)(1 - p) * a.Vh + sx) * NV, acc);
-    hop_dir<S, 1, DAG>(a, s + yf, sy, r, false, false, a.U, ((int64_t)(2 + p) * a.Vh + s) * NV, a.U,
+    hop_dir<S, 1, DAG, MIX>(a, s + yf, sy, r, false, false, a.U, ((int64_t)(2 + p) * a.Vh + s) * NV, a.U,
                        ((int64_t)(3 - p) * a.Vh + sy) * NV, acc);
-    hop_dir<S, 2, DAG>(a, s + zf, sz, r, false, false, a.U, ((int64_t)(4 + p) * a.Vh + s) * NV, a.U,
+    hop_dir<S, 2, DAG, MIX>(a, s + zf, sz, r, false, false, a.U, ((int64_t)(4 + p) * a.Vh + s) * NV, a.U,
                        ((int64_t)(5 - p) * a.Vh + sz) * NV, acc);
     {
         Cx<T> wb[6];
@@ -450,7 +468,7 @@ __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, 
     {
         const int sn = (t + 1 == a.Lt ? 0 : t + 1) * V3 + s3;
         Cx<T> psi[12], h[6], u[9], w[6];
-        load_spinor<S>(a.in, ((int64_t)sn << a.bshift) + r, vstride, psi);
+        load_operand<S, (MIX & HOP_IN16) != 0, false>(a.in, ((int64_t)sn << a.bshift) + r, vstride, psi);
         project<3, SF>(psi, h);
         load_link<S>(a.U, ((int64_t)(6 + p) * a.Vh + s) * NV, u);
         mul_link<false>(u, h, w);
@@ -463,11 +481,11 @@ __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, 
             wb_store(wbs, w);
         }
     }
-    hop_epilogue<S, G5OUT, XPAY, DOT>(a, s, r, acc, d0, d1);
+    hop_epilogue<S, G5OUT, XPAY, DOT, MIX>(a, s, r, acc, d0, d1);
     fence_acc(acc);   // the next step's loads stay below this step's arithmetic
 }
 
-template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT>
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, int MIX>
 __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
     extern __shared__ uint4 hop_lds[];   // [2][6][HOP_THREADS] Cx<T>
@@ -495,13 +513,13 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
         // pending backward t-hops of the even / odd steps of the chunk
         Cx<T>* wb0 = (Cx<T>*)hop_lds;
         Cx<T>* wb1 = wb0 + 6 * HOP_THREADS;
-        t_back<S, -SF>(a, (t0 == 0 ? a.Lt - 1 : t0 - 1) * V3 + s3, r, vstride,
+        t_back<S, -SF, MIX>(a, (t0 == 0 ? a.Lt - 1 : t0 - 1) * V3 + s3, r, vstride,
                        (a.antiperiodic && t0 == 0) ? T(-1) : T(1), wb0);
-        t_back<S, -SF>(a, t0 * V3 + s3, r, vstride, T(1), wb1);
+        t_back<S, -SF, MIX>(a, t0 * V3 + s3, r, vstride, T(1), wb1);
 #pragma nounroll
         for (int t = t0; t < t1; t += 2) {
-            tm_step<S, DAG, G5OUT, XPAY, DOT>(a, t, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb0, d0, d1);
-            tm_step<S, DAG, G5OUT, XPAY, DOT>(a, t + 1, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb1, d0, d1);
+            tm_step<S, DAG, G5OUT, XPAY, DOT, MIX>(a, t, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb0, d0, d1);
+            tm_step<S, DAG, G5OUT, XPAY, DOT, MIX>(a, t + 1, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb1, d0, d1);
         }
     }
     hop_block_reduce<NP>(a, blk, g, d0, d1);
@@ -569,7 +587,7 @@ int hop_blocks(const dht_ctx* c, int nrhs) {
 
 template <typename S>
 static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, const void* x, double ca, double cb,
-                      int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz) {
+                      int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz, int mix) {
     HopArgs a;
     a.out = out;
     a.in = in;
@@ -616,16 +634,17 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     if (dot) dot->nblocks = nb;
     dim3 grid(nb), block(HOP_THREADS);
     bool xp = x != nullptr;
-#define DHT_HOP_CASE(D_, G_, X_, K_)                                                                         \
-    if (dagger == D_ && g5out == G_ && xp == X_ && kind == K_) {                                             \
+#define DHT_HOP_CASE_M(D_, G_, X_, K_, M_)                                                                   \
+    if (dagger == D_ && g5out == G_ && xp == X_ && kind == K_ && mix == M_) {                                \
         if (mode == DHT_HOP_TMARCH)                                                                          \
-            hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_>), grid, block, tm_lds, c->stream, a);       \
+            hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_, M_>), grid, block, tm_lds, c->stream, a);   \
         else if (mode == DHT_HOP_SITE_LDS)                                                                   \
-            hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_, true>), grid, block, lds, c->stream, a);       \
+            hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_, true, M_>), grid, block, lds, c->stream, a);   \
         else                                                                                                 \
-            hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_, false>), grid, block, 0, c->stream, a);        \
+            hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_, false, M_>), grid, block, 0, c->stream, a);    \
         goto launched;                                                                                       \
     }
+#define DHT_HOP_CASE(D_, G_, X_, K_) DHT_HOP_CASE_M(D_, G_, X_, K_, 0)
     DHT_HOP_CASE(false, false, false, HOPDOT_NONE)
     DHT_HOP_CASE(false, false, true, HOPDOT_NONE)
     DHT_HOP_CASE(false, true, false, HOPDOT_NONE)
@@ -638,7 +657,17 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     DHT_HOP_CASE(false, false, true, HOPDOT_OUT_X)
     DHT_HOP_CASE(false, false, true, HOPDOT_NORM)
     DHT_HOP_CASE(false, false, true, HOPDOT_NORM_ZX)
+    if constexpr (std::is_same<S, double>::value) {
+        // FP64 residuals whose probe operand is held in BF16 (exact values):
+        // the Schur right-hand side from z, the odd sites, the final residual
+        DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM, HOP_IN16 | HOP_X16)
+        DHT_HOP_CASE_M(false, false, true, HOPDOT_NONE, HOP_X16)
+        DHT_HOP_CASE_M(false, false, true, HOPDOT_OUT_X, HOP_X16)
+        DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM, HOP_Z16)
+        DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM_ZX, HOP_Z16)
+    }
 #undef DHT_HOP_CASE
+#undef DHT_HOP_CASE_M
     return set_error(DHT_ERR_INVALID_ARG, "unsupported hop variant");
 launched:
     DHT_HIP(hipGetLastError());
@@ -646,23 +675,25 @@ launched:
 }
 
 int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
-        int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz) {
+        int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz, int mix) {
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
+    if (mix != 0 && prec != DHT_FP64) return set_error(DHT_ERR_INVALID_ARG, "BF16 operands only in FP64 hops");
     int tok;
     DHT_TRY(prof_begin(c, &tok));
     int rc = DHT_OK;
     switch (prec) {
-        case DHT_FP64: rc = launch_hop<double>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz); break;
-        case DHT_FP32: rc = launch_hop<float>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz); break;
-        case DHT_BF16: rc = launch_hop<bf16x2>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz); break;
+        case DHT_FP64: rc = launch_hop<double>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz, mix); break;
+        case DHT_FP32: rc = launch_hop<float>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz, mix); break;
+        case DHT_BF16: rc = launch_hop<bf16x2>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz, mix); break;
     }
     if (rc != DHT_OK) return rc;
     // algorithmic bytes: read the input half field (and the xpay / dot operand),
     // write the output, read each of the 8 Vh link matrices of this parity once
-    const double eb = (double)elem_bytes(prec);
-    double nfield = 2.0 + (x ? 1.0 : 0.0) + (z ? 1.0 : 0.0) + ((dot && dot->kind == HOPDOT_A_OUT) ? 1.0 : 0.0);
-    const double bytes = nfield * 12.0 * c->g.Vh * nrhs * eb + 72.0 * c->g.Vh * eb;
+    const double eb = (double)elem_bytes(prec), e16 = (double)elem_bytes(DHT_BF16);
+    const double nbytes = eb + ((mix & HOP_IN16) ? e16 : eb) + (x ? ((mix & HOP_X16) ? e16 : eb) : 0.0) +
+                          (z ? ((mix & HOP_Z16) ? e16 : eb) : 0.0) + ((dot && dot->kind == HOPDOT_A_OUT) ? eb : 0.0);
+    const double bytes = nbytes * 12.0 * c->g.Vh * nrhs + 72.0 * c->g.Vh * eb;
     return prof_end(c, tok, PROF_HOP64 + prec, bytes);
 }
 

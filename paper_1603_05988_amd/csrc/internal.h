@@ -388,8 +388,13 @@ struct HopDot {
     Cx<double>* partial = nullptr;
     int nblocks = 0;
 };
+// Operands of an FP64 hop that hold values exact in BF16 (probe fields) may
+// be passed in the BF16 layout: mix is a set of HOP_IN16 (the stencil input),
+// HOP_X16 (the x-pay source), HOP_Z16 (the second axpy source).
+enum { HOP_IN16 = 1, HOP_X16 = 2, HOP_Z16 = 4 };
 int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
-        int nrhs, bool dagger, bool g5out, HopDot* dot = nullptr, const void* z = nullptr, double cz = 0.0);
+        int nrhs, bool dagger, bool g5out, HopDot* dot = nullptr, const void* z = nullptr, double cz = 0.0,
+        int mix = 0);
 int hop_blocks(const dht_ctx* c, int nrhs);   // workgroups of one hop launch
 constexpr int HOP_LANES = 256;   // lanes per hop workgroup
 // the shape a hop launch for (prec, nrhs) uses (t chunk resolved), and a check

@@ -108,9 +108,12 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
 // stats has nrhs entries (the padded batch).
 // zn2_known (host, nrhs, may be null): ||Z||^2 per RHS when the caller knows it exactly;
 // zx_out (host, nrhs, may be null; BiCGStab methods only): z^H x per RHS, summed in
-// the epilogues of the final full-lattice residual
+// the epilogues of the final full-lattice residual.
+// zprec DHT_BF16: Z is in the BF16 layout ([2][3][Vh][B][4]) and holds values exact
+// in BF16 (probes); needs zn2_known and a BiCGStab method; results equal those of the
+// same Z in FP64
 int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats,
-                 const double* zn2_known = nullptr, Cx<double>* zx_out = nullptr);
+                 const double* zn2_known = nullptr, Cx<double>* zx_out = nullptr, int zprec = DHT_FP64);
 
 // fgmres.hip: FP64 defect correction around FGMRES(m) cycles (FP32) on the
 // full lattice with the network (use_nn) or the identity as right

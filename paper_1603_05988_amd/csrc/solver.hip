@@ -165,10 +165,10 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
 // norms reduced from the hop's fused epilogue sums; `slot` selects where the
 // sums are kept so that two residuals can be summed on the host.  With zx
 // non-null the same epilogue also sums z^H x per RHS (z and x are the
-// epilogue's operands) into *zx.
+// epilogue's operands) into *zx.  mix marks operands held in BF16 (see hop).
 static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const void* x, double ca, double cb,
                         const void* z, int nrhs, int slot, std::vector<double>& n2,
-                        std::vector<Cx<double>>* zx = nullptr) {
+                        std::vector<Cx<double>>* zx = nullptr, int mix = 0) {
     void *part, *sums;
     DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
     DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs, &sums));
@@ -176,7 +176,7 @@ static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const
     HopDot d;
     d.kind = zx ? HOPDOT_NORM_ZX : HOPDOT_NORM;
     d.partial = (Cx<double>*)part;
-    DHT_TRY(hop(c, DHT_FP64, parity, in, out, x, ca, cb, nrhs, false, false, &d, z, z ? 1.0 : 0.0));
+    DHT_TRY(hop(c, DHT_FP64, parity, in, out, x, ca, cb, nrhs, false, false, &d, z, z ? 1.0 : 0.0, mix));
     Cx<double>* s = (Cx<double>*)sums + (size_t)slot * 2 * nrhs;
     DHT_TRY(finalize(c, d.partial, d.nblocks, np, nrhs, nullptr, FIN_SUM, 0.0, s));
     std::vector<Cx<double>> h((size_t)np * nrhs);
@@ -189,18 +189,21 @@ static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const
 }
 
 // odd sites from the even ones, x_o = (z_o + Hop_oe x_e / 2) / a; with zx
-// non-null the epilogue also sums z_o^H x_o per RHS into *zx
+// non-null the epilogue also sums z_o^H x_o per RHS into *zx; z16: z_o is
+// held in BF16
 static int odd_from_even(dht_ctx* c, const void* X_e, void* X_o, const void* Z_o, int nrhs,
-                         std::vector<Cx<double>>* zx) {
+                         std::vector<Cx<double>>* zx, bool z16) {
     const double a = 4.0 + c->mass;
-    if (!zx) return hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false);
+    const int mix = z16 ? HOP_X16 : 0;
+    if (!zx) return hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false, nullptr, nullptr,
+                        0.0, mix);
     void *part, *sums;
     DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
     DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs, &sums));
     HopDot d;
     d.kind = HOPDOT_OUT_X;   // (x_o, z_o) and (x_o, x_o)
     d.partial = (Cx<double>*)part;
-    DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false, &d));
+    DHT_TRY(hop(c, DHT_FP64, 1, X_e, X_o, Z_o, 1.0 / a, 1.0 / (2.0 * a), nrhs, false, false, &d, nullptr, 0.0, mix));
     Cx<double>* s = (Cx<double>*)sums + (size_t)2 * 2 * nrhs;
     DHT_TRY(finalize(c, d.partial, d.nblocks, 2, nrhs, nullptr, FIN_SUM, 0.0, s));
     std::vector<Cx<double>> h(nrhs);
@@ -226,14 +229,21 @@ static int norms2(dht_ctx* c, const void* f, size_t nvec, int nrhs, std::vector<
 }
 
 int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats,
-                 const double* zn2_known, Cx<double>* zx_out) {
+                 const double* zn2_known, Cx<double>* zx_out, int zprec) {
     const double a = 4.0 + c->mass;
     const size_t nh = half_elems(c, nrhs);   // complex entries (= FP64 vectors) per half field
     const size_t bh = nh * 16;
+    // Z in the BF16 layout (values exact in BF16, as probes are): the FP64
+    // hops that read it widen it exactly, so every result is the one of an
+    // FP64 Z
+    const bool z16 = zprec == DHT_BF16;
+    if (zprec != DHT_FP64 && !z16) return set_error(DHT_ERR_INVALID_ARG, "bad right-hand side precision");
+    if (z16 && (!zn2_known || prm->method == DHT_SOLVER_DC_FGMRES_NN || prm->method == DHT_SOLVER_DC_FGMRES))
+        return set_error(DHT_ERR_INVALID_ARG, "a BF16 right-hand side needs its norms and a BiCGStab method");
     const char* Zc = (const char*)Z;
     char* Xc = (char*)X;
     const void* Z_e = Zc;
-    const void* Z_o = Zc + bh;
+    const void* Z_o = Zc + (z16 ? nh * elem_bytes(DHT_BF16) : bh);
     void* X_e = Xc;
     void* X_o = Xc + bh;
     void *bhat, *r_e, *scl, *tmp_o;
@@ -256,7 +266,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         p2.inner = DHT_FP32;
         std::vector<dht_solve_stats> st2(nrhs);
         std::vector<dht_solve_stats> st1(stats ? stats : st2.data(), (stats ? stats : st2.data()) + nrhs);
-        rc = solve_fields(c, &p2, Z, X, nrhs, st2.data(), zn2_known, nullptr);
+        rc = solve_fields(c, &p2, Z, X, nrhs, st2.data(), zn2_known, nullptr, zprec);
         if (stats)
             for (int i = 0; i < nrhs; i++) {
                 stats[i] = st2[i];
@@ -275,7 +285,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
 
     // right-hand side of the Schur system with its norms, and ||Z||^2
     std::vector<double> zn2, rn2;
-    DHT_TRY(residual_hop(c, 0, Z_o, bhat, Z_e, 1.0, 1.0 / (2.0 * a), nullptr, nrhs, 0, rn2));
+    DHT_TRY(residual_hop(c, 0, Z_o, bhat, Z_e, 1.0, 1.0 / (2.0 * a), nullptr, nrhs, 0, rn2, nullptr,
+                         z16 ? HOP_IN16 | HOP_X16 : 0));
     if (zn2_known) zn2.assign(zn2_known, zn2_known + nrhs);
     else DHT_TRY(norms2(c, Z, 2 * nh, nrhs, zn2));
     std::vector<double> target2(nrhs);
@@ -384,8 +395,9 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         for (int i = 0; i < nrhs; i++)
             if (sup[i] > 0 && !(rn2[i] * br.rnorm2[i] <= target2[i])) predict = false;
         if (predict) {
-            DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr));
-            DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, zx_out ? &zx_e : nullptr));
+            DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr, z16));
+            DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, zx_out ? &zx_e : nullptr,
+                                 z16 ? HOP_Z16 : 0));
             bool done = true;
             full2 = rn2;
             for (int i = 0; i < nrhs; i++)
@@ -431,8 +443,9 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         // odd sites and the FP64 full-lattice true residual: its even half
         // r_e = z_e - (a x_e - Hop_eo x_o / 2) with norms fused (the odd half
         // vanishes by the construction of x_o)
-        DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr));
-        DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, fr2, zx_out ? &zx_e : nullptr));
+        DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr, z16));
+        DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, fr2, zx_out ? &zx_e : nullptr,
+                             z16 ? HOP_Z16 : 0));
     }
     if (zx_out)
         for (int i = 0; i < nrhs; i++) zx_out[i] = zx_e[i] + zx_o[i];

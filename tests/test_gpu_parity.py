@@ -243,6 +243,34 @@ def test_trace_batch_c1_mc_and_deflated(c1, c1_inv):
 
 
 @pytest.mark.parametrize("method", ["fp64", "dc_bf16"])
+def test_trace_batch_c1_without_deflation(c1, c1_inv, method):
+    """Without a deflation basis the batch solves take the probes from a BF16
+    field (probe values are exact there; the FP64 hops widen them exactly):
+    q matches the exact inverse, and the solve of the same probes handed in
+    as an FP64 field, to the solver's tolerance."""
+    w, U, D, ctx = c1
+    L = _lib()
+    ctx.clear_deflation()
+    ctx.reset_estimate()
+    prm = (ctx.params(L.SOLVER_BICGSTAB_FP64, tol=1e-12) if method == "fp64"
+           else ctx.params(L.SOLVER_DC_BICGSTAB, inner=L.BF16, tol=1e-10))
+    n = 2 * w.batch
+    recs = []
+    for b in range(0, n, w.batch):
+        recs += ctx.trace_batch(w.seed, 1, True, b, w.batch, prm)
+    Z = rng.probes(w.L, w.seed, 1, True, 0, n)
+    q_ref = np.einsum("ja,ab,jb->j", Z.conj(), c1_inv, Z)
+    q = np.array([r["q"] for r in recs])
+    tol = 1e-10 if method == "fp64" else 1e-8
+    scale = np.abs(q_ref).max()
+    assert np.abs(q - q_ref).max() <= tol * scale
+    X, st, rc = ctx.solve(cuda(Z.reshape((n,) + ctx._spinor_shape())), prm)
+    q2 = np.einsum("ja,ja->j", Z.conj(), X.cpu().numpy().reshape(n, -1))
+    assert np.abs(q - q2).max() <= tol * scale
+    assert ctx.estimate()["n"] == n
+
+
+@pytest.mark.parametrize("method", ["fp64", "dc_bf16"])
 def test_solve_zero_right_hand_sides(c1, c1_inv, method):
     """A zero right-hand side has the solution 0 (the solver writes it although
     no correction is ever applied), alone or next to a non-zero one, and the
