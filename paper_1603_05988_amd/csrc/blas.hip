@@ -26,6 +26,26 @@ static int red_blocks(size_t nvec) {
     return (int)std::max<size_t>(1, std::min<size_t>(nb, RED_MAX_BLOCKS));
 }
 
+// Position v = cv * SB + sr of a grid-stride loop over vectors whose
+// component groups lie SB apart, advanced without a 64-bit division per step
+struct StridePos {
+    int64_t cv, sr, qs, rs, SB;
+    __device__ StridePos(size_t v0, size_t stride, int64_t SB_) : SB(SB_) {
+        cv = (int64_t)v0 / SB;
+        sr = (int64_t)v0 - cv * SB;
+        qs = (int64_t)stride / SB;
+        rs = (int64_t)stride - qs * SB;
+    }
+    __device__ void next() {
+        cv += qs;
+        sr += rs;
+        if (sr >= SB) {
+            sr -= SB;
+            cv++;
+        }
+    }
+};
+
 // fixed-order tree over the RED_THREADS lanes down to B entries (lane r keeps RHS r)
 template <int NP>
 __device__ inline void block_reduce_rhs(Cx<double> (*red)[RED_THREADS], int B) {
@@ -400,19 +420,30 @@ __global__ __launch_bounds__(RED_THREADS) void r_update_kernel(void* r_, const v
     }
     if (x.active) {
         Cx<T> om = cscal<T>(x.omega);
-        for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nvec; i += stride) {
-            Cx<T> sv[VW], tv[VW], hv[VW];
-            Store<S>::ldv(s, i, sv);
-            Store<S>::ldv(t, i, tv);
-            Store<S>::ldv(rh, i, hv);
+        // two vectors per step, both loaded before either is used; the sums
+        // keep the order of a one-vector loop
+        for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nvec; i += 2 * stride) {
+            const bool two = i + stride < nvec;
+            Cx<T> sv[2][VW], tv[2][VW], hv[2][VW];
 #pragma unroll
-            for (int j = 0; j < VW; j++) {
-                sv[j] = Store<S>::round(sv[j] - om * tv[j]);   // the new r, as stored
-                Cx<double> rd = cmake<double>(sv[j].re, sv[j].im);
-                d0 = d0 + conjmul(cmake<double>(hv[j].re, hv[j].im), rd);
-                d1.re += rd.re * rd.re + rd.im * rd.im;
-            }
-            Store<S>::stv(r_, i, sv);
+            for (int u = 0; u < 2; u++)
+                if (u == 0 || two) {
+                    Store<S>::ldv(s, i + u * stride, sv[u]);
+                    Store<S>::ldv(t, i + u * stride, tv[u]);
+                    Store<S>::ldv(rh, i + u * stride, hv[u]);
+                }
+#pragma unroll
+            for (int u = 0; u < 2; u++)
+                if (u == 0 || two) {
+#pragma unroll
+                    for (int j = 0; j < VW; j++) {
+                        sv[u][j] = Store<S>::round(sv[u][j] - om * tv[u][j]);   // the new r, as stored
+                        Cx<double> rd = cmake<double>(sv[u][j].re, sv[u][j].im);
+                        d0 = d0 + conjmul(cmake<double>(hv[u][j].re, hv[u][j].im), rd);
+                        d1.re += rd.re * rd.re + rd.im * rd.im;
+                    }
+                    Store<S>::stv(r_, i + u * stride, sv[u]);
+                }
         }
     }
     red[0][threadIdx.x] = d0;
@@ -496,18 +527,39 @@ __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* 
     __shared__ Cx<double> red[1][RED_THREADS];
     Cx<double> d0 = cmake(0.0, 0.0);
     const double sc = scale[threadIdx.x & (B - 1)];   // the stride keeps each lane on one RHS
-    for (size_t v = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; v < nvec32; v += (size_t)gridDim.x * RED_THREADS) {
-        const int64_t cv = (int64_t)v / SB, sr = (int64_t)v - cv * SB;
-        Cx<float> wv[2];
-        Store<float>::ldv(w, v, wv);
+    const size_t stride = (size_t)gridDim.x * RED_THREADS;
+    const size_t v0 = (size_t)blockIdx.x * RED_THREADS + threadIdx.x;
+    StridePos pos(v0, stride, SB);
+    // two vectors per step, both loaded before either is used (sums in the
+    // order of a one-vector loop)
+    for (size_t v = v0; v < nvec32; v += 2 * stride) {
+        const bool two = v + stride < nvec32;
+        Cx<float> wv[2][2];
+        Cx<double> ri[2][2];
+        int64_t e[2][2];
 #pragma unroll
-        for (int q = 0; q < 2; q++) {
-            const int64_t e = (cv * 2 + q) * SB + sr;
-            const Cx<double> ri = r_in[e];
-            const Cx<double> nr = cmake(ri.re - sc * (double)wv[q].re, ri.im - sc * (double)wv[q].im);
-            r[e] = nr;
-            d0.re += nr.re * nr.re + nr.im * nr.im;
+        for (int u = 0; u < 2; u++) {
+            if (u == 0 || two) {
+                Store<float>::ldv(w, v + u * stride, wv[u]);
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    e[u][q] = (pos.cv * 2 + q) * SB + pos.sr;
+                    ri[u][q] = r_in[e[u][q]];
+                }
+            }
+            pos.next();
         }
+#pragma unroll
+        for (int u = 0; u < 2; u++)
+            if (u == 0 || two) {
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    const Cx<double> nr =
+                        cmake(ri[u][q].re - sc * (double)wv[u][q].re, ri[u][q].im - sc * (double)wv[u][q].im);
+                    r[e[u][q]] = nr;
+                    d0.re += nr.re * nr.re + nr.im * nr.im;
+                }
+            }
     }
     red[0][threadIdx.x] = d0;
     block_reduce_rhs<1>(red, B);
@@ -580,18 +632,36 @@ __global__ __launch_bounds__(RED_THREADS) void solve_init_kernel(const Cx<double
     __shared__ Cx<double> red[1][RED_THREADS];
     Cx<double> d0 = cmake(0.0, 0.0);
     const double sc = scale[threadIdx.x & (B - 1)];   // the stride keeps each lane on one RHS
-    for (size_t v = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; v < nlo; v += (size_t)gridDim.x * RED_THREADS) {
-        int64_t cv = (int64_t)(v / SB), sr = (int64_t)v - cv * SB;
-        Cx<T> e[VW];
+    const size_t stride = (size_t)gridDim.x * RED_THREADS;
+    const size_t v0 = (size_t)blockIdx.x * RED_THREADS + threadIdx.x;
+    StridePos pos(v0, stride, SB);
+    // two vectors per step, both loaded before either is used (sums in the
+    // order of a one-vector loop)
+    for (size_t v = v0; v < nlo; v += 2 * stride) {
+        const bool two = v + stride < nlo;
+        Cx<double> d[2][VW];
 #pragma unroll
-        for (int j = 0; j < VW; j++) {
-            Cx<double> d = in[(cv * VW + j) * SB + sr];
-            e[j] = Store<SO>::round(cmake<T>((T)(sc * d.re), (T)(sc * d.im)));
-            d0.re += (double)e[j].re * e[j].re + (double)e[j].im * e[j].im;
+        for (int u = 0; u < 2; u++) {
+            if (u == 0 || two) {
+#pragma unroll
+                for (int j = 0; j < VW; j++) d[u][j] = in[(pos.cv * VW + j) * SB + pos.sr];
+            }
+            pos.next();
         }
-        if (r) Store<SO>::stv(r, v, e);
-        Store<SO>::stv(rh, v, e);
-        if (p) Store<SO>::stv(p, v, e);
+#pragma unroll
+        for (int u = 0; u < 2; u++)
+            if (u == 0 || two) {
+                Cx<T> e[VW];
+#pragma unroll
+                for (int j = 0; j < VW; j++) {
+                    e[j] = Store<SO>::round(cmake<T>((T)(sc * d[u][j].re), (T)(sc * d[u][j].im)));
+                    d0.re += (double)e[j].re * e[j].re + (double)e[j].im * e[j].im;
+                }
+                const size_t vu = v + u * stride;
+                if (r) Store<SO>::stv(r, vu, e);
+                Store<SO>::stv(rh, vu, e);
+                if (p) Store<SO>::stv(p, vu, e);
+            }
     }
     red[0][threadIdx.x] = d0;
     block_reduce_rhs<1>(red, B);
