@@ -261,7 +261,10 @@ int dht_project_probes(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, 
 
 /* The loop body of Algorithm 1 for probes j = first .. first+nrhs-1: generate the
  * probes on the device, solve, form q = z^H x in FP64, project on the
- * deflation basis (when set) and accumulate the running estimates.  records
+ * deflation basis (when set) and accumulate the running estimates.  With a
+ * BiCGStab method the probes are generated in BF16 storage (their values
+ * i^k * (+-1) are exact there) and the FP64 hops that read them widen them
+ * exactly, so results equal those of FP64 probes.  records
  * (host, nrhs entries, may be NULL) receives per-probe results; coef_host
  * (may be NULL) receives the projection coefficients c1, c2 as complex128
  * [2][k][nrhs] for playback with other k (Section 6.4). */

@@ -141,7 +141,8 @@ __device__ void state_update(RhsState& x, const Cx<double>* v, int op, double bd
         x.omega = cmake(1.0, 0.0);
         x.beta = cmake(0.0, 0.0);
         x.iters = 0;
-        if (!isfinite(v[0].re)) { x.active = 0; x.status = RS_NAN; }
+        if (x.target2 < 0.0) { x.active = 0; x.status = RS_CONVERGED; }   // not part of this solve
+        else if (!isfinite(v[0].re)) { x.active = 0; x.status = RS_NAN; }
         else if (x.rnorm2 <= x.target2) { x.active = 0; x.status = RS_CONVERGED; }
         else { x.active = 1; x.status = RS_RUNNING; }
         return;
@@ -519,14 +520,18 @@ __global__ void accum_hist_kernel(Cx<double>* X, const void* P, const void* Sv, 
 }
 
 // r = r_in - scale_r * w (FP64 half fields r, r_in; FP32 w), with the
-// per-RHS partials of (r, r) for the new r
+// per-RHS partials of (r, r) for the new r; with rh16 also s16_r * r in BF16
+// (the next inner solve's right-hand side: each FP32 vector of w fills one
+// half of a BF16 vector)
 __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* r, const Cx<double>* r_in,
                                                                     const void* w, const double* scale,
                                                                     size_t nvec32, int64_t SB, int B,
-                                                                    Cx<double>* partial) {
+                                                                    Cx<double>* partial, void* rh16,
+                                                                    const double* s16) {
     __shared__ Cx<double> red[1][RED_THREADS];
     Cx<double> d0 = cmake(0.0, 0.0);
     const double sc = scale[threadIdx.x & (B - 1)];   // the stride keeps each lane on one RHS
+    const double s16r = rh16 ? s16[threadIdx.x & (B - 1)] : 0.0;
     const size_t stride = (size_t)gridDim.x * RED_THREADS;
     const size_t v0 = (size_t)blockIdx.x * RED_THREADS + threadIdx.x;
     StridePos pos(v0, stride, SB);
@@ -536,7 +541,7 @@ __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* 
         const bool two = v + stride < nvec32;
         Cx<float> wv[2][2];
         Cx<double> ri[2][2];
-        int64_t e[2][2];
+        int64_t e[2][2], h16[2];
 #pragma unroll
         for (int u = 0; u < 2; u++) {
             if (u == 0 || two) {
@@ -546,19 +551,24 @@ __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* 
                     e[u][q] = (pos.cv * 2 + q) * SB + pos.sr;
                     ri[u][q] = r_in[e[u][q]];
                 }
+                // 8-byte half (cv mod 2) of BF16 vector (cv / 2) * SB + sr
+                h16[u] = (((pos.cv >> 1) * SB + pos.sr) << 1) + (pos.cv & 1);
             }
             pos.next();
         }
 #pragma unroll
         for (int u = 0; u < 2; u++)
             if (u == 0 || two) {
+                uint32_t hb[2];
 #pragma unroll
                 for (int q = 0; q < 2; q++) {
                     const Cx<double> nr =
                         cmake(ri[u][q].re - sc * (double)wv[u][q].re, ri[u][q].im - sc * (double)wv[u][q].im);
                     r[e[u][q]] = nr;
                     d0.re += nr.re * nr.re + nr.im * nr.im;
+                    hb[q] = Store<bf16x2>::pack(cmake<float>((float)(s16r * nr.re), (float)(s16r * nr.im)));
                 }
+                if (rh16) ((uint2*)rh16)[h16[u]] = make_uint2(hb[0], hb[1]);
             }
     }
     red[0][threadIdx.x] = d0;
@@ -567,13 +577,14 @@ __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* 
 }
 
 int residual_step(dht_ctx* c, void* r, const void* r_in, const void* w32, const double* scale, int nrhs,
-                  Cx<double>* partial, int* nblocks) {
+                  Cx<double>* partial, int* nblocks, void* rh16, const double* s16) {
+    if (rh16 && !s16) return set_error(DHT_ERR_INVALID_ARG, "BF16 residual copy needs its scales");
     const int64_t SB = c->g.Vh * (int64_t)nrhs;
     const size_t nvec32 = half_vecs(c, nrhs, DHT_FP32);
     const int nb = red_blocks(nvec32);
     *nblocks = nb;
     hipLaunchKernelGGL(residual_step_kernel, dim3(nb), dim3(RED_THREADS), 0, c->stream, (Cx<double>*)r,
-                       (const Cx<double>*)r_in, w32, scale, nvec32, SB, nrhs, partial);
+                       (const Cx<double>*)r_in, w32, scale, nvec32, SB, nrhs, partial, rh16, s16);
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }

@@ -346,7 +346,7 @@ enum Slot {
     WS_NORMS, WS_FOLD,
     WS_EIG_V, WS_EIG_W, WS_EIG_T, WS_EIG_U, WS_EIG_PART, WS_EIG_SMALL, WS_EIG_RPART, WS_EIG_LAM, WS_EIG_CANON, WS_DEFL_GET,
     WS_PW_CODE, WS_PW_COEF,
-    WS_RING_P, WS_RING_S, WS_HIST, WS_HIST_SCALE, WS_E32, WS_W32, WS_T32,
+    WS_RING_P, WS_RING_S, WS_HIST, WS_HIST_SCALE, WS_E32, WS_W32, WS_T32, WS_S16,
     WS_NSLOTS
 };
 int ws_get(dht_ctx* c, int slot, size_t bytes, void** out);

@@ -62,9 +62,10 @@ int r_update_dots(dht_ctx* c, int prec, void* r, const void* s, const void* t, c
 // (E32 non-null: the sum is also accumulated into that FP32 field, assigned when e_assign)
 int accum_hist(dht_ctx* c, int prec, void* X, const void* P, const void* Sv, const Cx<double>* hist, int n, int nrhs,
                const double* scale, bool assign, const void* P0 = nullptr, void* E32 = nullptr, bool e_assign = false);
-// r = r_in - scale * w (r, r_in FP64, may alias; w FP32), with the (r, r) partials of the new r
+// r = r_in - scale * w (r, r_in FP64, may alias; w FP32), with the (r, r) partials of the new r;
+// rh16 non-null: also writes s16 * r (device scales per RHS) as a BF16 half field
 int residual_step(dht_ctx* c, void* r, const void* r_in, const void* w32, const double* scale, int nrhs,
-                  Cx<double>* partial, int* nblocks);
+                  Cx<double>* partial, int* nblocks, void* rh16 = nullptr, const double* s16 = nullptr);
 int sub(dht_ctx* c, const void* a, const void* b, void* y, size_t ncomplex);
 int zero(dht_ctx* c, void* p, size_t bytes);
 
@@ -99,10 +100,12 @@ struct XAccum {
     bool assign = false;           // the first contribution assigns X
     void* E32 = nullptr;           // optional FP32 half field that receives x itself
 };
-// x32: the solution x is kept in FP32 storage (BF16 vectors only); xa: see XAccum (x unused)
+// x32: the solution x is kept in FP32 storage (BF16 vectors only); xa: see XAccum (x unused);
+// r0n2 (host, nrhs; with xa only): the right-hand side is already in rhat (the BF16
+// copy written by residual_step), with these squared norms; src and scale are unused
 int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
              const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32 = false,
-             XAccum* xa = nullptr);
+             XAccum* xa = nullptr, const double* r0n2 = nullptr);
 
 // Top-level solve of D X = Z on internal full FP64 fields (Z, X: [2][12][Vh][B]);
 // stats has nrhs entries (the padded batch).

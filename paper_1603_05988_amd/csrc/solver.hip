@@ -38,7 +38,9 @@ int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o
 static int slot_base(int prec) { return prec == DHT_FP64 ? WS_K64 : WS_KLO; }
 
 int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
-             const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32, XAccum* xa) {
+             const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32, XAccum* xa,
+             const double* r0n2) {
+    if (r0n2 && !xa) return set_error(DHT_ERR_INVALID_ARG, "a prepared right-hand side needs the stored iterations");
     const size_t nvec = half_vecs(c, nrhs, prec);
     const size_t bytes = nvec * 16;
     const int base = slot_base(prec);
@@ -90,7 +92,14 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     // with XAccum, r_0 and the first direction p_0 = r_0 are rhat itself (not
     // copied): iteration 0 reads rhat for both, and r is first written by its
     // residual update
-    DHT_TRY(solve_init(c, src, prec, scale, xa ? nullptr : r, rh, xa ? nullptr : ringP, nrhs, partial, &nb));
+    if (r0n2) {   // rhat was written by the residual update, with norms known on the host
+        std::vector<Cx<double>> h0(nrhs);
+        for (int i = 0; i < nrhs; i++) h0[i] = cmake(r0n2[i], 0.0);
+        DHT_HIP(hipMemcpyAsync(partial, h0.data(), sizeof(Cx<double>) * nrhs, hipMemcpyHostToDevice, c->stream));
+        nb = 1;
+    } else {
+        DHT_TRY(solve_init(c, src, prec, scale, xa ? nullptr : r, rh, xa ? nullptr : ringP, nrhs, partial, &nb));
+    }
     DHT_TRY(finalize(c, partial, nb, 1, nrhs, st, FIN_INIT, bd_eps));
     // add the stored iterations [0, n) to X (after a synchronisation, so hs
     // holds the current states)
@@ -303,6 +312,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     std::vector<double> full2;     // its squared norms
     std::vector<Cx<double>> zx_e, zx_o;   // z^H x per parity from the same epilogues
     bool x_written = false;        // X_e holds the solution so far (else it is 0)
+    bool prep = false;             // the last in-place update also wrote the next BF16 rhat
+    std::vector<double> sdp(nrhs, 0.0);   // ... scaled per RHS by these factors
     void* e;
     for (; outer < max_outer; outer++) {
         bool any = false, stalled = false;
@@ -327,6 +338,30 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         // a BF16 solve adds its solution to X_e itself, rebuilt in FP64 from its
         // stored iterations; the others return it in their storage precision
         const bool hist = inner == DHT_BF16;
+        // After an in-place residual update the same pass has written this
+        // cycle's BF16 right-hand side, scaled by the predicted 1 / ||r||
+        // (the exact norm is known only after the pass): the inner solve
+        // starts from it, with ||rhat||^2 = ||r||^2 sdp^2 and the correction
+        // scaled back by 1 / sdp, instead of reading r once more.  RHS that
+        // take no part get a negative target (their rhat is not zero).
+        bool use_prep = prep && hist && !((prm->fault_inject & 1u) && outer == 0);
+        for (int i = 0; i < nrhs && use_prep; i++)
+            if (sup[i] > 0 && !(sdp[i] > 0 && isfinite(sdp[i]))) use_prep = false;
+        std::vector<double> r0n2;
+        if (use_prep) {
+            r0n2.assign(nrhs, 0.0);
+            for (int i = 0; i < nrhs; i++) {
+                if (sup[i] > 0) {
+                    sdown[i] = sdp[i];
+                    sup[i] = 1.0 / sdp[i];
+                    r0n2[i] = rn2[i] * sdp[i] * sdp[i];
+                    itarget[i] *= r0n2[i];
+                } else {
+                    itarget[i] = -1.0;
+                }
+            }
+        }
+        prep = false;
         const size_t lbytes = nh * elem_bytes(inner);
         const int base = slot_base(inner);
         e = nullptr;
@@ -366,7 +401,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             xa.E32 = E32;
         }
         DHT_TRY(bicgstab(c, inner, outer == 0 ? bhat : r_e, (const double*)scl, e, nrhs, itarget,
-                         prm->maxiter - total_iters, &br, false, hist ? &xa : nullptr));
+                         prm->maxiter - total_iters, &br, false, hist ? &xa : nullptr,
+                         use_prep ? r0n2.data() : nullptr));
         int maxit = 0;
         bool bad = false;
         for (int i = 0; i < nrhs; i++) {
@@ -391,9 +427,10 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         // from it, while a right one saves a hop of the Schur residual.  The odd
         // residual z_o - a x_o + Hop_oe x_e / 2 vanishes by the construction of
         // x_o (to FP64 rounding), so the even one is the full residual.
+        // the inner residual in units of r: ||r_new||^2 ~ sup^2 ||r_inner||^2
         bool predict = true;
         for (int i = 0; i < nrhs; i++)
-            if (sup[i] > 0 && !(rn2[i] * br.rnorm2[i] <= target2[i])) predict = false;
+            if (sup[i] > 0 && !(sup[i] * sup[i] * br.rnorm2[i] <= target2[i])) predict = false;
         if (predict) {
             DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr, z16));
             DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, zx_out ? &zx_e : nullptr,
@@ -416,13 +453,34 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             void *part, *sums;
             DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
             DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs, &sums));
+            // the next cycle's BF16 right-hand side in the same pass, scaled
+            // by the inverse of each residual norm that this cycle predicts
+            std::vector<double> sdn(nrhs, 0.0);
+            bool can = true;
+            for (int i = 0; i < nrhs; i++) {
+                if (!(sup[i] > 0)) continue;
+                const double pr = sup[i] * sup[i] * br.rnorm2[i];
+                if (pr > 0 && isfinite(pr)) sdn[i] = 1.0 / sqrt(pr);
+                else can = false;
+            }
+            void *rh16 = nullptr, *s16 = nullptr;
+            if (can) {
+                DHT_TRY(ws_get(c, slot_base(DHT_BF16) + 1, half_vecs(c, nrhs, DHT_BF16) * 16, &rh16));
+                DHT_TRY(ws_get(c, WS_S16, sizeof(double) * nrhs, &s16));
+                DHT_HIP(hipMemcpyAsync(s16, sdn.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+            }
             int nbr;
-            DHT_TRY(residual_step(c, r_e, r_e, W32, (const double*)scl, nrhs, (Cx<double>*)part, &nbr));
+            DHT_TRY(residual_step(c, r_e, r_e, W32, (const double*)scl, nrhs, (Cx<double>*)part, &nbr, rh16,
+                                  (const double*)s16));
             DHT_TRY(finalize(c, (const Cx<double>*)part, nbr, 1, nrhs, nullptr, FIN_SUM, 0.0, (Cx<double>*)sums));
             std::vector<Cx<double>> h(nrhs);
             DHT_HIP(hipMemcpyAsync(h.data(), sums, sizeof(Cx<double>) * nrhs, hipMemcpyDeviceToHost, c->stream));
             DHT_HIP(hipStreamSynchronize(c->stream));
             for (int i = 0; i < nrhs; i++) rn2[i] = h[i].re;
+            if (can) {
+                prep = true;
+                sdp = sdn;
+            }
         } else {
             // FP64 true residual of the Schur system, r = bhat - (a x - Hop_eo Hop_oe x / (4a)),
             // and its norms, in the second hop's epilogue
