@@ -92,8 +92,9 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     // with XAccum, r_0 and the first direction p_0 = r_0 are rhat itself (not
     // copied): iteration 0 reads rhat for both, and r is first written by its
     // residual update
+    std::vector<Cx<double>> h0;   // alive until the copy below has run (the polls synchronise)
     if (r0n2) {   // rhat was written by the residual update, with norms known on the host
-        std::vector<Cx<double>> h0(nrhs);
+        h0.resize(nrhs);
         for (int i = 0; i < nrhs; i++) h0[i] = cmake(r0n2[i], 0.0);
         DHT_HIP(hipMemcpyAsync(partial, h0.data(), sizeof(Cx<double>) * nrhs, hipMemcpyHostToDevice, c->stream));
         nb = 1;
