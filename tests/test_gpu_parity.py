@@ -270,6 +270,26 @@ def test_trace_batch_c1_without_deflation(c1, c1_inv, method):
     assert ctx.estimate()["n"] == n
 
 
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_trace_batch_bf16_probe_operands_every_hop_form(c1, c1_inv, form):
+    """The FP64 hops that read the probes from BF16 storage (Schur right-hand
+    side, odd sites, final residual), forced into each launch form: a trace
+    batch matches the exact inverse to the solver's tolerance."""
+    w, U, D, ctx = c1
+    L = _lib()
+    ctx.clear_deflation()
+    ctx.reset_estimate()
+    ctx.set_hop_config(L.FP64, w.batch, {"form": form, "streaming_stores": 1, "t_chunk": 2 if form == 2 else 0})
+    try:
+        recs = ctx.trace_batch(w.seed, 2, True, 0, w.batch, ctx.params(L.SOLVER_BICGSTAB_FP64, tol=1e-12))
+    finally:
+        ctx.set_hop_config(L.FP64, w.batch, None)
+    Z = rng.probes(w.L, w.seed, 2, True, 0, w.batch)
+    q_ref = np.einsum("ja,ab,jb->j", Z.conj(), c1_inv, Z)
+    q = np.array([r["q"] for r in recs])
+    assert np.abs(q - q_ref).max() <= 1e-10 * np.abs(q_ref).max()
+
+
 @pytest.mark.parametrize("method", ["fp64", "dc_bf16"])
 def test_solve_zero_right_hand_sides(c1, c1_inv, method):
     """A zero right-hand side has the solution 0 (the solver writes it although
