@@ -45,6 +45,8 @@ struct HopArgs {
     int tc, nchunk;      // t-marching: slices per chunk (even, divides Lt) and chunks
     int nt;              // non-temporal (streaming) output stores
     double ca, cb, cz;   // out = ca * x + cb * Hop(in) + cz * z
+    void* out16;         // HOP_OUT16: s16[r] * out also stored in BF16 (an inner right-hand side)
+    const double* s16;
 };
 
 static constexpr int HOP_THREADS = HOP_LANES;
@@ -275,6 +277,14 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
 #pragma unroll
     for (int i = 0; i < 12; i++)
         if (G5OUT && i >= 6) acc[i] = neg(acc[i]);
+    if constexpr ((MIX & HOP_OUT16) != 0) {
+        const double sc = a.s16[r];
+        Cx<float> o16[12];
+#pragma unroll
+        for (int i = 0; i < 12; i++) o16[i] = cmake<float>((float)(sc * acc[i].re), (float)(sc * acc[i].im));
+#pragma unroll
+        for (int j = 0; j < 3; j++) Store<bf16x2>::stv(a.out16, v0 + j * vstride, o16 + 4 * j);
+    }
 #pragma unroll
     for (int j = 0; j < 12 / VW; j++) {
         if (a.nt) Store<S>::stv_nt(a.out, v0 + j * vstride, acc + j * VW);
@@ -587,7 +597,8 @@ int hop_blocks(const dht_ctx* c, int nrhs) {
 
 template <typename S>
 static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, const void* x, double ca, double cb,
-                      int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz, int mix) {
+                      int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz, int mix, void* out16,
+                      const double* s16) {
     HopArgs a;
     a.out = out;
     a.in = in;
@@ -613,6 +624,10 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     int kind = dot ? dot->kind : HOPDOT_NONE;
     a.da = dot ? dot->a : nullptr;
     a.partial = dot ? dot->partial : nullptr;
+    a.out16 = out16;
+    a.s16 = s16;
+    if (((mix & HOP_OUT16) != 0) != (out16 != nullptr) || (out16 && !s16))
+        return set_error(DHT_ERR_INVALID_ARG, "BF16 output copy needs its buffer and scales");
     if (kind == HOPDOT_OUT_X && !x) return set_error(DHT_ERR_INVALID_ARG, "fused (out, x) needs an xpay source");
     if (kind == HOPDOT_NORM_ZX && !z) return set_error(DHT_ERR_INVALID_ARG, "fused (z, x) needs both axpy sources");
     const int cls = (dot && kind == HOPDOT_A_OUT) ? HOP_FUSED_A : ((x || dot) ? HOP_FUSED : HOP_PLAIN);
@@ -635,7 +650,7 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     dim3 grid(nb), block(HOP_THREADS);
     bool xp = x != nullptr;
 #define DHT_HOP_CASE_M(D_, G_, X_, K_, M_)                                                                   \
-    if (dagger == D_ && g5out == G_ && xp == X_ && kind == K_ && mix == M_) {                                \
+    if (dagger == D_ && g5out == G_ && xp == X_ && kind == K_ && mix == (M_)) {                              \
         if (mode == DHT_HOP_TMARCH)                                                                          \
             hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_, M_>), grid, block, tm_lds, c->stream, a);   \
         else if (mode == DHT_HOP_SITE_LDS)                                                                   \
@@ -661,6 +676,8 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
         // FP64 residuals whose probe operand is held in BF16 (exact values):
         // the Schur right-hand side from z, the odd sites, the final residual
         DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM, HOP_IN16 | HOP_X16)
+        DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM, HOP_IN16 | HOP_X16 | HOP_OUT16)
+        DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM, HOP_OUT16)
         DHT_HOP_CASE_M(false, false, true, HOPDOT_NONE, HOP_X16)
         DHT_HOP_CASE_M(false, false, true, HOPDOT_OUT_X, HOP_X16)
         DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM, HOP_Z16)
@@ -675,7 +692,8 @@ launched:
 }
 
 int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
-        int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz, int mix) {
+        int nrhs, bool dagger, bool g5out, HopDot* dot, const void* z, double cz, int mix, void* out16,
+        const double* s16) {
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
     if (mix != 0 && prec != DHT_FP64) return set_error(DHT_ERR_INVALID_ARG, "BF16 operands only in FP64 hops");
@@ -683,16 +701,20 @@ int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const v
     DHT_TRY(prof_begin(c, &tok));
     int rc = DHT_OK;
     switch (prec) {
-        case DHT_FP64: rc = launch_hop<double>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz, mix); break;
-        case DHT_FP32: rc = launch_hop<float>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz, mix); break;
-        case DHT_BF16: rc = launch_hop<bf16x2>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz, mix); break;
+        case DHT_FP64: rc = launch_hop<double>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz, mix, out16, s16);
+            break;
+        case DHT_FP32: rc = launch_hop<float>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz, mix, out16, s16);
+            break;
+        case DHT_BF16: rc = launch_hop<bf16x2>(c, out_parity, in, out, x, a, b, nrhs, dagger, g5out, dot, z, cz, mix, out16, s16);
+            break;
     }
     if (rc != DHT_OK) return rc;
     // algorithmic bytes: read the input half field (and the xpay / dot operand),
     // write the output, read each of the 8 Vh link matrices of this parity once
     const double eb = (double)elem_bytes(prec), e16 = (double)elem_bytes(DHT_BF16);
     const double nbytes = eb + ((mix & HOP_IN16) ? e16 : eb) + (x ? ((mix & HOP_X16) ? e16 : eb) : 0.0) +
-                          (z ? ((mix & HOP_Z16) ? e16 : eb) : 0.0) + ((dot && dot->kind == HOPDOT_A_OUT) ? eb : 0.0);
+                          (z ? ((mix & HOP_Z16) ? e16 : eb) : 0.0) + ((dot && dot->kind == HOPDOT_A_OUT) ? eb : 0.0) +
+                          ((mix & HOP_OUT16) ? e16 : 0.0);
     const double bytes = nbytes * 12.0 * c->g.Vh * nrhs + 72.0 * c->g.Vh * eb;
     return prof_end(c, tok, PROF_HOP64 + prec, bytes);
 }

@@ -178,7 +178,8 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
 // epilogue's operands) into *zx.  mix marks operands held in BF16 (see hop).
 static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const void* x, double ca, double cb,
                         const void* z, int nrhs, int slot, std::vector<double>& n2,
-                        std::vector<Cx<double>>* zx = nullptr, int mix = 0) {
+                        std::vector<Cx<double>>* zx = nullptr, int mix = 0, void* out16 = nullptr,
+                        const double* s16 = nullptr) {
     void *part, *sums;
     DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
     DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs, &sums));
@@ -186,7 +187,8 @@ static int residual_hop(dht_ctx* c, int parity, const void* in, void* out, const
     HopDot d;
     d.kind = zx ? HOPDOT_NORM_ZX : HOPDOT_NORM;
     d.partial = (Cx<double>*)part;
-    DHT_TRY(hop(c, DHT_FP64, parity, in, out, x, ca, cb, nrhs, false, false, &d, z, z ? 1.0 : 0.0, mix));
+    DHT_TRY(hop(c, DHT_FP64, parity, in, out, x, ca, cb, nrhs, false, false, &d, z, z ? 1.0 : 0.0,
+                mix | (out16 ? HOP_OUT16 : 0), out16, s16));
     Cx<double>* s = (Cx<double>*)sums + (size_t)slot * 2 * nrhs;
     DHT_TRY(finalize(c, d.partial, d.nblocks, np, nrhs, nullptr, FIN_SUM, 0.0, s));
     std::vector<Cx<double>> h((size_t)np * nrhs);
@@ -236,6 +238,19 @@ static int norms2(dht_ctx* c, const void* f, size_t nvec, int nrhs, std::vector<
     out.resize(nrhs);
     for (int i = 0; i < nrhs; i++) out[i] = h[i].re;
     return DHT_OK;
+}
+
+// 1 / (the residual norm a finished inner solve predicts) per RHS taking part
+// (sup > 0; 0 for the others); false if a prediction is not positive and finite
+static bool predict_scales(const std::vector<double>& sup, const BicgResult& br, std::vector<double>& sdn) {
+    for (size_t i = 0; i < sup.size(); i++) {
+        sdn[i] = 0.0;
+        if (!(sup[i] > 0)) continue;
+        const double pr = sup[i] * sup[i] * br.rnorm2[i];
+        if (!(pr > 0 && isfinite(pr))) return false;
+        sdn[i] = 1.0 / sqrt(pr);
+    }
+    return true;
 }
 
 int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats,
@@ -293,12 +308,36 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     if (inner < DHT_FP64 || inner > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad inner precision");
     const int max_outer = prm->max_outer > 0 ? prm->max_outer : 50;
 
-    // right-hand side of the Schur system with its norms, and ||Z||^2
+    // ||Z||^2, and the right-hand side of the Schur system with its norms
     std::vector<double> zn2, rn2;
-    DHT_TRY(residual_hop(c, 0, Z_o, bhat, Z_e, 1.0, 1.0 / (2.0 * a), nullptr, nrhs, 0, rn2, nullptr,
-                         z16 ? HOP_IN16 | HOP_X16 : 0));
     if (zn2_known) zn2.assign(zn2_known, zn2_known + nrhs);
     else DHT_TRY(norms2(c, Z, 2 * nh, nrhs, zn2));
+    // A residual pass that precedes a BF16 inner solve also writes that
+    // solve's right-hand side in BF16, scaled per RHS by sdp (any positive
+    // scale serves; the inner solve is told ||rhat||^2 = ||r||^2 sdp^2 and
+    // scales its correction back by 1 / sdp), so that the solve need not read
+    // the FP64 residual once more.  prep: the last residual pass did so.
+    bool prep = false;
+    std::vector<double> sdp(nrhs, 0.0), sdn(nrhs, 0.0);   // sdn: host source of the device scales
+    void *rh16 = nullptr, *s16 = nullptr;
+    auto want16 = [&]() -> int {
+        DHT_TRY(ws_get(c, slot_base(DHT_BF16) + 1, half_vecs(c, nrhs, DHT_BF16) * 16, &rh16));
+        DHT_TRY(ws_get(c, WS_S16, sizeof(double) * nrhs, &s16));
+        DHT_HIP(hipMemcpyAsync(s16, sdn.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+        return DHT_OK;
+    };
+    // the first cycle's: bhat itself, scaled by 1 / ||z||
+    const bool first16 = inner == DHT_BF16 && !(prm->fault_inject & 1u);
+    if (first16) {
+        for (int i = 0; i < nrhs; i++) sdn[i] = zn2[i] > 0 && isfinite(zn2[i]) ? 1.0 / sqrt(zn2[i]) : 0.0;
+        DHT_TRY(want16());
+    }
+    DHT_TRY(residual_hop(c, 0, Z_o, bhat, Z_e, 1.0, 1.0 / (2.0 * a), nullptr, nrhs, 0, rn2, nullptr,
+                         z16 ? HOP_IN16 | HOP_X16 : 0, first16 ? rh16 : nullptr, (const double*)s16));
+    if (first16) {
+        prep = true;
+        sdp = sdn;
+    }
     std::vector<double> target2(nrhs);
     // the Schur loop aims 10% below the tolerance so that the reconstructed
     // full-lattice residual, checked last, is not lost to rounding
@@ -313,8 +352,6 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     std::vector<double> full2;     // its squared norms
     std::vector<Cx<double>> zx_e, zx_o;   // z^H x per parity from the same epilogues
     bool x_written = false;        // X_e holds the solution so far (else it is 0)
-    bool prep = false;             // the last in-place update also wrote the next BF16 rhat
-    std::vector<double> sdp(nrhs, 0.0);   // ... scaled per RHS by these factors
     void* e;
     for (; outer < max_outer; outer++) {
         bool any = false, stalled = false;
@@ -339,12 +376,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         // a BF16 solve adds its solution to X_e itself, rebuilt in FP64 from its
         // stored iterations; the others return it in their storage precision
         const bool hist = inner == DHT_BF16;
-        // After an in-place residual update the same pass has written this
-        // cycle's BF16 right-hand side, scaled by the predicted 1 / ||r||
-        // (the exact norm is known only after the pass): the inner solve
-        // starts from it, with ||rhat||^2 = ||r||^2 sdp^2 and the correction
-        // scaled back by 1 / sdp, instead of reading r once more.  RHS that
-        // take no part get a negative target (their rhat is not zero).
+        // A prepared BF16 right-hand side (see prep): RHS that take no part
+        // get a negative target (their rhat need not be zero).
         bool use_prep = prep && hist && !((prm->fault_inject & 1u) && outer == 0);
         for (int i = 0; i < nrhs && use_prep; i++)
             if (sup[i] > 0 && !(sdp[i] > 0 && isfinite(sdp[i]))) use_prep = false;
@@ -456,23 +489,11 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs, &sums));
             // the next cycle's BF16 right-hand side in the same pass, scaled
             // by the inverse of each residual norm that this cycle predicts
-            std::vector<double> sdn(nrhs, 0.0);
-            bool can = true;
-            for (int i = 0; i < nrhs; i++) {
-                if (!(sup[i] > 0)) continue;
-                const double pr = sup[i] * sup[i] * br.rnorm2[i];
-                if (pr > 0 && isfinite(pr)) sdn[i] = 1.0 / sqrt(pr);
-                else can = false;
-            }
-            void *rh16 = nullptr, *s16 = nullptr;
-            if (can) {
-                DHT_TRY(ws_get(c, slot_base(DHT_BF16) + 1, half_vecs(c, nrhs, DHT_BF16) * 16, &rh16));
-                DHT_TRY(ws_get(c, WS_S16, sizeof(double) * nrhs, &s16));
-                DHT_HIP(hipMemcpyAsync(s16, sdn.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-            }
+            const bool can = predict_scales(sup, br, sdn);
+            if (can) DHT_TRY(want16());
             int nbr;
-            DHT_TRY(residual_step(c, r_e, r_e, W32, (const double*)scl, nrhs, (Cx<double>*)part, &nbr, rh16,
-                                  (const double*)s16));
+            DHT_TRY(residual_step(c, r_e, r_e, W32, (const double*)scl, nrhs, (Cx<double>*)part, &nbr,
+                                  can ? rh16 : nullptr, (const double*)s16));
             DHT_TRY(finalize(c, (const Cx<double>*)part, nbr, 1, nrhs, nullptr, FIN_SUM, 0.0, (Cx<double>*)sums));
             std::vector<Cx<double>> h(nrhs);
             DHT_HIP(hipMemcpyAsync(h.data(), sums, sizeof(Cx<double>) * nrhs, hipMemcpyDeviceToHost, c->stream));
@@ -484,9 +505,17 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             }
         } else {
             // FP64 true residual of the Schur system, r = bhat - (a x - Hop_eo Hop_oe x / (4a)),
-            // and its norms, in the second hop's epilogue
+            // and its norms, in the second hop's epilogue (after a BF16 cycle
+            // with the next BF16 right-hand side, scaled as predicted)
+            const bool can = hist && !bad && predict_scales(sup, br, sdn);
+            if (can) DHT_TRY(want16());
             DHT_TRY(hop(c, DHT_FP64, 1, X_e, tmp_o, nullptr, 0.0, 1.0, nrhs, false, false));
-            DHT_TRY(residual_hop(c, 0, tmp_o, r_e, X_e, -a, 1.0 / (4.0 * a), bhat, nrhs, 0, rn2));
+            DHT_TRY(residual_hop(c, 0, tmp_o, r_e, X_e, -a, 1.0 / (4.0 * a), bhat, nrhs, 0, rn2, nullptr, 0,
+                                 can ? rh16 : nullptr, (const double*)s16));
+            if (can) {
+                prep = true;
+                sdp = sdn;
+            }
         }
         if (bad && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
         last_bad = bad;
