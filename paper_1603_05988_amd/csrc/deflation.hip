@@ -662,7 +662,6 @@ void deflation_corrections(const dht_ctx* c, const Cx<double>* c1, const Cx<doub
     for (int r = 0; r < nuse; r++) {
         for (int a = 0; a < k; a++) {
             std::complex<double> s = 0.0;
-            std::complex<double> c2b;
             if (c->M_diag) {
                 s = M[(size_t)a * k + a] * std::complex<double>(c2[(size_t)a * B + r].re, c2[(size_t)a * B + r].im);
             } else {
