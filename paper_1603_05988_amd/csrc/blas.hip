@@ -521,11 +521,11 @@ __global__ void accum_hist_kernel(Cx<double>* X, const void* P, const void* Sv, 
 
 // r = r_in - scale_r * w (FP64 half fields r, r_in; FP32 w), with the
 // per-RHS partials of (r, r) for the new r; with rh16 also s16_r * r in BF16
-// (the next inner solve's right-hand side: each FP32 vector of w fills one
-// half of a BF16 vector)
+// (the next inner solve's right-hand side).  One item is one BF16 vector:
+// components 4m .. 4m+3 of one (site, RHS), i.e. FP32 vectors 2m and 2m+1.
 __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* r, const Cx<double>* r_in,
                                                                     const void* w, const double* scale,
-                                                                    size_t nvec32, int64_t SB, int B,
+                                                                    size_t nitem, int64_t SB, int B,
                                                                     Cx<double>* partial, void* rh16,
                                                                     const double* s16) {
     __shared__ Cx<double> red[1][RED_THREADS];
@@ -534,41 +534,39 @@ __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* 
     const double s16r = rh16 ? s16[threadIdx.x & (B - 1)] : 0.0;
     const size_t stride = (size_t)gridDim.x * RED_THREADS;
     const size_t v0 = (size_t)blockIdx.x * RED_THREADS + threadIdx.x;
-    StridePos pos(v0, stride, SB);
-    // two vectors per step, both loaded before either is used (sums in the
-    // order of a one-vector loop)
-    for (size_t v = v0; v < nvec32; v += 2 * stride) {
-        const bool two = v + stride < nvec32;
-        Cx<float> wv[2][2];
-        Cx<double> ri[2][2];
-        int64_t e[2][2], h16[2];
+    StridePos pos(v0, stride, SB);   // pos.cv = m
+    // two items per step, both loaded before either is used (sums in the
+    // order of a one-item loop)
+    for (size_t v = v0; v < nitem; v += 2 * stride) {
+        const bool two = v + stride < nitem;
+        Cx<float> wv[2][4];
+        Cx<double> ri[2][4];
+        int64_t e0[2];
 #pragma unroll
         for (int u = 0; u < 2; u++) {
             if (u == 0 || two) {
-                Store<float>::ldv(w, v + u * stride, wv[u]);
+                const int64_t w0 = pos.cv * 2 * SB + pos.sr;
+                Store<float>::ldv(w, w0, wv[u]);
+                Store<float>::ldv(w, w0 + SB, wv[u] + 2);
+                e0[u] = pos.cv * 4 * SB + pos.sr;
 #pragma unroll
-                for (int q = 0; q < 2; q++) {
-                    e[u][q] = (pos.cv * 2 + q) * SB + pos.sr;
-                    ri[u][q] = r_in[e[u][q]];
-                }
-                // 8-byte half (cv mod 2) of BF16 vector (cv / 2) * SB + sr
-                h16[u] = (((pos.cv >> 1) * SB + pos.sr) << 1) + (pos.cv & 1);
+                for (int q = 0; q < 4; q++) ri[u][q] = r_in[e0[u] + q * SB];
             }
             pos.next();
         }
 #pragma unroll
         for (int u = 0; u < 2; u++)
             if (u == 0 || two) {
-                uint32_t hb[2];
+                Cx<float> o16[4];
 #pragma unroll
-                for (int q = 0; q < 2; q++) {
+                for (int q = 0; q < 4; q++) {
                     const Cx<double> nr =
                         cmake(ri[u][q].re - sc * (double)wv[u][q].re, ri[u][q].im - sc * (double)wv[u][q].im);
-                    r[e[u][q]] = nr;
+                    r[e0[u] + q * SB] = nr;
                     d0.re += nr.re * nr.re + nr.im * nr.im;
-                    hb[q] = Store<bf16x2>::pack(cmake<float>((float)(s16r * nr.re), (float)(s16r * nr.im)));
+                    o16[q] = cmake<float>((float)(s16r * nr.re), (float)(s16r * nr.im));
                 }
-                if (rh16) ((uint2*)rh16)[h16[u]] = make_uint2(hb[0], hb[1]);
+                if (rh16) Store<bf16x2>::stv(rh16, v + u * stride, o16);
             }
     }
     red[0][threadIdx.x] = d0;
@@ -580,11 +578,11 @@ int residual_step(dht_ctx* c, void* r, const void* r_in, const void* w32, const 
                   Cx<double>* partial, int* nblocks, void* rh16, const double* s16) {
     if (rh16 && !s16) return set_error(DHT_ERR_INVALID_ARG, "BF16 residual copy needs its scales");
     const int64_t SB = c->g.Vh * (int64_t)nrhs;
-    const size_t nvec32 = half_vecs(c, nrhs, DHT_FP32);
-    const int nb = red_blocks(nvec32);
+    const size_t nitem = half_vecs(c, nrhs, DHT_BF16);
+    const int nb = red_blocks(nitem);
     *nblocks = nb;
     hipLaunchKernelGGL(residual_step_kernel, dim3(nb), dim3(RED_THREADS), 0, c->stream, (Cx<double>*)r,
-                       (const Cx<double>*)r_in, w32, scale, nvec32, SB, nrhs, partial, rh16, s16);
+                       (const Cx<double>*)r_in, w32, scale, nitem, SB, nrhs, partial, rh16, s16);
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }
