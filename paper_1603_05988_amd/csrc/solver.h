@@ -99,6 +99,10 @@ struct XAccum {
     std::vector<double> scale;     // per RHS (0: leave the RHS alone)
     bool assign = false;           // the first contribution assigns X
     void* E32 = nullptr;           // optional FP32 half field that receives x itself
+    // with E32: the outer targets (units of the caller's residual); E32 is left
+    // unwritten when every RHS's predicted residual scale^2 ||r_inner||^2 meets
+    // them (the caller then checks the full residual and never reads E32)
+    const std::vector<double>* predict_t2 = nullptr;
 };
 // x32: the solution x is kept in FP32 storage (BF16 vectors only); xa: see XAccum (x unused);
 // r0n2 (host, nrhs; with xa only): the right-hand side is already in rhat (the BF16

@@ -106,11 +106,18 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     // holds the current states)
     bool first_flush = true;
     std::vector<double> fs(nrhs);
-    auto flush = [&](int n) -> int {
+    auto flush = [&](int n, bool last) -> int {
         for (int i = 0; i < nrhs; i++) fs[i] = hs[i].status == RS_NAN ? 0.0 : xa->scale[i];
+        void* e32 = xa->E32;
+        if (e32 && last && first_flush && xa->predict_t2) {   // a single flush: E32 may be skipped whole
+            bool pred = true;
+            for (int i = 0; i < nrhs; i++)
+                if (fs[i] > 0 && !(fs[i] * fs[i] * hs[i].rnorm2 <= (*xa->predict_t2)[i])) pred = false;
+            if (pred) e32 = nullptr;
+        }
         DHT_HIP(hipMemcpyAsync(hscale, fs.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
         DHT_TRY(accum_hist(c, prec, xa->X, ringP, ringS, hist, n, nrhs, hscale, xa->assign && first_flush,
-                           first_flush ? rh : nullptr, xa->E32, first_flush));
+                           first_flush ? rh : nullptr, e32, first_flush));
         first_flush = false;
         return DHT_OK;
     };
@@ -153,11 +160,11 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
         for (int i = 0; i < nrhs; i++) any |= hs[i].active != 0;
         if (!any) break;
         if (xa && stored == K) {   // the rings are full
-            DHT_TRY(flush(K));
+            DHT_TRY(flush(K, false));
             stored = 0;
         }
     }
-    if (xa && (stored > 0 || first_flush)) DHT_TRY(flush(stored));
+    if (xa && (stored > 0 || first_flush)) DHT_TRY(flush(stored, true));
     DHT_HIP(hipMemcpyAsync(hs, st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, c->stream));
     DHT_HIP(hipStreamSynchronize(c->stream));
     res->iters.assign(nrhs, 0);
@@ -433,6 +440,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             xa.scale = sup;
             xa.assign = !x_written;
             xa.E32 = E32;
+            xa.predict_t2 = &target2;
         }
         DHT_TRY(bicgstab(c, inner, outer == 0 ? bhat : r_e, (const double*)scl, e, nrhs, itarget,
                          prm->maxiter - total_iters, &br, false, hist ? &xa : nullptr,
