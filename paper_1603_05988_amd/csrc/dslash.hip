@@ -285,10 +285,12 @@ __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename 
 #pragma unroll
         for (int j = 0; j < 3; j++) Store<bf16x2>::stv(a.out16, v0 + j * vstride, o16 + 4 * j);
     }
+    if constexpr ((MIX & HOP_NOOUT) == 0) {   // else only the epilogue sums are wanted
 #pragma unroll
-    for (int j = 0; j < 12 / VW; j++) {
-        if (a.nt) Store<S>::stv_nt(a.out, v0 + j * vstride, acc + j * VW);
-        else Store<S>::stv(a.out, v0 + j * vstride, acc + j * VW);
+        for (int j = 0; j < 12 / VW; j++) {
+            if (a.nt) Store<S>::stv_nt(a.out, v0 + j * vstride, acc + j * VW);
+            else Store<S>::stv(a.out, v0 + j * vstride, acc + j * VW);
+        }
     }
     if (DOT != HOPDOT_NONE) {
         Cx<T> ov[12];
@@ -682,6 +684,8 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
         DHT_HOP_CASE_M(false, false, true, HOPDOT_OUT_X, HOP_X16)
         DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM, HOP_Z16)
         DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM_ZX, HOP_Z16)
+        DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM_ZX, HOP_Z16 | HOP_NOOUT)
+        DHT_HOP_CASE_M(false, false, true, HOPDOT_NORM_ZX, HOP_NOOUT)
     }
 #undef DHT_HOP_CASE
 #undef DHT_HOP_CASE_M
@@ -712,9 +716,9 @@ int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const v
     // algorithmic bytes: read the input half field (and the xpay / dot operand),
     // write the output, read each of the 8 Vh link matrices of this parity once
     const double eb = (double)elem_bytes(prec), e16 = (double)elem_bytes(DHT_BF16);
-    const double nbytes = eb + ((mix & HOP_IN16) ? e16 : eb) + (x ? ((mix & HOP_X16) ? e16 : eb) : 0.0) +
-                          (z ? ((mix & HOP_Z16) ? e16 : eb) : 0.0) + ((dot && dot->kind == HOPDOT_A_OUT) ? eb : 0.0) +
-                          ((mix & HOP_OUT16) ? e16 : 0.0);
+    const double nbytes = ((mix & HOP_NOOUT) ? 0.0 : eb) + ((mix & HOP_IN16) ? e16 : eb) +
+                          (x ? ((mix & HOP_X16) ? e16 : eb) : 0.0) + (z ? ((mix & HOP_Z16) ? e16 : eb) : 0.0) +
+                          ((dot && dot->kind == HOPDOT_A_OUT) ? eb : 0.0) + ((mix & HOP_OUT16) ? e16 : 0.0);
     const double bytes = nbytes * 12.0 * c->g.Vh * nrhs + 72.0 * c->g.Vh * eb;
     return prof_end(c, tok, PROF_HOP64 + prec, bytes);
 }

@@ -392,8 +392,9 @@ struct HopDot {
 // be passed in the BF16 layout: mix is a set of HOP_IN16 (the stencil input),
 // HOP_X16 (the x-pay source), HOP_Z16 (the second axpy source).  HOP_OUT16:
 // the result scaled by s16[r] (device, per RHS) is also stored in BF16 at
-// out16 (a residual that starts the next BF16 inner solve).
-enum { HOP_IN16 = 1, HOP_X16 = 2, HOP_Z16 = 4, HOP_OUT16 = 8 };
+// out16 (a residual that starts the next BF16 inner solve).  HOP_NOOUT: the
+// result itself is not stored (only the fused sums are wanted; out unused).
+enum { HOP_IN16 = 1, HOP_X16 = 2, HOP_Z16 = 4, HOP_OUT16 = 8, HOP_NOOUT = 16 };
 int hop(dht_ctx* c, int prec, int out_parity, const void* in, void* out, const void* x, double a, double b,
         int nrhs, bool dagger, bool g5out, HopDot* dot = nullptr, const void* z = nullptr, double cz = 0.0,
         int mix = 0, void* out16 = nullptr, const double* s16 = nullptr);

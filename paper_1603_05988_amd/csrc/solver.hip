@@ -474,9 +474,12 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         for (int i = 0; i < nrhs; i++)
             if (sup[i] > 0 && !(sup[i] * sup[i] * br.rnorm2[i] <= target2[i])) predict = false;
         if (predict) {
+            // with the fused z^H x the even residual itself is not stored
+            // (only its norms and z^H x are wanted if it meets the tolerance)
+            const int nofield = zx_out ? HOP_NOOUT : 0;
             DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr, z16));
             DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, zx_out ? &zx_e : nullptr,
-                                 z16 ? HOP_Z16 : 0));
+                                 (z16 ? HOP_Z16 : 0) | nofield));
             bool done = true;
             full2 = rn2;
             for (int i = 0; i < nrhs; i++)
@@ -486,6 +489,8 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
                 outer++;
                 break;
             }
+            if (nofield)   // the loop goes on from this residual: store it
+                DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, &zx_e, z16 ? HOP_Z16 : 0));
         } else if (inc && !bad) {
             // r -= sigma Dhat e: Dhat e in FP32, the update and its norms in FP64
             // (after a NaN the discarded RHS's x may hold part of the
@@ -541,7 +546,7 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
         // vanishes by the construction of x_o)
         DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr, z16));
         DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, fr2, zx_out ? &zx_e : nullptr,
-                             z16 ? HOP_Z16 : 0));
+                             (z16 ? HOP_Z16 : 0) | (zx_out ? HOP_NOOUT : 0)));
     }
     if (zx_out)
         for (int i = 0; i < nrhs; i++) zx_out[i] = zx_e[i] + zx_o[i];
