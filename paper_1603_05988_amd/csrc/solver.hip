@@ -86,7 +86,8 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     }
     DHT_HIP(hipMemcpyAsync(st, hs, sizeof(RhsState) * nrhs, hipMemcpyHostToDevice, c->stream));
     // x = 0 is never materialised: the first x update writes x; r, rhat and
-    // p = r come out of one pass over the FP64 source with the (r, r) sums
+    // p = r come out of one pass over the FP64 source with the (r, r) sums,
+    // unless the caller's residual pass has already written rhat (r0n2)
     const double bd_eps = prec == DHT_FP64 ? 1e-14 : 1e-6;
     int nb;
     // with XAccum, r_0 and the first direction p_0 = r_0 are rhat itself (not
@@ -412,8 +413,9 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
             for (int i = 0; i < nrhs; i++) sdown[i] = NAN;
         }
         DHT_HIP(hipMemcpyAsync(scl, sdown.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-        // the inner right-hand side is the normalised Schur residual; in the
-        // first cycle that is bhat itself
+        // the inner right-hand side is the scaled Schur residual (normalised
+        // by the one-pass start, or prepared as above); in the first cycle
+        // that is bhat itself
         // After the first cycle, once every active residual is below
         // 1e-2 ||z||, the Schur residual of a BF16 cycle is updated instead of
         // recomputed: r_new = r_old - sigma Dhat e, with the cycle's correction
