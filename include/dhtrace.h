@@ -119,7 +119,13 @@ typedef struct {
     int restart;       /* FGMRES restart length (<= 64)                         */
     double inner_tol;  /* relative reduction per inner solve (0: 1e-2 BF16, 1e-5 FP32) */
     int max_outer;     /* cap on defect-correction cycles (0: default 50)       */
-    uint32_t fault_inject; /* testing only: bit 0 forces an inner NaN           */
+    uint32_t fault_inject; /* testing only, conditions forced from the host:
+                              bit 0: the first inner right-hand side is NaN;
+                              bit 1: one full-residual check after a predicted
+                                     convergence is treated as failed;
+                              bit 2: one in-place residual update reports
+                                     norms 1e-12 of the true ones (the loop
+                                     must then catch the miss in FP64)      */
     int history;       /* BF16 inner solves: iterations whose p and s are kept
                           before x is rebuilt from them (0: automatic, up to 16
                           within a 12 GB budget; else 2..16)                   */
@@ -267,7 +273,11 @@ int dht_project_probes(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, 
  * exactly, so results equal those of FP64 probes.  records
  * (host, nrhs entries, may be NULL) receives per-probe results; coef_host
  * (may be NULL) receives the projection coefficients c1, c2 as complex128
- * [2][k][nrhs] for playback with other k (Section 6.4). */
+ * [2][k][nrhs] for playback with other k (Section 6.3).  Only probes whose
+ * solve met the tolerance (status != DHT_STATUS_NOT_CONVERGED) enter the
+ * running estimates; the others are still reported in records, and the call
+ * then returns DHT_ERR_NOT_CONVERGED, so a batch that is retried is counted
+ * once. */
 int dht_trace_batch(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int nrhs,
                     const dht_solver_params* prm, dht_record* records, double* coef_host);
 
@@ -336,6 +346,14 @@ int dht_nn_make_pairs(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, i
                       double* E_dev, int cap, int* count);
 
 /* ---- instrumentation ------------------------------------------------------ */
+
+/* Counts of defect-correction branches taken since dht_create, out[0..3]:
+ * full-residual checks after an inner solve predicted convergence; such
+ * checks that missed (the loop continued from the stored FP64 residual);
+ * in-place residual updates (r -= sigma Dhat e, Dhat e in FP32); loops that
+ * stopped on in-place norms whose FP64 residual then missed the tolerance
+ * and were resumed from it.  n must be >= 4. */
+int dht_solver_counters(dht_ctx* ctx, int64_t* out, int n);
 
 /* Timing of the last dht_trace_batch / dht_solve, from HIP events, in
  * milliseconds: [0] probes, [1] solve, [2] projection (a batch's own pass

@@ -56,7 +56,7 @@ def masked_offdiag_frobenius2(A: np.ndarray, colours: np.ndarray, nbits: int) ->
     """||offdiag(M_s . A)||_F^2 where M_s(a, b) = [c_m(a) == c_m(b)], m = nbits.
 
     Variance over the Z4 base vector of one complete hierarchical-probing
-    sweep over 2^m Hadamard vectors (Section 6.3's masked Frobenius norms).
+    sweep over 2^m Hadamard vectors (Section 6.2's masked Frobenius norms).
     `colours` is per component (length N).
     """
     cm = colours & ((1 << nbits) - 1)

@@ -117,6 +117,7 @@ SIGNATURES = {
     "dht_estimate_get": (_i, [_vp, ctypes.POINTER(Estimate)]),
     "dht_estimate_reset": (_i, [_vp]),
     "dht_last_timings": (_i, [_vp, _dp, _i]),
+    "dht_solver_counters": (_i, [_vp, ctypes.POINTER(_i64), _i]),
     "dht_bench_hop": (_i, [_vp, _i, _i, _i, _i, _dp]),
     "dht_nn_num_weights": (_i64, []),
     "dht_nn_init": (_i, [_vp, _u64]),
@@ -382,6 +383,13 @@ class Context:
         t = np.zeros(5)
         check(load().dht_last_timings(self.h, _np_dp(t), 5))
         return dict(probes=t[0], solve=t[1], project=t[2], qform=t[3], total=t[4])
+
+    SOLVER_COUNTERS = ("predicted_checks", "predicted_failed", "inplace_updates", "reentries")
+
+    def solver_counters(self):
+        out = (_i64 * 4)()
+        check(load().dht_solver_counters(self.h, out, 4))
+        return dict(zip(self.SOLVER_COUNTERS, list(out)))
 
     # -- learned preconditioner ------------------------------------------
     @staticmethod

@@ -594,8 +594,14 @@ int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int n
     for (int r = 0; r < nrhs; r++) {
         double qre = q[r].re, qim = q[r].im;
         double dqre = qre - dre[r], dqim = qim - dim[r];
-        c->est_q.add(qre, qim);
-        c->est_qd.add(dqre, dqim);
+        // only a solve that met the tolerance is a sample of the estimator: a
+        // probe that missed it is reported but left out of the running
+        // estimates, so that a batch retried after DHT_ERR_NOT_CONVERGED is
+        // counted once
+        if (st[r].status != DHT_STATUS_NOT_CONVERGED) {
+            c->est_q.add(qre, qim);
+            c->est_qd.add(dqre, dqim);
+        }
         if (records) {
             records[r].q_re = qre;
             records[r].q_im = qim;
@@ -700,6 +706,12 @@ int dht_state_load(dht_ctx* c, const char* path) {
         w[i]->m2re = m[i][2];
         w[i]->m2im = m[i][3];
     }
+    return DHT_OK;
+}
+
+int dht_solver_counters(dht_ctx* c, int64_t* out, int n) {
+    if (!c || !out || n < SC_NCOUNT) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    for (int i = 0; i < SC_NCOUNT; i++) out[i] = c->solver_count[i];
     return DHT_OK;
 }
 

@@ -585,14 +585,18 @@ int deflation_finalize(dht_ctx* c, bool diagonal) {
     void *wb, *qwb, *cc;
     DHT_TRY(ws_get(c, WS_QW, fb, &wb));
     DHT_TRY(ws_get(c, WS_XF, fb, &qwb));
-    DHT_TRY(ws_get(c, WS_COEF, sizeof(Cx<double>) * 4 * (size_t)k * nb, &cc));
+    // four [k][nbp] blocks (H columns, their g5 twins, W^H W, W^H g5 W): the
+    // stride is the padded block width, which exceeds nb when nb is not a
+    // power of two
+    const size_t coef_elems = (size_t)4 * k * nbp;
+    DHT_TRY(ws_get(c, WS_COEF, sizeof(Cx<double>) * coef_elems, &cc));
     std::vector<std::complex<double>> H, G5;
     std::vector<double> hdiag(k), gdiag(k);
     if (!diagonal) {
         H.assign((size_t)k * k, 0.0);
         G5.assign((size_t)k * k, 0.0);
     }
-    std::vector<Cx<double>> hb((size_t)4 * k * nbp);
+    std::vector<Cx<double>> hb(coef_elems);
     Cx<double>* h1 = (Cx<double>*)cc;
     const size_t fvec = full_elems(c, 1);   // FP64 vectors per column
     for (int j0 = 0; j0 < k; j0 += nb) {
@@ -619,7 +623,7 @@ int deflation_finalize(dht_ctx* c, bool diagonal) {
         Cx<double>* g5m = g1 + (size_t)k * nbp;
         DHT_TRY(project_field(c, qwb, DHT_FP64, bp, h1, h2));
         DHT_TRY(project_field(c, wb, DHT_FP64, bp, g1, g5m));
-        DHT_HIP(hipMemcpyAsync(hb.data(), cc, sizeof(Cx<double>) * 4 * k * nbp, hipMemcpyDeviceToHost, c->stream));
+        DHT_HIP(hipMemcpyAsync(hb.data(), cc, sizeof(Cx<double>) * coef_elems, hipMemcpyDeviceToHost, c->stream));
         DHT_HIP(hipStreamSynchronize(c->stream));
         for (int i = 0; i < k; i++)
             for (int jj = 0; jj < n; jj++) {

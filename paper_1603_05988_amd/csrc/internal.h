@@ -252,6 +252,9 @@ struct NNState {
     float skip = 0.f;                              // M(r) = net(r) + skip r
 };
 
+// solver branch counters (dht_solver_counters)
+enum { SC_PREDICT = 0, SC_PREDICT_FAILED, SC_INPLACE, SC_REENTRY, SC_NCOUNT };
+
 struct Welford {   // running mean / second moments of complex samples (Chan et al. update)
     int64_t n = 0;
     double mre = 0, mim = 0;   // means
@@ -290,6 +293,8 @@ struct dht_ctx {
     dht::ProfStat prof_stat[dht::PROF_NCLASS];
     // estimator
     dht::Welford est_q, est_qd;
+    // defect-correction branch counts since creation (dht_solver_counters)
+    int64_t solver_count[dht::SC_NCOUNT] = {0, 0, 0, 0};
     // learned preconditioner
     dht::NNState nn;
     // hopping-kernel shape per (precision, log2 batch); hop_force overrides

@@ -360,195 +360,232 @@ int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* 
     std::vector<double> full2;     // its squared norms
     std::vector<Cx<double>> zx_e, zx_o;   // z^H x per parity from the same epilogues
     bool x_written = false;        // X_e holds the solution so far (else it is 0)
+    // rn2 comes from the in-place update (FP32 arithmetic on D e): a loop that
+    // stops on it must confirm it with an FP64 residual from X
+    bool rn2_inplace = false;
+    bool forced_predict = false, forced_drift = false;   // host-forced test conditions, once each
+    std::vector<double> fr2;
     void* e;
-    for (; outer < max_outer; outer++) {
-        bool any = false, stalled = false;
-        std::vector<double> sdown(nrhs), sup(nrhs), itarget(nrhs);
-        for (int i = 0; i < nrhs; i++) {
-            bool act = rn2[i] > target2[i] && isfinite(rn2[i]);
-            any |= act;
-            if (act && rn2[i] > 0.25 * last_rn2[i] && outer > 0 && !last_bad) stalled = true;
-            sdown[i] = act ? 1.0 / sqrt(rn2[i]) : 0.0;
-            sup[i] = act ? sqrt(rn2[i]) : 0.0;
-            last_rn2[i] = act ? rn2[i] : last_rn2[i];
-        }
-        if (!any) break;
-        if (stalled && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
-        if (total_iters >= prm->maxiter) break;
-        for (int i = 0; i < nrhs; i++) {
-            double itol = prm->inner_tol > 0 ? prm->inner_tol
-                                             : (inner == DHT_BF16 ? 1e-2 : (inner == DHT_FP32 ? 1e-5 : 0.0));
-            double need = sup[i] > 0 ? 0.25 * target2[i] / rn2[i] : 1.0;
-            itarget[i] = std::max(itol * itol, need);
-        }
-        // a BF16 solve adds its solution to X_e itself, rebuilt in FP64 from its
-        // stored iterations; the others return it in their storage precision
-        const bool hist = inner == DHT_BF16;
-        // A prepared BF16 right-hand side (see prep): RHS that take no part
-        // get a negative target (their rhat need not be zero).
-        bool use_prep = prep && hist && !((prm->fault_inject & 1u) && outer == 0);
-        for (int i = 0; i < nrhs && use_prep; i++)
-            if (sup[i] > 0 && !(sdp[i] > 0 && isfinite(sdp[i]))) use_prep = false;
-        std::vector<double> r0n2;
-        if (use_prep) {
-            r0n2.assign(nrhs, 0.0);
+    for (;;) {
+        for (; outer < max_outer; outer++) {
+            bool any = false, stalled = false;
+            std::vector<double> sdown(nrhs), sup(nrhs), itarget(nrhs);
             for (int i = 0; i < nrhs; i++) {
-                if (sup[i] > 0) {
-                    sdown[i] = sdp[i];
-                    sup[i] = 1.0 / sdp[i];
-                    r0n2[i] = rn2[i] * sdp[i] * sdp[i];
-                    itarget[i] *= r0n2[i];
-                } else {
-                    itarget[i] = -1.0;
+                bool act = rn2[i] > target2[i] && isfinite(rn2[i]);
+                any |= act;
+                if (act && rn2[i] > 0.25 * last_rn2[i] && outer > 0 && !last_bad) stalled = true;
+                sdown[i] = act ? 1.0 / sqrt(rn2[i]) : 0.0;
+                sup[i] = act ? sqrt(rn2[i]) : 0.0;
+                last_rn2[i] = act ? rn2[i] : last_rn2[i];
+            }
+            if (!any) break;
+            if (stalled && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
+            if (total_iters >= prm->maxiter) break;
+            for (int i = 0; i < nrhs; i++) {
+                double itol = prm->inner_tol > 0 ? prm->inner_tol
+                                                 : (inner == DHT_BF16 ? 1e-2 : (inner == DHT_FP32 ? 1e-5 : 0.0));
+                double need = sup[i] > 0 ? 0.25 * target2[i] / rn2[i] : 1.0;
+                itarget[i] = std::max(itol * itol, need);
+            }
+            // a BF16 solve adds its solution to X_e itself, rebuilt in FP64 from its
+            // stored iterations; the others return it in their storage precision
+            const bool hist = inner == DHT_BF16;
+            // A prepared BF16 right-hand side (see prep): RHS that take no part
+            // get a negative target (their rhat need not be zero).
+            bool use_prep = prep && hist && !((prm->fault_inject & 1u) && outer == 0);
+            for (int i = 0; i < nrhs && use_prep; i++)
+                if (sup[i] > 0 && !(sdp[i] > 0 && isfinite(sdp[i]))) use_prep = false;
+            std::vector<double> r0n2;
+            if (use_prep) {
+                r0n2.assign(nrhs, 0.0);
+                for (int i = 0; i < nrhs; i++) {
+                    if (sup[i] > 0) {
+                        sdown[i] = sdp[i];
+                        sup[i] = 1.0 / sdp[i];
+                        r0n2[i] = rn2[i] * sdp[i] * sdp[i];
+                        itarget[i] *= r0n2[i];
+                    } else {
+                        itarget[i] = -1.0;
+                    }
                 }
             }
-        }
-        prep = false;
-        const size_t lbytes = nh * elem_bytes(inner);
-        const int base = slot_base(inner);
-        e = nullptr;
-        if (!hist) DHT_TRY(ws_get(c, base + 8, lbytes, &e));     // inner solution
-        if ((prm->fault_inject & 1u) && outer == 0 && inner != DHT_FP64) {
-            // testing hook: poison the first inner right-hand side to exercise the fallback
-            for (int i = 0; i < nrhs; i++) sdown[i] = NAN;
-        }
-        DHT_HIP(hipMemcpyAsync(scl, sdown.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-        // the inner right-hand side is the scaled Schur residual (normalised
-        // by the one-pass start, or prepared as above); in the first cycle
-        // that is bhat itself
-        // After the first cycle, once every active residual is below
-        // 1e-2 ||z||, the Schur residual of a BF16 cycle is updated instead of
-        // recomputed: r_new = r_old - sigma Dhat e, with the cycle's correction
-        // e kept in FP32 (X moves by exactly sigma e) and Dhat e applied in
-        // FP32 arithmetic.  Its rounding is of the order of 1e-7 of the old
-        // residual (measured at 32^3x64: final residuals unchanged; from the
-        // first cycle on, where the old residual is ||bhat||, the drift stalls
-        // the loop).  The final residual is recomputed in FP64 from X, and the
-        // loop goes on from it if it misses the tolerance.
-        bool inc = hist && x_written;
-        for (int i = 0; i < nrhs && inc; i++)
-            if (sup[i] > 0 && !(rn2[i] <= INC_REL2 * zn2[i])) inc = false;
-        void *E32 = nullptr, *W32 = nullptr, *T32 = nullptr;
-        if (inc) {
-            DHT_TRY(ws_get(c, WS_E32, nh * elem_bytes(DHT_FP32), &E32));
-            DHT_TRY(ws_get(c, WS_W32, nh * elem_bytes(DHT_FP32), &W32));
-            DHT_TRY(ws_get(c, WS_T32, nh * elem_bytes(DHT_FP32), &T32));
-        }
-        BicgResult br;
-        XAccum xa;
-        if (hist) {
-            xa.ring = prm->history;
-            xa.X = X_e;
-            xa.scale = sup;
-            xa.assign = !x_written;
-            xa.E32 = E32;
-            xa.predict_t2 = &target2;
-        }
-        DHT_TRY(bicgstab(c, inner, outer == 0 ? bhat : r_e, (const double*)scl, e, nrhs, itarget,
-                         prm->maxiter - total_iters, &br, false, hist ? &xa : nullptr,
-                         use_prep ? r0n2.data() : nullptr));
-        int maxit = 0;
-        bool bad = false;
-        for (int i = 0; i < nrhs; i++) {
-            iters[i] += br.iters[i];
-            maxit = std::max(maxit, br.iters[i]);
-            if (br.status[i] == RS_NAN || br.status[i] == RS_BREAKDOWN) {
-                if (br.status[i] == RS_NAN) sup[i] = 0.0;   // discard a poisoned correction
-                bad = true;
+            prep = false;
+            const size_t lbytes = nh * elem_bytes(inner);
+            const int base = slot_base(inner);
+            e = nullptr;
+            if (!hist) DHT_TRY(ws_get(c, base + 8, lbytes, &e));     // inner solution
+            if ((prm->fault_inject & 1u) && outer == 0 && inner != DHT_FP64) {
+                // testing hook: poison the first inner right-hand side to exercise the fallback
+                for (int i = 0; i < nrhs; i++) sdown[i] = NAN;
             }
-        }
-        total_iters += std::max(maxit, 1);
-        if (!hist) {
-            DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-            // the first correction is x itself: X_e = 0 is never materialised
-            DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nrhs, !x_written));
-        }
-        x_written = true;
-        // When the inner solver's own residual says this correction finishes
-        // every RHS, go straight to the full-lattice check: its even residual
-        // z_e - a x_e + Hop_eo x_o / 2 is the Schur residual (x_o reconstructed
-        // from x_e), so a wrong guess costs one hop (x_o) and the loop continues
-        // from it, while a right one saves a hop of the Schur residual.  The odd
-        // residual z_o - a x_o + Hop_oe x_e / 2 vanishes by the construction of
-        // x_o (to FP64 rounding), so the even one is the full residual.
-        // the inner residual in units of r: ||r_new||^2 ~ sup^2 ||r_inner||^2
-        bool predict = true;
-        for (int i = 0; i < nrhs; i++)
-            if (sup[i] > 0 && !(sup[i] * sup[i] * br.rnorm2[i] <= target2[i])) predict = false;
-        if (predict) {
-            // with the fused z^H x the even residual itself is not stored
-            // (only its norms and z^H x are wanted if it meets the tolerance)
-            const int nofield = zx_out ? HOP_NOOUT : 0;
-            DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr, z16));
-            DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, zx_out ? &zx_e : nullptr,
-                                 (z16 ? HOP_Z16 : 0) | nofield));
-            bool done = true;
-            full2 = rn2;
+            DHT_HIP(hipMemcpyAsync(scl, sdown.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+            // the inner right-hand side is the scaled Schur residual (normalised
+            // by the one-pass start, or prepared as above); in the first cycle
+            // that is bhat itself
+            // After the first cycle, once every active residual is below
+            // 1e-2 ||z||, the Schur residual of a BF16 cycle is updated instead of
+            // recomputed: r_new = r_old - sigma Dhat e, with the cycle's correction
+            // e kept in FP32 (X moves by exactly sigma e) and Dhat e applied in
+            // FP32 arithmetic.  Its rounding is of the order of 1e-7 of the old
+            // residual (measured at 32^3x64: final residuals unchanged; from the
+            // first cycle on, where the old residual is ||bhat||, the drift stalls
+            // the loop).  The final residual is recomputed in FP64 from X, and the
+            // loop goes on from it if it misses the tolerance.
+            bool inc = hist && x_written;
+            for (int i = 0; i < nrhs && inc; i++)
+                if (sup[i] > 0 && !(rn2[i] <= INC_REL2 * zn2[i])) inc = false;
+            void *E32 = nullptr, *W32 = nullptr, *T32 = nullptr;
+            if (inc) {
+                DHT_TRY(ws_get(c, WS_E32, nh * elem_bytes(DHT_FP32), &E32));
+                DHT_TRY(ws_get(c, WS_W32, nh * elem_bytes(DHT_FP32), &W32));
+                DHT_TRY(ws_get(c, WS_T32, nh * elem_bytes(DHT_FP32), &T32));
+            }
+            BicgResult br;
+            XAccum xa;
+            if (hist) {
+                xa.ring = prm->history;
+                xa.X = X_e;
+                xa.scale = sup;
+                xa.assign = !x_written;
+                xa.E32 = E32;
+                xa.predict_t2 = &target2;
+            }
+            DHT_TRY(bicgstab(c, inner, outer == 0 ? bhat : r_e, (const double*)scl, e, nrhs, itarget,
+                             prm->maxiter - total_iters, &br, false, hist ? &xa : nullptr,
+                             use_prep ? r0n2.data() : nullptr));
+            int maxit = 0;
+            bool bad = false;
+            for (int i = 0; i < nrhs; i++) {
+                iters[i] += br.iters[i];
+                maxit = std::max(maxit, br.iters[i]);
+                if (br.status[i] == RS_NAN || br.status[i] == RS_BREAKDOWN) {
+                    if (br.status[i] == RS_NAN) sup[i] = 0.0;   // discard a poisoned correction
+                    bad = true;
+                }
+            }
+            total_iters += std::max(maxit, 1);
+            if (!hist) {
+                DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+                // the first correction is x itself: X_e = 0 is never materialised
+                DHT_TRY(accum_up(c, X_e, e, inner, (const double*)scl, nrhs, !x_written));
+            }
+            x_written = true;
+            // When the inner solver's own residual says this correction finishes
+            // every RHS, go straight to the full-lattice check: its even residual
+            // z_e - a x_e + Hop_eo x_o / 2 is the Schur residual (x_o reconstructed
+            // from x_e), so a wrong guess costs one hop (x_o) and the loop continues
+            // from it, while a right one saves a hop of the Schur residual.  The odd
+            // residual z_o - a x_o + Hop_oe x_e / 2 vanishes by the construction of
+            // x_o (to FP64 rounding), so the even one is the full residual.
+            // the inner residual in units of r: ||r_new||^2 ~ sup^2 ||r_inner||^2
+            bool predict = true;
             for (int i = 0; i < nrhs; i++)
-                if (zn2[i] > 0 && !(full2[i] <= prm->tol * prm->tol * zn2[i])) done = false;
-            if (done) {
-                have_full = true;
-                outer++;
-                break;
+                if (sup[i] > 0 && !(sup[i] * sup[i] * br.rnorm2[i] <= target2[i])) predict = false;
+            if (predict) {
+                // with the fused z^H x the even residual itself is not stored
+                // (only its norms and z^H x are wanted if it meets the tolerance)
+                const int nofield = zx_out ? HOP_NOOUT : 0;
+                c->solver_count[SC_PREDICT]++;
+                DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr, z16));
+                DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, zx_out ? &zx_e : nullptr,
+                                     (z16 ? HOP_Z16 : 0) | nofield));
+                rn2_inplace = false;
+                bool done = true;
+                full2 = rn2;
+                for (int i = 0; i < nrhs; i++)
+                    if (zn2[i] > 0 && !(full2[i] <= prm->tol * prm->tol * zn2[i])) done = false;
+                if ((prm->fault_inject & 2u) && !forced_predict) {   // testing hook: reject one good prediction
+                    forced_predict = true;
+                    done = false;
+                }
+                if (done) {
+                    have_full = true;
+                    outer++;
+                    break;
+                }
+                c->solver_count[SC_PREDICT_FAILED]++;
+                if (nofield)   // the loop goes on from this residual: store it
+                    DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, &zx_e, z16 ? HOP_Z16 : 0));
+            } else if (inc && !bad) {
+                // r -= sigma Dhat e: Dhat e in FP32, the update and its norms in FP64
+                // (after a NaN the discarded RHS's x may hold part of the
+                // correction: that cycle recomputes the residual from x instead)
+                DHT_TRY(apply_schur(c, DHT_FP32, E32, W32, T32, nrhs, nullptr));
+                DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+                void *part, *sums;
+                DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
+                DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs, &sums));
+                // the next cycle's BF16 right-hand side in the same pass, scaled
+                // by the inverse of each residual norm that this cycle predicts
+                const bool can = predict_scales(sup, br, sdn);
+                if (can) DHT_TRY(want16());
+                int nbr;
+                DHT_TRY(residual_step(c, r_e, r_e, W32, (const double*)scl, nrhs, (Cx<double>*)part, &nbr,
+                                      can ? rh16 : nullptr, (const double*)s16));
+                DHT_TRY(finalize(c, (const Cx<double>*)part, nbr, 1, nrhs, nullptr, FIN_SUM, 0.0, (Cx<double>*)sums));
+                std::vector<Cx<double>> h(nrhs);
+                DHT_HIP(hipMemcpyAsync(h.data(), sums, sizeof(Cx<double>) * nrhs, hipMemcpyDeviceToHost, c->stream));
+                DHT_HIP(hipStreamSynchronize(c->stream));
+                for (int i = 0; i < nrhs; i++) rn2[i] = h[i].re;
+                c->solver_count[SC_INPLACE]++;
+                rn2_inplace = true;
+                if ((prm->fault_inject & 4u) && !forced_drift) {
+                    // testing hook: the in-place norms understate the residual once, as
+                    // an FP32 drift past the margin of the target would
+                    forced_drift = true;
+                    for (int i = 0; i < nrhs; i++) rn2[i] *= 1e-12;
+                }
+                if (can) {
+                    prep = true;
+                    sdp = sdn;
+                }
+            } else {
+                // FP64 true residual of the Schur system, r = bhat - (a x - Hop_eo Hop_oe x / (4a)),
+                // and its norms, in the second hop's epilogue (after a BF16 cycle
+                // with the next BF16 right-hand side, scaled as predicted)
+                const bool can = hist && !bad && predict_scales(sup, br, sdn);
+                if (can) DHT_TRY(want16());
+                DHT_TRY(hop(c, DHT_FP64, 1, X_e, tmp_o, nullptr, 0.0, 1.0, nrhs, false, false));
+                DHT_TRY(residual_hop(c, 0, tmp_o, r_e, X_e, -a, 1.0 / (4.0 * a), bhat, nrhs, 0, rn2, nullptr, 0,
+                                     can ? rh16 : nullptr, (const double*)s16));
+                rn2_inplace = false;
+                if (can) {
+                    prep = true;
+                    sdp = sdn;
+                }
             }
-            if (nofield)   // the loop goes on from this residual: store it
-                DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, rn2, &zx_e, z16 ? HOP_Z16 : 0));
-        } else if (inc && !bad) {
-            // r -= sigma Dhat e: Dhat e in FP32, the update and its norms in FP64
-            // (after a NaN the discarded RHS's x may hold part of the
-            // correction: that cycle recomputes the residual from x instead)
-            DHT_TRY(apply_schur(c, DHT_FP32, E32, W32, T32, nrhs, nullptr));
-            DHT_HIP(hipMemcpyAsync(scl, sup.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-            void *part, *sums;
-            DHT_TRY(ws_get(c, WS_PARTIAL, partial_bytes(c, nrhs), &part));
-            DHT_TRY(ws_get(c, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs, &sums));
-            // the next cycle's BF16 right-hand side in the same pass, scaled
-            // by the inverse of each residual norm that this cycle predicts
-            const bool can = predict_scales(sup, br, sdn);
-            if (can) DHT_TRY(want16());
-            int nbr;
-            DHT_TRY(residual_step(c, r_e, r_e, W32, (const double*)scl, nrhs, (Cx<double>*)part, &nbr,
-                                  can ? rh16 : nullptr, (const double*)s16));
-            DHT_TRY(finalize(c, (const Cx<double>*)part, nbr, 1, nrhs, nullptr, FIN_SUM, 0.0, (Cx<double>*)sums));
-            std::vector<Cx<double>> h(nrhs);
-            DHT_HIP(hipMemcpyAsync(h.data(), sums, sizeof(Cx<double>) * nrhs, hipMemcpyDeviceToHost, c->stream));
-            DHT_HIP(hipStreamSynchronize(c->stream));
-            for (int i = 0; i < nrhs; i++) rn2[i] = h[i].re;
-            if (can) {
-                prep = true;
-                sdp = sdn;
-            }
-        } else {
-            // FP64 true residual of the Schur system, r = bhat - (a x - Hop_eo Hop_oe x / (4a)),
-            // and its norms, in the second hop's epilogue (after a BF16 cycle
-            // with the next BF16 right-hand side, scaled as predicted)
-            const bool can = hist && !bad && predict_scales(sup, br, sdn);
-            if (can) DHT_TRY(want16());
-            DHT_TRY(hop(c, DHT_FP64, 1, X_e, tmp_o, nullptr, 0.0, 1.0, nrhs, false, false));
-            DHT_TRY(residual_hop(c, 0, tmp_o, r_e, X_e, -a, 1.0 / (4.0 * a), bhat, nrhs, 0, rn2, nullptr, 0,
-                                 can ? rh16 : nullptr, (const double*)s16));
-            if (can) {
-                prep = true;
-                sdp = sdn;
-            }
+            if (bad && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
+            last_bad = bad;
+            for (int i = 0; i < nrhs; i++)
+                if (inner != start_inner && rn2[i] > target2[i])
+                    escalated[i] = inner == DHT_FP32 ? DHT_STATUS_FALLBACK_FP32 : DHT_STATUS_FALLBACK_FP64;
         }
-        if (bad && inner != DHT_FP64) inner = inner == DHT_BF16 ? DHT_FP32 : DHT_FP64;
-        last_bad = bad;
-        for (int i = 0; i < nrhs; i++)
-            if (inner != start_inner && rn2[i] > target2[i])
-                escalated[i] = inner == DHT_FP32 ? DHT_STATUS_FALLBACK_FP32 : DHT_STATUS_FALLBACK_FP64;
-    }
-    if (!x_written) DHT_TRY(zero(c, X_e, bh));
-    std::vector<double> fr2;
-    if (have_full) {
-        fr2 = full2;
-    } else {
+        if (!x_written) DHT_TRY(zero(c, X_e, bh));
+        if (have_full) {
+            fr2 = full2;
+            break;
+        }
         // odd sites and the FP64 full-lattice true residual: its even half
         // r_e = z_e - (a x_e - Hop_eo x_o / 2) with norms fused (the odd half
         // vanishes by the construction of x_o)
         DHT_TRY(odd_from_even(c, X_e, X_o, Z_o, nrhs, zx_out ? &zx_o : nullptr, z16));
         DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, fr2, zx_out ? &zx_e : nullptr,
                              (z16 ? HOP_Z16 : 0) | (zx_out ? HOP_NOOUT : 0)));
+        bool met = true;
+        for (int i = 0; i < nrhs; i++)
+            if (zn2[i] > 0 && !(fr2[i] <= prm->tol * prm->tol * zn2[i])) met = false;
+        // The loop stopped on residual norms from the in-place update, and the
+        // FP64 residual of X misses the tolerance: go on from that residual while
+        // cycles and iterations remain (it is the Schur residual of X_e, which the
+        // next cycle needs stored)
+        if (met || !rn2_inplace || outer >= max_outer || total_iters >= prm->maxiter) break;
+        c->solver_count[SC_REENTRY]++;
+        if (zx_out)
+            DHT_TRY(residual_hop(c, 0, X_o, r_e, X_e, -a, 0.5, Z_e, nrhs, 0, fr2, &zx_e, z16 ? HOP_Z16 : 0));
+        rn2 = fr2;
+        rn2_inplace = false;
+        prep = false;
+        std::fill(last_rn2.begin(), last_rn2.end(), INFINITY);   // not a stall of the inner solves
     }
     if (zx_out)
         for (int i = 0; i < nrhs; i++) zx_out[i] = zx_e[i] + zx_o[i];

@@ -122,3 +122,27 @@ def test_c5_projection_window_exact(c5_basis):
         assert all(r["true_resid"] <= W5.tol for r in recs)
         _check_exact(c1, c2, first, (0, B - 1))
     ctx.set_projection_window(0)
+
+
+def test_c5_quadratic_forms_vs_oracle_solve(c5_basis):
+    """q = z^H x of the timed trace_batch path (BF16 probes, fused z^H x in
+    the final residual hops, predicted final check, in-place residual updates,
+    64-probe projection window) for two probes of a 32^3x64 batch, against
+    z^H x* with x* from the oracle's C-stencil FP64 BiCGStab to 1e-10:
+    relative 1e-8 (the tolerance after mixed-precision refinement)."""
+    U, ctx = c5_basis
+    Lb = _lib()
+    B = W5.batch
+    prm = ctx.params(Lb.SOLVER_DC_BICGSTAB, inner=Lb.BF16, tol=W5.tol, maxiter=5000)
+    ctx.set_projection_window(4 * B)
+    recs = ctx.trace_batch(W5.seed, 0, W5.hp, B, B, prm)
+    ctx.set_projection_window(0)
+    for r in (0, B - 1):
+        z = rng.probe(W5.L, W5.seed, 0, W5.hp, B + r)
+        x, st, it, rr = stencil.solve(U, W5.L, W5.mass, z, 1e-10, 5000)
+        assert st == 0 and rr <= 1e-10, (st, it, rr)
+        qs = np.vdot(z, x.ravel())
+        q = recs[r]["q"]
+        print("probe %d: q = %.12e%+.12ei, oracle %.12e%+.12ei, rel %.2e" % (B + r, q.real, q.imag, qs.real,
+                                                                            qs.imag, abs(q - qs) / abs(qs)))
+        assert abs(q - qs) <= 1e-8 * abs(qs), (r, q, qs)

@@ -6,7 +6,7 @@
 - Hadamard columns: sum_{j<2^m} h_j(x) h_j(y) = 2^m [c_m(x) == c_m(y)];
 - colour closings: with 2, 32 and 512 vectors the same-colour site pairs lie
   at torus Manhattan distances that are multiples of 2, 4 and 8 -- the paper
-  states that 32 vectors remove distances 1, 2, 3, 5, 6, 7 (Section 6.3);
+  states that 32 vectors remove distances 1, 2, 3, 5, 6, 7 (Section 6.2);
 - a complete sweep equals z0^H (M_s . A) z0 for any A.
 """
 import os
@@ -78,7 +78,7 @@ def test_colour_closing_distances(L, nbits, modulus):
                 seen.add(d)
     assert 0 in seen and modulus in seen
     if nbits == 5:
-        # Section 6.3: 32 probing vectors remove distances 1, 2, 3, 5, 6, 7
+        # Section 6.2: 32 probing vectors remove distances 1, 2, 3, 5, 6, 7
         assert not seen & {1, 2, 3, 5, 6, 7}
 
 
