@@ -178,6 +178,23 @@ int dht_set_gauge(dht_ctx* ctx, const double* U_dev);
  * entry; Y is returned in complex128).  X and Y must not overlap. */
 int dht_apply(dht_ctx* ctx, int op, int prec, const double* X_dev, double* Y_dev, int nrhs);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same Y = op(X) as dht_apply, with the library's internal even/odd
+ * copies of each chunk of up to 64 right-hand sides held in a fixed
+ * device-resident scratch array of DHT_NOALLOC_SCRATCH_BYTES per GPU instead
+ * of allocated workspace.  The call makes no hipMalloc / hipFree and does not
+ * synchronise: the work is enqueued on the context stream and Y is complete
+ * when that stream reaches it (launches are not counted by dht_profile_*).
+ * Limit: 2 * 12 * V * pad(min(nrhs, 64)) * s bytes must not exceed
+ * DHT_NOALLOC_SCRATCH_BYTES (pad = next power of two, s = 16 / 8 / 4 bytes
+ * per complex for FP64 / FP32 / BF16), else DHT_ERR_INVALID_ARG and nothing
+ * is enqueued.  Every call on one GPU (any context) shares that GPU's array,
+ * and the last call's contents stay in it: calls that may overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller. */
+#define DHT_NOALLOC_SCRATCH_BYTES (32u << 20)
+int dht_apply_noalloc(dht_ctx* ctx, int op, int prec, const double* X_dev, double* Y_dev, int nrhs);
+
 /* Write probes j = first .. first+nrhs-1 to Z_dev (canonical complex128). */
 int dht_make_probes(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int nrhs, double* Z_dev);
 

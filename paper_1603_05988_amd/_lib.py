@@ -95,6 +95,7 @@ SIGNATURES = {
     "dht_version": (ctypes.c_char_p, []),
     "dht_set_gauge": (_i, [_vp, _vp]),
     "dht_apply": (_i, [_vp, _i, _i, _vp, _vp, _i]),
+    "dht_apply_noalloc": (_i, [_vp, _i, _i, _vp, _vp, _i]),
     "dht_make_probes": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _vp]),
     "dht_probe_indices": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _vp, _vp]),
     "dht_solve": (_i, [_vp, ctypes.POINTER(SolverParams), _vp, _vp, _i, ctypes.POINTER(SolveStats)]),
@@ -227,6 +228,12 @@ class Context:
         Y = self.torch.empty_like(X)
         nrhs = X.shape[0]
         check(load().dht_apply(self.h, op, prec, _as_f64_view(X), _as_f64_view(Y), nrhs))
+        return Y
+
+    def apply_noalloc(self, X, Y, op: int = OP_D, prec: int = FP64):
+        """Y = op(X) into a caller tensor Y with no device allocation in the
+        library (fixed per-GPU scratch); asynchronous on the context stream."""
+        check(load().dht_apply_noalloc(self.h, op, prec, _as_f64_view(X), _as_f64_view(Y), X.shape[0]))
         return Y
 
     def make_probes(self, seed: int, run: int, hp: bool, first: int, nrhs: int):

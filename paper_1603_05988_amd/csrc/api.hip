@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 
 #include "solver.h"
@@ -17,6 +18,33 @@
 namespace dht {
 
 static thread_local std::string g_err;
+
+// Scratch of dht_apply_noalloc: the two internal even/odd fields of one chunk
+// of right-hand sides, in a device-resident array that exists for the life of
+// the process (no allocation at call time).  Every GPU the library runs on
+// holds its own copy at its own address; host code uses only the per-device
+// address that hipGetSymbolAddress returned, never the array's name.
+static __device__ __align__(256) unsigned char scratch[DHT_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;   // per device; null until set up
+
+// once per device, with that device current (called by dht_create)
+static int scratch_setup(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (g_scratch_ptr[device]) return DHT_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return set_error(DHT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return DHT_OK;
+}
+
+static void* scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return device >= 0 && device < (int)g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
+}
 
 int set_error(int code, const std::string& msg) {
     g_err = msg;
@@ -165,6 +193,7 @@ int dht_create(const dht_lattice* lat, int device, void* hip_stream, dht_ctx** o
     DHT_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return set_error(DHT_ERR_INVALID_ARG, "no such device");
     DHT_HIP(hipSetDevice(device));
+    DHT_TRY(scratch_setup(device));
     dht_ctx* c = new (std::nothrow) dht_ctx;
     if (!c) return set_error(DHT_ERR_OOM, "out of host memory");
     for (int i = 0; i < 4; i++) c->g.L[i] = lat->L[i];
@@ -251,6 +280,37 @@ int dht_apply(dht_ctx* c, int op, int prec, const double* X, double* Y, int nrhs
     DHT_HIP(hipStreamSynchronize(c->stream));
     DHT_TRY(prof_harvest(c));
     return DHT_OK;
+}
+
+int dht_apply_noalloc(dht_ctx* c, int op, int prec, const double* X, double* Y, int nrhs) {
+    DHT_TRY(check_ctx(c));
+    if (!X || !Y || nrhs <= 0 || !valid_prec(prec) || op < DHT_OP_D || op > DHT_OP_Q)
+        return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (op != DHT_OP_G5 && !c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    const int bp0 = pad_rhs(std::min(64, nrhs));
+    const size_t need = 2 * full_elems(c, bp0) * elem_bytes(prec);
+    if (need > (size_t)DHT_NOALLOC_SCRATCH_BYTES)
+        return set_error(DHT_ERR_INVALID_ARG, "dht_apply_noalloc: " + std::to_string(need) +
+                                                  " bytes of scratch needed, the limit is " +
+                                                  std::to_string((size_t)DHT_NOALLOC_SCRATCH_BYTES));
+    char* base = (char*)scratch_ptr(c->device);
+    if (!base) return set_error(DHT_ERR_STATE, "no-alloc scratch not set up on this device");
+    // the per-launch events of the instrumentation would come from a pool
+    // that grows on demand: these launches are not profiled
+    const bool prof = c->prof;
+    c->prof = false;
+    int rc = DHT_OK;
+    const int64_t N = 12 * c->g.V;
+    for (int r0 = 0; r0 < nrhs && rc == DHT_OK; r0 += 64) {   // chunks of at most 64, in stream order
+        const int n = std::min(64, nrhs - r0), bp = pad_rhs(n);
+        void* fi = base;
+        void* fo = base + full_elems(c, bp) * elem_bytes(prec);
+        rc = pack_spinor(c, X + 2 * N * r0, fi, prec, n, bp);
+        if (rc == DHT_OK) rc = apply_full(c, op, prec, fi, fo, bp);
+        if (rc == DHT_OK) rc = unpack_spinor(c, fo, prec, Y + 2 * N * r0, n, bp);
+    }
+    c->prof = prof;
+    return rc;
 }
 
 int dht_make_probes(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, double* Z) {
