@@ -405,13 +405,18 @@ int dht_bench_hop(dht_ctx* ctx, int prec, int nrhs, int warmup, int reps, double
  *                     (needs 256 / nrhs <= 32, i.e. nrhs >= 8);
  *   DHT_HOP_TMARCH    one lane per (x, y, z column, RHS) walking t_chunk
  *                     slices in t, the backward t-neighbour kept in registers
- *                     (t_chunk even, divides Lt; 0 = automatic).
+ *                     (t_chunk even, divides Lt; 0 = automatic);
+ *   DHT_HOP_SITE_ROWL, DHT_HOP_TMARCH_ROWL  as SITE / TMARCH, with each
+ *                     site's links loaded once per 16-lane row (the row's 16
+ *                     right-hand sides) and broadcast within the row; BF16
+ *                     sweeps of >= 16 right-hand sides only (other precisions
+ *                     and smaller sweeps run the plain form).
  * streaming_stores = 1 writes the output with non-temporal stores.
  * rhs_group = G (a power of two dividing nrhs; 0 = nrhs): the lattice is swept
  * once per group of G right-hand sides, the groups side by side on the chip,
  * so fewer bytes per site share the caches while the links are read once per
  * group (the LDS form needs G >= 8). */
-enum { DHT_HOP_SITE = 0, DHT_HOP_SITE_LDS = 1, DHT_HOP_TMARCH = 2 };
+enum { DHT_HOP_SITE = 0, DHT_HOP_SITE_LDS = 1, DHT_HOP_TMARCH = 2, DHT_HOP_SITE_ROWL = 3, DHT_HOP_TMARCH_ROWL = 4 };
 typedef struct dht_hop_config {
     int form;
     int streaming_stores;

@@ -67,10 +67,11 @@ class TuneResult(ctypes.Structure):
                 ("candidates", ctypes.c_int), ("rejected", ctypes.c_int), ("max_rel_diff", ctypes.c_double)]
 
 
-HOP_SITE, HOP_SITE_LDS, HOP_TMARCH = 0, 1, 2
+HOP_SITE, HOP_SITE_LDS, HOP_TMARCH, HOP_SITE_ROWL, HOP_TMARCH_ROWL = 0, 1, 2, 3, 4
 HOP_PLAIN, HOP_FUSED, HOP_FUSED_A = 0, 1, 2
 HOP_CLASSES = {HOP_PLAIN: "plain", HOP_FUSED: "fused", HOP_FUSED_A: "fused_a"}
-HOP_FORMS = {HOP_SITE: "site", HOP_SITE_LDS: "site_lds", HOP_TMARCH: "tmarch"}
+HOP_FORMS = {HOP_SITE: "site", HOP_SITE_LDS: "site_lds", HOP_TMARCH: "tmarch", HOP_SITE_ROWL: "site_rowl",
+             HOP_TMARCH_ROWL: "tmarch_rowl"}
 
 
 class Estimate(ctypes.Structure):

@@ -150,6 +150,170 @@ __device__ inline void mul_link(const Cx<T>* u, const Cx<T>* h, Cx<T>* w) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 storage: the link product on packed values.  A BF16 complex is one
+// 32-bit word as stored (re in the low half, im in the high half).  For a link
+// entry L and an operand x, Re(L x) and Im(L x) are each Lr a + Li b for a pair
+// (a, b) made of +-xr, +-xi; v_dot2_f32_bf16 forms Lr a + Li b + acc in FP32
+// straight from the packed link entry and the packed pair, so neither operand
+// is unpacked and each pair of products costs one instruction (the products of
+// two BF16 values are exact in FP32).  The pairs are signed selections of the
+// stored (vr, vi) of v with x = i^K v: one half swap and one sign-bit xor at
+// most, fixed at compile time.
+//   Re(U x) = Ur xr - Ui xi -> (xr, -xi)      Im(U x) = Ur xi + Ui xr -> (xi, xr)
+//   Re(U* x) = Ur xr + Ui xi -> (xr, xi)      Im(U* x) = Ur xi - Ui xr -> (xi, -xr)
+// (U* is the entry U_ba of U^H at (a, b), so ADJ reads U transposed.)
+// ---------------------------------------------------------------------------
+template <bool ADJ, bool IMPART, int K>
+struct PairForm {
+    // x = i^K v in terms of v: xr = sgn_r * v[sel_r], xi = sgn_i * v[sel_i] (sel 0 = re, 1 = im)
+    static constexpr int sel_r = (K & 1) ? 1 : 0;
+    static constexpr int sgn_r = (K == 0 || K == 3) ? 1 : -1;
+    static constexpr int sel_i = (K & 1) ? 0 : 1;
+    static constexpr int sgn_i = (K == 0 || K == 1) ? 1 : -1;
+    static constexpr int lo_sel = IMPART ? sel_i : sel_r;
+    static constexpr int lo_sgn = IMPART ? sgn_i : sgn_r;
+    static constexpr int hi_sgn = IMPART ? (ADJ ? -sgn_r : sgn_r) : (ADJ ? sgn_i : -sgn_i);
+    static constexpr bool swap = lo_sel == 1;
+    static constexpr uint32_t mask = (lo_sgn < 0 ? 0x8000u : 0u) | (hi_sgn < 0 ? 0x80000000u : 0u);
+};
+// acc + Lr a + Li b for the pair (a, b) of PairForm, built from v and its half
+// swap vs (the sign bits by xor).  A chain that starts at zero uses the VOP3
+// form with the inline constant 0 as its accumulator (the compiler's VOP2
+// v_dot2c form accumulates into its destination, which then needs a zeroing
+// move per chain).
+template <bool ADJ, bool IMPART, int K, bool FIRST>
+__device__ inline float dot2_form(uint32_t l, uint32_t v, uint32_t vs, float acc) {
+    typedef PairForm<ADJ, IMPART, K> F;
+    uint32_t x = F::swap ? vs : v;
+    if constexpr (F::mask != 0u) x ^= F::mask;
+    if constexpr (FIRST) {
+        float d;
+        asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(d) : "v"(l), "v"(x));
+        return d;
+    } else {
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_vec_t, l), __builtin_bit_cast(bf16x2_vec_t, x),
+                                               acc, false);
+    }
+}
+__device__ inline uint32_t half_swap(uint32_t v) { return (v >> 16) | (v << 16); }
+
+// The projected half spinor of (1 - SGN g_mu) is h_sp = u_sp + i^K_sp l_(pi_sp)
+// for the upper spins sp = 0, 1 (u) and a lower spin pi_sp (l), read off the
+// chiral g_mu (the same combination as project<MU, SGN>).
+template <int MU, int SGN, int SP> struct HalfSpin {
+    static constexpr int kp = SGN > 0 ? 0 : 2;   // i^kp = SGN
+    static constexpr int K = MU == 0 ? (1 + kp) & 3
+                           : MU == 1 ? (SP == 0 ? kp : (2 + kp) & 3)
+                           : MU == 2 ? (SP == 0 ? (1 + kp) & 3 : (3 + kp) & 3)
+                                     : (2 + kp) & 3;
+    static constexpr int lower = MU == 0 ? (SP == 0 ? 3 : 2) : MU == 1 ? (SP == 0 ? 3 : 2) : (SP == 0 ? 2 : 3);
+};
+
+// w = L h_SP for one half-spinor spin (3 colours), h_SP = u_SP + i^K l_lower
+template <int MU, int SGN, bool ADJ, int SP>
+__device__ inline void link_mult_spin(const uint32_t* p, const uint32_t* u, Cx<float>* w) {
+    constexpr int K = HalfSpin<MU, SGN, SP>::K, LO = HalfSpin<MU, SGN, SP>::lower;
+    uint32_t us[3], ls[3];
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        us[b] = half_swap(p[3 * SP + b]);
+        ls[b] = half_swap(p[3 * LO + b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        float re, im;
+#define DHT_L(b) (ADJ ? u[3 * (b) + a] : u[3 * a + (b)])
+        re = dot2_form<ADJ, false, 0, true>(DHT_L(0), p[3 * SP], us[0], 0.f);
+        im = dot2_form<ADJ, true, 0, true>(DHT_L(0), p[3 * SP], us[0], 0.f);
+        re = dot2_form<ADJ, false, K, false>(DHT_L(0), p[3 * LO], ls[0], re);
+        im = dot2_form<ADJ, true, K, false>(DHT_L(0), p[3 * LO], ls[0], im);
+#pragma unroll
+        for (int b = 1; b < 3; b++) {
+            re = dot2_form<ADJ, false, 0, false>(DHT_L(b), p[3 * SP + b], us[b], re);
+            im = dot2_form<ADJ, true, 0, false>(DHT_L(b), p[3 * SP + b], us[b], im);
+            re = dot2_form<ADJ, false, K, false>(DHT_L(b), p[3 * LO + b], ls[b], re);
+            im = dot2_form<ADJ, true, K, false>(DHT_L(b), p[3 * LO + b], ls[b], im);
+        }
+#undef DHT_L
+        w[a] = cmake(re, im);
+    }
+}
+
+// w = L h of both half-spinor spins, L = U or U^H (ADJ), h of (1 - SGN g_mu),
+// from the packed spinor p[12] (index 3 spin + colour) and packed link u[9]
+template <int MU, int SGN, bool ADJ>
+__device__ inline void link_mult_bf16(const uint32_t* p, const uint32_t* u, Cx<float>* w) {
+    link_mult_spin<MU, SGN, ADJ, 0>(p, u, w);
+    link_mult_spin<MU, SGN, ADJ, 1>(p, u, w + 3);
+}
+
+// 12 packed components of (site s, rhs r) and the 9 packed entries of a link
+__device__ inline void load_packed_spinor(const void* base, int64_t v0, int64_t vstride, uint32_t* p) {
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        uint4 d = ((const uint4*)base)[v0 + j * vstride];
+        p[4 * j] = d.x;
+        p[4 * j + 1] = d.y;
+        p[4 * j + 2] = d.z;
+        p[4 * j + 3] = d.w;
+    }
+}
+__device__ inline void load_packed_link(const void* base, int64_t v0, uint32_t* u) {
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        uint4 d = ((const uint4*)base)[v0 + j];
+        u[4 * j] = d.x;
+        if (4 * j + 1 < 9) u[4 * j + 1] = d.y;
+        if (4 * j + 2 < 9) u[4 * j + 2] = d.z;
+        if (4 * j + 3 < 9) u[4 * j + 3] = d.w;
+    }
+}
+
+// Row-shared links (BF16, sweeps of >= 16 right-hand sides).  The 16 lanes of
+// a DPP row hold the 16 right-hand sides of one site and need the same 8 link
+// matrices.  Lane q of the row loads half (6 words) of the step's link slot
+// q / 2 -- slots 2 mu and 2 mu + 1 are U_mu at the output site (forward) and
+// U_mu at its backward link site (other parity) -- and each link's 9 words
+// are broadcast from its two owner lanes (DPP row_newbcast) just before its
+// product: 3 eight-byte loads per lane and step instead of the 16-byte link
+// loads that every lane of the row would otherwise repeat.
+struct RowLinks {
+    uint32_t w[6];
+};
+__device__ inline void row_links_load(const void* U, int Vh, int p, int s, int sbx, int sby, int sbz, int sbt,
+                                      RowLinks& rl) {
+    const int q = threadIdx.x & 15, d = q >> 1, mu = d >> 1;
+    const bool bwd = d & 1;
+    int site = s;
+    if (bwd) site = mu == 0 ? sbx : (mu == 1 ? sby : (mu == 2 ? sbz : sbt));
+    const int64_t v = ((int64_t)(mu * 2 + (bwd ? 1 - p : p)) * Vh + site) * 3;   // 3 vectors per BF16 link
+    const uint2* ptr = (const uint2*)((const uint4*)U + v) + 3 * (q & 1);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const uint2 d2 = ptr[k];
+        rl.w[2 * k] = d2.x;
+        rl.w[2 * k + 1] = d2.y;
+    }
+}
+template <int D, int K>
+__device__ inline uint32_t row_link_word(const RowLinks& rl) {   // word K of slot D, from its owner lane
+    constexpr int lane = 2 * D + (K < 6 ? 0 : 1), slot = K < 6 ? K : K - 6;
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)rl.w[slot], 0x150 + lane, 0xf, 0xf, false);
+}
+template <int D>
+__device__ inline void row_link_get(const RowLinks& rl, uint32_t* u) {
+    u[0] = row_link_word<D, 0>(rl);
+    u[1] = row_link_word<D, 1>(rl);
+    u[2] = row_link_word<D, 2>(rl);
+    u[3] = row_link_word<D, 3>(rl);
+    u[4] = row_link_word<D, 4>(rl);
+    u[5] = row_link_word<D, 5>(rl);
+    u[6] = row_link_word<D, 6>(rl);
+    u[7] = row_link_word<D, 7>(rl);
+    u[8] = row_link_word<D, 8>(rl);
+}
+
 // Ordering fence for the accumulation: the accumulators pass through an
 // empty asm (so the arithmetic producing them cannot sink below it) that also
 // clobbers memory (so later loads cannot rise above it).  Emits no code.
@@ -164,12 +328,36 @@ __device__ inline void fence_acc(Cx<T>* acc) { fence_n<12>(acc); }
 // one direction: forward neighbour sf with its link at (lf, lfv), backward
 // neighbour sb with its link at (lb, lbv) (16-byte vector indices; the links
 // come from global memory or from the workgroup's LDS copy)
-template <typename S, int MU, bool DAG, int MIX>
+template <typename S, int MU, bool DAG, int MIX, bool ROWL = false>
 __device__ inline void hop_dir(const HopArgs& a, int sf, int sb, int r, bool phf, bool phb, const void* lf,
-                               int64_t lfv, const void* lb, int64_t lbv, Cx<typename Store<S>::acc>* acc) {
+                               int64_t lfv, const void* lb, int64_t lbv, Cx<typename Store<S>::acc>* acc,
+                               const RowLinks* rl = nullptr) {
     typedef typename Store<S>::acc T;
     const int64_t vstride = (int64_t)a.Vh << a.bshift;
     constexpr int SF = DAG ? -1 : 1;   // sign of the forward projector (1 - SF g)
+    if constexpr (std::is_same<S, bf16x2>::value) {
+        {
+            uint32_t psi[12], u[12];
+            Cx<float> w[6];
+            load_packed_spinor(a.in, ((int64_t)sf << a.bshift) + r, vstride, psi);
+            if constexpr (ROWL) row_link_get<2 * MU>(*rl, u);
+            else load_packed_link(lf, lfv, u);
+            link_mult_bf16<MU, SF, false>(psi, u, w);
+            reconstruct<MU, SF>(acc, w, phf ? -1.f : 1.f);
+        }
+        fence_acc(acc);
+        {
+            uint32_t psi[12], u[12];
+            Cx<float> w[6];
+            load_packed_spinor(a.in, ((int64_t)sb << a.bshift) + r, vstride, psi);
+            if constexpr (ROWL) row_link_get<2 * MU + 1>(*rl, u);
+            else load_packed_link(lb, lbv, u);
+            link_mult_bf16<MU, -SF, true>(psi, u, w);
+            reconstruct<MU, -SF>(acc, w, phb ? -1.f : 1.f);
+        }
+        fence_acc(acc);
+        return;
+    }
     {
         Cx<T> psi[12], h[6], u[9], w[6];
         load_operand<S, (MIX & HOP_IN16) != 0, false>(a.in, ((int64_t)sf << a.bshift) + r, vstride, psi);
@@ -351,7 +539,7 @@ __device__ inline void hop_block_reduce(const HopArgs& a, int blk, int g, Cx<dou
 
 // Site-parallel form: one lane per (site, RHS), RHS fastest.  With LDSL the
 // workgroup's ns = 256 / B sites take their links from LDS.
-template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, bool LDSL, int MIX>
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, bool LDSL, int MIX, bool ROWL = false>
 __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
     constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
@@ -390,8 +578,12 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
         Cx<T> acc[12];
 #pragma unroll
         for (int i = 0; i < 12; i++) acc[i] = cmake<T>(0, 0);
+        RowLinks rl;
+        if constexpr (ROWL) row_links_load(a.U, a.Vh, p, s, sn[1], sn[3], sn[5], sn[7], rl);
 #define DHT_DIR(MU, PHF, PHB)                                                                              \
-    if (LDSL)                                                                                            \
+    if (ROWL)                                                                                            \
+        hop_dir<S, MU, DAG, MIX, ROWL>(a, sn[2 * MU], sn[2 * MU + 1], r, PHF, PHB, nullptr, 0, nullptr, 0, acc, &rl); \
+    else if (LDSL)                                                                                       \
         hop_dir<S, MU, DAG, MIX>(a, sn[2 * MU], sn[2 * MU + 1], r, PHF, PHB, hop_lds,                         \
                             (int64_t)((2 * MU) * ns + sl) * NV, hop_lds, (int64_t)((2 * MU + 1) * ns + sl) * NV, acc); \
     else                                                                                                 \
@@ -436,17 +628,25 @@ __device__ inline void t_back(const HopArgs& a, int sin, int r, int64_t vstride,
                               Cx<typename Store<S>::acc>* wbs) {
     typedef typename Store<S>::acc T;
     constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
-    Cx<T> psi[12], h[6], u[9], wb[6];
-    load_operand<S, (MIX & HOP_IN16) != 0, false>(a.in, ((int64_t)sin << a.bshift) + r, vstride, psi);
-    project<3, SGN>(psi, h);
-    load_link<S>(a.U, ((int64_t)(6 + 1 - a.out_parity) * a.Vh + sin) * NV, u);
-    mul_link<true>(u, h, wb);
+    Cx<T> wb[6];
+    if constexpr (std::is_same<S, bf16x2>::value) {
+        uint32_t psi[12], u[12];
+        load_packed_spinor(a.in, ((int64_t)sin << a.bshift) + r, vstride, psi);
+        load_packed_link(a.U, ((int64_t)(6 + 1 - a.out_parity) * a.Vh + sin) * NV, u);
+        link_mult_bf16<3, SGN, true>(psi, u, wb);
+    } else {
+        Cx<T> psi[12], h[6], u[9];
+        load_operand<S, (MIX & HOP_IN16) != 0, false>(a.in, ((int64_t)sin << a.bshift) + r, vstride, psi);
+        project<3, SGN>(psi, h);
+        load_link<S>(a.U, ((int64_t)(6 + 1 - a.out_parity) * a.Vh + sin) * NV, u);
+        mul_link<true>(u, h, wb);
+    }
 #pragma unroll
     for (int i = 0; i < 6; i++) wb[i] = ph * wb[i];
     wb_store(wbs, wb);
 }
 
-template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, int MIX>
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, int MIX, bool ROWL = false>
 __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, int y, int z, int r, int V3, int yf,
                                int yb, int zf, int zb, Cx<typename Store<S>::acc>* wbs, Cx<double>& d0,
                                Cx<double>& d1) {
@@ -466,19 +666,36 @@ __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, 
 #pragma unroll
     for (int i = 0; i < 12; i++) acc[i] = cmake<T>(0, 0);
     const int sx = row + (xb >> 1), sy = s + yb, sz = s + zb;
-    hop_dir<S, 0, DAG, MIX>(a, row + (xf >> 1), sx, r, false, false, a.U, ((int64_t)p * a.Vh + s) * NV, a.U,
-                       ((int64_t)(1 - p) * a.Vh + sx) * NV, acc);
-    hop_dir<S, 1, DAG, MIX>(a, s + yf, sy, r, false, false, a.U, ((int64_t)(2 + p) * a.Vh + s) * NV, a.U,
-                       ((int64_t)(3 - p) * a.Vh + sy) * NV, acc);
-    hop_dir<S, 2, DAG, MIX>(a, s + zf, sz, r, false, false, a.U, ((int64_t)(4 + p) * a.Vh + s) * NV, a.U,
-                       ((int64_t)(5 - p) * a.Vh + sz) * NV, acc);
+    const int sn = (t + 1 == a.Lt ? 0 : t + 1) * V3 + s3;
+    RowLinks rl;
+    if constexpr (ROWL) row_links_load(a.U, a.Vh, p, s, sx, sy, sz, sn, rl);
+    hop_dir<S, 0, DAG, MIX, ROWL>(a, row + (xf >> 1), sx, r, false, false, a.U, ((int64_t)p * a.Vh + s) * NV, a.U,
+                       ((int64_t)(1 - p) * a.Vh + sx) * NV, acc, &rl);
+    hop_dir<S, 1, DAG, MIX, ROWL>(a, s + yf, sy, r, false, false, a.U, ((int64_t)(2 + p) * a.Vh + s) * NV, a.U,
+                       ((int64_t)(3 - p) * a.Vh + sy) * NV, acc, &rl);
+    hop_dir<S, 2, DAG, MIX, ROWL>(a, s + zf, sz, r, false, false, a.U, ((int64_t)(4 + p) * a.Vh + s) * NV, a.U,
+                       ((int64_t)(5 - p) * a.Vh + sz) * NV, acc, &rl);
     {
         Cx<T> wb[6];
         wb_load(wbs, wb);
         reconstruct<3, -SF>(acc, wb, T(1));
     }
-    {
-        const int sn = (t + 1 == a.Lt ? 0 : t + 1) * V3 + s3;
+    if constexpr (std::is_same<S, bf16x2>::value) {
+        uint32_t psi[12], u[12];
+        Cx<float> w[6];
+        load_packed_spinor(a.in, ((int64_t)sn << a.bshift) + r, vstride, psi);
+        if constexpr (ROWL) row_link_get<6>(rl, u);
+        else load_packed_link(a.U, ((int64_t)(6 + p) * a.Vh + s) * NV, u);
+        link_mult_bf16<3, SF, false>(psi, u, w);
+        reconstruct<3, SF>(acc, w, (a.antiperiodic && t == a.Lt - 1) ? -1.f : 1.f);
+        if (t + 2 < t1) {   // backward t-hop of step t + 2, from the same input spinor
+            fence_acc(acc);
+            if constexpr (ROWL) row_link_get<7>(rl, u);
+            else load_packed_link(a.U, ((int64_t)(6 + 1 - p) * a.Vh + sn) * NV, u);
+            link_mult_bf16<3, -SF, true>(psi, u, w);
+            wb_store(wbs, w);
+        }
+    } else {
         Cx<T> psi[12], h[6], u[9], w[6];
         load_operand<S, (MIX & HOP_IN16) != 0, false>(a.in, ((int64_t)sn << a.bshift) + r, vstride, psi);
         project<3, SF>(psi, h);
@@ -497,7 +714,7 @@ __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, 
     fence_acc(acc);   // the next step's loads stay below this step's arithmetic
 }
 
-template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, int MIX>
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, int MIX, bool ROWL = false>
 __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
     extern __shared__ uint4 hop_lds[];   // [2][6][HOP_THREADS] Cx<T>
@@ -530,8 +747,9 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
         t_back<S, -SF, MIX>(a, t0 * V3 + s3, r, vstride, T(1), wb1);
 #pragma nounroll
         for (int t = t0; t < t1; t += 2) {
-            tm_step<S, DAG, G5OUT, XPAY, DOT, MIX>(a, t, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb0, d0, d1);
-            tm_step<S, DAG, G5OUT, XPAY, DOT, MIX>(a, t + 1, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb1, d0, d1);
+            tm_step<S, DAG, G5OUT, XPAY, DOT, MIX, ROWL>(a, t, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb0, d0, d1);
+            tm_step<S, DAG, G5OUT, XPAY, DOT, MIX, ROWL>(a, t + 1, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb1, d0,
+                                                         d1);
         }
     }
     hop_block_reduce<NP>(a, blk, g, d0, d1);
@@ -557,13 +775,13 @@ static int auto_chunk(const dht_ctx* c, int nrhs) {
 
 int hop_config_check(const dht_ctx* c, int nrhs, const HopConfig& h) {
     if (log2_batch(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
-    if (h.form < DHT_HOP_SITE || h.form > DHT_HOP_TMARCH || (h.nt != 0 && h.nt != 1))
+    if (h.form < DHT_HOP_SITE || h.form > DHT_HOP_TMARCH_ROWL || (h.nt != 0 && h.nt != 1))
         return set_error(DHT_ERR_INVALID_ARG, "bad hop form");
     const int G = h.rg > 0 ? h.rg : nrhs;
     if (log2_batch(G) < 0 || G > nrhs) return set_error(DHT_ERR_INVALID_ARG, "RHS group must be a power of two <= nrhs");
     if (h.form == DHT_HOP_SITE_LDS && (HOP_THREADS / G) > 32)
         return set_error(DHT_ERR_INVALID_ARG, "LDS-link form needs at least 8 right-hand sides per sweep");
-    if (h.form == DHT_HOP_TMARCH && h.tc != 0 && (h.tc < 2 || (h.tc & 1) || c->g.L[3] % h.tc))
+    if (hop_form_tmarch(h.form) && h.tc != 0 && (h.tc < 2 || (h.tc & 1) || c->g.L[3] % h.tc))
         return set_error(DHT_ERR_INVALID_ARG, "t chunk must be even and divide Lt");
     return DHT_OK;
 }
@@ -637,7 +855,12 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     a.tc = cfg.tc;
     a.nchunk = a.Lt / cfg.tc;
     a.nt = cfg.nt;
-    const int mode = cfg.form;
+    // the row-shared forms need BF16 rows of one site (>= 16 RHS per sweep);
+    // otherwise they run as their plain form
+    const int G0 = cfg.rg > 0 ? cfg.rg : nrhs;
+    const bool rowl = std::is_same<S, bf16x2>::value && G0 >= 16 &&
+                      (cfg.form == DHT_HOP_SITE_ROWL || cfg.form == DHT_HOP_TMARCH_ROWL);
+    const int mode = hop_form_tmarch(cfg.form) ? DHT_HOP_TMARCH : (cfg.form == DHT_HOP_SITE_ROWL ? DHT_HOP_SITE : cfg.form);
     const int G = cfg.rg > 0 ? cfg.rg : nrhs;   // RHS per sweep
     a.gshift = log2_batch(G);
     if (a.gshift < 0 || G > nrhs) return set_error(DHT_ERR_INVALID_ARG, "bad RHS group");
@@ -653,6 +876,17 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     bool xp = x != nullptr;
 #define DHT_HOP_CASE_M(D_, G_, X_, K_, M_)                                                                   \
     if (dagger == D_ && g5out == G_ && xp == X_ && kind == K_ && mix == (M_)) {                              \
+        if constexpr (std::is_same<S, bf16x2>::value) {                                                      \
+            if (rowl) {                                                                                      \
+                if (mode == DHT_HOP_TMARCH)                                                                  \
+                    hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_, M_, true>), grid, block, tm_lds,    \
+                                       c->stream, a);                                                        \
+                else                                                                                         \
+                    hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_, false, M_, true>), grid, block, 0,     \
+                                       c->stream, a);                                                        \
+                goto launched;                                                                               \
+            }                                                                                                \
+        }                                                                                                    \
         if (mode == DHT_HOP_TMARCH)                                                                          \
             hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_, M_>), grid, block, tm_lds, c->stream, a);   \
         else if (mode == DHT_HOP_SITE_LDS)                                                                   \

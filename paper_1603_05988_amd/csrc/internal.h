@@ -232,6 +232,7 @@ struct ProfStat {
 
 // learned preconditioner weights (device)
 // hopping-kernel launch shape (dht_hop_config); form < 0: unset
+inline bool hop_form_tmarch(int form) { return form == DHT_HOP_TMARCH || form == DHT_HOP_TMARCH_ROWL; }
 struct HopConfig {
     int form = -1;
     int nt = 1;

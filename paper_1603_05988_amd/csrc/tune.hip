@@ -156,6 +156,17 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
                     h.tc = tc;
                     cand.push_back(h);
                 }
+            if (prec == DHT_BF16 && G >= 16) {   // links shared across each site's row of 16 lanes
+                h.tc = 0;
+                h.form = DHT_HOP_SITE_ROWL;
+                cand.push_back(h);
+                h.form = DHT_HOP_TMARCH_ROWL;
+                for (int tc = 2; tc <= c->g.L[3]; tc += 2)
+                    if (c->g.L[3] % tc == 0) {
+                        h.tc = tc;
+                        cand.push_back(h);
+                    }
+            }
         }
     int rejected = 0;
     double worst_ok = 0.0;
@@ -190,11 +201,11 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
             }
         }
         c->hop_force = false;
-        if (best.form == DHT_HOP_TMARCH && best.tc == 0) best.tc = hop_config(c, prec, nrhs, cls).tc;
+        if (hop_form_tmarch(best.form) && best.tc == 0) best.tc = hop_config(c, prec, nrhs, cls).tc;
         c->hop_cfg[prec][b][cls] = best;
         res->best[cls].form = best.form;
         res->best[cls].streaming_stores = best.nt;
-        res->best[cls].t_chunk = best.form == DHT_HOP_TMARCH ? best.tc : 0;
+        res->best[cls].t_chunk = hop_form_tmarch(best.form) ? best.tc : 0;
         res->best[cls].rhs_group = best.rg > 0 ? best.rg : nrhs;
         res->best_ms[cls] = best_ms;
         res->default_ms[cls] = def_ms;
@@ -224,7 +235,7 @@ int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, int epilogue, const dht_h
     HopConfig h;
     h.form = cfg->form;
     h.nt = cfg->streaming_stores;
-    h.tc = cfg->form == DHT_HOP_TMARCH ? cfg->t_chunk : 0;
+    h.tc = hop_form_tmarch(cfg->form) ? cfg->t_chunk : 0;
     h.rg = cfg->rhs_group == nrhs ? 0 : cfg->rhs_group;
     DHT_TRY(hop_config_check(c, nrhs, h));
     c->hop_cfg[prec][b][epilogue] = h;
@@ -239,7 +250,7 @@ int dht_hop_config_get(dht_ctx* c, int prec, int nrhs, int epilogue, dht_hop_con
     HopConfig h = hop_config(c, prec, nrhs, epilogue);
     out->form = h.form;
     out->streaming_stores = h.nt;
-    out->t_chunk = h.form == DHT_HOP_TMARCH ? h.tc : 0;
+    out->t_chunk = hop_form_tmarch(h.form) ? h.tc : 0;
     out->rhs_group = h.rg > 0 ? h.rg : nrhs;
     return DHT_OK;
 }

@@ -1,8 +1,9 @@
 """Every launch shape of the hopping kernel against the dense oracle, and the
 autotuner that chooses among them.
 
-The forms (one lane per site with links per lane or staged in LDS; one lane
-per (x, y, z) column walking t in chunks, with or without streaming stores,
+The forms (one lane per site with links per lane, staged in LDS or shared
+across the 16-lane row of a site; one lane per (x, y, z) column walking t in
+chunks, with links per lane or row-shared, with or without streaming stores,
 sweeping the lattice once for all right-hand sides or once per group of them)
 accumulate the same 8 neighbour terms in different orders, so each must match
 the dense Wilson matrix to the storage precision: FP64 1e-13 relative
@@ -33,7 +34,7 @@ def cuda(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def forms(L, nrhs):
+def forms(L, nrhs, rowl=True):
     out = []
     for G in sorted({nrhs, max(1, nrhs // 2), max(1, nrhs // 4)}, reverse=True):
         for nt in (0, 1):
@@ -43,6 +44,11 @@ def forms(L, nrhs):
             for tc in range(2, L[3] + 1, 2):
                 if L[3] % tc == 0:
                     out.append({"form": 2, "streaming_stores": nt, "t_chunk": tc, "rhs_group": G})
+            if G >= 16 and rowl:   # links shared across the 16-lane row of a site (BF16; plain forms otherwise)
+                out.append({"form": 3, "streaming_stores": nt, "t_chunk": 0, "rhs_group": G})
+                for tc in range(2, L[3] + 1, 2):
+                    if L[3] % tc == 0:
+                        out.append({"form": 4, "streaming_stores": nt, "t_chunk": tc, "rhs_group": G})
     return out
 
 
@@ -76,7 +82,7 @@ def test_every_form_matches_dense(L, nrhs):
                 got = ctx.hop_config(prec, nrhs, cls)
                 assert got["form"] == cfg["form"] and got["streaming_stores"] == cfg["streaming_stores"]
                 assert got["rhs_group"] == cfg["rhs_group"]
-                if cfg["form"] == 2:
+                if cfg["form"] in (2, 4):
                     assert got["t_chunk"] == cfg["t_chunk"]
             for op, ref in refs.items():
                 Y = ctx.apply(cuda(X), op, prec).cpu().numpy().reshape(nrhs, -1)
@@ -151,7 +157,7 @@ def test_autotune_c2(tmp_path):
     for prec in (0, 1, 2):
         r = ctx.autotune_hop(prec, 16, reps=3)
         res[prec] = r
-        assert r["rejected"] == 0 and r["candidates"] == len(forms(w.L, 16)), r
+        assert r["rejected"] == 0 and r["candidates"] == len(forms(w.L, 16, rowl=prec == 2)), r
         assert r["max_rel_diff"] <= {0: 1e-12, 1: 1e-5, 2: 1.6e-2}[prec], r
         for cls, name in Lb.HOP_CLASSES.items():
             assert 0 < r["best_ms"][name] <= r["default_ms"][name] * (1 + 1e-9), r
