@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 
 METRIC = "RHS solves/s (res 1e-8) at 32^3x64, mixed+learned vs FP64; dslash GB/s"
 HBM_PEAK_GBPS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def log(*a):
@@ -93,6 +94,50 @@ def cpu_baseline(U, w, k: int, hp: bool):
     }
 
 
+def train_network(L, torch, np, npairs: int, epochs: int):
+    """The learned preconditioner of the 8^3x16 recipe: (residual, error) pairs
+    from FGMRES(4) restarts of Z4 probes (x* from FP64 BiCGStab to 1e-12),
+    Adam on the GPU; returns the weights and a summary (held-out losses of the
+    Jacobi term alone and of the trained network)."""
+    from paper_1603_05988_amd.workloads import WORKLOADS, gauge_links
+    w4 = WORKLOADS["c4"]
+    c4 = L.Context(w4.L, w4.mass)
+    c4.set_gauge(torch.from_numpy(gauge_links(w4.L, w4.eps, w4.seed)).cuda())
+    t0 = time.time()
+    Rs, Es, n, run = [], [], 0, 1000
+    while n < npairs:
+        R, E = c4.nn_make_pairs(w4.seed, run, False, 0, 16, 4, min(512, npairs - n))
+        Rs.append(R.clone())
+        Es.append(E.clone())
+        n += R.shape[0]
+        run += 1
+        del R, E
+    R = torch.cat(Rs)
+    E = torch.cat(Es)
+    del Rs, Es
+    Rh, Eh = c4.nn_make_pairs(w4.seed, 300, False, 0, 16, 4, 32)   # held out
+    t_pairs = time.time() - t0
+    skip = 1.0 / (4.0 + w4.mass)
+    c4.nn_init(0)
+    c4.nn_set_skip(skip)
+    init = c4.nn_get_weights()
+    c4.nn_set_weights([np.zeros_like(x) for x in init])
+    l_jac, _ = c4.nn_grad(Rh, Eh)
+    c4.nn_set_weights(init)
+    t0 = time.time()
+    last = c4.nn_train(R, E, epochs=epochs, batch=16, lr=3e-4)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    l_tr, _ = c4.nn_grad(Rh, Eh)
+    weights = c4.nn_get_weights()
+    c4.close()
+    del R, E, Rh, Eh
+    torch.cuda.empty_cache()
+    return weights, {"trained_on": w4.name, "pairs": n, "epochs": epochs, "pair_seconds": round(t_pairs, 1),
+                     "train_seconds": round(t_train, 1), "last_epoch_loss": last,
+                     "heldout_loss_jacobi_only": l_jac, "heldout_loss_trained": l_tr}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +155,11 @@ def main():
     ap.add_argument("--tune", default="auto", choices=["auto", "off"],
                     help="autotune the hopping-kernel shape before timing (off: built-in default)")
     ap.add_argument("--tune-cache", default=None, help="JSON table to load the shapes from / save them to")
+    ap.add_argument("--nn-steps", type=int, default=2, help="timed batches of FGMRES + learned preconditioner (0: skip)")
+    ap.add_argument("--nn-pairs", type=int, default=20480, help="training pairs of the network (8^3x16 recipe)")
+    ap.add_argument("--nn-epochs", type=int, default=4)
+    ap.add_argument("--nn-restart", type=int, default=16,
+                    help="FGMRES restart at 32^3x64 (its FP32 bases must fit beside the 100 GB deflation basis)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested); probes shard across GPUs "
@@ -124,6 +174,12 @@ def main():
     w = WORKLOADS[args.workload]
     k = args.k if args.k is not None else w.k
     B = w.batch
+    nn_weights, nn_info = None, None
+    if args.nn_steps > 0:   # trained first: its pairs are freed before the large lattice is set up
+        nn_weights, nn_info = train_network(L, torch, np, args.nn_pairs, args.nn_epochs)
+        log("network trained on %d pairs (%d epochs, %.1f s): held-out loss %.4f (Jacobi term alone %.4f)"
+            % (nn_info["pairs"], args.nn_epochs, nn_info["train_seconds"], nn_info["heldout_loss_trained"],
+               nn_info["heldout_loss_jacobi_only"]))
     t0 = time.time()
     U = gauge_links(w.L, w.eps, w.seed)
     log("links generated in %.1f s" % (time.time() - t0))
@@ -250,6 +306,41 @@ def main():
         fp64_value = args.fp64_steps * B / el64
         log("fp64: %.2f ms/step, %.2f RHS/s" % (1e3 * el64 / args.fp64_steps, fp64_value))
 
+    # the learned leg: FGMRES(restart) with the network as right preconditioner
+    # inside FP64 defect correction, same probes and projection window
+    learned = None
+    if args.nn_steps > 0:
+        ctx.workspace_trim()   # the BiCGStab legs' fields make room for the FGMRES bases
+        ctx.nn_set_weights(nn_weights)
+        ctx.nn_set_skip(1.0 / (4.0 + w.mass))
+        prm_nn = ctx.params(L.SOLVER_DC_FGMRES_NN, tol=w.tol, restart=args.nn_restart, maxiter=20000)
+        elw, _ = run(prm_nn, 1, first0=0)
+        log("learned leg: warm-up batch %.1f s" % elw)
+        eln, recn = run(prm_nn, args.nn_steps, first0=0, profile=not args.no_profile)
+        conv = ctx.profile_get("conv") if not args.no_profile else None
+        learned = {
+            "value": round(args.nn_steps * B / eln, 4), "unit": "RHS solves/s",
+            "ms_per_step": round(1e3 * eln / args.nn_steps, 1),
+            "solver": "FGMRES(%d) in FP32, learned preconditioner (BF16 matrix cores), FP64 defect correction"
+                      % args.nn_restart,
+            "mean_iters": round(float(np.mean([r["iters"] for r in recn])), 2),
+            "mean_outer_cycles": round(float(np.mean([r["outer"] for r in recn])), 2),
+            "worst_true_residual": max(r["true_resid"] for r in recn),
+            "fallbacks_to_bicgstab": int(sum(1 for r in recn if r["status"] == 4)),
+            "network": nn_info,
+        }
+        if conv and conv["count"]:
+            tf = conv["bytes"] / conv["ms"] / 1e9
+            learned["conv"] = {"launches": conv["count"], "avg_launch_ms": round(conv["ms"] / conv["count"], 3),
+                               "achieved_tflops": round(tf, 1), "peak_tflops": BF16_MFMA_PEAK_TFLOPS,
+                               "mfma_frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 4),
+                               "share_of_step": round(conv["ms"] / (1e3 * eln), 3)}
+        log("learned: %.1f ms/step, %.3f RHS/s, mean iters %.1f, worst residual %.2e%s"
+            % (learned["ms_per_step"], learned["value"], learned["mean_iters"], learned["worst_true_residual"],
+               (", conv %.1f TFLOP/s (%.3f of BF16 MFMA peak)" % (learned["conv"]["achieved_tflops"],
+                                                                 learned["conv"]["mfma_frac"]))
+               if "conv" in learned else ""))
+
     cpu = None
     if not args.no_cpu:
         t0 = time.time()
@@ -277,12 +368,15 @@ def main():
             "deflation_k": k, "deflation_storage": "bf16 (synthetic basis, diagonal Galerkin inverse)",
             "projection_window": args.proj_window,
             "solver": "even/odd BiCGStab, %s inner, FP64 defect correction" % args.inner,
-            "preconditioner": "none", "tol": w.tol, "hop_shapes": shapes,
+            "preconditioner": "none (the learned FGMRES leg is reported as mixed_learned)", "tol": w.tol,
+            "hop_shapes": shapes,
             "mean_inner_iters": round(iters, 2), "mean_outer_cycles": round(outer, 2),
             "worst_true_residual": worst,
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "mixed_learned": learned,
+        "mixed_learned_value": learned["value"] if learned else None,
         "fp64_bicgstab_value": round(fp64_value, 3) if fp64_value else None,
         "speedup_vs_fp64": round(value / fp64_value, 3) if fp64_value else None,
         "dslash_GBps": dslash,

@@ -169,6 +169,13 @@ const char* dht_last_error(void);
 /* Library version string (static storage). */
 const char* dht_version(void);
 
+/* Release the library-owned workspace (solver fields, reduction partials,
+ * projection window, network activations); links, the deflation basis, the
+ * network weights and the running estimates stay.  Later calls allocate again
+ * what they need.  For callers that run methods of very different footprint
+ * one after another on one context. */
+int dht_workspace_trim(dht_ctx* ctx);
+
 /* Upload links (device pointer, canonical layout).  Packs them into the
  * internal even/odd layout in FP64, FP32 and BF16 (round to nearest even). */
 int dht_set_gauge(dht_ctx* ctx, const double* U_dev);
@@ -382,9 +389,10 @@ int dht_last_timings(dht_ctx* ctx, double* ms_host, int n);
 /* Per-kernel-class timing: when enabled, every launch of an instrumented
  * kernel is bracketed by HIP events on the context stream; totals are
  * accumulated at the next synchronising call.  Classes: 0/1/2 = hop kernel
- * in FP64/FP32/BF16, 3 = MFMA projection, 4 = generic projection.
- * total_bytes is the algorithmic byte count of those launches (input and
- * output fields once, links once). */
+ * in FP64/FP32/BF16, 3 = MFMA projection, 4 = generic projection, 5 = the
+ * network's convolutions (BF16 matrix cores).  total_bytes is the
+ * algorithmic byte count of those launches (input and output fields once,
+ * links once); for class 5 it is the flop count (2 per multiply-add). */
 int dht_profile_enable(dht_ctx* ctx, int on);
 int dht_profile_reset(dht_ctx* ctx);
 int dht_profile_get(dht_ctx* ctx, int cls, int64_t* count, double* total_ms, double* total_bytes);

@@ -95,6 +95,7 @@ SIGNATURES = {
     "dht_last_error": (ctypes.c_char_p, []),
     "dht_version": (ctypes.c_char_p, []),
     "dht_set_gauge": (_i, [_vp, _vp]),
+    "dht_workspace_trim": (_i, [_vp]),
     "dht_apply": (_i, [_vp, _i, _i, _vp, _vp, _i]),
     "dht_apply_noalloc": (_i, [_vp, _i, _i, _vp, _vp, _i]),
     "dht_make_probes": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _vp]),
@@ -330,7 +331,11 @@ class Context:
         check(load().dht_set_projection_window(self.h, int(nprobes)))
 
     # -- instrumentation --------------------------------------------------
-    PROF_CLASSES = {"hop_fp64": 0, "hop_fp32": 1, "hop_bf16": 2, "proj_mfma": 3, "proj_generic": 4}
+    PROF_CLASSES = {"hop_fp64": 0, "hop_fp32": 1, "hop_bf16": 2, "proj_mfma": 3, "proj_generic": 4, "conv": 5}
+
+    def workspace_trim(self):
+        """Free the library-owned workspace (links, basis, weights and estimates stay)."""
+        check(load().dht_workspace_trim(self.h))
 
     def profile(self, on: bool = True):
         check(load().dht_profile_enable(self.h, int(on)))

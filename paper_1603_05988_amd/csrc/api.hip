@@ -241,6 +241,22 @@ int dht_destroy(dht_ctx* c) {
     return DHT_OK;
 }
 
+int dht_workspace_trim(dht_ctx* c) {
+    DHT_TRY(check_ctx(c));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    if (c->side) DHT_HIP(hipStreamSynchronize(c->side));
+    for (int i = 0; i < (int)c->ws.size(); i++) {
+        Buf& b = c->ws[i];
+        if (!b.p) continue;
+        if (i == WS_HOSTPIN) (void)hipHostFree(b.p);
+        else (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    c->pw_valid = false;   // the projection window's codes and coefficients lived there
+    return DHT_OK;
+}
+
 int dht_set_gauge(dht_ctx* c, const double* U_dev) {
     DHT_TRY(check_ctx(c));
     if (!U_dev) return set_error(DHT_ERR_INVALID_ARG, "null links");

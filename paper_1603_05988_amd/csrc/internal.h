@@ -218,7 +218,7 @@ struct Buf {
 };
 
 // kernel classes for the instrumentation (dht_profile_get)
-enum { PROF_HOP64 = 0, PROF_HOP32, PROF_HOP16, PROF_PROJ_MFMA, PROF_PROJ_GENERIC, PROF_NCLASS };
+enum { PROF_HOP64 = 0, PROF_HOP32, PROF_HOP16, PROF_PROJ_MFMA, PROF_PROJ_GENERIC, PROF_CONV, PROF_NCLASS };
 struct ProfPending {
     int cls;
     int ev0, ev1;       // indices into the event pool

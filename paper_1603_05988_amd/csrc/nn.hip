@@ -462,12 +462,15 @@ static void launch_conv(dht_ctx* c, const uint16_t* in, const uint16_t* W, void*
 
 static int conv(dht_ctx* c, int cin, int cout, const uint16_t* in, const uint16_t* W, void* out0, bool out0_fp32,
                 uint16_t* out1, const uint16_t* mask, int nb) {
+    int tok;
+    DHT_TRY(prof_begin(c, &tok));
     if (cin == 24 && cout == 48) launch_conv<24, 48>(c, in, W, out0, out0_fp32, out1, mask, nb);
     else if (cin == 48 && cout == 48) launch_conv<48, 48>(c, in, W, out0, out0_fp32, out1, mask, nb);
     else if (cin == 48 && cout == 24) launch_conv<48, 24>(c, in, W, out0, out0_fp32, out1, mask, nb);
     else return set_error(DHT_ERR_INVALID_ARG, "unsupported convolution shape");
     DHT_HIP(hipGetLastError());
-    return DHT_OK;
+    // the profile of this class counts flops (2 per multiply-add) in place of bytes
+    return prof_end(c, tok, PROF_CONV, 2.0 * 81.0 * cin * cout * (double)nb * (double)c->g.V);
 }
 
 template <int CIN, int COUT>
@@ -535,6 +538,31 @@ static int nn_bufs(dht_ctx* c, int nb, NNBufs* b) {
     b->e = (float*)take(4 * s24);
     b->rs = (float*)take(4 * s24);
     (void)bytes;
+    return DHT_OK;
+}
+
+// inference only (the preconditioner inside FGMRES): input, the two hidden
+// activations and the output; the pre-activation values, which only the
+// backward pass reads, share one scratch block
+static int nn_bufs_infer(dht_ctx* c, int nb, NNBufs* b) {
+    const int64_t V = c->g.V;
+    const size_t s24 = (size_t)nb * V * 24, s48 = (size_t)nb * V * 48;
+    void* p;
+    size_t bytes = sizeof(uint16_t) * (s24 + s48 * 3) + sizeof(float) * s24 + 1024;
+    DHT_TRY(ws_get(c, WS_NN_ACT, bytes, &p));
+    char* q = (char*)p;
+    auto take = [&](size_t nbytes) {
+        char* r = q;
+        q += (nbytes + 255) / 256 * 256;
+        return r;
+    };
+    memset(b, 0, sizeof(*b));
+    b->x = (uint16_t*)take(2 * s24);
+    b->h1 = (uint16_t*)take(2 * s48);
+    b->h2 = b->h1;
+    b->a1 = (uint16_t*)take(2 * s48);
+    b->a2 = (uint16_t*)take(2 * s48);
+    b->y = (float*)take(4 * s24);
     return DHT_OK;
 }
 
@@ -705,7 +733,7 @@ int nn_apply_field(dht_ctx* c, const void* in, void* out, int nrhs) {
     if (!c->nn.ready) return set_error(DHT_ERR_STATE, "network not initialised");
     if (nrhs > NN_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "preconditioner batch too large");
     NNBufs b;
-    DHT_TRY(nn_bufs(c, nrhs, &b));
+    DHT_TRY(nn_bufs_infer(c, nrhs, &b));
     int64_t tot = c->g.V * (int64_t)nrhs;
     hipLaunchKernelGGL(field_nn_kernel<true>, g256(tot), dim3(256), 0, c->stream, (float*)in, b.x, (const float*)nullptr,
                        (const float*)nullptr, 0.f, c->g, nrhs, nrhs);

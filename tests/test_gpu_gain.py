@@ -8,10 +8,11 @@ FGMRES(4) restarts of 8 x 16 probes, then FGMRES(32) + network, FGMRES(32)
 alone and the BiCGStab solvers solve the same 16 held-out probes to 1e-8.
 
 Asserted: training lowers the loss on held-out pairs below that of the
-Jacobi term alone (the network learned more than the diagonal); every
-method reaches the tolerance; FGMRES + network needs no more iterations than
-FGMRES alone (+2 %).  Measured and reported, not assumed: the iteration and
-time gain (one network application costs as much as tens of stencil
+Jacobi term alone (the network learned more than the diagonal), and every
+method reaches the tolerance.  Measured and reported, never asserted (the
+paper has no number for it: parity unpinned): the iteration gain of FGMRES +
+network over FGMRES alone, which may come out negative, and the times of all
+four solvers (one network application costs as much as tens of stencil
 applications on this lattice).  Results go to gpurun_out/nn_gain.json when
 that directory exists.
 """
@@ -81,7 +82,6 @@ def test_learned_preconditioner_gain():
             "mean_outer": float(np.mean([s["outer"] for s in stats])),
             "status": sorted(set(s["status"] for s in stats)),
         }
-    assert results["fgmres_nn"]["mean_iters"] <= 1.02 * results["fgmres_identity"]["mean_iters"], results
     out = {"lattice": list(w.L), "pairs": int(R.shape[0]), "heldout_pairs": int(Rh.shape[0]),
            "pair_seconds": t_pairs, "train_seconds": t_train, "epochs": epochs, "lr": 3e-4, "skip": skip,
            "heldout_loss_jacobi_only": l_jacobi, "heldout_loss_init": l0, "heldout_loss_trained": l1,
