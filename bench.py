@@ -207,6 +207,9 @@ def main():
 
     inner = L.FP32 if args.inner == "fp32" else L.BF16
     prm = ctx.params(L.SOLVER_DC_BICGSTAB, inner=inner, tol=w.tol, maxiter=5000, inner_tol=args.inner_tol)
+    ctx.set_projection_window(args.proj_window)
+    ws_bytes = ctx.workspace_size(B, prm)   # the caller-owned workspace this configuration would need
+    log("workspace plan for batches of %d: %.2f GB" % (B, ws_bytes / 1e9))
 
     # launch shapes of the hopping kernel for the inner and the FP64 outer
     # precision (and FP32, which updates the late residuals of BF16 solves)
@@ -370,6 +373,7 @@ def main():
             "solver": "even/odd BiCGStab, %s inner, FP64 defect correction" % args.inner,
             "preconditioner": "none (the learned FGMRES leg is reported as mixed_learned)", "tol": w.tol,
             "hop_shapes": shapes,
+            "workspace_bytes": ws_bytes,
             "mean_inner_iters": round(iters, 2), "mean_outer_cycles": round(outer, 2),
             "worst_true_residual": worst,
         },

@@ -24,9 +24,11 @@
  *  - Pointers named *_dev are device pointers on the context's device; all
  *    other pointers are host pointers.  The caller owns every buffer it
  *    passes; the library never frees caller memory and keeps no pointer to it
- *    after the call returns.  The library owns its internal copies (links in
- *    three precisions, the deflation basis, solver workspace), allocated with
- *    hipMalloc on first use and released by dht_destroy.
+ *    after the call returns (except a workspace handed over with
+ *    dht_set_workspace).  The library owns its internal copies (links in
+ *    three precisions, the deflation basis) and, unless the caller provides
+ *    one, its workspace, allocated with hipMalloc on first use and released by
+ *    dht_destroy or dht_workspace_trim.
  *  - Streams: all device work is enqueued on the stream given to dht_create,
  *    except dht_trace_batch's per-batch projection, which runs on a second
  *    stream of the library's own (default priority) after the probes are made
@@ -168,6 +170,27 @@ int dht_destroy(dht_ctx* ctx);
 const char* dht_last_error(void);
 /* Library version string (static storage). */
 const char* dht_version(void);
+
+/* Caller-owned workspace.  dht_workspace_size plans the device scratch of
+ * dht_trace_batch and dht_solve for batches of up to max_nrhs right-hand
+ * sides with the parameters prm (its method, inner precision and history,
+ * with every precision fallback they can reach), the current deflation basis
+ * and projection window, and returns the bytes needed.  dht_set_workspace then
+ * hands over a device buffer of at least that size (256-byte aligned, e.g. a
+ * torch.empty uint8 tensor; the caller keeps it alive and owns it): those
+ * calls take all their device scratch from it and allocate none -- a request
+ * beyond the plan (a larger batch, another method, a basis or window changed
+ * afterwards) fails with DHT_ERR_OOM instead.  Other calls (dht_apply,
+ * dht_project*, the eigensolver, the autotuner, the network's training) use
+ * the buffer where the plan covers their request and library workspace
+ * otherwise.  The library-owned device workspace is released when the buffer
+ * is set; ptr = NULL returns to library-owned workspace.  A small pinned host
+ * buffer of the solver's per-RHS states stays library-owned.  The buffer is
+ * scratch except for the projection window's probe codes and coefficients,
+ * which later batches of the window read: the caller must leave it untouched
+ * while it is set. */
+int dht_workspace_size(dht_ctx* ctx, int max_nrhs, const dht_solver_params* prm, size_t* bytes);
+int dht_set_workspace(dht_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Release the library-owned workspace (solver fields, reduction partials,
  * projection window, network activations); links, the deflation basis, the

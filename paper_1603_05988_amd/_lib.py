@@ -96,6 +96,8 @@ SIGNATURES = {
     "dht_version": (ctypes.c_char_p, []),
     "dht_set_gauge": (_i, [_vp, _vp]),
     "dht_workspace_trim": (_i, [_vp]),
+    "dht_workspace_size": (_i, [_vp, _i, ctypes.POINTER(SolverParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "dht_set_workspace": (_i, [_vp, _vp, ctypes.c_size_t]),
     "dht_apply": (_i, [_vp, _i, _i, _vp, _vp, _i]),
     "dht_apply_noalloc": (_i, [_vp, _i, _i, _vp, _vp, _i]),
     "dht_make_probes": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, _vp]),
@@ -332,6 +334,24 @@ class Context:
 
     # -- instrumentation --------------------------------------------------
     PROF_CLASSES = {"hop_fp64": 0, "hop_fp32": 1, "hop_bf16": 2, "proj_mfma": 3, "proj_generic": 4, "conv": 5}
+
+    def workspace_size(self, max_nrhs: int, prm: SolverParams) -> int:
+        """Device bytes that trace_batch / solve need for batches up to max_nrhs with prm."""
+        n = ctypes.c_size_t(0)
+        check(load().dht_workspace_size(self.h, int(max_nrhs), ctypes.byref(prm), ctypes.byref(n)))
+        return n.value
+
+    def set_workspace(self, buf):
+        """Hand over a caller-owned device buffer (a uint8 CUDA tensor of at least
+        workspace_size bytes; kept referenced here), or None for library workspace."""
+        if buf is None:
+            check(load().dht_set_workspace(self.h, None, 0))
+            self._workspace = None
+            return
+        if not buf.is_cuda or not buf.is_contiguous():
+            raise ValueError("expected a contiguous CUDA tensor")
+        check(load().dht_set_workspace(self.h, _vp(_ptr(buf)), buf.numel() * buf.element_size()))
+        self._workspace = buf
 
     def workspace_trim(self):
         """Free the library-owned workspace (links, basis, weights and estimates stay)."""

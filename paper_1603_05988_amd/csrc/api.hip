@@ -53,6 +53,19 @@ int set_error(int code, const std::string& msg) {
 
 int ws_get(dht_ctx* c, int slot, size_t bytes, void** out) {
     if (slot < 0 || slot >= WS_NSLOTS) return set_error(DHT_ERR_INVALID_ARG, "bad workspace slot");
+    // caller-owned workspace: the planned slots live at fixed offsets of the
+    // caller's buffer; inside a planned call nothing else may be allocated
+    if (c->arena && slot != WS_HOSTPIN) {
+        if (c->plan[slot] > 0 && bytes <= c->plan[slot]) {
+            *out = c->arena + c->plan_off[slot];
+            return DHT_OK;
+        }
+        if (c->planned_call > 0)
+            return set_error(DHT_ERR_OOM, "caller workspace: slot " + std::to_string(slot) + " needs " +
+                                              std::to_string(bytes) + " bytes, the plan holds " +
+                                              std::to_string(c->plan[slot]) +
+                                              " (size the workspace for this batch and these parameters)");
+    }
     Buf& b = c->ws[slot];
     if (b.bytes < bytes) {
         if (b.p) {
@@ -137,6 +150,37 @@ int prof_harvest(dht_ctx* c) {
 }
 
 static bool valid_prec(int p) { return p == DHT_FP64 || p == DHT_FP32 || p == DHT_BF16; }
+
+// a call whose workspace the caller's plan covers (see ws_get)
+struct PlannedCall {
+    dht_ctx* c;
+    explicit PlannedCall(dht_ctx* cc) : c(cc) { c->planned_call++; }
+    ~PlannedCall() { c->planned_call--; }
+};
+
+// workspace of dht_trace_batch for a padded batch bp (see its ws_get calls)
+static void ws_plan_trace(const dht_ctx* c, const dht_solver_params* prm, int bp, size_t* plan) {
+    const size_t fb = full_elems(c, bp) * 16;
+    plan_max(plan, WS_Z, fb);
+    plan_max(plan, WS_PACK_OUT, fb);
+    const int k = c->defl_ready ? c->k : 0;
+    const bool mfma = k > 0 && c->wprec == DHT_BF16 && bp <= 64;
+    plan_max(plan, WS_COEF, sizeof(Cx<double>) * (2 * (size_t)k * bp + bp) + 64);
+    if (mfma) {
+        plan_max(plan, WS_ZCODE, full_elems(c, bp));
+        ws_plan_project_codes(c, bp, plan);
+        if (c->proj_window > 0) {   // a window of more probes than the batch
+            const int wpad = pad_rhs(c->proj_window);
+            plan_max(plan, WS_PW_CODE, full_elems(c, wpad));
+            plan_max(plan, WS_PW_COEF, sizeof(Cx<double>) * 2 * (size_t)k * wpad);
+            ws_plan_project_codes(c, wpad, plan);
+        }
+    } else if (k > 0) {
+        ws_plan_project_field(c, bp, plan);
+    }
+    ws_plan_dots(c, bp, plan);   // q = z^H x of the methods that do not fuse it
+    ws_plan_solve(c, prm, bp, plan);
+}
 
 // device coefficients [k][bp] -> host [k][n] (first n columns), after a sync
 static int copy_coefs(dht_ctx* c, const Cx<double>* d1, const Cx<double>* d2, int bp, int n, double* c1h, double* c2h) {
@@ -257,6 +301,62 @@ int dht_workspace_trim(dht_ctx* c) {
     return DHT_OK;
 }
 
+int dht_workspace_size(dht_ctx* c, int max_nrhs, const dht_solver_params* prm, size_t* bytes) {
+    DHT_TRY(check_ctx(c));
+    if (!prm || !bytes || max_nrhs <= 0 || max_nrhs > DHT_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (c->W && !c->defl_ready) return set_error(DHT_ERR_STATE, "deflation basis set but not finalized");
+    std::vector<size_t> plan(WS_NSLOTS, 0);
+    for (int bp = 1; bp <= pad_rhs(max_nrhs); bp <<= 1) {   // every padded batch up to max_nrhs
+        ws_plan_trace(c, prm, bp, plan.data());
+        const size_t fb = full_elems(c, bp) * 16;   // dht_solve's packed fields
+        plan_max(plan.data(), WS_PACK_IN, fb);
+        plan_max(plan.data(), WS_PACK_OUT, fb);
+    }
+    plan[WS_HOSTPIN] = 0;   // a small pinned host buffer, not device workspace
+    size_t total = 0;
+    for (int s = 0; s < WS_NSLOTS; s++) total += (plan[s] + 255) / 256 * 256;
+    c->plan_next = plan;
+    c->plan_next_total = total;
+    *bytes = total;
+    return DHT_OK;
+}
+
+int dht_set_workspace(dht_ctx* c, void* ptr, size_t bytes) {
+    DHT_TRY(check_ctx(c));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    if (c->side) DHT_HIP(hipStreamSynchronize(c->side));
+    c->pw_valid = false;   // the projection window's codes and coefficients move
+    if (!ptr) {            // back to library-owned workspace
+        c->arena = nullptr;
+        c->arena_bytes = 0;
+        c->plan.clear();
+        c->plan_off.clear();
+        return DHT_OK;
+    }
+    if (c->plan_next.empty()) return set_error(DHT_ERR_STATE, "call dht_workspace_size first");
+    if (((uintptr_t)ptr & 255) != 0) return set_error(DHT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (bytes < c->plan_next_total)
+        return set_error(DHT_ERR_INVALID_ARG, "workspace of " + std::to_string(bytes) + " bytes is smaller than the " +
+                                                  std::to_string(c->plan_next_total) + " bytes planned");
+    c->plan = c->plan_next;
+    c->plan_off.assign(WS_NSLOTS, 0);
+    size_t off = 0;
+    for (int s = 0; s < WS_NSLOTS; s++) {
+        c->plan_off[s] = off;
+        off += (c->plan[s] + 255) / 256 * 256;
+    }
+    c->arena = (char*)ptr;
+    c->arena_bytes = bytes;
+    for (int i = 0; i < (int)c->ws.size(); i++) {   // library-owned device slots are no longer needed
+        Buf& b = c->ws[i];
+        if (!b.p || i == WS_HOSTPIN) continue;
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    return DHT_OK;
+}
+
 int dht_set_gauge(dht_ctx* c, const double* U_dev) {
     DHT_TRY(check_ctx(c));
     if (!U_dev) return set_error(DHT_ERR_INVALID_ARG, "null links");
@@ -353,6 +453,7 @@ int dht_probe_indices(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int
 
 int dht_solve(dht_ctx* c, const dht_solver_params* prm, const double* Z, double* X, int nrhs, dht_solve_stats* stats) {
     DHT_TRY(check_ctx(c));
+    PlannedCall pc(c);
     if (!prm || !Z || !X || nrhs <= 0 || nrhs > DHT_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     const int bp = pad_rhs(nrhs);
@@ -548,6 +649,7 @@ int dht_set_projection_window(dht_ctx* c, int nprobes) {
 int dht_trace_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first, int nrhs, const dht_solver_params* prm,
                     dht_record* records, double* coef_host) {
     DHT_TRY(check_ctx(c));
+    PlannedCall pc(c);
     if (!spec || !prm || nrhs <= 0 || nrhs > DHT_MAX_BATCH) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
     if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
     if (c->W && !c->defl_ready) return set_error(DHT_ERR_STATE, "deflation basis set but not finalized");

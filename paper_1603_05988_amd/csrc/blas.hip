@@ -247,6 +247,13 @@ size_t partial_bytes(const dht_ctx* c, int nrhs) {
     return nb * 3 * nrhs * sizeof(Cx<double>);
 }
 
+// reduction workspace of a fused epilogue or a generic dot: partials and the
+// fold of a long partial list
+void ws_plan_dots(const dht_ctx* c, int nrhs, size_t* plan) {
+    plan_max(plan, WS_PARTIAL, partial_bytes(c, nrhs));
+    plan_max(plan, WS_FOLD, sizeof(Cx<double>) * FOLD_ROWS * RED_THREADS);
+}
+
 // --------------------------------------------------------------------------
 // vector updates (one lane per 16-byte vector; r = v & (B - 1))
 // --------------------------------------------------------------------------

@@ -132,16 +132,32 @@ __global__ void proj_sum_kernel(const Cx<double>* p1, const Cx<double>* p2, int 
     c2[idx] = s2;
 }
 
+// split of the basis entries over workgroups of the generic projection: at
+// most 256 chunks of at least 8192 entries
+static int field_chunks(const dht_ctx* c, int64_t* chunk_out) {
+    const int64_t Kn = 24 * c->g.Vh;
+    int64_t chunk = 8192;
+    int nchunk = (int)((Kn + chunk - 1) / chunk);
+    while (nchunk > 256) {
+        chunk *= 2;
+        nchunk = (int)((Kn + chunk - 1) / chunk);
+    }
+    if (chunk_out) *chunk_out = chunk;
+    return nchunk;
+}
+
+void ws_plan_project_field(const dht_ctx* c, int nrhs, size_t* plan) {
+    const size_t pb = (size_t)field_chunks(c, nullptr) * c->k * nrhs * sizeof(Cx<double>);
+    plan_max(plan, WS_PROJ, pb);
+    plan_max(plan, WS_PROJ2, pb);
+}
+
 int project_field(dht_ctx* c, const void* Z, int zprec, int nrhs, Cx<double>* c1, Cx<double>* c2) {
     if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "no deflation basis");
     const WLayout wl = wlayout(c);
     const int k = c->k;
-    int64_t chunk = 8192;
-    int nchunk = (int)((wl.Kn + chunk - 1) / chunk);
-    while (nchunk > 256) {
-        chunk *= 2;
-        nchunk = (int)((wl.Kn + chunk - 1) / chunk);
-    }
+    int64_t chunk;
+    const int nchunk = field_chunks(c, &chunk);
     void *p1, *p2;
     size_t pb = (size_t)nchunk * k * nrhs * sizeof(Cx<double>);
     DHT_TRY(ws_get(c, WS_PROJ, pb, &p1));
@@ -381,33 +397,56 @@ __global__ void proj_mfma_sum_kernel(const double* partial, int nwg, int wg_per_
     c2[idx] = cmake(a2r, a2i);
 }
 
+// launch shape of the MFMA projection for nrhs probes: the K chunk, the
+// column tiles of 32 (NT) and row tiles per wave (RT), the row groups of
+// workgroups and the workgroups per K group; the partials it writes
+struct MfmaShape {
+    int kc, chunks_per_group, NT, RT, rowgroups, wpg, nwg;
+    size_t partial_bytes;
+};
+static MfmaShape mfma_shape(const dht_ctx* c, int nrhs) {
+    const WLayout wl = wlayout(c);
+    MfmaShape sh;
+    const int64_t group_len = 6 * c->g.Vh;
+    sh.kc = 8;
+    for (int kc = 64; kc >= 8; kc >>= 1)
+        if (group_len % kc == 0) { sh.kc = kc; break; }
+    sh.chunks_per_group = (int)(group_len / sh.kc);
+    sh.NT = (2 * nrhs + 31) / 32;
+    if (sh.NT == 3) sh.NT = 4;
+    sh.RT = sh.NT == 1 ? 2 : 1;
+    const int rows_per_wg = MP_WAVES * sh.RT * 32;
+    sh.rowgroups = (wl.kp + rows_per_wg - 1) / rows_per_wg;
+    sh.wpg = (int)std::min<int64_t>(sh.chunks_per_group, std::max(1, 512 / (4 * sh.rowgroups)));
+    sh.nwg = 4 * sh.wpg;
+    sh.partial_bytes = (size_t)sh.nwg * wl.kp * sh.NT * 32 * sizeof(double);
+    return sh;
+}
+
+void ws_plan_project_codes(const dht_ctx* c, int nrhs, size_t* plan) {
+    if (c->k > 0 && c->wprec == DHT_BF16) plan_max(plan, WS_PROJ, mfma_shape(c, nrhs).partial_bytes);
+}
+
 int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<double>* c2) {
     if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "no deflation basis");
     if (c->wprec != DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "MFMA projection needs a BF16 basis");
     if (nrhs <= 0 || nrhs > 64) return set_error(DHT_ERR_INVALID_ARG, "1..64 right-hand sides per projection");
     const WLayout wl = wlayout(c);
+    const MfmaShape sh = mfma_shape(c, nrhs);
     MfmaProjArgs a;
     a.W = (const uint4*)c->W;
     a.zc = zc;
     a.nsteps = wl.nsteps;
     a.group_len = 6 * c->g.Vh;
-    a.kc = 8;
-    for (int kc = 64; kc >= 8; kc >>= 1)
-        if (a.group_len % kc == 0) { a.kc = kc; break; }
-    a.chunks_per_group = a.group_len / a.kc;
+    a.kc = sh.kc;
+    a.chunks_per_group = sh.chunks_per_group;
     a.B = nrhs;
     a.kp = wl.kp;
     a.ntiles = wl.kp / 32;
-    int NT = (2 * nrhs + 31) / 32;
-    if (NT == 3) NT = 4;
-    const int RT = NT == 1 ? 2 : 1;
-    const int rows_per_wg = MP_WAVES * RT * 32;
-    const int rowgroups = (wl.kp + rows_per_wg - 1) / rows_per_wg;
-    int wpg = (int)std::min<int64_t>(a.chunks_per_group, std::max(1, 512 / (4 * rowgroups)));
+    const int NT = sh.NT, rowgroups = sh.rowgroups, wpg = sh.wpg, nwg = sh.nwg;
     a.wg_per_group = wpg;
-    const int nwg = 4 * wpg;
     void* part;
-    DHT_TRY(ws_get(c, WS_PROJ, (size_t)nwg * wl.kp * NT * 32 * sizeof(double), &part));
+    DHT_TRY(ws_get(c, WS_PROJ, sh.partial_bytes, &part));
     a.partial = (double*)part;
     DHT_TRY(zero(c, part, (size_t)nwg * wl.kp * NT * 32 * sizeof(double)));
     dim3 grid(nwg, rowgroups), block(MP_THREADS);

@@ -281,6 +281,24 @@ int PairSink::take(dht_ctx* c, const void* r, const void* x, const std::vector<b
     return DHT_OK;
 }
 
+void ws_plan_fgmres(const dht_ctx* c, const dht_solver_params* prm, int B, bool use_nn, size_t* plan) {
+    const int m = prm->restart > 0 ? std::min(prm->restart, 64) : 32;
+    const size_t fb = full_elems(c, B) * 16, fbytes = full_elems(c, B) / 2 * 16;
+    plan_max(plan, WS_RE, fb);
+    plan_max(plan, WS_XF, fb);
+    plan_max(plan, WS_FLAGS, sizeof(double) * B);
+    plan_max(plan, WS_FG_R, fb / 2);
+    plan_max(plan, WS_FG_E, fb / 2);
+    plan_max(plan, WS_SCAL2, sizeof(Cx<double>) * 3 * B);
+    plan_max(plan, WS_FG_V, fbytes * (m + 1));
+    plan_max(plan, WS_FG_Z, fbytes * m);
+    plan_max(plan, WS_FG_W, fbytes);
+    plan_max(plan, WS_FG_COEF, sizeof(Cx<double>) * (m + 2) * B * 2);
+    ws_plan_dots(c, B, plan);
+    plan_max(plan, WS_PARTIAL, partial_bytes(c, B) * 4);   // the basis dots
+    if (use_nn) plan_max(plan, WS_NN_ACT, nn_infer_bytes(c, B));
+}
+
 int solve_fgmres(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int B, dht_solve_stats* stats,
                  bool use_nn, PairSink* sink) {
     if (use_nn && !c->nn.ready) return set_error(DHT_ERR_STATE, "network not initialised");

@@ -305,6 +305,14 @@ struct dht_ctx {
     dht::HopConfig hop_forced;
     // workspace slots (grow-only)
     std::vector<dht::Buf> ws;
+    // caller-owned workspace (dht_set_workspace): the planned slots at fixed
+    // offsets of one caller buffer; plan from dht_workspace_size
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::vector<size_t> plan, plan_off;      // in effect (set with the buffer)
+    std::vector<size_t> plan_next;           // from the last dht_workspace_size
+    size_t plan_next_total = 0;
+    int planned_call = 0;   // > 0 inside a call the plan covers
     // timings of the last call (ms)
     double timings[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[6];
@@ -356,6 +364,10 @@ enum Slot {
     WS_NSLOTS
 };
 int ws_get(dht_ctx* c, int slot, size_t bytes, void** out);
+// workspace plan: plan[slot] = max(plan[slot], bytes)
+inline void plan_max(size_t* plan, int slot, size_t bytes) {
+    if (bytes > plan[slot]) plan[slot] = bytes;
+}
 
 // instrumentation: bracket one launch of class `cls` (no-op unless profiling)
 int prof_begin(dht_ctx* c, int* token);

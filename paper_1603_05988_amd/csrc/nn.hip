@@ -544,12 +544,16 @@ static int nn_bufs(dht_ctx* c, int nb, NNBufs* b) {
 // inference only (the preconditioner inside FGMRES): input, the two hidden
 // activations and the output; the pre-activation values, which only the
 // backward pass reads, share one scratch block
+size_t nn_infer_bytes(const dht_ctx* c, int nb) {
+    const size_t s24 = (size_t)nb * c->g.V * 24, s48 = (size_t)nb * c->g.V * 48;
+    return sizeof(uint16_t) * (s24 + s48 * 3) + sizeof(float) * s24 + 1024;
+}
+
 static int nn_bufs_infer(dht_ctx* c, int nb, NNBufs* b) {
     const int64_t V = c->g.V;
     const size_t s24 = (size_t)nb * V * 24, s48 = (size_t)nb * V * 48;
     void* p;
-    size_t bytes = sizeof(uint16_t) * (s24 + s48 * 3) + sizeof(float) * s24 + 1024;
-    DHT_TRY(ws_get(c, WS_NN_ACT, bytes, &p));
+    DHT_TRY(ws_get(c, WS_NN_ACT, nn_infer_bytes(c, nb), &p));
     char* q = (char*)p;
     auto take = [&](size_t nbytes) {
         char* r = q;

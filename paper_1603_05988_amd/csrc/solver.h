@@ -122,6 +122,16 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
 int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats,
                  const double* zn2_known = nullptr, Cx<double>* zx_out = nullptr, int zprec = DHT_FP64);
 
+// workspace plans (bytes per slot, maxima over the call's code paths, with
+// the precision fallbacks) of solve_fields, the FGMRES solver, the network's
+// inference and the two projections, for a padded batch nrhs
+void ws_plan_solve(const dht_ctx* c, const dht_solver_params* prm, int nrhs, size_t* plan);
+void ws_plan_fgmres(const dht_ctx* c, const dht_solver_params* prm, int nrhs, bool use_nn, size_t* plan);
+size_t nn_infer_bytes(const dht_ctx* c, int nrhs);
+void ws_plan_project_codes(const dht_ctx* c, int nrhs, size_t* plan);
+void ws_plan_project_field(const dht_ctx* c, int nrhs, size_t* plan);
+void ws_plan_dots(const dht_ctx* c, int nrhs, size_t* plan);
+
 // fgmres.hip: FP64 defect correction around FGMRES(m) cycles (FP32) on the
 // full lattice with the network (use_nn) or the identity as right
 // preconditioner.  A PairSink, if given, records (r_k / ||r_k||,

@@ -37,6 +37,13 @@ int apply_schur(dht_ctx* c, int prec, const void* in_e, void* out_e, void* tmp_o
 
 static int slot_base(int prec) { return prec == DHT_FP64 ? WS_K64 : WS_KLO; }
 
+// the rings of stored iterations of a BF16 inner solve (see bicgstab)
+static int ring_slots(int history, size_t bytes) {
+    const size_t budget = (size_t)12 << 30;   // bytes for both rings
+    return history > 0 ? history : (int)std::min<size_t>(16, std::max<size_t>(2, budget / (2 * bytes)));
+}
+
+
 int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x, int nrhs,
              const std::vector<double>& target2, int maxiter, BicgResult* res, bool x32, XAccum* xa,
              const double* r0n2) {
@@ -56,8 +63,7 @@ int bicgstab(dht_ctx* c, int prec, const void* src, const double* scale, void* x
     Cx<double>* hist = nullptr;
     double* hscale = nullptr;
     if (xa) {
-        const size_t budget = (size_t)12 << 30;   // bytes for both rings
-        K = xa->ring > 0 ? xa->ring : (int)std::min<size_t>(16, std::max<size_t>(2, budget / (2 * bytes)));
+        K = ring_slots(xa->ring, bytes);
         void *pp, *ss, *hh, *sc;
         DHT_TRY(ws_get(c, WS_RING_P, (size_t)K * bytes, &pp));
         DHT_TRY(ws_get(c, WS_RING_S, (size_t)K * bytes, &ss));
@@ -259,6 +265,51 @@ static bool predict_scales(const std::vector<double>& sup, const BicgResult& br,
         sdn[i] = 1.0 / sqrt(pr);
     }
     return true;
+}
+
+// workspace of one inner BiCGStab in storage precision prec (see bicgstab)
+static void ws_plan_bicgstab(const dht_ctx* c, int prec, int nrhs, bool hist, int history, size_t* plan) {
+    const size_t bytes = half_vecs(c, nrhs, prec) * 16;
+    const int base = slot_base(prec);
+    for (int i : {0, 1, 3, 5, 6}) plan_max(plan, base + i, bytes);
+    if (hist) {
+        const int K = ring_slots(history, bytes);
+        plan_max(plan, WS_RING_P, (size_t)K * bytes);
+        plan_max(plan, WS_RING_S, (size_t)K * bytes);
+        plan_max(plan, WS_HIST, sizeof(Cx<double>) * 2 * (size_t)K * nrhs);
+        plan_max(plan, WS_HIST_SCALE, sizeof(double) * nrhs);
+    } else {
+        plan_max(plan, base + 2, bytes);
+        plan_max(plan, base + 4, bytes);
+        plan_max(plan, base + 8, bytes);   // the inner solution of a defect-correction cycle
+    }
+    plan_max(plan, WS_SCAL, sizeof(RhsState) * nrhs);
+    ws_plan_dots(c, nrhs, plan);
+}
+
+void ws_plan_solve(const dht_ctx* c, const dht_solver_params* prm, int nrhs, size_t* plan) {
+    if (prm->method == DHT_SOLVER_DC_FGMRES_NN || prm->method == DHT_SOLVER_DC_FGMRES) {
+        ws_plan_fgmres(c, prm, nrhs, prm->method == DHT_SOLVER_DC_FGMRES_NN, plan);
+        dht_solver_params p2 = *prm;   // the BiCGStab fallback
+        p2.method = DHT_SOLVER_DC_BICGSTAB;
+        p2.inner = DHT_FP32;
+        ws_plan_solve(c, &p2, nrhs, plan);
+        return;
+    }
+    const size_t nh = half_elems(c, nrhs), bh = nh * 16;
+    for (int s : {WS_B, WS_RE, WS_TMPO}) plan_max(plan, s, bh);
+    plan_max(plan, WS_FLAGS, sizeof(double) * nrhs);
+    plan_max(plan, WS_SCAL2, sizeof(Cx<double>) * 3 * nrhs);
+    plan_max(plan, WS_NORMS, sizeof(Cx<double>) * 6 * nrhs);
+    ws_plan_dots(c, nrhs, plan);
+    // every inner precision the escalation BF16 -> FP32 -> FP64 can reach
+    const int start = prm->method == DHT_SOLVER_DC_BICGSTAB ? prm->inner : DHT_FP64;
+    for (int prec = start; prec >= DHT_FP64; prec--) ws_plan_bicgstab(c, prec, nrhs, prec == DHT_BF16, prm->history, plan);
+    if (start == DHT_BF16) {
+        plan_max(plan, slot_base(DHT_BF16) + 1, half_vecs(c, nrhs, DHT_BF16) * 16);   // prepared right-hand side
+        plan_max(plan, WS_S16, sizeof(double) * nrhs);
+        for (int s : {WS_E32, WS_W32, WS_T32}) plan_max(plan, s, nh * elem_bytes(DHT_FP32));
+    }
 }
 
 int solve_fields(dht_ctx* c, const dht_solver_params* prm, const void* Z, void* X, int nrhs, dht_solve_stats* stats,
