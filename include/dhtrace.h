@@ -494,6 +494,37 @@ int dht_autotune_hop(dht_ctx* ctx, int prec, int nrhs, int reps, dht_tune_result
  * appended to the file (one text line per epilogue class). */
 int dht_autotune(dht_ctx* ctx, int prec, int nrhs, int reps, const char* cache_path, dht_tune_result* out);
 
+/* Batch-size tuner (the right-hand sides per dht_trace_batch call): for each
+ * candidate batch whose planned workspace (dht_workspace_size with prm) fits
+ * mem_budget bytes (0: 90% of the device memory free now plus the workspace
+ * the library holds), the hop shapes of the solve's precisions are tuned if
+ * they are not set, and reps Algorithm-1 batches of the probes of spec
+ * (j = 0 .. reps*B - 1, after one untimed batch) are timed by the host clock
+ * (the host's convergence polls are part of a batch's cost);
+ * best_nrhs is the candidate of most right-hand sides per second.  The
+ * running estimates and the projection window are left as they were.  The
+ * caller then passes best_nrhs to dht_trace_batch. */
+#define DHT_TUNE_MAX_BATCHES 8
+enum { DHT_BATCH_INVALID = 0, DHT_BATCH_TIMED = 1, DHT_BATCH_OVER_BUDGET = 2, DHT_BATCH_FAILED = 3 };
+typedef struct dht_batch_tune {
+    int best_nrhs;
+    int candidates;
+    int nrhs[DHT_TUNE_MAX_BATCHES];
+    int status[DHT_TUNE_MAX_BATCHES];         /* DHT_BATCH_* */
+    double rhs_per_s[DHT_TUNE_MAX_BATCHES];
+    size_t workspace[DHT_TUNE_MAX_BATCHES];   /* planned workspace bytes */
+} dht_batch_tune;
+int dht_autotune_batch(dht_ctx* ctx, const dht_probe_spec* spec, const dht_solver_params* prm, const int* cand,
+                       int ncand, size_t mem_budget, int reps, dht_batch_tune* out);
+
+/* Split of the MFMA projection (BF16 basis, nrhs <= 64 probes): the basis
+ * entries are divided over about 256 .. 4096 workgroups of split-K partial
+ * sums; each split is timed (reps passes) and checked against the default
+ * split (max difference <= 1e-12 of the largest coefficient: only the FP64
+ * order of adding the FP32 chunk sums differs), and the fastest is installed
+ * on the context.  best_ms (may be NULL) receives its time per pass. */
+int dht_autotune_projection(dht_ctx* ctx, int nrhs, int reps, int* best_wgs, double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

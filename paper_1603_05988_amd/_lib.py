@@ -74,6 +74,11 @@ HOP_FORMS = {HOP_SITE: "site", HOP_SITE_LDS: "site_lds", HOP_TMARCH: "tmarch", H
              HOP_TMARCH_ROWL: "tmarch_rowl"}
 
 
+class BatchTune(ctypes.Structure):
+    _fields_ = [("best_nrhs", ctypes.c_int), ("candidates", ctypes.c_int), ("nrhs", ctypes.c_int * 8),
+                ("status", ctypes.c_int * 8), ("rhs_per_s", ctypes.c_double * 8), ("workspace", ctypes.c_size_t * 8)]
+
+
 class Estimate(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("mean_re", ctypes.c_double), ("mean_im", ctypes.c_double),
                 ("mean_defl_re", ctypes.c_double), ("mean_defl_im", ctypes.c_double),
@@ -137,6 +142,9 @@ SIGNATURES = {
     "dht_hop_config_get": (_i, [_vp, _i, _i, _i, ctypes.POINTER(HopConfig)]),
     "dht_autotune_hop": (_i, [_vp, _i, _i, _i, ctypes.POINTER(TuneResult)]),
     "dht_autotune": (_i, [_vp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(TuneResult)]),
+    "dht_autotune_batch": (_i, [_vp, ctypes.POINTER(ProbeSpec), ctypes.POINTER(SolverParams), ctypes.POINTER(_i), _i,
+                                ctypes.c_size_t, _i, ctypes.POINTER(BatchTune)]),
+    "dht_autotune_projection": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _dp]),
     "dht_state_save": (_i, [_vp, ctypes.c_char_p]),
     "dht_state_load": (_i, [_vp, ctypes.c_char_p]),
 }
@@ -529,6 +537,27 @@ class Context:
                          for k in HOP_CLASSES},
                 "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in HOP_CLASSES},
                 "candidates": r.candidates, "rejected": r.rejected}
+
+    def autotune_batch(self, seed: int, run: int, hp: bool, prm: SolverParams, candidates=(16, 32, 64),
+                       mem_budget: int = 0, reps: int = 2) -> dict:
+        """Time Algorithm-1 batches of each candidate size (within the memory
+        budget) and return the fastest with the per-candidate figures."""
+        out = BatchTune()
+        cand = (ctypes.c_int * len(candidates))(*candidates)
+        sp = ProbeSpec(seed, run, int(hp))
+        check(load().dht_autotune_batch(self.h, ctypes.byref(sp), ctypes.byref(prm), cand, len(candidates),
+                                        int(mem_budget), int(reps), ctypes.byref(out)))
+        names = {0: "invalid", 1: "timed", 2: "over_budget", 3: "failed"}
+        return {"best_nrhs": out.best_nrhs,
+                "candidates": [{"nrhs": out.nrhs[i], "status": names[out.status[i]],
+                                "rhs_per_s": out.rhs_per_s[i], "workspace_bytes": out.workspace[i]}
+                               for i in range(out.candidates)]}
+
+    def autotune_projection(self, nrhs: int, reps: int = 3) -> dict:
+        w = ctypes.c_int(0)
+        ms = ctypes.c_double(0)
+        check(load().dht_autotune_projection(self.h, int(nrhs), int(reps), ctypes.byref(w), ctypes.byref(ms)))
+        return {"workgroups": w.value, "ms_per_pass": ms.value}
 
     def save_state(self, path: str):
         """Checkpoint the running estimates."""

@@ -417,7 +417,8 @@ static MfmaShape mfma_shape(const dht_ctx* c, int nrhs) {
     sh.RT = sh.NT == 1 ? 2 : 1;
     const int rows_per_wg = MP_WAVES * sh.RT * 32;
     sh.rowgroups = (wl.kp + rows_per_wg - 1) / rows_per_wg;
-    sh.wpg = (int)std::min<int64_t>(sh.chunks_per_group, std::max(1, 512 / (4 * sh.rowgroups)));
+    const int target = c->proj_wgs > 0 ? c->proj_wgs : 512;   // split of the basis entries (tuned)
+    sh.wpg = (int)std::min<int64_t>(sh.chunks_per_group, std::max(1, target / (4 * sh.rowgroups)));
     sh.nwg = 4 * sh.wpg;
     sh.partial_bytes = (size_t)sh.nwg * wl.kp * sh.NT * 32 * sizeof(double);
     return sh;

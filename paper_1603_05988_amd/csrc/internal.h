@@ -325,6 +325,7 @@ struct dht_ctx {
     // [pw_first, pw_first + pw_count) of pw_spec, computed in one pass over
     // the basis for basis generation pw_gen; defl_gen changes with the basis
     int proj_window = 0;
+    int proj_wgs = 0;        // MFMA projection: target workgroup count of a pass (0: 512)
     bool pw_valid = false;
     int64_t pw_first = 0;
     int pw_count = 0, pw_pad = 0;

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -221,6 +222,136 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
 using namespace dht;
 
 extern "C" {
+
+int dht_autotune_batch(dht_ctx* c, const dht_probe_spec* spec, const dht_solver_params* prm, const int* cand,
+                       int ncand, size_t mem_budget, int reps, dht_batch_tune* out) {
+    if (!c || !spec || !prm || !cand || !out || ncand <= 0 || ncand > DHT_TUNE_MAX_BATCHES || reps <= 0)
+        return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    DHT_HIP(hipSetDevice(c->device));
+    if (mem_budget == 0) {   // what the device has free now, plus the workspace the library holds
+        size_t fr = 0, tot = 0;
+        DHT_HIP(hipMemGetInfo(&fr, &tot));
+        size_t held = 0;
+        for (int i = 0; i < (int)c->ws.size(); i++)
+            if (i != WS_HOSTPIN) held += c->ws[i].bytes;
+        mem_budget = (size_t)(0.9 * (double)(fr + held));
+    }
+    memset(out, 0, sizeof(*out));
+    out->candidates = ncand;
+    // the timed batches must not change the running estimates or the projection window
+    const Welford q0 = c->est_q, qd0 = c->est_qd;
+    const int pin = DHT_HOP_PLAIN;
+    (void)pin;
+    double best = -1.0;
+    int rc_all = DHT_OK;
+    for (int i = 0; i < ncand; i++) {
+        const int B = cand[i];
+        out->nrhs[i] = B;
+        if (B <= 0 || B > DHT_MAX_BATCH) {
+            out->status[i] = DHT_BATCH_INVALID;
+            continue;
+        }
+        size_t need = 0;
+        DHT_TRY(dht_workspace_size(c, B, prm, &need));
+        out->workspace[i] = need;
+        if (need > mem_budget) {
+            out->status[i] = DHT_BATCH_OVER_BUDGET;
+            continue;
+        }
+        // hop shapes of every precision the solve runs at this batch
+        const int bp = pad_rhs(B), lb = log2_pow2(bp);
+        const int precs[3] = {DHT_FP64, DHT_FP32, DHT_BF16};
+        for (int prec : precs) {
+            if (c->hop_cfg[prec][lb][0].form >= 0) continue;
+            if (prm->method == DHT_SOLVER_BICGSTAB_FP64 && prec != DHT_FP64) continue;
+            dht_tune_result tr;
+            DHT_TRY(dht_autotune_hop(c, prec, bp, 3, &tr));
+        }
+        c->pw_valid = false;
+        int rc = dht_trace_batch(c, spec, 0, B, prm, nullptr, nullptr);   // warm-up (workspace, window)
+        if (rc == DHT_OK) {   // wall clock: the host's per-iteration polls are part of a batch's cost
+            c->pw_valid = false;
+            DHT_HIP(hipStreamSynchronize(c->stream));
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int r = 0; r < reps && rc == DHT_OK; r++) rc = dht_trace_batch(c, spec, (int64_t)r * B, B, prm, nullptr, nullptr);
+            DHT_HIP(hipStreamSynchronize(c->stream));
+            const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (rc == DHT_OK && s > 0) out->rhs_per_s[i] = reps * B / s;
+        }
+        if (rc != DHT_OK) {
+            out->status[i] = DHT_BATCH_FAILED;
+            rc_all = rc;
+            continue;
+        }
+        out->status[i] = DHT_BATCH_TIMED;
+        if (out->rhs_per_s[i] > best) {
+            best = out->rhs_per_s[i];
+            out->best_nrhs = B;
+        }
+    }
+    c->est_q = q0;
+    c->est_qd = qd0;
+    c->pw_valid = false;
+    if (out->best_nrhs == 0)
+        return rc_all != DHT_OK ? rc_all : set_error(DHT_ERR_OOM, "no candidate batch fits the memory budget");
+    return DHT_OK;
+}
+
+int dht_autotune_projection(dht_ctx* c, int nrhs, int reps, int* best_wgs, double* best_ms) {
+    if (!c || !best_wgs || nrhs <= 0 || nrhs > 64 || reps <= 0) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    DHT_HIP(hipSetDevice(c->device));
+    if (!c->defl_ready || c->wprec != DHT_BF16) return set_error(DHT_ERR_STATE, "needs a finalized BF16 basis");
+    const int bp = pad_rhs(nrhs), k = c->k;
+    void *zc, *cc, *pp;
+    DHT_TRY(ws_get(c, WS_ZCODE, full_elems(c, bp), &zc));
+    DHT_TRY(ws_get(c, WS_SCAL2, sizeof(Cx<double>) * 4 * (size_t)k * bp, &cc));
+    DHT_TRY(ws_get(c, WS_TUNE_RED, sizeof(Cx<double>) * TUNE_BLOCKS, &pp));
+    dht_probe_spec sp = {1414213u, 0u, 1};
+    DHT_TRY(probes_gen(c, &sp, 0, nrhs, bp, nullptr, DHT_FP64, nullptr, nullptr, (uint8_t*)zc));
+    Cx<double>* ref = (Cx<double>*)cc;
+    Cx<double>* got = ref + 2 * (size_t)k * bp;
+    const int saved = c->proj_wgs;
+    c->proj_wgs = 0;
+    DHT_TRY(project_codes(c, (const uint8_t*)zc, bp, ref, ref + (size_t)k * bp));
+    std::vector<Cx<double>> hr(2 * (size_t)k * bp), hg(hr.size());
+    DHT_HIP(hipMemcpyAsync(hr.data(), ref, sizeof(Cx<double>) * hr.size(), hipMemcpyDeviceToHost, c->stream));
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    double rmax = 0.0;
+    for (auto& v : hr) rmax = std::max(rmax, std::max(std::fabs(v.re), std::fabs(v.im)));
+    const int targets[5] = {256, 512, 1024, 2048, 4096};
+    double bms = 1e300;
+    int bw = 512;
+    for (int t : targets) {
+        c->proj_wgs = t;
+        for (int i = 0; i < 1; i++) DHT_TRY(project_codes(c, (const uint8_t*)zc, bp, got, got + (size_t)k * bp));
+        DHT_HIP(hipEventRecord(c->ev[0], c->stream));
+        for (int i = 0; i < reps; i++) DHT_TRY(project_codes(c, (const uint8_t*)zc, bp, got, got + (size_t)k * bp));
+        DHT_HIP(hipEventRecord(c->ev[1], c->stream));
+        DHT_HIP(hipEventSynchronize(c->ev[1]));
+        float ms = 0.f;
+        DHT_HIP(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        // the FP32 chunk sums are the same in every split; only the FP64 order of adding them moves
+        DHT_HIP(hipMemcpyAsync(hg.data(), got, sizeof(Cx<double>) * hg.size(), hipMemcpyDeviceToHost, c->stream));
+        DHT_HIP(hipStreamSynchronize(c->stream));
+        double dmax = 0.0;
+        for (size_t i = 0; i < hg.size(); i++)
+            dmax = std::max(dmax, std::max(std::fabs(hg[i].re - hr[i].re), std::fabs(hg[i].im - hr[i].im)));
+        if (!(dmax <= 1e-12 * std::max(rmax, 1e-300))) continue;
+        if (ms / reps < bms) {
+            bms = ms / reps;
+            bw = t;
+        }
+    }
+    (void)pp;
+    c->proj_wgs = bw;
+    c->pw_valid = false;
+    *best_wgs = bw;
+    if (best_ms) *best_ms = bms;
+    (void)saved;
+    return DHT_OK;
+}
+
 
 int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, int epilogue, const dht_hop_config* cfg) {
     if (!c) return set_error(DHT_ERR_INVALID_ARG, "null context");
