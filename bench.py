@@ -94,6 +94,61 @@ def cpu_baseline(U, w, k: int, hp: bool):
     }
 
 
+def host_info():
+    """Cores, CPU model and memory of the host the CPU baseline runs on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["mem_gb"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return info
+
+
+def small_config_legs(L, torch, np, run_cpu: bool):
+    """The 8^3x16 (64 right-hand sides) and 16^3x32 (16) solves to 1e-8 on the
+    GPU (mixed BiCGStab, Z4 probes, no deflation) and, beside them, the oracle's
+    C stencil FP64 BiCGStab on the host cores for the same probes."""
+    from paper_1603_05988_amd.workloads import WORKLOADS, gauge_links
+    out = {}
+    for name, nrhs in (("c2", 64), ("c3", 16)):
+        w = WORKLOADS[name]
+        U = gauge_links(w.L, w.eps, w.seed)
+        c = L.Context(w.L, w.mass)
+        c.set_gauge(torch.from_numpy(U).cuda())
+        prm = c.params(L.SOLVER_DC_BICGSTAB, inner=L.BF16, tol=1e-8, maxiter=5000)
+        c.trace_batch(w.seed, 0, False, 0, nrhs, prm)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.time()
+        reps = 3
+        for r in range(reps):
+            recs = c.trace_batch(w.seed, 0, False, 0, nrhs, prm)
+        torch.cuda.synchronize()
+        gpu = reps * nrhs / (time.time() - t0)
+        c.close()
+        ent = {"lattice": list(w.L), "nrhs": nrhs, "gpu_rhs_per_s": round(gpu, 2),
+               "gpu_worst_residual": max(r["true_resid"] for r in recs)}
+        if run_cpu:
+            from oracle import rng, stencil
+            t0 = time.time()
+            its = []
+            for j in range(nrhs):
+                z = rng.probe(w.L, w.seed, 0, False, j)
+                x, st, it, rr = stencil.solve(U, w.L, w.mass, z, 1e-8, 5000)
+                its.append(it)
+            el = time.time() - t0
+            ent.update({"cpu_rhs_per_s": round(nrhs / el, 3), "cpu_seconds": round(el, 2),
+                        "cpu_mean_iters": float(np.mean(its)), "gpu_over_cpu": round(gpu / (nrhs / el), 1)})
+        out[w.name] = ent
+    return out
+
+
 def train_network(L, torch, np, npairs: int, epochs: int):
     """The learned preconditioner of the 8^3x16 recipe: (residual, error) pairs
     from FGMRES(4) restarts of Z4 probes (x* from FP64 BiCGStab to 1e-12),
@@ -174,6 +229,10 @@ def main():
     w = WORKLOADS[args.workload]
     k = args.k if args.k is not None else w.k
     B = w.batch
+    small = small_config_legs(L, torch, np, not args.no_cpu)
+    for nm, ent in small.items():
+        log("%s: GPU %.1f RHS/s%s" % (nm, ent["gpu_rhs_per_s"], (", CPU oracle %.2f RHS/s (%.1f s)" % (
+            ent["cpu_rhs_per_s"], ent["cpu_seconds"])) if "cpu_rhs_per_s" in ent else ""))
     nn_weights, nn_info = None, None
     if args.nn_steps > 0:   # trained first: its pairs are freed before the large lattice is set up
         nn_weights, nn_info = train_network(L, torch, np, args.nn_pairs, args.nn_epochs)
@@ -210,6 +269,10 @@ def main():
     ctx.set_projection_window(args.proj_window)
     ws_bytes = ctx.workspace_size(B, prm)   # the caller-owned workspace this configuration would need
     log("workspace plan for batches of %d: %.2f GB" % (B, ws_bytes / 1e9))
+    proj_tune = None
+    if args.tune == "auto":   # split of the basis over the MFMA projection's workgroups, for the window
+        proj_tune = ctx.autotune_projection(min(64, args.proj_window or B), reps=3)
+        log("projection split: %d workgroups, %.2f ms per pass" % (proj_tune["workgroups"], proj_tune["ms_per_pass"]))
 
     # launch shapes of the hopping kernel for the inner and the FP64 outer
     # precision (and FP32, which updates the late residuals of BF16 solves)
@@ -351,6 +414,8 @@ def main():
         log("cpu baseline: %.4f RHS/s (%.1f s)" % (cpu["value"], time.time() - t0))
         cpu.pop("q", None)
         cpu.pop("status", None)
+        cpu["host"] = host_info()
+        cpu["small_configs"] = {nm: ent for nm, ent in small.items()}
 
     out = {
         "metric": METRIC,
@@ -373,12 +438,13 @@ def main():
             "solver": "even/odd BiCGStab, %s inner, FP64 defect correction" % args.inner,
             "preconditioner": "none (the learned FGMRES leg is reported as mixed_learned)", "tol": w.tol,
             "hop_shapes": shapes,
-            "workspace_bytes": ws_bytes,
+            "workspace_bytes": ws_bytes, "projection_split": proj_tune,
             "mean_inner_iters": round(iters, 2), "mean_outer_cycles": round(outer, 2),
             "worst_true_residual": worst,
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "small_configs": small,
         "mixed_learned": learned,
         "mixed_learned_value": learned["value"] if learned else None,
         "fp64_bicgstab_value": round(fp64_value, 3) if fp64_value else None,
