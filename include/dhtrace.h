@@ -494,6 +494,41 @@ int dht_autotune_hop(dht_ctx* ctx, int prec, int nrhs, int reps, dht_tune_result
  * appended to the file (one text line per epilogue class). */
 int dht_autotune(dht_ctx* ctx, int prec, int nrhs, int reps, const char* cache_path, dht_tune_result* out);
 
+/* ---- variance analysis (Sections 6.1-6.3; host arrays, no device) -------- */
+
+/* Run-to-run statistics of the hierarchical-probing estimate.  q holds, for R
+ * independent runs of Algorithm 1 (different base vectors z0), the quadratic
+ * forms of their first S probes (complex128 [R][S]; deflated or not).  For
+ * each s of s_list the run estimates t_r(s) = (1/s) sum_{j<s} q[r][j] give:
+ * mean (over runs) and its standard error sqrt(var / R); var = V_hp(s), the
+ * unbiased variance over runs of t_r(s), with its Jackknife error (leave one
+ * run out); and, when v_stoc > 0 (the variance per probe of plain Z4 noise),
+ * the speedup over Monte Carlo R_s = v_stoc / (V_hp(s) s) with its Jackknife
+ * error.  Needs R >= 3. */
+typedef struct dht_hp_var {
+    int s;
+    double mean_re, mean_im, mean_err;
+    double var, var_err;
+    double rs, rs_err;
+} dht_hp_var;
+int dht_hp_variance(const double* q_host, int R, int S, const int* s_list, int ns, double v_stoc, dht_hp_var* out);
+
+/* Playback with fewer deflation vectors (Section 6.3: the stored inner
+ * products replayed with a smaller subspace).  From the Galerkin matrices
+ * H = W^H Q W and G5 = W^H g5 W of a basis of k vectors (complex128 k x k
+ * row-major, as dht_deflation_get_galerkin returns them; diagonal = 1 uses
+ * their diagonals only, as dht_deflation_finalize_diag does), the projection
+ * coefficients of n probes (complex128 [2][k][n]: c1 = W^H z, c2 = W^H g5 z,
+ * as dht_trace_batch returns them) and their quadratic forms q (complex128
+ * [n]), computes for each kk of k_list (0..k) the deflated quadratures
+ * q - c1'^H M' c2' with M' = (H[:kk, :kk])^-1 over the leading kk vectors
+ * (qd_out, complex128 [nk][n]) and T_D' = Tr(M' G5[:kk, :kk]) (TD_out,
+ * complex128 [nk]): the estimator of Algorithm 1 with a basis of kk vectors. */
+int dht_playback(const double* H, const double* G5, int k, int diagonal, const double* coef, const double* q, int n,
+                 const int* k_list, int nk, double* qd_out, double* TD_out);
+/* The Galerkin matrices of the finalized basis (H, G5: 2 k^2 doubles each). */
+int dht_deflation_get_galerkin(dht_ctx* ctx, double* H, double* G5, int* diagonal);
+
 /* Batch-size tuner (the right-hand sides per dht_trace_batch call): for each
  * candidate batch whose planned workspace (dht_workspace_size with prm) fits
  * mem_budget bytes (0: 90% of the device memory free now plus the workspace

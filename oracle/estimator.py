@@ -171,3 +171,48 @@ def hutchinson_enumeration(A: np.ndarray):
     q = np.einsum("sa,ab,sb->s", Z.conj(), A, Z)
     mean = q.mean()
     return complex(mean), float(np.mean(np.abs(q - mean) ** 2))
+
+
+# --------------------------------------------------------------------------
+# variance analysis over runs (Sections 6.1-6.3)
+# --------------------------------------------------------------------------
+def jackknife_error(values: np.ndarray, statistic) -> float:
+    """Jackknife standard error of statistic(values) from its leave-one-out
+    values: sqrt((R - 1) / R * sum (s_(-r) - mean s_(-))^2) (Section 6.1 quotes
+    Jackknife error bars over 40 runs)."""
+    R = len(values)
+    loo = np.array([statistic(np.delete(values, r)) for r in range(R)])
+    return float(np.sqrt((R - 1) / R * np.sum((loo - loo.mean()) ** 2)))
+
+
+def complex_variance(t: np.ndarray) -> float:
+    """Unbiased E|t - tbar|^2 of complex samples."""
+    return float(np.sum(np.abs(t - t.mean()) ** 2) / (len(t) - 1))
+
+
+def hp_run_statistics(q_runs: np.ndarray, s: int, v_stoc: float = 0.0) -> dict:
+    """Runs r of Algorithm 1 with the quadratic forms q_runs[r, :] of their
+    probes: the estimate after s probes t_r = mean of the first s, the variance
+    over runs V_hp(s) with its Jackknife error, and the speedup over plain
+    noise R_s = V_stoc / (V_hp(s) s) (Section 6.2)."""
+    t = q_runs[:, :s].mean(axis=1)
+    V = complex_variance(t)
+    out = {"mean": complex(t.mean()), "mean_err": float(np.sqrt(V / len(t))), "var": V,
+           "var_err": jackknife_error(t, complex_variance)}
+    if v_stoc > 0:
+        out["rs"] = v_stoc / (V * s)
+        out["rs_err"] = jackknife_error(t, lambda x: v_stoc / (complex_variance(x) * s))
+    return out
+
+
+def playback(W: np.ndarray, D: np.ndarray, g5diag: np.ndarray, Z: np.ndarray, q: np.ndarray, kk: int,
+             diagonal: bool = False):
+    """Section 6.3's playback: the deflated quadratures q_j - z_j^H P' z_j and
+    T_D' = Tr P' of the basis restricted to its leading kk vectors, with the
+    Galerkin (or diagonal Rayleigh) M of that smaller basis."""
+    if kk == 0:
+        return q.copy(), 0.0
+    Wk = W[:, :kk]
+    M = rayleigh_diag_M(Wk, D, g5diag) if diagonal else galerkin_M(Wk, D, g5diag)
+    c1, c2 = projection_coefficients(Wk, Z, g5diag)
+    return q - deflation_corrections(c1, c2, M), deflated_trace(Wk, M, g5diag)

@@ -79,6 +79,12 @@ class BatchTune(ctypes.Structure):
                 ("status", ctypes.c_int * 8), ("rhs_per_s", ctypes.c_double * 8), ("workspace", ctypes.c_size_t * 8)]
 
 
+class HPVar(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int), ("mean_re", ctypes.c_double), ("mean_im", ctypes.c_double),
+                ("mean_err", ctypes.c_double), ("var", ctypes.c_double), ("var_err", ctypes.c_double),
+                ("rs", ctypes.c_double), ("rs_err", ctypes.c_double)]
+
+
 class Estimate(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("mean_re", ctypes.c_double), ("mean_im", ctypes.c_double),
                 ("mean_defl_re", ctypes.c_double), ("mean_defl_im", ctypes.c_double),
@@ -145,6 +151,9 @@ SIGNATURES = {
     "dht_autotune_batch": (_i, [_vp, ctypes.POINTER(ProbeSpec), ctypes.POINTER(SolverParams), ctypes.POINTER(_i), _i,
                                 ctypes.c_size_t, _i, ctypes.POINTER(BatchTune)]),
     "dht_autotune_projection": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _dp]),
+    "dht_hp_variance": (_i, [_dp, _i, _i, ctypes.POINTER(_i), _i, _d, ctypes.POINTER(HPVar)]),
+    "dht_playback": (_i, [_dp, _dp, _i, _i, _dp, _dp, _i, ctypes.POINTER(_i), _i, _dp, _dp]),
+    "dht_deflation_get_galerkin": (_i, [_vp, _dp, _dp, ctypes.POINTER(_i)]),
     "dht_state_save": (_i, [_vp, ctypes.c_char_p]),
     "dht_state_load": (_i, [_vp, ctypes.c_char_p]),
 }
@@ -168,6 +177,36 @@ def load(path: str = LIB_PATH):
             fn.argtypes = args
         _lib = lib
     return _lib
+
+
+def hp_variance(q, s_list, v_stoc: float = 0.0):
+    """Run-to-run variance V_hp(s) of the HP estimate with Jackknife errors and
+    the speedup R_s over plain noise; q: complex array [runs][probes]."""
+    q = np.ascontiguousarray(q, dtype=np.complex128)
+    R, S = q.shape
+    sl = (ctypes.c_int * len(s_list))(*[int(s) for s in s_list])
+    out = (HPVar * len(s_list))()
+    check(load().dht_hp_variance(q.view(np.float64).ctypes.data_as(_dp), R, S, sl, len(s_list), float(v_stoc), out))
+    return [{f[0]: getattr(o, f[0]) for f in HPVar._fields_} for o in out]
+
+
+def playback(H, G5, coef, q, k_list, diagonal: bool = False):
+    """Deflated quadratures and T_D with the leading kk basis vectors for each kk
+    of k_list, from stored coefficients coef [2][k][n] and quadratic forms q [n]."""
+    H = np.ascontiguousarray(H, dtype=np.complex128)
+    G5 = np.ascontiguousarray(G5, dtype=np.complex128)
+    coef = np.ascontiguousarray(coef, dtype=np.complex128)
+    q = np.ascontiguousarray(q, dtype=np.complex128)
+    k = H.shape[0]
+    n = q.shape[0]
+    kl = (ctypes.c_int * len(k_list))(*[int(v) for v in k_list])
+    qd = np.zeros((len(k_list), n), dtype=np.complex128)
+    td = np.zeros(len(k_list), dtype=np.complex128)
+    check(load().dht_playback(H.view(np.float64).ctypes.data_as(_dp), G5.view(np.float64).ctypes.data_as(_dp), k,
+                              int(diagonal), coef.view(np.float64).ctypes.data_as(_dp),
+                              q.view(np.float64).ctypes.data_as(_dp), n, kl, len(k_list),
+                              qd.view(np.float64).ctypes.data_as(_dp), td.view(np.float64).ctypes.data_as(_dp)))
+    return qd, td
 
 
 class DhtError(RuntimeError):
@@ -379,6 +418,15 @@ class Context:
         by = ctypes.c_double(0)
         check(load().dht_profile_get(self.h, cls, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
         return dict(count=n.value, ms=ms.value, bytes=by.value)
+
+    def deflation_galerkin(self):
+        """(H = W^H Q W, G5 = W^H g5 W, diagonal) of the finalized basis."""
+        H = np.zeros(2 * self.k * self.k)
+        G = np.zeros(2 * self.k * self.k)
+        d = ctypes.c_int(0)
+        check(load().dht_deflation_get_galerkin(self.h, _np_dp(H), _np_dp(G), ctypes.byref(d)))
+        return (H.view(np.complex128).reshape(self.k, self.k), G.view(np.complex128).reshape(self.k, self.k),
+                bool(d.value))
 
     def deflation_M(self):
         M = np.zeros(2 * self.k * self.k)

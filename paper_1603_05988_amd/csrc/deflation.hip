@@ -673,6 +673,22 @@ int deflation_finalize(dht_ctx* c, bool diagonal) {
                 G5[(size_t)i * k + j0 + jj] = std::complex<double>(gv.re, gv.im);
             }
     }
+    // the Galerkin matrices stay with the context: playback over fewer vectors
+    // inverts their leading blocks (Section 6.3)
+    c->Hq.assign((size_t)2 * k * k, 0.0);
+    c->G5q.assign((size_t)2 * k * k, 0.0);
+    for (int i = 0; i < k; i++)
+        for (int j = 0; j < k; j++) {
+            const size_t o = 2 * ((size_t)i * k + j);
+            std::complex<double> h = diagonal ? (i == j ? hdiag[i] : 0.0) : H[(size_t)i * k + j];
+            std::complex<double> g = diagonal ? (i == j ? gdiag[i] : 0.0) : G5[(size_t)i * k + j];
+            if (!diagonal && j >= i) h = 0.5 * (H[(size_t)i * k + j] + std::conj(H[(size_t)j * k + i]));
+            if (!diagonal && j < i) h = 0.5 * (std::conj(H[(size_t)j * k + i]) + H[(size_t)i * k + j]);
+            c->Hq[o] = h.real();
+            c->Hq[o + 1] = h.imag();
+            c->G5q[o] = g.real();
+            c->G5q[o + 1] = g.imag();
+        }
     if (diagonal) {
         std::vector<std::complex<double>> M((size_t)k * k, 0.0);
         std::complex<double> td = 0.0;

@@ -285,6 +285,7 @@ struct dht_ctx {
     void* W = nullptr;                 // [k][2][12][Vh] complex<wprec>
     std::vector<double> M;             // k x k complex128 row-major (host)
     bool M_diag = false;               // M is diagonal (Rayleigh-quotient finalize)
+    std::vector<double> Hq, G5q;       // W^H Q W and W^H g5 W (k x k complex128; diagonals only when M_diag)
     double TD[2] = {0, 0};
     // per-kernel-class timing with HIP events (off unless enabled)
     bool prof = false;

@@ -1,0 +1,83 @@
+"""Variance analysis on the 8^3x16 operator over 40 runs of Algorithm 1
+(Sections 6.2-6.3): k = 64 eigenvectors of Q from the library's eigensolver
+(FP64 storage, Galerkin M), 40 runs (base vectors z0) of 32 hierarchical-
+probing probes each, solved in mixed precision to 1e-8, with their projection
+coefficients; 256 plain Z4 probes give the Monte Carlo variance V_stoc.
+The report (gpurun_out/variance_c2.json when that directory exists) holds
+V_hp(s) with Jackknife errors and R_s at s = 1 .. 32, undeflated and
+deflated, and the playback of the deflated estimate with k = 0 .. 64.
+
+Asserted (consistency, not the size of the gains, which the paper's
+matrices do not share): playback with all 64 vectors reproduces the records'
+deflated quadratures and T_D; with none, the undeflated ones; the deflated
+estimate equals the undeflated one within their errors (both are unbiased).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1603_05988_amd.workloads import WORKLOADS, gauge_links
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def test_variance_report_c2():
+    from paper_1603_05988_amd import _lib as L
+    w = WORKLOADS["c2"]
+    U = gauge_links(w.L, w.eps, w.seed)
+    ctx = L.Context(w.L, w.mass)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    lam, res, st, TD = ctx.eigensolve(w.k, L.FP64, tol=1e-9, max_iter=400, degree=16, seed=11)
+    assert st["converged"] == w.k
+    H, G5, diag = ctx.deflation_galerkin()
+    prm = ctx.params(L.SOLVER_DC_BICGSTAB, inner=L.BF16, tol=1e-8, maxiter=5000)
+    R, S = 40, 32
+    q = np.zeros((R, S), dtype=np.complex128)
+    qd = np.zeros((R, S), dtype=np.complex128)
+    coef = np.zeros((R, 2, w.k, S), dtype=np.complex128)
+    for r in range(R):
+        recs, c1, c2 = ctx.trace_batch(w.seed, 100 + r, True, 0, S, prm, want_coef=True)
+        q[r] = [x["q"] for x in recs]
+        qd[r] = [x["q_defl"] for x in recs]
+        coef[r, 0], coef[r, 1] = c1, c2
+    mc = []
+    for b in range(0, 256, 64):
+        mc += [x["q"] for x in ctx.trace_batch(w.seed, 7, False, b, 64, prm)]
+    mc = np.array(mc)
+    v_stoc = float(np.sum(np.abs(mc - mc.mean()) ** 2) / (len(mc) - 1))
+    s_list = list(range(1, S + 1))
+    und = L.hp_variance(q, s_list, v_stoc)
+    dfl = L.hp_variance(qd, s_list, v_stoc)
+    # playback over k at s = 32, all runs
+    k_list = [0, 8, 16, 32, 48, 64]
+    play = []
+    t_runs = {kk: [] for kk in k_list}
+    for r in range(R):
+        pq, ptd = L.playback(H, G5, coef[r], q[r], k_list, diagonal=diag)
+        if r == 0:
+            assert np.abs(pq[-1] - qd[r]).max() <= 1e-10 * np.abs(q[r]).max()
+            assert abs(ptd[-1] - TD) <= 1e-12 * abs(TD)
+            assert np.array_equal(pq[0], q[r])
+        for a, kk in enumerate(k_list):
+            t_runs[kk].append(pq[a])
+    for kk in k_list:
+        o = L.hp_variance(np.array(t_runs[kk]), [S], v_stoc)[0]
+        play.append({"k": kk, "var": o["var"], "var_err": o["var_err"], "rs": o["rs"], "rs_err": o["rs_err"]})
+    m_u = complex(und[-1]["mean_re"], und[-1]["mean_im"])
+    m_d = complex(dfl[-1]["mean_re"], dfl[-1]["mean_im"]) + TD
+    assert abs(m_u - m_d) <= 5 * np.hypot(und[-1]["mean_err"], dfl[-1]["mean_err"]), (m_u, m_d)
+    out = {"lattice": list(w.L), "runs": R, "probes_per_run": S, "k": w.k, "T_D": [TD.real, TD.imag],
+           "sigma_min": float(np.abs(lam).min()), "v_stoc": v_stoc, "mc_probes": len(mc),
+           "trace_undeflated": [m_u.real, m_u.imag], "trace_deflated": [m_d.real, m_d.imag],
+           "hp": [{"s": a["s"], "var": a["var"], "var_err": a["var_err"], "rs": a["rs"], "rs_err": a["rs_err"],
+                   "var_defl": b["var"], "var_defl_err": b["var_err"], "rs_defl": b["rs"], "rs_defl_err": b["rs_err"]}
+                  for a, b in zip(und, dfl)],
+           "playback_s32": play}
+    print(json.dumps(out)[:2000])
+    if os.path.isdir("gpurun_out"):
+        with open("gpurun_out/variance_c2.json", "w") as f:
+            json.dump(out, f, indent=1)
+    ctx.close()
