@@ -344,6 +344,50 @@ int dht_trace_batch(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int
 int dht_set_projection_window(dht_ctx* ctx, int nprobes);
 int dht_estimate_get(dht_ctx* ctx, dht_estimate* est);
 int dht_estimate_reset(dht_ctx* ctx);
+
+/* ---- Traces Tr(Gamma D^-1) over one deflation space ----------------------- */
+
+/* End of Section 5.2: the deflated split Tr(Gamma D^-1) = Tr(Gamma P) +
+ * Tr(Gamma (D^-1 - P)) holds for any inexpensive matrix Gamma, the estimator
+ * takes one Gamma product per probe, and the deflation space is shared.  Here
+ * Gamma is a 4 x 4 complex spin matrix acting alike on every site and colour,
+ * (Gamma psi)(x, s, c) = sum_t Gamma[s][t] psi(x, t, c) -- the Dirac matrices
+ * and their products, or any other; P = W M W^H g5 is the current deflated
+ * part (T_D(Gamma) = Tr(M W^H g5 Gamma W)).
+ *
+ * dht_gamma_set registers ng matrices (host, complex128 [ng][4][4], row-major),
+ * resets their running estimates and, when TD_host is not NULL, writes
+ * T_D(Gamma) for each (complex128 [ng]; 0 without a basis).  T_D(Gamma) comes
+ * from the 16 spin-pair traces sum_ab M_ab W_b,s^H W_a,t, accumulated in FP64
+ * from the stored basis once per basis: k spin-pair self products for a
+ * diagonal M, and for a full M four times the FP64 basis products of
+ * dht_deflation_finalize.  Errors: DHT_ERR_INVALID_ARG for ng outside
+ * 1..DHT_MAX_GAMMA or a non-finite entry, DHT_ERR_STATE for a basis set but
+ * not finalized. */
+#define DHT_MAX_GAMMA 64
+int dht_gamma_set(dht_ctx* ctx, const double* gamma_host, int ng, double* TD_host);
+/* Algorithm 1's loop body for every registered matrix at once, on the probes
+ * j = first .. first+nrhs-1 of spec (generated in FP64 storage).  One solve
+ * x = D^-1 z per probe serves all matrices: z^H Gamma x = sum_st Gamma[s][t]
+ * z_s^H x_t from the 16 spin-pair forms of (z, x) (one pass over both), and
+ * with a basis z^H Gamma P z = (W^H Gamma^H z)^H M (W^H g5 z) from the 16
+ * spin-pair projections W_s^H z_t (v_s: the spin-s entries of v) -- one pass
+ * over the basis per 16 probes with a BF16 basis (MFMA over the probes' exact
+ * 2-bit codes, FP32 sums flushed to FP64 every 64 entries, as in
+ * dht_project_probes), one FP64 pass per batch otherwise.  records (host, may
+ * be NULL) receives [ng][nrhs] entries: q = z^H Gamma x, qd = q - z^H Gamma P z
+ * and the probe's solve stats.  The running estimates per matrix take only
+ * converged probes; the call then returns DHT_ERR_NOT_CONVERGED if a probe
+ * missed the tolerance.  The estimates are not reset when the basis changes
+ * (dht_gamma_set resets them).  This call is outside the workspace plan of
+ * dht_workspace_size: slots it needs beyond the plan are allocated by the
+ * library.  Errors: DHT_ERR_STATE without registered matrices or gauge field,
+ * or with a basis set but not finalized. */
+int dht_trace_gamma_batch(dht_ctx* ctx, const dht_probe_spec* spec, int64_t first, int nrhs,
+                          const dht_solver_params* prm, dht_record* records);
+/* Running estimate of Tr(Gamma_g D^-1), g = 0..ng-1, with the fields of
+ * dht_estimate_get (TD = T_D(Gamma_g)). */
+int dht_gamma_estimate_get(dht_ctx* ctx, int g, dht_estimate* est);
 /* Checkpoint / resume of the running estimates (Algorithm 1 accumulates over
  * probes; a long run can be split across processes).  save writes a small text
  * file at `path` (exact round trip of the moments); load restores them into a
@@ -412,8 +456,9 @@ int dht_last_timings(dht_ctx* ctx, double* ms_host, int n);
 /* Per-kernel-class timing: when enabled, every launch of an instrumented
  * kernel is bracketed by HIP events on the context stream; totals are
  * accumulated at the next synchronising call.  Classes: 0/1/2 = hop kernel
- * in FP64/FP32/BF16, 3 = MFMA projection, 4 = generic projection, 5 = the
- * network's convolutions (BF16 matrix cores).  total_bytes is the
+ * in FP64/FP32/BF16, 3 = MFMA projection, 4 = generic projection (also its
+ * spin-pair form), 5 = the network's convolutions (BF16 matrix cores), 6 =
+ * spin-pair MFMA projection (dht_trace_gamma_batch).  total_bytes is the
  * algorithmic byte count of those launches (input and output fields once,
  * links once); for class 5 it is the flop count (2 per multiply-add). */
 int dht_profile_enable(dht_ctx* ctx, int on);

@@ -131,6 +131,10 @@ SIGNATURES = {
     "dht_trace_batch": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, ctypes.POINTER(SolverParams),
                              ctypes.POINTER(Record), _dp]),
     "dht_estimate_get": (_i, [_vp, ctypes.POINTER(Estimate)]),
+    "dht_gamma_set": (_i, [_vp, _dp, _i, _dp]),
+    "dht_trace_gamma_batch": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, ctypes.POINTER(SolverParams),
+                                   ctypes.POINTER(Record)]),
+    "dht_gamma_estimate_get": (_i, [_vp, _i, ctypes.POINTER(Estimate)]),
     "dht_estimate_reset": (_i, [_vp]),
     "dht_last_timings": (_i, [_vp, _dp, _i]),
     "dht_solver_counters": (_i, [_vp, ctypes.POINTER(_i64), _i]),
@@ -380,7 +384,7 @@ class Context:
         check(load().dht_set_projection_window(self.h, int(nprobes)))
 
     # -- instrumentation --------------------------------------------------
-    PROF_CLASSES = {"hop_fp64": 0, "hop_fp32": 1, "hop_bf16": 2, "proj_mfma": 3, "proj_generic": 4, "conv": 5}
+    PROF_CLASSES = {"hop_fp64": 0, "hop_fp32": 1, "hop_bf16": 2, "proj_mfma": 3, "proj_generic": 4, "conv": 5, "proj_sp": 6}
 
     def workspace_size(self, max_nrhs: int, prm: SolverParams) -> int:
         """Device bytes that trace_batch / solve need for batches up to max_nrhs with prm."""
@@ -467,6 +471,34 @@ class Context:
 
     def reset_estimate(self):
         check(load().dht_estimate_reset(self.h))
+
+    # -- traces Tr(Gamma D^-1) over the same deflation space ----------------
+    def gamma_set(self, gammas) -> np.ndarray:
+        """Register spin matrices (array [ng][4][4] complex); returns T_D(Gamma) per matrix."""
+        G = np.ascontiguousarray(np.asarray(gammas, dtype=np.complex128).reshape(-1, 4, 4))
+        self._ng = G.shape[0]
+        td = np.zeros(self._ng, dtype=np.complex128)
+        check(load().dht_gamma_set(self.h, _np_dp(G.view(np.float64)), self._ng, _np_dp(td.view(np.float64))))
+        return td
+
+    def trace_gamma_batch(self, seed: int, run: int, hp: bool, first: int, nrhs: int, prm: SolverParams,
+                          allow_not_converged: bool = False):
+        """Returns (q [ng][nrhs], q_defl [ng][nrhs], per-probe solve stats)."""
+        sp = ProbeSpec(seed, run, int(hp))
+        ng = getattr(self, "_ng", 0)
+        rec = (Record * max(1, ng * nrhs))()
+        allow = (DHT_ERR_NOT_CONVERGED,) if allow_not_converged else ()
+        check(load().dht_trace_gamma_batch(self.h, ctypes.byref(sp), first, nrhs, ctypes.byref(prm), rec), allow)
+        q = np.array([complex(r.q_re, r.q_im) for r in rec[:ng * nrhs]]).reshape(ng, nrhs)
+        qd = np.array([complex(r.qd_re, r.qd_im) for r in rec[:ng * nrhs]]).reshape(ng, nrhs)
+        stats = [dict(iters=r.s.iters, outer=r.s.outer, true_resid=r.s.true_resid, status=r.s.status)
+                 for r in rec[:nrhs]]
+        return q, qd, stats
+
+    def gamma_estimate(self, g: int):
+        e = Estimate()
+        check(load().dht_gamma_estimate_get(self.h, g, ctypes.byref(e)))
+        return {f[0]: getattr(e, f[0]) for f in Estimate._fields_}
 
     def timings(self):
         t = np.zeros(5)

@@ -234,10 +234,17 @@ __device__ inline uint32_t bf16_unit(int v) { return v > 0 ? 0x3F80u : (v < 0 ? 
 static constexpr int MP_FILL = 4;
 static constexpr int MP_KC_MAX = 64;   // largest chunk (complex entries)
 
-template <int RT, int NT>
+// Spin-pair form (SP): the groups are (parity, spin s) of 3 Vh entries, and
+// the B operand holds the probe codes of all four spins t at the same
+// (parity, colour, site) entries, one run of codes per t, so that one pass
+// gives W_s^H z_t for the 16 pairs (s, t); the column of probe r and spin t
+// is slot t B + r.
+template <int RT, int NT, bool SP>
 __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
     extern __shared__ uint4 bfr[];   // [MP_FILL][kc/8][NT][64] B fragments, then the raw codes
-    // raw codes of one fill: MP_FILL * kc * B bytes <= MP_FILL * 64 * NT * 16
+    // raw codes of one fill: RUNS * MP_FILL * kc * B bytes <= MP_FILL * 64 * NT * 16
+    // (2 RUNS B <= 32 NT columns)
+    constexpr int RUNS = SP ? 4 : 1;
     constexpr int RAW_PER_THREAD = (MP_FILL * MP_KC_MAX * NT * 16 / 8 + MP_THREADS - 1) / MP_THREADS;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -268,12 +275,16 @@ __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
     uint2 rv[RAW_PER_THREAD];
     auto fetch = [&](int64_t cf) {
         const int nfill = (int)(c_end - cf < MP_FILL ? c_end - cf : MP_FILL);
-        const int nwords = (nfill * a.kc * a.B) >> 3;
-        const uint2* src = (const uint2*)(a.zc + ((int64_t)g * a.group_len + cf * a.kc) * a.B);
+        const int run_words = (nfill * a.kc * a.B) >> 3;
 #pragma unroll
         for (int j = 0; j < RAW_PER_THREAD; j++) {
             const int w = tid + j * MP_THREADS;
-            if (w < nwords) rv[j] = src[w];
+            if (w < RUNS * run_words) {
+                const int t = SP ? w / run_words : 0;
+                const int64_t grp = SP ? (int64_t)(g & ~3) + t : g;   // (parity, spin t) for SP
+                const uint2* src = (const uint2*)(a.zc + (grp * a.group_len + cf * a.kc) * a.B);
+                rv[j] = src[w - t * run_words];
+            }
         }
     };
     if (c_begin < c_end) fetch(c_begin);
@@ -282,8 +293,9 @@ __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
         const int nfill = (int)(c_end - cf < MP_FILL ? c_end - cf : MP_FILL);
         const int64_t K0 = (int64_t)g * a.group_len + cf * a.kc;
         __syncthreads();   // the previous fill's fragments and codes are no longer read
+        const int run_bytes = nfill * a.kc * a.B;
         {
-            const int nwords = (nfill * a.kc * a.B) >> 3;
+            const int nwords = (RUNS * run_bytes) >> 3;
 #pragma unroll
             for (int j = 0; j < RAW_PER_THREAD; j++) {
                 const int w = tid + j * MP_THREADS;
@@ -304,8 +316,9 @@ __global__ __launch_bounds__(MP_THREADS) void proj_mfma_kernel(MfmaProjArgs a) {
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 uint32_t z0 = 0, z1 = 0;
-                if (r < a.B) {
-                    const int code = raw[(8 * ks + 4 * hh + e) * a.B + r] & 3;
+                if (r < RUNS * a.B) {
+                    const int t = SP ? r / a.B : 0;
+                    const int code = raw[t * run_bytes + (8 * ks + 4 * hh + e) * a.B + (r - t * a.B)] & 3;
                     const int zr = code == 0 ? 1 : (code == 2 ? -1 : 0);
                     const int zi = code == 1 ? 1 : (code == 3 ? -1 : 0);
                     z0 = bf16_unit(zr) | (bf16_unit(zi) << 16);
@@ -404,22 +417,24 @@ struct MfmaShape {
     int kc, chunks_per_group, NT, RT, rowgroups, wpg, nwg;
     size_t partial_bytes;
 };
-static MfmaShape mfma_shape(const dht_ctx* c, int nrhs) {
+// (sp: the spin-pair form, 8 groups of 3 Vh entries, four code slots per probe)
+static MfmaShape mfma_shape(const dht_ctx* c, int nrhs, bool sp = false) {
     const WLayout wl = wlayout(c);
     MfmaShape sh;
-    const int64_t group_len = 6 * c->g.Vh;
+    const int ngroups = sp ? 8 : 4;
+    const int64_t group_len = (sp ? 3 : 6) * c->g.Vh;
     sh.kc = 8;
     for (int kc = 64; kc >= 8; kc >>= 1)
         if (group_len % kc == 0) { sh.kc = kc; break; }
     sh.chunks_per_group = (int)(group_len / sh.kc);
-    sh.NT = (2 * nrhs + 31) / 32;
+    sh.NT = (2 * (sp ? 4 * nrhs : nrhs) + 31) / 32;
     if (sh.NT == 3) sh.NT = 4;
     sh.RT = sh.NT == 1 ? 2 : 1;
     const int rows_per_wg = MP_WAVES * sh.RT * 32;
     sh.rowgroups = (wl.kp + rows_per_wg - 1) / rows_per_wg;
     const int target = c->proj_wgs > 0 ? c->proj_wgs : 512;   // split of the basis entries (tuned)
-    sh.wpg = (int)std::min<int64_t>(sh.chunks_per_group, std::max(1, target / (4 * sh.rowgroups)));
-    sh.nwg = 4 * sh.wpg;
+    sh.wpg = (int)std::min<int64_t>(sh.chunks_per_group, std::max(1, target / (ngroups * sh.rowgroups)));
+    sh.nwg = ngroups * sh.wpg;
     sh.partial_bytes = (size_t)sh.nwg * wl.kp * sh.NT * 32 * sizeof(double);
     return sh;
 }
@@ -456,9 +471,9 @@ int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<do
     size_t lds = (size_t)MP_FILL * (a.kc / 8) * NT * 64 * sizeof(uint4) + (size_t)MP_FILL * a.kc * nrhs;
     int tok;
     DHT_TRY(prof_begin(c, &tok));
-    if (NT == 1) hipLaunchKernelGGL((proj_mfma_kernel<2, 1>), grid, block, lds, c->stream, a);
-    else if (NT == 2) hipLaunchKernelGGL((proj_mfma_kernel<1, 2>), grid, block, lds, c->stream, a);
-    else hipLaunchKernelGGL((proj_mfma_kernel<1, 4>), grid, block, lds, c->stream, a);
+    if (NT == 1) hipLaunchKernelGGL((proj_mfma_kernel<2, 1, false>), grid, block, lds, c->stream, a);
+    else if (NT == 2) hipLaunchKernelGGL((proj_mfma_kernel<1, 2, false>), grid, block, lds, c->stream, a);
+    else hipLaunchKernelGGL((proj_mfma_kernel<1, 4, false>), grid, block, lds, c->stream, a);
     DHT_HIP(hipGetLastError());
     // algorithmic bytes: the stored basis once, the probe codes once per row group, the partials
     DHT_TRY(prof_end(c, tok, PROF_PROJ_MFMA,
@@ -466,6 +481,199 @@ int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<do
                          (double)nwg * wl.kp * NT * 32 * 8.0));
     hipLaunchKernelGGL(proj_mfma_sum_kernel, dim3((c->k * nrhs + 127) / 128), dim3(128), 0, c->stream,
                        (const double*)part, nwg, wpg, wl.kp, NT * 32, c->k, nrhs, c1, c2);
+    DHT_HIP(hipGetLastError());
+    return DHT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// spin-pair projections (traces with a spin matrix Gamma, end of Section 5.2)
+//
+// P_st[i][r] = sum over parity, colour and site of conj(W_i(s, c, x)) z_r(t, c, x)
+// for the 16 spin pairs (s, t), stored [4 s + t][k][B].  For any 4 x 4 spin
+// matrix Gamma, W^H Gamma^H z = sum_st conj(Gamma_ts) P_st, and W^H g5 z =
+// sum_s g5_s P_ss: one pass serves every Gamma.
+// ---------------------------------------------------------------------------
+__global__ void proj_mfma_sp_sum_kernel(const double* partial, int wpg, int kp, int ncol, int k, int B,
+                                        Cx<double>* P) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)16 * k * B) return;
+    const int st = (int)(idx / ((int64_t)k * B));
+    const int rem = (int)(idx - (int64_t)st * k * B);
+    const int i = rem / B, r = rem - i * B;
+    const int s = st >> 2, t = st & 3;
+    double re = 0, im = 0;
+    for (int par = 0; par < 2; par++)
+        for (int w = 0; w < wpg; w++) {
+            const int wg = (par * 4 + s) * wpg + w;
+            const double* p = partial + ((int64_t)wg * kp + i) * ncol + 2 * (t * B + r);
+            re += p[0];
+            im += p[1];
+        }
+    P[idx] = cmake(re, im);
+}
+
+int project_codes_sp(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* P) {
+    if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "no deflation basis");
+    if (c->wprec != DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "MFMA projection needs a BF16 basis");
+    if (nrhs <= 0 || nrhs > 16) return set_error(DHT_ERR_INVALID_ARG, "1..16 right-hand sides per spin-pair projection");
+    const WLayout wl = wlayout(c);
+    const MfmaShape sh = mfma_shape(c, nrhs, true);
+    MfmaProjArgs a;
+    a.W = (const uint4*)c->W;
+    a.zc = zc;
+    a.nsteps = wl.nsteps;
+    a.group_len = 3 * c->g.Vh;
+    a.kc = sh.kc;
+    a.chunks_per_group = sh.chunks_per_group;
+    a.B = nrhs;
+    a.kp = wl.kp;
+    a.ntiles = wl.kp / 32;
+    a.wg_per_group = sh.wpg;
+    if (a.group_len % 8 != 0 || a.kc > MP_KC_MAX)
+        return set_error(DHT_ERR_INVALID_ARG, "lattice half volume not a multiple of 8");
+    void* part;
+    DHT_TRY(ws_get(c, WS_PROJ, sh.partial_bytes, &part));
+    a.partial = (double*)part;
+    DHT_TRY(zero(c, part, sh.partial_bytes));
+    dim3 grid(sh.nwg, sh.rowgroups), block(MP_THREADS);
+    const size_t lds = (size_t)MP_FILL * (a.kc / 8) * sh.NT * 64 * sizeof(uint4) + (size_t)MP_FILL * a.kc * 4 * nrhs;
+    int tok;
+    DHT_TRY(prof_begin(c, &tok));
+    if (sh.NT == 1) hipLaunchKernelGGL((proj_mfma_kernel<2, 1, true>), grid, block, lds, c->stream, a);
+    else if (sh.NT == 2) hipLaunchKernelGGL((proj_mfma_kernel<1, 2, true>), grid, block, lds, c->stream, a);
+    else hipLaunchKernelGGL((proj_mfma_kernel<1, 4, true>), grid, block, lds, c->stream, a);
+    DHT_HIP(hipGetLastError());
+    // algorithmic bytes: the basis once, four code runs per row group, the partials
+    DHT_TRY(prof_end(c, tok, PROF_PROJ_SP,
+                     (double)wl.kp * wl.Kn * 4.0 + (double)sh.rowgroups * wl.Kn * nrhs +
+                         (double)sh.partial_bytes));
+    hipLaunchKernelGGL(proj_mfma_sp_sum_kernel, dim3((unsigned)((16 * (int64_t)c->k * nrhs + 127) / 128)), dim3(128),
+                       0, c->stream, (const double*)part, sh.wpg, wl.kp, sh.NT * 32, c->k, nrhs, P);
+    DHT_HIP(hipGetLastError());
+    return DHT_OK;
+}
+
+// generic form: any storage precision of W, FP64 probe fields ([2][12][Vh][B]),
+// FP64 accumulation; each workgroup takes one basis row and one run of
+// (parity, colour, site) entries for SPG_RT right-hand sides
+static constexpr int SPG_THREADS = 256;
+static constexpr int SPG_RT = 2;
+
+template <typename SW>
+__global__ __launch_bounds__(SPG_THREADS) void proj_sp_generic_kernel(const typename Store<SW>::elem* W, WLayout wl,
+                                                                      const Cx<double>* Z, int64_t Vh, int B, int r0,
+                                                                      int nr, int64_t chunk, Cx<double>* part, int k) {
+    __shared__ Cx<double> red[SPG_THREADS / 64][SPG_RT * 16];
+    const int i = blockIdx.y;
+    const int64_t nE = 6 * Vh;
+    const int64_t ebeg = (int64_t)blockIdx.x * chunk;
+    const int64_t eend = ebeg + chunk < nE ? ebeg + chunk : nE;
+    Cx<double> acc[SPG_RT][16];
+#pragma unroll
+    for (int q = 0; q < SPG_RT; q++)
+#pragma unroll
+        for (int st = 0; st < 16; st++) acc[q][st] = cmake(0.0, 0.0);
+    for (int64_t E = ebeg + threadIdx.x; E < eend; E += SPG_THREADS) {
+        // entry E = (parity, colour, site): spin s sits at K = 12 Vh parity + 3 Vh s + (E - 3 Vh parity)
+        const int64_t par = E / (3 * Vh);
+        const int64_t K0 = E + 9 * Vh * par;
+        Cx<double> w[4];
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            auto v = Store<SW>::ld(W + w_index(wl, i, K0 + s * 3 * Vh));
+            w[s] = cmake<double>(v.re, v.im);
+        }
+#pragma unroll
+        for (int q = 0; q < SPG_RT; q++) {
+            if (q >= nr) break;
+            Cx<double> z[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) z[t] = Z[(K0 + t * 3 * Vh) * B + r0 + q];
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int t = 0; t < 4; t++) acc[q][s * 4 + t] = acc[q][s * 4 + t] + conjmul(w[s], z[t]);
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < SPG_RT; q++)
+#pragma unroll
+        for (int st = 0; st < 16; st++) {
+            double re = acc[q][st].re, im = acc[q][st].im;
+            for (int off = 32; off > 0; off >>= 1) {
+                re += __shfl_xor(re, off);
+                im += __shfl_xor(im, off);
+            }
+            if (lane == 0) red[wave][q * 16 + st] = cmake(re, im);
+        }
+    __syncthreads();
+    if (threadIdx.x < SPG_RT * 16) {
+        const int q = threadIdx.x / 16, st = threadIdx.x % 16;
+        if (q < nr) {
+            Cx<double> sum = cmake(0.0, 0.0);
+            for (int wv = 0; wv < SPG_THREADS / 64; wv++) sum = sum + red[wv][threadIdx.x];
+            part[(((int64_t)blockIdx.x * 16 + st) * k + i) * B + r0 + q] = sum;
+        }
+    }
+}
+
+__global__ void proj_sp_sum_kernel(const Cx<double>* part, int nchunk, int64_t n, Cx<double>* P) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    Cx<double> s = cmake(0.0, 0.0);
+    for (int ch = 0; ch < nchunk; ch++) s = s + part[(int64_t)ch * n + idx];
+    P[idx] = s;
+}
+
+// split of the (parity, colour, site) entries: at most 64 runs of at least 4096
+static int sp_chunks(const dht_ctx* c, int64_t* chunk_out) {
+    const int64_t nE = 6 * c->g.Vh;
+    int64_t chunk = 4096;
+    int n = (int)((nE + chunk - 1) / chunk);
+    while (n > 64) {
+        chunk *= 2;
+        n = (int)((nE + chunk - 1) / chunk);
+    }
+    if (chunk_out) *chunk_out = chunk;
+    return n;
+}
+
+int project_field_sp(dht_ctx* c, const void* Z, int nrhs, Cx<double>* P) {
+    if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "no deflation basis");
+    const WLayout wl = wlayout(c);
+    const int k = c->k;
+    int64_t chunk;
+    const int nchunk = sp_chunks(c, &chunk);
+    const int64_t n = (int64_t)16 * k * nrhs;
+    void* part;
+    DHT_TRY(ws_get(c, WS_GAM_PART, (size_t)nchunk * n * sizeof(Cx<double>), &part));
+    int tok;
+    DHT_TRY(prof_begin(c, &tok));
+    for (int r0 = 0; r0 < nrhs; r0 += SPG_RT) {
+        const int nr = std::min(SPG_RT, nrhs - r0);
+        dim3 grid(nchunk, k), block(SPG_THREADS);
+        switch (c->wprec) {
+            case DHT_FP64:
+                hipLaunchKernelGGL(proj_sp_generic_kernel<double>, grid, block, 0, c->stream, (const Cx<double>*)c->W,
+                                   wl, (const Cx<double>*)Z, c->g.Vh, nrhs, r0, nr, chunk, (Cx<double>*)part, k);
+                break;
+            case DHT_FP32:
+                hipLaunchKernelGGL(proj_sp_generic_kernel<float>, grid, block, 0, c->stream, (const Cx<float>*)c->W,
+                                   wl, (const Cx<double>*)Z, c->g.Vh, nrhs, r0, nr, chunk, (Cx<double>*)part, k);
+                break;
+            case DHT_BF16:
+                hipLaunchKernelGGL(proj_sp_generic_kernel<bf16x2>, grid, block, 0, c->stream, (const bf16x2*)c->W,
+                                   wl, (const Cx<double>*)Z, c->g.Vh, nrhs, r0, nr, chunk, (Cx<double>*)part, k);
+                break;
+            default: return set_error(DHT_ERR_INVALID_ARG, "bad basis precision");
+        }
+        DHT_HIP(hipGetLastError());
+    }
+    DHT_TRY(prof_end(c, tok, PROF_PROJ_GENERIC,
+                     (double)k * wl.Kn * elem_bytes(c->wprec) + (double)wl.Kn * nrhs * 16.0));
+    hipLaunchKernelGGL(proj_sp_sum_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, c->stream,
+                       (const Cx<double>*)part, nchunk, n, P);
     DHT_HIP(hipGetLastError());
     return DHT_OK;
 }

@@ -218,7 +218,7 @@ struct Buf {
 };
 
 // kernel classes for the instrumentation (dht_profile_get)
-enum { PROF_HOP64 = 0, PROF_HOP32, PROF_HOP16, PROF_PROJ_MFMA, PROF_PROJ_GENERIC, PROF_CONV, PROF_NCLASS };
+enum { PROF_HOP64 = 0, PROF_HOP32, PROF_HOP16, PROF_PROJ_MFMA, PROF_PROJ_GENERIC, PROF_CONV, PROF_PROJ_SP, PROF_NCLASS };
 struct ProfPending {
     int cls;
     int ev0, ev1;       // indices into the event pool
@@ -295,6 +295,15 @@ struct dht_ctx {
     dht::ProfStat prof_stat[dht::PROF_NCLASS];
     // estimator
     dht::Welford est_q, est_qd;
+    // traces Tr(Gamma D^-1) (dht_gamma_set): ng spin matrices, complex128
+    // [ng][4][4]; the spin-pair traces T_st of the deflated part (complex128
+    // [16]) for basis generation gam_gen; running estimates per matrix
+    std::vector<double> gam;
+    int ng = 0;
+    double gamT[32] = {0};
+    bool gamT_valid = false;
+    uint64_t gam_gen = 0;
+    std::vector<dht::Welford> gest_q, gest_qd;
     // defect-correction branch counts since creation (dht_solver_counters)
     int64_t solver_count[dht::SC_NCOUNT] = {0, 0, 0, 0};
     // learned preconditioner
@@ -363,6 +372,7 @@ enum Slot {
     WS_EIG_V, WS_EIG_W, WS_EIG_T, WS_EIG_U, WS_EIG_PART, WS_EIG_SMALL, WS_EIG_RPART, WS_EIG_LAM, WS_EIG_CANON, WS_DEFL_GET,
     WS_PW_CODE, WS_PW_COEF,
     WS_RING_P, WS_RING_S, WS_HIST, WS_HIST_SCALE, WS_E32, WS_W32, WS_T32, WS_S16,
+    WS_GAM_PART, WS_GAM_FPART, WS_GAM_OUT, WS_GAM_CODE,
     WS_NSLOTS
 };
 int ws_get(dht_ctx* c, int slot, size_t bytes, void** out);

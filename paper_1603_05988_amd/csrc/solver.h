@@ -169,5 +169,10 @@ void deflation_corrections(const dht_ctx* c, const Cx<double>* c1, const Cx<doub
                            double* dre, double* dim);
 int gather_columns(dht_ctx* c, int j0, int n, int bp, void* out);
 int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<double>* c2);
+// spin-pair projections P[4 s + t][k][nrhs] = W_s^H z_t (traces with a spin
+// matrix): MFMA form over probe codes (BF16 basis, nrhs <= 16), generic form
+// over FP64 probe fields (any basis precision)
+int project_codes_sp(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* P);
+int project_field_sp(dht_ctx* c, const void* Z, int nrhs, Cx<double>* P);
 
 }  // namespace dht
