@@ -7,6 +7,17 @@
   (eq. varAr); the difference to the undeflated variance is eq. vA-vAR.
 - The 3x3 example of Section 2 (deflating the largest triplet of a symmetric
   3x3 matrix can raise, keep or lower the variance).
+- Theorem 2 (Section 2.1): the expected variance after deflating the k
+  largest singular triplets when the singular vectors are random unitary,
+  from the mean mu_k and variance V_k of the N - k remaining values; Remark 4
+  (k = 0) and the Corollary (when deflation lowers the expected variance).
+  Reading for Hermitian matrices: the values are the eigenvalues with their
+  signs (the right singular vector of an eigenvalue of negative sign is minus
+  the left one, so the cross terms of the proof carry the product of signs);
+  for a positive definite matrix they are the singular values, as printed.
+- The distance profile W_d of Section 6.2: for sampled rows i, the mean of
+  |B_ij|^2 over the entries j whose lattice site lies at torus Manhattan
+  distance d from the site of i.
 """
 from __future__ import annotations
 
@@ -67,3 +78,103 @@ def example_3x3_ratio(s: float, d: float) -> float:
     Ar = U[:, 1:] @ np.diag([1 + s, 1.0]) @ U[:, 1:].T
     off = lambda M: np.sum(M ** 2) - np.sum(np.diag(M) ** 2)
     return float(off(A) / off(Ar))
+
+
+# --------------------------------------------------------------------------
+# Theorem 2, Remark 4, Corollary (Section 2.1)
+# --------------------------------------------------------------------------
+def _remaining(values, k: int):
+    v = np.asarray(values, dtype=np.float64)
+    order = np.argsort(-np.abs(v), kind="stable")
+    return v[order][:k], v[order][k:]
+
+
+def theorem2_expected_variance(values, k: int, hermitian: bool) -> float:
+    """E(Var(t(A_R))) after deflating the k values of largest modulus:
+    (N - k)(1 - 1/N)(V_k + mu_k^2) for non-Hermitian A, and
+    (N - k)(V_k N / (N + 1) + mu_k^2 k / (N + 1)) for Hermitian A."""
+    N = len(values)
+    _, r = _remaining(values, k)
+    if len(r) == 0:
+        return 0.0
+    mu = float(np.mean(r))
+    Vk = float(np.mean((r - mu) ** 2))
+    if not hermitian:
+        return (N - k) * (1.0 - 1.0 / N) * (Vk + mu ** 2)
+    return (N - k) * (Vk * N / (N + 1) + mu ** 2 * k / (N + 1))
+
+
+def remark4_undeflated(values, hermitian: bool) -> float:
+    """k = 0: (N - 1)(V_0 + mu_0^2) non-Hermitian, N^2 V_0 / (N + 1) Hermitian."""
+    v = np.asarray(values, dtype=np.float64)
+    N = len(v)
+    mu, V0 = float(np.mean(v)), float(np.var(v))
+    return (N - 1) * (V0 + mu ** 2) if not hermitian else N * N * V0 / (N + 1)
+
+
+def corollary_hermitian_reduces(values, k: int) -> bool:
+    """Deflation lowers the expected variance of a Hermitian A iff
+    mu_0^2 - ((N - k) / N)^2 mu_k^2 < (1/N) sum_{i <= k} sigma_i^2."""
+    v = np.asarray(values, dtype=np.float64)
+    N = len(v)
+    top, r = _remaining(v, k)
+    mu0, muk = float(np.mean(v)), float(np.mean(r))
+    return mu0 ** 2 - ((N - k) / N) ** 2 * muk ** 2 < float(np.sum(top ** 2)) / N
+
+
+def haar_unitary(N: int, rs) -> np.ndarray:
+    """A Haar-distributed N x N unitary: QR of a complex Gaussian matrix with the
+    phases of R's diagonal moved into Q (Mezzadri, Notices AMS 54, 2007)."""
+    Z = (rs.standard_normal((N, N)) + 1j * rs.standard_normal((N, N))) / np.sqrt(2.0)
+    Q, R = np.linalg.qr(Z)
+    d = np.diagonal(R)
+    return Q * (d / np.abs(d))[None, :]
+
+
+def random_vector_matrix(values, rs, hermitian: bool):
+    """(A, A_R-builder) with the given spectrum and Haar singular vectors:
+    A = U diag(sigma) V^H with independent U, V, or U diag(lambda) U^H."""
+    v = np.asarray(values, dtype=np.float64)
+    order = np.argsort(-np.abs(v), kind="stable")
+    v = v[order]
+    N = len(v)
+    U = haar_unitary(N, rs)
+    V = U if hermitian else haar_unitary(N, rs)
+    A = (U * v) @ V.conj().T
+
+    def remainder(k):
+        return (U[:, k:] * v[k:]) @ V[:, k:].conj().T
+
+    return A, remainder
+
+
+# --------------------------------------------------------------------------
+# distance profile W_d (Section 6.2)
+# --------------------------------------------------------------------------
+def torus_distance(a, b, L) -> int:
+    """Manhattan distance of two sites on the periodic lattice."""
+    d = 0
+    for mu in range(4):
+        x = abs(a[mu] - b[mu])
+        d += min(x, L[mu] - x)
+    return d
+
+
+def distance_profile(B: np.ndarray, rows, L):
+    """(W, m): W[i_row][d] = sum of |B_ij|^2 over the entries j (12 per site) whose
+    site lies at distance d from the site of row i, divided by m_d, the number of
+    such entries; the profile W_d of the paper is the mean of W over the rows."""
+    from .lattice import site_coords, volume
+    V = volume(L)
+    dmax = sum(l // 2 for l in L)
+    coords = [site_coords(n, L) for n in range(V)]
+    m = np.zeros(dmax + 1, dtype=np.int64)
+    for n in range(V):
+        m[torus_distance(coords[0], coords[n], L)] += 12
+    W = np.zeros((len(rows), dmax + 1))
+    for a, i in enumerate(rows):
+        si = coords[i // 12]
+        for n in range(V):
+            d = torus_distance(si, coords[n], L)
+            W[a, d] += float(np.sum(np.abs(B[i, 12 * n:12 * n + 12]) ** 2))
+    return W / m[None, :], m

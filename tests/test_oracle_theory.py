@@ -3,12 +3,27 @@
 - Theorem 1, eq. varAr: equals ||offdiag(A_R)||_F^2 computed directly, for a
   random complex matrix and for the inverse of a small Wilson matrix;
 - eq. vA-vAR: equals the difference of the two direct norms;
-- the 3x3 example of Section 2 reproduces the four regimes the paper states.
+- the 3x3 example of Section 2 reproduces the four regimes the paper states;
+- Theorem 2 (Section 2.1): the mean, over matrices with a fixed spectrum and
+  Haar-random singular vectors, of the exact Z4 variance ||offdiag(A_R)||_F^2
+  of the deflated remainder agrees with the predicted E(Var(t(A_R))) within
+  4 standard errors (non-Hermitian, Hermitian positive definite and
+  indefinite, several k); a multiple of the identity has zero variance, as
+  the Hermitian formula gives at k = 0; Remark 4 is the k = 0 case; the
+  Corollary's Hermitian condition is exactly "E_k < E_0", and for
+  non-Hermitian spectra E_k <= E_0 always;
+- the distance profile W_d (Section 6.2): the counts m_d are 12 times the
+  coefficients of the product of the four one-dimensional ring-distance
+  polynomials; sum_d m_d W_d is the squared norm of the row; with the 32
+  hierarchical-probing vectors' mask only distances that are multiples of 4
+  survive (the pattern the paper reports); and rows and columns of D^-1 and
+  of D^-1 - P have the same profile (g5-hermiticity: |B_ij| = |B_ji|), which
+  lets point-source solves (columns) stand for sampled rows.
 """
 import numpy as np
 import pytest
 
-from oracle import estimator, lattice, theory
+from oracle import estimator, lattice, rng, theory
 from paper_1603_05988_amd.workloads import gauge_links
 
 
@@ -44,3 +59,88 @@ def test_3x3_example_regimes():
     assert all(theory.example_3x3_ratio(1.0, d) > 1 for d in ds if d > 1.0 + 1e-9)
     # s = 2: reduction for all d (away from the degenerate d -> 0 limit)
     assert all(theory.example_3x3_ratio(2.0, d) > 1 for d in ds if d >= 0.05)
+
+
+SPECTRA = {
+    "nonherm": (lambda rs, N: 1.0 / (0.05 + rs.uniform(0, 1, N)), False),
+    "hpd": (lambda rs, N: 1.0 / (0.05 + rs.uniform(0, 1, N)), True),
+    "indefinite": (lambda rs, N: rs.choice([-1.0, 1.0], N) / (0.05 + rs.uniform(0, 1, N)), True),
+}
+
+
+@pytest.mark.parametrize("kind", list(SPECTRA))
+@pytest.mark.parametrize("k", [0, 3, 8])
+def test_theorem2_against_haar_monte_carlo(kind, k):
+    rs = np.random.default_rng(100 + k)
+    make, herm = SPECTRA[kind]
+    N, draws = 16, 2000
+    vals = make(rs, N)
+    var = np.empty(draws)
+    for j in range(draws):
+        _, rem = theory.random_vector_matrix(vals, rs, herm)
+        var[j] = estimator.offdiag_frobenius2(rem(k))
+    pred = theory.theorem2_expected_variance(vals, k, herm)
+    se = np.std(var, ddof=1) / np.sqrt(draws)
+    assert abs(var.mean() - pred) <= 4 * se, (var.mean(), pred, se)
+
+
+def test_theorem2_identity_and_remark4():
+    rs = np.random.default_rng(7)
+    A, _ = theory.random_vector_matrix(np.full(20, 2.5), rs, True)
+    assert estimator.offdiag_frobenius2(A) <= 1e-24
+    assert theory.theorem2_expected_variance(np.full(20, 2.5), 0, True) == 0.0
+    for herm in (False, True):
+        v = rs.uniform(-1, 3, 30) if herm else rs.uniform(0.1, 3, 30)
+        assert abs(theory.theorem2_expected_variance(v, 0, herm) - theory.remark4_undeflated(v, herm)) <= \
+            1e-12 * theory.remark4_undeflated(v, herm)
+
+
+def test_corollary():
+    rs = np.random.default_rng(8)
+    for trial in range(300):
+        N = int(rs.integers(4, 60))
+        k = int(rs.integers(1, N))
+        sv = np.exp(rs.normal(0, 1.5, N))
+        assert theory.theorem2_expected_variance(sv, k, False) <= theory.theorem2_expected_variance(sv, 0, False) * (1 + 1e-12)
+        lam = sv * rs.choice([-1.0, 1.0], N) if trial % 2 else sv
+        reduces = theory.theorem2_expected_variance(lam, k, True) < theory.theorem2_expected_variance(lam, 0, True)
+        assert theory.corollary_hermitian_reduces(lam, k) == reduces
+
+
+def test_distance_profile_pins():
+    L = (4, 2, 2, 2)
+    V = lattice.volume(L)
+    N = 12 * V
+    rs = np.random.default_rng(9)
+    B = rs.standard_normal((N, N)) + 1j * rs.standard_normal((N, N))
+    rows = [0, 13, 100, N - 1]
+    W, m = theory.distance_profile(B, rows, L)
+    poly = np.array([1])
+    for l in L:
+        ring = np.zeros(l // 2 + 1)
+        for x in range(l):
+            ring[min(x, l - x)] += 1
+        poly = np.polymul(poly, ring)
+    assert np.array_equal(m, 12 * poly.astype(np.int64))
+    assert np.allclose((W * m[None, :]).sum(axis=1), np.sum(np.abs(B[rows]) ** 2, axis=1), rtol=1e-12)
+
+
+def test_distance_profile_hp_mask_and_symmetry():
+    L = (4, 4, 4, 4)
+    U = gauge_links(L, 0.5, 4)
+    D = lattice.dense_wilson(U, L, -0.2)
+    V = lattice.volume(L)
+    g5 = lattice.gamma5_full(V)
+    Dinv = estimator.exact_inverse(D)
+    lam, W = estimator.q_eigenpairs(D, g5, 12)
+    AR = Dinv - estimator.deflation_matrix(W, estimator.galerkin_M(W, D, g5), g5)
+    rows = [5, 400, 2000]
+    for B in (Dinv, AR):
+        Wr, _ = theory.distance_profile(B, rows, L)
+        Wc, _ = theory.distance_profile(B.T, rows, L)
+        assert np.allclose(Wr, Wc, rtol=1e-9, atol=0)
+    colours = np.repeat(rng.hp_colours(L), 12)
+    mask = (colours[:, None] & 31) == (colours[None, :] & 31)
+    Wm, _ = theory.distance_profile(np.where(mask, Dinv, 0), rows, L)
+    d = np.arange(Wm.shape[1])
+    assert np.all(Wm[:, d % 4 != 0] == 0) and np.all(Wm[:, d % 4 == 0] > 0)
