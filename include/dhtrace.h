@@ -574,6 +574,52 @@ int dht_playback(const double* H, const double* G5, int k, int diagonal, const d
 /* The Galerkin matrices of the finalized basis (H, G5: 2 k^2 doubles each). */
 int dht_deflation_get_galerkin(dht_ctx* ctx, double* H, double* G5, int* diagonal);
 
+/* Theorem 2 (Section 2.1): the expected Z4 variance of the deflated estimator
+ * when the singular vectors are random unitary, from the mean mu_k and the
+ * variance V_k of the N - k values left after deflating the k of largest
+ * modulus: (N - k)(1 - 1/N)(V_k + mu_k^2) for a non-Hermitian matrix, and
+ * (N - k)(V_k N / (N + 1) + mu_k^2 k / (N + 1)) for a Hermitian one; var_0
+ * is Remark 4's undeflated value and `reduces` the Corollary's verdict
+ * (always 1 for non-Hermitian matrices).  Inputs (host): sumsq_all = the sum
+ * of the squares of all N values (||A||_F^2; for A = D^-1 the mean of
+ * ||D^-1 z||^2 over probes, or N times the mean squared row norm that
+ * dht_distance_profile samples); sum_all = the sum of all N values (needed
+ * for Hermitian matrices; for non-Hermitian ones only mu_k and V_k use it,
+ * NaN allowed); top = the k deflated values (for D^-1 = Q^-1 g5 these are
+ * 1 / |lambda| of the deflated eigenvalues of Q = g5 D).  For Hermitian
+ * matrices the values are the eigenvalues with their signs (equal to the
+ * singular values when positive definite).  Errors: DHT_ERR_INVALID_ARG for
+ * N < 1, k outside 0..N, non-finite input, or deflated squares above
+ * sumsq_all. */
+typedef struct dht_thm2 {
+    double var_k;     /* E(Var(t(A_R)))                                      */
+    double var_0;     /* E(Var(t(A))) (k = 0)                                */
+    double ratio;     /* var_k / var_0                                       */
+    double mu_k, V_k; /* mean and variance of the N - k remaining values     */
+    int reduces;      /* 1 if var_k < var_0                                  */
+} dht_thm2;
+int dht_theorem2(int64_t N, int k, int hermitian, double sum_all, double sumsq_all, const double* top, dht_thm2* out);
+
+/* The distance profile W_d of Section 6.2, for nrows sampled rows (matrix
+ * indices n = 12 site + 3 spin + colour, host array) of B = D^-1, or of the
+ * deflated remainder D^-1 - P (deflate != 0, current finalized basis), each
+ * optionally masked to the entries that the first hp_vectors
+ * hierarchical-probing vectors leave in the variance (hp_vectors = 2^m: the
+ * entries whose sites' colours agree on the low m bits; 0 = no mask).
+ * W_host[r][d] (host, nrows x (dmax + 1), dmax = sum_mu L_mu / 2) receives the
+ * sum of |B_ij|^2 over the entries j whose site lies at torus Manhattan
+ * distance d from the site of row i = rows[r], divided by m_d, the number of
+ * such entries (12 per site); m_host (host, dmax + 1, may be NULL) receives
+ * m_d.  The paper's W_d is the mean of W_host over the rows.  Each row is
+ * obtained as a column (|B_ij| = |B_ji| by g5-hermiticity of D and P): one
+ * point-source solve with prm per row, batched by 16, minus W M (W^H g5 e_i)
+ * when deflated.  Returns DHT_ERR_NOT_CONVERGED (with every row filled) if
+ * a solve missed the tolerance.  Errors: DHT_ERR_INVALID_ARG for a row
+ * outside 0..N-1 or hp_vectors not 0 or a power of two <= 65536;
+ * DHT_ERR_STATE without gauge field, or with deflate and no finalized basis. */
+int dht_distance_profile(dht_ctx* ctx, const int64_t* rows, int nrows, int deflate, int hp_vectors,
+                         const dht_solver_params* prm, double* W_host, int64_t* m_host);
+
 /* Batch-size tuner (the right-hand sides per dht_trace_batch call): for each
  * candidate batch whose planned workspace (dht_workspace_size with prm) fits
  * mem_budget bytes (0: 90% of the device memory free now plus the workspace

@@ -160,21 +160,32 @@ def torus_distance(a, b, L) -> int:
     return d
 
 
-def distance_profile(B: np.ndarray, rows, L):
-    """(W, m): W[i_row][d] = sum of |B_ij|^2 over the entries j (12 per site) whose
-    site lies at distance d from the site of row i, divided by m_d, the number of
-    such entries; the profile W_d of the paper is the mean of W over the rows."""
+def distance_counts(L) -> np.ndarray:
+    """m_d: the number of entries (12 per site) at distance d from a site."""
     from .lattice import site_coords, volume
     V = volume(L)
-    dmax = sum(l // 2 for l in L)
-    coords = [site_coords(n, L) for n in range(V)]
-    m = np.zeros(dmax + 1, dtype=np.int64)
+    o = site_coords(0, L)
+    m = np.zeros(sum(l // 2 for l in L) + 1, dtype=np.int64)
     for n in range(V):
-        m[torus_distance(coords[0], coords[n], L)] += 12
-    W = np.zeros((len(rows), dmax + 1))
-    for a, i in enumerate(rows):
-        si = coords[i // 12]
-        for n in range(V):
-            d = torus_distance(si, coords[n], L)
-            W[a, d] += float(np.sum(np.abs(B[i, 12 * n:12 * n + 12]) ** 2))
+        m[torus_distance(o, site_coords(n, L), L)] += 12
+    return m
+
+
+def distance_sums(v: np.ndarray, i: int, L) -> np.ndarray:
+    """sum of |v_j|^2 over the entries j whose site lies at distance d from the
+    site of entry i, for every d (v: one row of B, length 12 V)."""
+    from .lattice import site_coords, volume
+    V = volume(L)
+    si = site_coords(i // 12, L)
+    out = np.zeros(sum(l // 2 for l in L) + 1)
+    for n in range(V):
+        out[torus_distance(si, site_coords(n, L), L)] += float(np.sum(np.abs(v[12 * n:12 * n + 12]) ** 2))
+    return out
+
+
+def distance_profile(B: np.ndarray, rows, L):
+    """(W, m): W[a][d] = distance_sums(row rows[a] of B)[d] / m_d; the profile
+    W_d of the paper is the mean of W over the sampled rows."""
+    m = distance_counts(L)
+    W = np.array([distance_sums(B[i], i, L) for i in rows])
     return W / m[None, :], m

@@ -85,6 +85,11 @@ class HPVar(ctypes.Structure):
                 ("rs", ctypes.c_double), ("rs_err", ctypes.c_double)]
 
 
+class Thm2(ctypes.Structure):
+    _fields_ = [("var_k", ctypes.c_double), ("var_0", ctypes.c_double), ("ratio", ctypes.c_double),
+                ("mu_k", ctypes.c_double), ("V_k", ctypes.c_double), ("reduces", ctypes.c_int)]
+
+
 class Estimate(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("mean_re", ctypes.c_double), ("mean_im", ctypes.c_double),
                 ("mean_defl_re", ctypes.c_double), ("mean_defl_im", ctypes.c_double),
@@ -132,6 +137,9 @@ SIGNATURES = {
                              ctypes.POINTER(Record), _dp]),
     "dht_estimate_get": (_i, [_vp, ctypes.POINTER(Estimate)]),
     "dht_gamma_set": (_i, [_vp, _dp, _i, _dp]),
+    "dht_theorem2": (_i, [_i64, _i, _i, ctypes.c_double, ctypes.c_double, _dp, ctypes.POINTER(Thm2)]),
+    "dht_distance_profile": (_i, [_vp, ctypes.POINTER(_i64), _i, _i, _i, ctypes.POINTER(SolverParams), _dp,
+                                  ctypes.POINTER(_i64)]),
     "dht_trace_gamma_batch": (_i, [_vp, ctypes.POINTER(ProbeSpec), _i64, _i, ctypes.POINTER(SolverParams),
                                    ctypes.POINTER(Record)]),
     "dht_gamma_estimate_get": (_i, [_vp, _i, ctypes.POINTER(Estimate)]),
@@ -192,6 +200,15 @@ def hp_variance(q, s_list, v_stoc: float = 0.0):
     out = (HPVar * len(s_list))()
     check(load().dht_hp_variance(q.view(np.float64).ctypes.data_as(_dp), R, S, sl, len(s_list), float(v_stoc), out))
     return [{f[0]: getattr(o, f[0]) for f in HPVar._fields_} for o in out]
+
+
+def theorem2(N: int, k: int, hermitian: bool, sum_all: float, sumsq_all: float, top) -> dict:
+    """Theorem 2's expected deflated variance (and Remark 4's undeflated one)."""
+    top = np.ascontiguousarray(np.asarray(top, dtype=np.float64).reshape(-1))
+    out = Thm2()
+    check(load().dht_theorem2(int(N), int(k), int(hermitian), float(sum_all), float(sumsq_all),
+                              top.ctypes.data_as(_dp) if top.size else None, ctypes.byref(out)))
+    return {f[0]: getattr(out, f[0]) for f in Thm2._fields_}
 
 
 def playback(H, G5, coef, q, k_list, diagonal: bool = False):
@@ -494,6 +511,19 @@ class Context:
         stats = [dict(iters=r.s.iters, outer=r.s.outer, true_resid=r.s.true_resid, status=r.s.status)
                  for r in rec[:nrhs]]
         return q, qd, stats
+
+    def distance_profile(self, rows, prm: SolverParams, deflate: bool = False, hp_vectors: int = 0,
+                         allow_not_converged: bool = False):
+        """(W [nrows][dmax+1], m [dmax+1]): Section 6.2's distance profile of sampled rows."""
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).reshape(-1))
+        nd = sum(l // 2 for l in self.L) + 1
+        W = np.zeros((rows.size, nd))
+        m = np.zeros(nd, dtype=np.int64)
+        allow = (DHT_ERR_NOT_CONVERGED,) if allow_not_converged else ()
+        check(load().dht_distance_profile(self.h, rows.ctypes.data_as(ctypes.POINTER(_i64)), rows.size, int(deflate),
+                                          int(hp_vectors), ctypes.byref(prm), _np_dp(W),
+                                          m.ctypes.data_as(ctypes.POINTER(_i64))), allow)
+        return W, m
 
     def gamma_estimate(self, g: int):
         e = Estimate()

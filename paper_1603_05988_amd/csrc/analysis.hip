@@ -149,6 +149,36 @@ int dht_playback(const double* H, const double* G5, int k, int diagonal, const d
     return DHT_OK;
 }
 
+int dht_theorem2(int64_t N, int k, int hermitian, double sum_all, double sumsq_all, const double* top,
+                 dht_thm2* out) {
+    if (!out || N < 1 || k < 0 || k > N || (k > 0 && !top)) return set_error(DHT_ERR_INVALID_ARG, "bad argument");
+    if (!isfinite(sumsq_all) || sumsq_all < 0 || (hermitian && !isfinite(sum_all)))
+        return set_error(DHT_ERR_INVALID_ARG, "sums must be finite (the plain sum is needed for Hermitian matrices)");
+    double st = 0.0, st2 = 0.0;
+    for (int i = 0; i < k; i++) {
+        if (!isfinite(top[i])) return set_error(DHT_ERR_INVALID_ARG, "non-finite deflated value");
+        st += top[i];
+        st2 += top[i] * top[i];
+    }
+    const double rest2 = sumsq_all - st2;   // sum of the squares of the N - k remaining values
+    if (rest2 < -1e-12 * sumsq_all) return set_error(DHT_ERR_INVALID_ARG, "deflated values exceed the total sum of squares");
+    const double Nd = (double)N, nr = (double)(N - k);
+    memset(out, 0, sizeof(*out));
+    out->mu_k = N > k ? (sum_all - st) / nr : 0.0;
+    out->V_k = N > k ? std::max(0.0, rest2) / nr - out->mu_k * out->mu_k : 0.0;
+    const double mu0 = sum_all / Nd, V0 = sumsq_all / Nd - mu0 * mu0;
+    if (!hermitian) {
+        out->var_k = (1.0 - 1.0 / Nd) * std::max(0.0, rest2);   // (N - k)(1 - 1/N)(V_k + mu_k^2)
+        out->var_0 = (1.0 - 1.0 / Nd) * sumsq_all;              // (N - 1)(V_0 + mu_0^2)
+    } else {
+        out->var_k = nr * (out->V_k * Nd / (Nd + 1.0) + out->mu_k * out->mu_k * k / (Nd + 1.0));
+        out->var_0 = Nd * Nd * V0 / (Nd + 1.0);
+    }
+    out->ratio = out->var_0 > 0 ? out->var_k / out->var_0 : NAN;
+    out->reduces = out->var_k < out->var_0 ? 1 : 0;
+    return DHT_OK;
+}
+
 int dht_deflation_get_galerkin(dht_ctx* c, double* H, double* G5, int* diagonal) {
     if (!c || !H || !G5 || !diagonal) return set_error(DHT_ERR_INVALID_ARG, "null argument");
     if (!c->defl_ready || c->Hq.empty()) return set_error(DHT_ERR_STATE, "deflation not finalized");

@@ -678,6 +678,37 @@ int project_field_sp(dht_ctx* c, const void* Z, int nrhs, Cx<double>* P) {
     return DHT_OK;
 }
 
+// X[K][r] -= sum_a W_a(K) v[a][r] (X: FP64 full field [2][12][Vh][bp]; v: device [k][bp])
+template <typename SW>
+__global__ void basis_subtract_kernel(const typename Store<SW>::elem* W, WLayout wl, const Cx<double>* v, int k,
+                                      int bp, Cx<double>* X) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= wl.Kn * bp) return;
+    const int64_t K = gid / bp;
+    const int r = (int)(gid - K * bp);
+    Cx<double> acc = cmake(0.0, 0.0);
+    for (int a = 0; a < k; a++) {
+        auto w = Store<SW>::ld(W + w_index(wl, a, K));
+        acc = acc + cmake<double>(w.re, w.im) * v[(int64_t)a * bp + r];
+    }
+    X[gid] = X[gid] - acc;
+}
+
+int basis_subtract(dht_ctx* c, const Cx<double>* v, int bp, void* X) {
+    if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "no deflation basis");
+    const WLayout wl = wlayout(c);
+    const int64_t tot = wl.Kn * bp;
+    dim3 grid((unsigned)((tot + 255) / 256)), block(256);
+    switch (c->wprec) {
+        case DHT_FP64: hipLaunchKernelGGL(basis_subtract_kernel<double>, grid, block, 0, c->stream, (const Cx<double>*)c->W, wl, v, c->k, bp, (Cx<double>*)X); break;
+        case DHT_FP32: hipLaunchKernelGGL(basis_subtract_kernel<float>, grid, block, 0, c->stream, (const Cx<float>*)c->W, wl, v, c->k, bp, (Cx<double>*)X); break;
+        case DHT_BF16: hipLaunchKernelGGL(basis_subtract_kernel<bf16x2>, grid, block, 0, c->stream, (const bf16x2*)c->W, wl, v, c->k, bp, (Cx<double>*)X); break;
+        default: return set_error(DHT_ERR_INVALID_ARG, "bad basis precision");
+    }
+    DHT_HIP(hipGetLastError());
+    return DHT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // basis management
 // ---------------------------------------------------------------------------

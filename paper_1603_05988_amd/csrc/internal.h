@@ -209,6 +209,21 @@ __device__ __host__ inline int64_t lex_index(const Geom& g, const int c[4]) {
     return (int64_t)c[0] + (int64_t)g.L[0] * ((int64_t)c[1] + (int64_t)g.L[1] * ((int64_t)c[2] + (int64_t)g.L[2] * c[3]));
 }
 
+// hierarchical-probing colour bits of a site for the levels that probe index j
+// reaches (bit 4l = parity of sum_mu floor(x_mu / 2^l), bits 4l+1..4l+3 =
+// floor(x_mu / 2^l) mod 2 for mu = x, y, z); the sign of probe j is
+// (-1)^popcount(colour & j) (Section 5.2)
+__device__ __host__ inline uint64_t hp_colour_bits(const int c[4], uint64_t j) {
+    uint64_t col = 0;
+    for (int l = 0; l < 16 && (j >> (4 * l)) != 0; l++) {
+        int q0 = c[0] >> l, q1 = c[1] >> l, q2 = c[2] >> l, q3 = c[3] >> l;
+        uint64_t bits = (uint64_t)((q0 + q1 + q2 + q3) & 1) | ((uint64_t)(q0 & 1) << 1) |
+                        ((uint64_t)(q1 & 1) << 2) | ((uint64_t)(q2 & 1) << 3);
+        col |= bits << (4 * l);
+    }
+    return col;
+}
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
@@ -372,7 +387,7 @@ enum Slot {
     WS_EIG_V, WS_EIG_W, WS_EIG_T, WS_EIG_U, WS_EIG_PART, WS_EIG_SMALL, WS_EIG_RPART, WS_EIG_LAM, WS_EIG_CANON, WS_DEFL_GET,
     WS_PW_CODE, WS_PW_COEF,
     WS_RING_P, WS_RING_S, WS_HIST, WS_HIST_SCALE, WS_E32, WS_W32, WS_T32, WS_S16,
-    WS_GAM_PART, WS_GAM_FPART, WS_GAM_OUT, WS_GAM_CODE,
+    WS_GAM_PART, WS_GAM_FPART, WS_GAM_OUT, WS_GAM_CODE, WS_WD_PART, WS_WD_OUT,
     WS_NSLOTS
 };
 int ws_get(dht_ctx* c, int slot, size_t bytes, void** out);

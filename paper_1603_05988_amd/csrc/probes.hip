@@ -31,17 +31,6 @@ __host__ __device__ inline uint64_t sm64_out(uint64_t state, uint64_t i) {
     return sm64_mix(state + (i + 1) * 0x9E3779B97F4A7C15ull);
 }
 
-__device__ inline uint64_t hp_colour_bits(const int c[4], uint64_t j) {
-    uint64_t col = 0;
-    for (int l = 0; l < 16 && (j >> (4 * l)) != 0; l++) {
-        int q0 = c[0] >> l, q1 = c[1] >> l, q2 = c[2] >> l, q3 = c[3] >> l;
-        uint64_t bits = (uint64_t)((q0 + q1 + q2 + q3) & 1) | ((uint64_t)(q0 & 1) << 1) |
-                        ((uint64_t)(q1 & 1) << 2) | ((uint64_t)(q2 & 1) << 3);
-        col |= bits << (4 * l);
-    }
-    return col;
-}
-
 struct ProbeArgs {
     Geom g;
     int n;      // real probes

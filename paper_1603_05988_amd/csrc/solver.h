@@ -174,5 +174,7 @@ int project_codes(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* c1, Cx<do
 // over FP64 probe fields (any basis precision)
 int project_codes_sp(dht_ctx* c, const uint8_t* zc, int nrhs, Cx<double>* P);
 int project_field_sp(dht_ctx* c, const void* Z, int nrhs, Cx<double>* P);
+// X -= W v for an FP64 full field X of bp columns (v: device [k][bp])
+int basis_subtract(dht_ctx* c, const Cx<double>* v, int bp, void* X);
 
 }  // namespace dht
