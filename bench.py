@@ -193,6 +193,21 @@ def train_network(L, torch, np, npairs: int, epochs: int):
                      "heldout_loss_jacobi_only": l_jac, "heldout_loss_trained": l_tr}
 
 
+def dirac_basis(np):
+    """The 16 products of the chiral-basis gamma matrices (g5 = diag(1, 1, -1, -1))."""
+    sig = [np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]])]
+    z, one = np.zeros((2, 2)), np.eye(2)
+    g = [np.block([[z, -1j * s_], [1j * s_, z]]) for s_ in sig] + [np.block([[z, one], [one, z]])]
+    out = []
+    for mask in range(16):
+        m = np.eye(4, dtype=np.complex128)
+        for mu in range(4):
+            if mask >> mu & 1:
+                m = m @ g[mu]
+        out.append(m)
+    return np.array(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +225,8 @@ def main():
     ap.add_argument("--tune", default="auto", choices=["auto", "off"],
                     help="autotune the hopping-kernel shape before timing (off: built-in default)")
     ap.add_argument("--tune-cache", default=None, help="JSON table to load the shapes from / save them to")
+    ap.add_argument("--gamma-steps", type=int, default=2,
+                    help="timed batches of Tr(Gamma D^-1) for the 16 Dirac matrices at once (0: skip)")
     ap.add_argument("--nn-steps", type=int, default=2, help="timed batches of FGMRES + learned preconditioner (0: skip)")
     ap.add_argument("--nn-pairs", type=int, default=20480, help="training pairs of the network (8^3x16 recipe)")
     ap.add_argument("--nn-epochs", type=int, default=4)
@@ -372,6 +389,35 @@ def main():
         fp64_value = args.fp64_steps * B / el64
         log("fp64: %.2f ms/step, %.2f RHS/s" % (1e3 * el64 / args.fp64_steps, fp64_value))
 
+    # the traces Tr(Gamma D^-1) of all 16 Dirac matrices from the same solves
+    # and deflation space (spin-pair projections and quadratic forms)
+    gam = None
+    if args.gamma_steps > 0:
+        td_g = ctx.gamma_set(dirac_basis(np))
+        ctx.trace_gamma_batch(w.seed, 0, w.hp, 0, B, prm, allow_not_converged=True)   # warm-up
+        ctx.profile(True)
+        ctx.profile_reset()
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for s_ in range(args.gamma_steps):
+            ctx.trace_gamma_batch(w.seed, 0, w.hp, (s_ * B) % nprobe, B, prm, allow_not_converged=True)
+        torch.cuda.synchronize()
+        elg = time.time() - t0
+        ctx.profile(False)
+        sp = ctx.profile_get("proj_sp")
+        gam = {"value": round(args.gamma_steps * B / elg, 3), "unit": "probes/s (16 traces each)",
+               "ms_per_step": round(1e3 * elg / args.gamma_steps, 1), "matrices": 16,
+               "time_vs_one_trace": round((elg / args.gamma_steps) / (ms_step / 1e3), 3)}
+        if sp["count"]:
+            gam["proj_sp"] = {"launches": sp["count"], "avg_launch_ms": round(sp["ms"] / sp["count"], 3),
+                              "alg_GBps": round(sp["bytes"] / sp["ms"] / 1e6, 1),
+                              "share_of_step": round(sp["ms"] / (1e3 * elg), 3)}
+        log("gamma traces: %.1f ms/step (%.3f of a plain trace step), %.2f probes/s for 16 matrices%s"
+            % (gam["ms_per_step"], gam["time_vs_one_trace"], gam["value"],
+               (", spin-pair projection %.2f ms/launch at %.0f GB/s" % (gam["proj_sp"]["avg_launch_ms"],
+                                                                        gam["proj_sp"]["alg_GBps"]))
+               if "proj_sp" in gam else ""))
+
     # the learned leg: FGMRES(restart) with the network as right preconditioner
     # inside FP64 defect correction, same probes and projection window
     learned = None
@@ -445,6 +491,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "small_configs": small,
+        "gamma_traces": gam,
         "mixed_learned": learned,
         "mixed_learned_value": learned["value"] if learned else None,
         "fp64_bicgstab_value": round(fp64_value, 3) if fp64_value else None,

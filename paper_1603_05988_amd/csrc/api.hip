@@ -217,6 +217,20 @@ static double elapsed(dht_ctx* c, int a, int b) {
     return ms;
 }
 
+int side_stream(dht_ctx* c) {
+    if (c->side) return DHT_OK;
+    DHT_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    for (int i = 0; i < 4; i++) {
+        if (hipEventCreate(&c->side_ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; j++) (void)hipEventDestroy(c->side_ev[j]);
+            (void)hipStreamDestroy(c->side);
+            c->side = nullptr;
+            return set_error(DHT_ERR_HIP, "hipEventCreate failed");
+        }
+    }
+    return DHT_OK;
+}
+
 }  // namespace dht
 
 using namespace dht;
@@ -621,20 +635,6 @@ int dht_project_probes(dht_ctx* c, const dht_probe_spec* spec, int64_t first, in
         DHT_TRY(project_field(c, buf, DHT_FP64, bp, d1, d2));
     }
     return copy_coefs(c, d1, d2, bp, nrhs, c1h, c2h);
-}
-
-static int side_stream(dht_ctx* c) {
-    if (c->side) return DHT_OK;
-    DHT_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-    for (int i = 0; i < 4; i++) {
-        if (hipEventCreate(&c->side_ev[i]) != hipSuccess) {
-            for (int j = 0; j < i; j++) (void)hipEventDestroy(c->side_ev[j]);
-            (void)hipStreamDestroy(c->side);
-            c->side = nullptr;
-            return set_error(DHT_ERR_HIP, "hipEventCreate failed");
-        }
-    }
-    return DHT_OK;
 }
 
 int dht_set_projection_window(dht_ctx* c, int nprobes) {

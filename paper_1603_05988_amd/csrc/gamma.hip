@@ -227,25 +227,44 @@ int dht_trace_gamma_batch(dht_ctx* c, const dht_probe_spec* spec, int64_t first,
     Cx<double>* dQ = (Cx<double>*)outb;
     Cx<double>* dP = dQ + pq;
     DHT_TRY(probes_gen(c, spec, first, nrhs, bp, fz, DHT_FP64, nullptr, nullptr, nullptr));
-    if (k > 0) {
-        // the 16 spin-pair projections of every probe (the solve below does not touch fz)
+    // The 16 spin-pair projections of every probe run on the side stream while
+    // the main stream solves: with a BF16 basis they regenerate the probes as
+    // codes of their own; otherwise they read fz, which the solve only reads.
+    const bool side = k > 0;
+    if (side) {
+        DHT_TRY(side_stream(c));
+        DHT_HIP(hipEventRecord(c->side_ev[0], c->stream));
+        DHT_HIP(hipStreamWaitEvent(c->side, c->side_ev[0], 0));
+        hipStream_t main_stream = c->stream;
+        c->stream = c->side;
+        int prc = DHT_OK;
         if (mfma) {
-            void* zc;
-            DHT_TRY(ws_get(c, WS_GAM_CODE, full_elems(c, slice), &zc));
-            for (int sl = 0; sl < nslice; sl++) {
+            void* zc = nullptr;
+            prc = ws_get(c, WS_GAM_CODE, full_elems(c, slice), &zc);
+            for (int sl = 0; sl < nslice && prc == DHT_OK; sl++) {
                 const int n0 = sl * slice, n = std::min(slice, nrhs - n0);
-                DHT_TRY(probes_gen(c, spec, first + n0, n, n, nullptr, DHT_FP64, nullptr, nullptr, (uint8_t*)zc));
-                DHT_TRY(project_codes_sp(c, (const uint8_t*)zc, n, dP + pn * sl));
+                prc = probes_gen(c, spec, first + n0, n, n, nullptr, DHT_FP64, nullptr, nullptr, (uint8_t*)zc);
+                if (prc == DHT_OK) prc = project_codes_sp(c, (const uint8_t*)zc, n, dP + pn * sl);
             }
         } else {
-            DHT_TRY(project_field_sp(c, fz, bp, dP));
+            prc = project_field_sp(c, fz, bp, dP);
+        }
+        if (prc == DHT_OK && hipEventRecord(c->side_ev[2], c->side) != hipSuccess) prc = set_error(DHT_ERR_HIP, "event");
+        c->stream = main_stream;
+        if (prc != DHT_OK) {
+            (void)hipStreamSynchronize(c->side);
+            return prc;
         }
     }
     std::vector<dht_solve_stats> st(bp);
     std::vector<double> zn2(bp, 0.0);
     for (int r = 0; r < nrhs; r++) zn2[r] = (double)(12 * c->g.V);
     int rc = solve_fields(c, prm, fz, fx, bp, st.data(), zn2.data(), nullptr, DHT_FP64);
-    if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) return rc;
+    if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) {
+        if (side) (void)hipStreamSynchronize(c->side);   // the next call rewrites its inputs
+        return rc;
+    }
+    if (side) DHT_HIP(hipStreamWaitEvent(c->stream, c->side_ev[2], 0));
     const std::string msg = dht_last_error();   // the solve's message, if it missed the tolerance
     DHT_TRY(spin_pair_forms(c, fz, fx, bp, (Cx<double>*)part, dQ));
     std::vector<Cx<double>> h(pq + pn * nslice);

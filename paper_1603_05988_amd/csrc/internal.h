@@ -400,6 +400,8 @@ inline void plan_max(size_t* plan, int slot, size_t bytes) {
 int prof_begin(dht_ctx* c, int* token);
 int prof_end(dht_ctx* c, int token, int cls, double bytes);
 int prof_harvest(dht_ctx* c);   // after a stream synchronisation
+// the context's second stream (default priority) and its events, created on first use
+int side_stream(dht_ctx* c);
 
 // field helpers -------------------------------------------------------------
 // (nrhs is the padded power-of-two batch in every internal call)
