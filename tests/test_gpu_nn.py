@@ -2,8 +2,13 @@
 
 The preconditioner is M(r) = net(r) + s r (s = 0, or 1 / (4 + m) for the
 point-Jacobi-plus-correction form).  Tolerances: the network runs on BF16 matrix cores (8-bit mantissas on
-weights and activations, FP32 accumulation), so outputs and the loss are
-compared to the FP64 oracle at 2e-2 relative (Frobenius), gradients at 5e-2;
+weights and activations, FP32 accumulation).  Measured over 3 weight seeds x 2 skips: forward 3.8-4.6e-3
+relative (Frobenius; largest element error 4.8e-3 of the largest element), loss 1e-4..4e-4, gradients of
+layers 2 and 3 2.0-5.3e-3, of layer 1 3.8-4.4e-2.  So the forward pass is held to 1e-2 both in norm and
+element by element (against the largest element), the loss to 2e-3, the gradients of layers 2 and 3 to
+2e-2; the first layer's gradient sums products of the raw input with a signal back-propagated through
+two BF16 layers over every site and sample, terms of both signs that cancel to a small total, so its
+relative error is that of the terms times the cancellation ratio: held to 5e-2;
 training pairs satisfy D e = r to the accuracy of the 1e-12 reference solve;
 FGMRES solutions match LU to the solve tolerance.
 """
@@ -69,7 +74,8 @@ def test_forward_matches_oracle(c1, skip):
     x = nn.spinor_to_channels(X.reshape(3, -1))
     y, _ = nn.forward(x, Ws, w.L, skip)
     ref = nn.channels_to_spinor(y)
-    assert rel(Y, ref) <= 2e-2, rel(Y, ref)
+    assert rel(Y, ref) <= 1e-2, rel(Y, ref)
+    assert np.abs(Y - ref).max() <= 1e-2 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("skip", SKIPS)
@@ -84,9 +90,9 @@ def test_gradient_matches_oracle(c1, skip):
     ctx.nn_set_skip(0.0)
     lref, gref = nn.loss_and_grad(nn.spinor_to_channels(R.reshape(4, -1)), nn.spinor_to_channels(E.reshape(4, -1)),
                                   Ws, w.L, skip)
-    assert abs(loss - lref) <= 2e-2 * lref
-    for l in range(3):
-        assert rel(grads[l], gref[l]) <= 5e-2, (l, rel(grads[l], gref[l]))
+    assert abs(loss - lref) <= 2e-3 * lref
+    for l, tol in enumerate((5e-2, 2e-2, 2e-2)):
+        assert rel(grads[l], gref[l]) <= tol, (l, rel(grads[l], gref[l]))
 
 
 def test_pairs_satisfy_residual_equation(c1):
