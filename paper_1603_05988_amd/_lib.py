@@ -493,10 +493,11 @@ class Context:
     def gamma_set(self, gammas) -> np.ndarray:
         """Register spin matrices (array [ng][4][4] complex); returns T_D(Gamma) per matrix."""
         G = np.ascontiguousarray(np.asarray(gammas, dtype=np.complex128).reshape(-1, 4, 4))
-        self._ng = G.shape[0]
-        td = np.zeros(self._ng, dtype=np.complex128)
-        check(load().dht_gamma_set(self.h, _np_dp(G.view(np.float64)), self._ng, _np_dp(td.view(np.float64))))
-        return td
+        ng = G.shape[0]
+        td = np.zeros(max(1, ng), dtype=np.complex128)
+        check(load().dht_gamma_set(self.h, _np_dp(G.view(np.float64)), ng, _np_dp(td.view(np.float64))))
+        self._ng = ng   # only once the library has accepted them
+        return td[:ng]
 
     def trace_gamma_batch(self, seed: int, run: int, hp: bool, first: int, nrhs: int, prm: SolverParams,
                           allow_not_converged: bool = False):

@@ -217,3 +217,27 @@ def test_gamma_corrections_c2_bf16_diagonal():
         bound = mfma_bound(Wr, M, g5, Z, G[g]) + 1e-12 * np.abs(q[g]).max()
         assert np.all(np.abs((q[g] - qd[g]) - d_ref) <= bound), g
     ctx.close()
+
+
+def test_two_row_tiles_and_four_slices(c1):
+    """k = 40 (two MFMA row tiles of 32, the second padded) and 64 probes (four
+    spin-pair passes of 16) with a BF16 basis and a full Galerkin M."""
+    w, D, Dinv, g5, W, ctx = c1
+    L = _lib()
+    lam, W40 = estimator.q_eigenpairs(D, g5, 40)
+    ctx.set_deflation(cuda(W40.T), L.BF16)
+    Wr = round_storage(W40, 2)
+    M = estimator.galerkin_M(Wr, D, g5)
+    G = gammas()[[2, 9, 16]]
+    td = ctx.gamma_set(G)
+    for g in range(len(G)):
+        ref = gamma.gamma_deflated_trace(Wr, M, g5, G[g])
+        assert abs(td[g] - ref) <= 1e-10 * max(1.0, abs(ref))
+    prm = ctx.params(L.SOLVER_BICGSTAB_FP64, tol=1e-12)
+    q, qd, _ = ctx.trace_gamma_batch(w.seed, 4, False, 0, 64, prm)
+    Z = rng.probes(w.L, w.seed, 4, False, 0, 64)
+    for g in range(len(G)):
+        d_ref = gamma.gamma_corrections(Wr, M, g5, Z, G[g])
+        bound = mfma_bound(Wr, M, g5, Z, G[g]) + 1e-12 * np.abs(q[g]).max()
+        assert np.all(np.abs((q[g] - qd[g]) - d_ref) <= bound), g
+    ctx.clear_deflation()

@@ -136,3 +136,21 @@ def test_report_profiles_c2():
         with open("gpurun_out/wd_profile_c2.json", "w") as f:
             json.dump(out, f, indent=1)
     ctx.close()
+
+
+def test_profile_c1_fp32_basis_full_M(c1):
+    """The deflated profile with an FP32 basis and the Galerkin M of the stored vectors."""
+    w, D, ctx = c1
+    L = _lib()
+    g5 = lattice.gamma5_full(w.V)
+    lam, W = estimator.q_eigenpairs(D, g5, 12)
+    ctx.set_deflation(cuda(W.T), L.FP32)
+    f = np.stack([W.real, W.imag], axis=-1).astype(np.float32).astype(np.float64)
+    Wr = f[..., 0] + 1j * f[..., 1]
+    B = estimator.exact_inverse(D) - estimator.deflation_matrix(Wr, estimator.galerkin_M(Wr, D, g5), g5)
+    rows = np.array([0, 1234, 3000])
+    Wg, m = ctx.distance_profile(rows, ctx.params(L.SOLVER_BICGSTAB_FP64, tol=1e-12), deflate=True)
+    Wref, _ = theory.distance_profile(B, rows, w.L)
+    for a in range(len(rows)):
+        assert np.abs(Wg[a] - Wref[a]).max() <= 1e-9 * Wref[a].max()
+    ctx.clear_deflation()
