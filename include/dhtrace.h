@@ -281,6 +281,41 @@ typedef struct dht_eig_stats {
  * max_iter cycles. */
 int dht_deflation_eigensolve(dht_ctx* ctx, const dht_eig_params* prm, double* lambda_host, double* resid_host,
                              dht_eig_stats* stats);
+/* Preconditioned block eigensolver with locking (Section 5.1: the paper
+ * computes its deflation space with a preconditioned Davidson-type method,
+ * a window of block vectors and locking).  LOBPCG on Q^2 = D^H D for its k
+ * smallest eigenvalues sigma^2 (sigma: the smallest singular values of D):
+ * a window of `block` (32 or 64) vectors, the preconditioned residuals and
+ * the previous directions, a Rayleigh-Ritz step on the three blocks per
+ * iteration; a leading Ritz vector is locked once ||Q^2 x - sigma^2 x|| <=
+ * tol ||Q||^2 (||Q|| taken as |4 + m| + 4), and its window slot refilled with
+ * Z4 noise.  precond != 0 applies (Q^2)^-1 = D^-1 g5 D^-1 g5 approximately by
+ * two mixed-precision (BF16) BiCGStab solves to the relative residual
+ * precond_tol each; precond = 0 runs plain LOBPCG.  The k locked vectors fill
+ * the columns set up by dht_deflation_begin (rounded to the storage
+ * precision; any basis of the space serves the Galerkin finalize that must
+ * follow).  sigma_host and resid_host (k doubles each, may be NULL) receive
+ * sigma and the relative residual of each locked vector in locking order.
+ * Returns DHT_ERR_NOT_CONVERGED (basis filled with the best Ritz vectors) if
+ * fewer than k converged within max_iter iterations.  Errors:
+ * DHT_ERR_INVALID_ARG for bad parameters, DHT_ERR_STATE without gauge field
+ * or dht_deflation_begin, DHT_ERR_BREAKDOWN if a block loses rank. */
+typedef struct dht_lobpcg_params {
+    double tol;          /* locking threshold, relative to ||Q||^2          */
+    int max_iter;        /* cap on block iterations                         */
+    int block;           /* window size: 32 or 64                           */
+    int precond;         /* 1: two loose solves with D; 0: none             */
+    double precond_tol;  /* relative residual of each preconditioner solve  */
+    uint64_t seed;       /* Z4 noise of the start and refill vectors        */
+} dht_lobpcg_params;
+typedef struct dht_lobpcg_stats {
+    int iters;                /* block iterations                            */
+    int converged;            /* locked vectors within tol                   */
+    int64_t q_applications;   /* applications of Q to a whole block          */
+    int64_t precond_solves;   /* right-hand sides solved by the preconditioner */
+} dht_lobpcg_stats;
+int dht_deflation_lobpcg(dht_ctx* ctx, const dht_lobpcg_params* prm, double* sigma_host, double* resid_host,
+                         dht_lobpcg_stats* stats);
 /* Copy columns first .. first+count-1 of the stored basis, as rounded to its
  * storage precision, to W_dev (device, canonical complex128, [count][N]). */
 int dht_deflation_get(dht_ctx* ctx, int first, int count, double* W_dev);

@@ -52,6 +52,16 @@ class EigParams(ctypes.Structure):
                 ("guard", ctypes.c_int), ("seed", ctypes.c_uint64)]
 
 
+class LobpcgParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("block", ctypes.c_int),
+                ("precond", ctypes.c_int), ("precond_tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class LobpcgStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("q_applications", ctypes.c_int64),
+                ("precond_solves", ctypes.c_int64)]
+
+
 class EigStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("block", ctypes.c_int),
                 ("matvecs", ctypes.c_int64)]
@@ -122,6 +132,7 @@ SIGNATURES = {
     "dht_deflation_begin": (_i, [_vp, _i, _i]),
     "dht_deflation_set": (_i, [_vp, _i, _i, _vp]),
     "dht_deflation_eigensolve": (_i, [_vp, ctypes.POINTER(EigParams), _dp, _dp, ctypes.POINTER(EigStats)]),
+    "dht_deflation_lobpcg": (_i, [_vp, ctypes.POINTER(LobpcgParams), _dp, _dp, ctypes.POINTER(LobpcgStats)]),
     "dht_deflation_finalize": (_i, [_vp, _dp]),
     "dht_deflation_get": (_i, [_vp, _i, _i, _vp]),
     "dht_deflation_finalize_diag": (_i, [_vp, _dp]),
@@ -374,6 +385,24 @@ class Context:
         stats["status"] = rc
         td = self.finalize_deflation() if finalize else None
         return lam, res, stats, td
+
+    def lobpcg(self, k: int, prec: int = FP64, tol: float = 1e-9, max_iter: int = 500, block: int = 32,
+               precond: bool = True, precond_tol: float = 1e-2, seed: int = 1, finalize: bool = True,
+               allow_not_converged: bool = False):
+        """Deflation basis from the preconditioned block eigensolver (LOBPCG on Q^2
+        with locking).  Returns (sigma, relative residuals, stats, T_D)."""
+        self.begin_deflation(k, prec)
+        sig = np.zeros(k)
+        res = np.zeros(k)
+        st = LobpcgStats()
+        prm = LobpcgParams(float(tol), int(max_iter), int(block), int(precond), float(precond_tol), int(seed))
+        rc = load().dht_deflation_lobpcg(self.h, ctypes.byref(prm), _np_dp(sig), _np_dp(res), ctypes.byref(st))
+        if rc != 0 and not (allow_not_converged and rc == DHT_ERR_NOT_CONVERGED):
+            check(rc)
+        stats = {f[0]: getattr(st, f[0]) for f in LobpcgStats._fields_}
+        stats["status"] = rc
+        td = self.finalize_deflation() if finalize else None
+        return sig, res, stats, td
 
     def deflation_columns(self, first: int, count: int):
         """Stored basis columns (rounded to the storage precision) as a

@@ -514,6 +514,17 @@ int dht_deflation_eigensolve(dht_ctx* c, const dht_eig_params* prm, double* lamb
     return rc;
 }
 
+int dht_deflation_lobpcg(dht_ctx* c, const dht_lobpcg_params* prm, double* sigma_host, double* resid_host,
+                         dht_lobpcg_stats* stats) {
+    DHT_TRY(check_ctx(c));
+    if (!prm) return set_error(DHT_ERR_INVALID_ARG, "null parameters");
+    const int rc = lobpcg(c, prm, sigma_host, resid_host, stats);
+    const std::string msg = g_err;
+    const int hr = prof_harvest(c);
+    if (rc != DHT_OK) return set_error(rc, msg);
+    return hr;
+}
+
 int dht_deflation_get(dht_ctx* c, int first, int count, double* W_dev) {
     DHT_TRY(check_ctx(c));
     if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "no deflation basis");

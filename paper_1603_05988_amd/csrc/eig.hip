@@ -15,6 +15,8 @@
 // N x nb row-major complex matrices; Gram matrices, rotations and residual
 // norms are tall-skinny kernels below, the small nb x nb eigenproblems and
 // factorisations run on the host in FP64.
+#include <string.h>
+
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -468,4 +470,361 @@ int eigensolve(dht_ctx* c, const dht_eig_params* prm, double* lambda_host, doubl
     return conv == k ? DHT_OK : set_error(DHT_ERR_NOT_CONVERGED, "eigensolver: not all k pairs reached the tolerance");
 }
 
+// ---------------------------------------------------------------------------
+// Preconditioned block eigensolver with locking (Section 5.1: the paper's route
+// to the deflation space is a preconditioned Davidson-type method with a
+// window of block vectors and locking of converged ones).  Here: LOBPCG on
+// Q^2 = D^H D, whose smallest eigenvalues are sigma^2 of the wanted singular
+// triplets, with the window X of m vectors, the preconditioned residuals W
+// and the previous directions P; a Rayleigh-Ritz step on [X, W, P] (the
+// generalised form, with the Gram matrix of the three blocks factored by
+// Cholesky, so that small losses of orthogonality between the blocks do no
+// harm) gives the next window.  Converged leading Ritz vectors are locked
+// (copied out, their slots refilled with fresh Z4 noise), and every new block
+// is kept orthogonal to the locked ones.  The preconditioner approximates
+// (Q^2)^-1 = D^-1 g5 D^-1 g5 by two loose mixed-precision solves with D.
+// ---------------------------------------------------------------------------
+
+// dst[:, d0 + j] = src[:, s0 + j] for j < ncols (both nrows x nb)
+__global__ void eig_copy_cols_kernel(const Cx<double>* src, Cx<double>* dst, int64_t nrows, int nb, int s0, int d0,
+                                     int ncols) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrows * ncols) return;
+    const int64_t r = e / ncols;
+    const int j = (int)(e - r * ncols);
+    dst[r * nb + d0 + j] = src[r * nb + s0 + j];
+}
+
+struct Lobpcg {
+    dht_ctx* c;
+    EigWork w;
+    int m;
+    Cx<double> *X, *AX, *W, *AW, *P, *AP, *NX, *NAX, *NP, *NAP, *T1, *T2, *T3;
+    std::vector<Cx<double>*> locked;   // chunks of m columns (unused columns zero)
+    int nl = 0;                        // locked vectors
+    int64_t qapps = 0, solves = 0;
+    const dht_solver_params* sp = nullptr;   // preconditioner solves (null: none)
+};
+
+static int copy_cols(Lobpcg& L, const Cx<double>* src, Cx<double>* dst, int s0, int d0, int n) {
+    const int64_t tot = L.w.rows * n;
+    hipLaunchKernelGGL(eig_copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, L.c->stream, src, dst,
+                       L.w.rows, L.w.nb, s0, d0, n);
+    DHT_HIP(hipGetLastError());
+    return DHT_OK;
+}
+
+static int apply_q2(Lobpcg& L, const Cx<double>* in, Cx<double>* out) {
+    DHT_TRY(apply_q(L.c, L.w, in, L.T3));
+    DHT_TRY(apply_q(L.c, L.w, L.T3, out));
+    L.qapps += 2;
+    return DHT_OK;
+}
+
+// V -= B (B^H V) over every locked chunk, twice
+static int project_locked(Lobpcg& L, Cx<double>* V) {
+    for (int pass = 0; pass < 2; pass++)
+        for (int ch = 0; ch * L.m < L.nl; ch++) {
+            CMat G;
+            DHT_TRY(gram(L.c, L.w, L.locked[ch], V, G));
+            DHT_TRY(rotate(L.c, L.w, L.locked[ch], G, L.T1));
+            DHT_TRY(lincomb(L.c, L.w, V, 1.0, V, -1.0, L.T1, 0.0, nullptr));
+        }
+    return DHT_OK;
+}
+
+// V -= B (B^H V) and, with AB/AV, AV -= AB (B^H V) (B orthonormal)
+static int project_block(Lobpcg& L, const Cx<double>* B, const Cx<double>* AB, Cx<double>* V, Cx<double>* AV) {
+    CMat G;
+    DHT_TRY(gram(L.c, L.w, B, V, G));
+    DHT_TRY(rotate(L.c, L.w, B, G, L.T1));
+    DHT_TRY(lincomb(L.c, L.w, V, 1.0, V, -1.0, L.T1, 0.0, nullptr));
+    if (AV) {
+        DHT_TRY(rotate(L.c, L.w, AB, G, L.T1));
+        DHT_TRY(lincomb(L.c, L.w, AV, 1.0, AV, -1.0, L.T1, 0.0, nullptr));
+    }
+    return DHT_OK;
+}
+
+// V <- V C, AV <- AV C with C = L^-H from V^H V = L L^H (Cholesky QR, twice);
+// returns false in *ok when the block has lost rank
+static int ortho_pair(Lobpcg& L, Cx<double>* V, Cx<double>* AV, bool* ok) {
+    *ok = true;
+    const size_t bytes = sizeof(Cx<double>) * (size_t)L.w.rows * L.w.nb;
+    for (int pass = 0; pass < 2; pass++) {
+        CMat G, Lc, C;
+        DHT_TRY(gram(L.c, L.w, V, V, G));
+        hermitise(G, L.m);
+        if (!cholesky(G, L.m, Lc)) {
+            *ok = false;
+            return DHT_OK;
+        }
+        inv_lower_h(Lc, L.m, C);
+        DHT_TRY(rotate(L.c, L.w, V, C, L.T1));
+        DHT_HIP(hipMemcpyAsync(V, L.T1, bytes, hipMemcpyDeviceToDevice, L.c->stream));
+        if (AV) {
+            DHT_TRY(rotate(L.c, L.w, AV, C, L.T1));
+            DHT_HIP(hipMemcpyAsync(AV, L.T1, bytes, hipMemcpyDeviceToDevice, L.c->stream));
+        }
+    }
+    return DHT_OK;
+}
+
+// out = D^-1 g5 D^-1 g5 in (two loose solves), or out = in without a preconditioner
+static int precondition(Lobpcg& L, const Cx<double>* in, Cx<double>* out) {
+    const size_t bytes = sizeof(Cx<double>) * (size_t)L.w.rows * L.w.nb;
+    if (!L.sp) {
+        DHT_HIP(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, L.c->stream));
+        return DHT_OK;
+    }
+    std::vector<dht_solve_stats> st(L.m);
+    for (int rep = 0; rep < 2; rep++) {
+        DHT_TRY(g5_field(L.c, DHT_FP64, rep == 0 ? in : out, L.T2, L.m));
+        const int rc = solve_fields(L.c, L.sp, L.T2, out, L.m, st.data(), nullptr, nullptr, DHT_FP64);
+        if (rc != DHT_OK && rc != DHT_ERR_NOT_CONVERGED) return rc;   // a loose solve may miss: it only preconditions
+        L.solves += L.m;
+    }
+    return DHT_OK;
+}
+
+// Rayleigh-Ritz on the blocks S[0..nbk) with images AS: the m smallest Ritz
+// pairs; new X = S C_X, and (nbk > 1) new P = the W and P part of the same
+// combination.  theta receives the m Ritz values (ascending).
+static int rayleigh_ritz_blocks(Lobpcg& L, int nbk, std::vector<double>& theta, bool* ok) {
+    Cx<double>* S[3] = {L.X, L.W, L.P};
+    Cx<double>* AS[3] = {L.AX, L.AW, L.AP};
+    const int m = L.m, n = nbk * m;
+    CMat G((size_t)n * n), M((size_t)n * n);
+    for (int i = 0; i < nbk; i++)
+        for (int j = i; j < nbk; j++) {
+            CMat g, h;
+            DHT_TRY(gram(L.c, L.w, S[i], AS[j], g));
+            DHT_TRY(gram(L.c, L.w, S[i], S[j], h));
+            for (int a = 0; a < m; a++)
+                for (int b = 0; b < m; b++) {
+                    G[(size_t)(i * m + a) * n + j * m + b] = g[(size_t)a * m + b];
+                    M[(size_t)(i * m + a) * n + j * m + b] = h[(size_t)a * m + b];
+                    G[(size_t)(j * m + b) * n + i * m + a] = cconj(g[(size_t)a * m + b]);
+                    M[(size_t)(j * m + b) * n + i * m + a] = cconj(h[(size_t)a * m + b]);
+                }
+        }
+    hermitise(G, n);
+    hermitise(M, n);
+    CMat Lc, Li;   // M = Lc Lc^H, Li = Lc^-H
+    *ok = cholesky(M, n, Lc);
+    if (!*ok) return DHT_OK;
+    inv_lower_h(Lc, n, Li);
+    // Gt = Li^H G Li
+    CMat T((size_t)n * n, cmake(0.0, 0.0)), Gt((size_t)n * n, cmake(0.0, 0.0));
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++) {
+            Cx<double> acc = cmake(0.0, 0.0);
+            for (int e = 0; e < n; e++) acc = acc + G[(size_t)a * n + e] * Li[(size_t)e * n + b];
+            T[(size_t)a * n + b] = acc;
+        }
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++) {
+            Cx<double> acc = cmake(0.0, 0.0);
+            for (int e = 0; e < n; e++) acc = acc + cconj(Li[(size_t)e * n + a]) * T[(size_t)e * n + b];
+            Gt[(size_t)a * n + b] = acc;
+        }
+    hermitise(Gt, n);
+    std::vector<double> ev;
+    CMat Y;
+    jacobi_eigh(Gt, n, ev, Y);   // ascending
+    theta.assign(ev.begin(), ev.begin() + m);
+    // C = Li Y[:, :m], split into m x m blocks C_i
+    std::vector<CMat> C(nbk, CMat((size_t)m * m));
+    for (int i = 0; i < nbk; i++)
+        for (int a = 0; a < m; a++)
+            for (int b = 0; b < m; b++) {
+                Cx<double> acc = cmake(0.0, 0.0);
+                for (int e = 0; e < n; e++) acc = acc + Li[(size_t)(i * m + a) * n + e] * Y[(size_t)e * n + b];
+                C[i][(size_t)a * m + b] = acc;
+            }
+    // new X, AX (and P, AP from the W and P parts)
+    for (int img = 0; img < 2; img++) {
+        Cx<double>** src = img ? AS : S;
+        Cx<double>* nx = img ? L.NAX : L.NX;
+        Cx<double>* np_ = img ? L.NAP : L.NP;
+        DHT_TRY(rotate(L.c, L.w, src[0], C[0], L.T1));
+        if (nbk == 1) {
+            DHT_HIP(hipMemcpyAsync(nx, L.T1, sizeof(Cx<double>) * (size_t)L.w.rows * L.w.nb, hipMemcpyDeviceToDevice,
+                                   L.c->stream));
+            continue;
+        }
+        DHT_TRY(rotate(L.c, L.w, src[1], C[1], L.T2));
+        if (nbk == 3) {
+            DHT_TRY(rotate(L.c, L.w, src[2], C[2], L.T3));
+            DHT_TRY(lincomb(L.c, L.w, nx, 1.0, L.T1, 1.0, L.T2, 1.0, L.T3));
+            DHT_TRY(lincomb(L.c, L.w, np_, 1.0, L.T2, 1.0, L.T3, 0.0, nullptr));
+        } else {
+            DHT_TRY(lincomb(L.c, L.w, nx, 1.0, L.T1, 1.0, L.T2, 0.0, nullptr));
+            DHT_TRY(lincomb(L.c, L.w, np_, 1.0, L.T2, 0.0, nullptr, 0.0, nullptr));
+        }
+    }
+    std::swap(L.X, L.NX);
+    std::swap(L.AX, L.NAX);
+    if (nbk > 1) {
+        std::swap(L.P, L.NP);
+        std::swap(L.AP, L.NAP);
+    }
+    return DHT_OK;
+}
+
+int lobpcg(dht_ctx* c, const dht_lobpcg_params* prm, double* sigma_host, double* resid_host, dht_lobpcg_stats* st) {
+    if (!c->have_gauge) return set_error(DHT_ERR_STATE, "gauge field not set");
+    if (!c->W || c->k <= 0) return set_error(DHT_ERR_STATE, "call dht_deflation_begin first");
+    if (!prm || !(prm->tol > 0) || prm->max_iter < 1 || (prm->block != 32 && prm->block != 64))
+        return set_error(DHT_ERR_INVALID_ARG, "bad LOBPCG parameters (block 32 or 64)");
+    if (prm->precond && !(prm->precond_tol > 0 && prm->precond_tol < 1))
+        return set_error(DHT_ERR_INVALID_ARG, "preconditioner tolerance must lie in (0, 1)");
+    const int k = c->k, m = prm->block;
+    Lobpcg L;
+    L.c = c;
+    L.m = m;
+    L.w.rows = c->g.V * 12;
+    L.w.nb = m;
+    L.w.rblocks = 512;
+    const size_t fb = sizeof(Cx<double>) * (size_t)L.w.rows * m;
+    const int nchunks = (k + m - 1) / m;
+    void *work, *lock, *pp, *ps, *pr, *pl;
+    DHT_TRY(ws_get(c, WS_EIG_U, fb * 13, &work));
+    DHT_TRY(ws_get(c, WS_EIG_T, fb * nchunks, &lock));
+    DHT_TRY(ws_get(c, WS_EIG_PART, sizeof(Cx<double>) * (size_t)EG_SPLITS * m * m, &pp));
+    DHT_TRY(ws_get(c, WS_EIG_SMALL, sizeof(Cx<double>) * (size_t)m * m, &ps));
+    DHT_TRY(ws_get(c, WS_EIG_RPART, sizeof(double) * (size_t)L.w.rblocks * m, &pr));
+    DHT_TRY(ws_get(c, WS_EIG_LAM, sizeof(double) * m, &pl));
+    L.w.part = (Cx<double>*)pp;
+    L.w.small = (Cx<double>*)ps;
+    L.w.rpart = (double*)pr;
+    L.w.lam = (double*)pl;
+    Cx<double>* bufs[13];
+    for (int i = 0; i < 13; i++) bufs[i] = (Cx<double>*)((char*)work + fb * i);
+    L.X = bufs[0]; L.AX = bufs[1]; L.W = bufs[2]; L.AW = bufs[3]; L.P = bufs[4]; L.AP = bufs[5];
+    L.NX = bufs[6]; L.NAX = bufs[7]; L.NP = bufs[8]; L.NAP = bufs[9]; L.T1 = bufs[10]; L.T2 = bufs[11]; L.T3 = bufs[12];
+    for (int ch = 0; ch < nchunks; ch++) L.locked.push_back((Cx<double>*)((char*)lock + fb * ch));
+    DHT_TRY(zero(c, lock, fb * nchunks));
+    dht_solver_params sp;
+    if (prm->precond) {
+        memset(&sp, 0, sizeof(sp));
+        sp.method = DHT_SOLVER_DC_BICGSTAB;
+        sp.inner = DHT_BF16;
+        sp.tol = prm->precond_tol;
+        sp.maxiter = 1000;
+        L.sp = &sp;
+    }
+    const double qn = std::fabs(4.0 + c->mass) + 4.0;   // ||Q|| <= |4 + m| + 4
+    const double tol = prm->tol * qn * qn;              // on ||Q^2 x - theta x||
+    std::vector<double> sig(k, 0.0), rres(k, 0.0);
+    // start block: Z4 noise
+    uint32_t run = 0;
+    dht_probe_spec spec = {(uint32_t)prm->seed, run, 0};
+    DHT_TRY(probes_gen(c, &spec, 0, m, m, L.X, DHT_FP64, nullptr, nullptr));
+    bool ok;
+    DHT_TRY(ortho_pair(L, L.X, nullptr, &ok));
+    if (!ok) return set_error(DHT_ERR_BREAKDOWN, "LOBPCG: start block lost rank");
+    DHT_TRY(apply_q2(L, L.X, L.AX));
+    std::vector<double> theta, res;
+    DHT_TRY(rayleigh_ritz_blocks(L, 1, theta, &ok));
+    if (!ok) return set_error(DHT_ERR_BREAKDOWN, "LOBPCG: start block lost rank");
+    bool havep = false;
+    int it = 0;
+    for (; it < prm->max_iter && L.nl < k; it++) {
+        DHT_TRY(resid_norms(c, L.w, L.AX, L.X, theta, res));
+        // lock the leading converged Ritz vectors
+        int nc = 0;
+        while (nc < m && L.nl + nc < k && res[nc] <= tol) nc++;
+        if (nc > 0) {
+            for (int j = 0; j < nc; j++) {
+                const int slot = L.nl + j;
+                DHT_TRY(copy_cols(L, L.X, L.locked[slot / m], j, slot % m, 1));
+                sig[slot] = std::sqrt(std::max(theta[j], 0.0));
+                rres[slot] = res[j] / (qn * qn);
+            }
+            L.nl += nc;
+            if (L.nl >= k) break;
+            // refill the locked slots with fresh noise, keep the rest of the window
+            spec.run = ++run;
+            DHT_TRY(probes_gen(c, &spec, 0, m, m, L.T2, DHT_FP64, nullptr, nullptr));
+            DHT_TRY(copy_cols(L, L.T2, L.X, 0, 0, nc));
+            DHT_TRY(project_locked(L, L.X));
+            DHT_TRY(ortho_pair(L, L.X, nullptr, &ok));
+            if (!ok) return set_error(DHT_ERR_BREAKDOWN, "LOBPCG: window lost rank after locking");
+            DHT_TRY(apply_q2(L, L.X, L.AX));
+            DHT_TRY(rayleigh_ritz_blocks(L, 1, theta, &ok));
+            if (!ok) return set_error(DHT_ERR_BREAKDOWN, "LOBPCG: window lost rank after locking");
+            havep = false;
+            continue;
+        }
+        // W = T (AX - X theta), orthogonal to the locked vectors, X and P
+        CMat D((size_t)m * m, cmake(0.0, 0.0));
+        for (int j = 0; j < m; j++) D[(size_t)j * m + j] = cmake(theta[j], 0.0);
+        DHT_TRY(rotate(c, L.w, L.X, D, L.T1));
+        DHT_TRY(lincomb(c, L.w, L.T2, 1.0, L.AX, -1.0, L.T1, 0.0, nullptr));   // R
+        DHT_HIP(hipMemcpyAsync(L.NX, L.T2, fb, hipMemcpyDeviceToDevice, c->stream));
+        DHT_TRY(precondition(L, L.NX, L.W));
+        DHT_TRY(project_locked(L, L.W));
+        DHT_TRY(project_block(L, L.X, nullptr, L.W, nullptr));
+        if (havep) DHT_TRY(project_block(L, L.P, nullptr, L.W, nullptr));
+        DHT_TRY(ortho_pair(L, L.W, nullptr, &ok));
+        if (!ok) {   // W fell into span(X, P): restart without P
+            havep = false;
+            DHT_TRY(precondition(L, L.NX, L.W));
+            DHT_TRY(project_locked(L, L.W));
+            DHT_TRY(project_block(L, L.X, nullptr, L.W, nullptr));
+            DHT_TRY(ortho_pair(L, L.W, nullptr, &ok));
+            if (!ok) return set_error(DHT_ERR_BREAKDOWN, "LOBPCG: residual block lost rank");
+        }
+        DHT_TRY(apply_q2(L, L.W, L.AW));
+        if (havep) {   // P orthonormal and orthogonal to X and W, its image alongside
+            DHT_TRY(project_block(L, L.X, L.AX, L.P, L.AP));
+            DHT_TRY(project_block(L, L.W, L.AW, L.P, L.AP));
+            DHT_TRY(ortho_pair(L, L.P, L.AP, &ok));
+            if (!ok) havep = false;
+        }
+        DHT_TRY(rayleigh_ritz_blocks(L, havep ? 3 : 2, theta, &ok));
+        if (!ok) {   // the three blocks were dependent: drop P and retry on [X, W]
+            havep = false;
+            DHT_TRY(rayleigh_ritz_blocks(L, 2, theta, &ok));
+            if (!ok) return set_error(DHT_ERR_BREAKDOWN, "LOBPCG: Rayleigh-Ritz basis lost rank");
+        }
+        havep = true;
+    }
+    // the locked vectors into the stored basis
+    if (L.nl < k) {   // not all converged: the best current Ritz vectors fill the rest
+        DHT_TRY(resid_norms(c, L.w, L.AX, L.X, theta, res));
+        for (int j = 0; L.nl < k && j < m; j++) {
+            const int slot = L.nl++;
+            DHT_TRY(copy_cols(L, L.X, L.locked[slot / m], j, slot % m, 1));
+            sig[slot] = std::sqrt(std::max(theta[j], 0.0));
+            rres[slot] = res[j] / (qn * qn);
+        }
+    }
+    const int filled = std::min(L.nl, k);
+    void* canon;
+    DHT_TRY(ws_get(c, WS_EIG_CANON, sizeof(double) * 2 * (size_t)L.w.rows * m, &canon));
+    for (int ch = 0; ch * m < filled; ch++) {
+        const int cnt = std::min(m, filled - ch * m);
+        DHT_TRY(unpack_spinor(c, L.locked[ch], DHT_FP64, (double*)canon, cnt, m));
+        DHT_TRY(deflation_set(c, ch * m, cnt, (const double*)canon));
+    }
+    DHT_HIP(hipStreamSynchronize(c->stream));
+    DHT_TRY(prof_harvest(c));
+    int conv = 0;
+    for (int j = 0; j < k; j++) {
+        if (sigma_host) sigma_host[j] = sig[j];
+        if (resid_host) resid_host[j] = rres[j];
+        if (rres[j] * qn * qn <= tol) conv++;
+    }
+    if (st) {
+        st->iters = it;
+        st->converged = conv;
+        st->q_applications = L.qapps;
+        st->precond_solves = L.solves;
+    }
+    return conv == k ? DHT_OK : set_error(DHT_ERR_NOT_CONVERGED, "LOBPCG: not all k vectors reached the tolerance");
+}
+
 }  // namespace dht
+

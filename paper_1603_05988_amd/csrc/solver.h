@@ -165,6 +165,8 @@ int deflation_set(dht_ctx* c, int first, int count, const double* W_dev);
 int deflation_finalize(dht_ctx* c, bool diagonal);
 // eigenvectors of Q of smallest |lambda| into the begun basis (eig.hip)
 int eigensolve(dht_ctx* c, const dht_eig_params* prm, double* lambda_host, double* resid_host, dht_eig_stats* st);
+// LOBPCG with locking for the same space (eig.hip)
+int lobpcg(dht_ctx* c, const dht_lobpcg_params* prm, double* sigma_host, double* resid_host, dht_lobpcg_stats* st);
 void deflation_corrections(const dht_ctx* c, const Cx<double>* c1, const Cx<double>* c2, int B, int nuse,
                            double* dre, double* dim);
 int gather_columns(dht_ctx* c, int j0, int n, int bp, void* out);
