@@ -12,7 +12,10 @@ any size:
 - bit-exact projection coefficients W^H z and W^H g5 z for sampled
   (column, probe) pairs: the basis entries are (+-1 +- i) 2^-13, exact in BF16,
   and every partial sum of their products with Z4 probes is exact in FP32 and
-  FP64, so the MFMA path must reproduce the oracle's sums exactly.
+  FP64, so the MFMA path must reproduce the oracle's sums exactly;
+- q = z^H x of the timed trace_batch path against the oracle's C-stencil
+  solve, and the 16 Dirac-matrix quadratic forms z^H Gamma x of the
+  Gamma-trace path against the same oracle solves.
 """
 import numpy as np
 import pytest
@@ -146,3 +149,34 @@ def test_c5_quadratic_forms_vs_oracle_solve(c5_basis):
         print("probe %d: q = %.12e%+.12ei, oracle %.12e%+.12ei, rel %.2e" % (B + r, q.real, q.imag, qs.real,
                                                                             qs.imag, abs(q - qs) / abs(qs)))
         assert abs(q - qs) <= 1e-8 * abs(qs), (r, q, qs)
+
+
+def test_c5_gamma_traces_vs_oracle_solve(c5_basis):
+    """Tr(Gamma D^-1) for the 16 Dirac matrices at the full size, the way bench.py
+    times it (one solve per probe, spin-pair projection on the k = 1000 BF16
+    basis): z^H Gamma x of two sampled probes against z^H Gamma x* with x* from
+    the oracle's C-stencil FP64 BiCGStab to 1e-10, within 1e-8 of |z^H x*|; with
+    Gamma = 1 the deflated quadratures equal those of dht_trace_batch on the
+    same probes up to the FP32 chunk sums of the two projections."""
+    from oracle import gamma
+    U, ctx = c5_basis
+    Lb = _lib()
+    B = W5.batch
+    prm = ctx.params(Lb.SOLVER_DC_BICGSTAB, inner=Lb.BF16, tol=W5.tol, maxiter=5000)
+    _, G = gamma.dirac_basis()
+    ctx.gamma_set(G)
+    q, qd, stats = ctx.trace_gamma_batch(W5.seed, 0, W5.hp, 3 * B, B, prm)
+    assert all(s["true_resid"] <= W5.tol for s in stats)
+    for r in (0, B - 1):
+        z = rng.probe(W5.L, W5.seed, 0, W5.hp, 3 * B + r)
+        x, st, it, rr = stencil.solve(U, W5.L, W5.mass, z, 1e-10, 5000)
+        assert st == 0 and rr <= 1e-10, (st, it, rr)
+        scale = abs(np.vdot(z, x.ravel()))
+        for g in range(16):
+            ref = gamma.gamma_quadratic_forms(z[None], x.ravel()[None], G[g])[0]
+            assert abs(q[g, r] - ref) <= 1e-8 * scale, (r, g, q[g, r], ref)
+    recs = ctx.trace_batch(W5.seed, 0, W5.hp, 3 * B, B, prm)
+    qd1 = np.array([rec["q_defl"] for rec in recs])
+    q1 = np.array([rec["q"] for rec in recs])
+    assert np.abs(q[0] - q1).max() <= 1e-8 * np.abs(q1).max()
+    assert np.abs(qd[0] - qd1).max() <= 1e-6 * np.abs(q1).max()
