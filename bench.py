@@ -361,6 +361,7 @@ def main():
 
     roof = None
     dslash = None
+    proj = None
     if not args.no_profile:
         stats = {name: ctx.profile_get(name) for name in ctx.PROF_CLASSES}
         for name, s in stats.items():
@@ -379,6 +380,21 @@ def main():
         hop = stats["hop_fp32" if inner == L.FP32 else "hop_bf16"]
         if hop["count"]:
             dslash = round(hop["bytes"] / hop["ms"] / 1e6, 1)
+        pm = stats["proj_mfma"]
+        if pm["count"]:
+            # each pass multiplies every complex entry of W (k x N) with the window's probes:
+            # 8 real flops per complex multiply-add
+            wprobes = min(64, args.proj_window or B)
+            fl = 8.0 * k * w.N * wprobes
+            avg = pm["ms"] / pm["count"]
+            proj = {"launches": pm["count"], "avg_launch_ms": round(avg, 3), "probes_per_pass": wprobes,
+                    "alg_GBps": round(pm["bytes"] / pm["ms"] / 1e6, 1),
+                    "hbm_frac": round(pm["bytes"] / pm["ms"] / 1e6 / HBM_PEAK_GBPS, 4),
+                    "mfma_tflops": round(fl / avg / 1e9, 1),
+                    "mfma_frac": round(fl / avg / 1e9 / BF16_MFMA_PEAK_TFLOPS, 4)}
+            log("projection: %.2f ms per %d-probe pass, %.0f GB/s algorithmic (%.3f of HBM), %.0f TFLOP/s "
+                "(%.3f of the BF16 MFMA peak)" % (avg, wprobes, proj["alg_GBps"], proj["hbm_frac"],
+                                                  proj["mfma_tflops"], proj["mfma_frac"]))
 
     # the plain FP64 BiCGStab path on the same GPU, same probes
     fp64_value = None
@@ -409,8 +425,11 @@ def main():
                "ms_per_step": round(1e3 * elg / args.gamma_steps, 1), "matrices": 16,
                "time_vs_one_trace": round((elg / args.gamma_steps) / (ms_step / 1e3), 3)}
         if sp["count"]:
+            # 16 probes x 4 target spins per entry of W: 8 real flops per complex multiply-add
+            spf = 8.0 * k * w.N * 64 / (sp["ms"] / sp["count"]) / 1e9
             gam["proj_sp"] = {"launches": sp["count"], "avg_launch_ms": round(sp["ms"] / sp["count"], 3),
                               "alg_GBps": round(sp["bytes"] / sp["ms"] / 1e6, 1),
+                              "mfma_tflops": round(spf, 1), "mfma_frac": round(spf / BF16_MFMA_PEAK_TFLOPS, 4),
                               "share_of_step": round(sp["ms"] / (1e3 * elg), 3)}
         log("gamma traces: %.1f ms/step (%.3f of a plain trace step), %.2f probes/s for 16 matrices%s"
             % (gam["ms_per_step"], gam["time_vs_one_trace"], gam["value"],
@@ -497,6 +516,7 @@ def main():
         "fp64_bicgstab_value": round(fp64_value, 3) if fp64_value else None,
         "speedup_vs_fp64": round(value / fp64_value, 3) if fp64_value else None,
         "dslash_GBps": dslash,
+        "projection": proj,
         "phase_ms_last_step": {kk: round(v, 3) for kk, v in tm.items()},
     }
     ctx.close()
