@@ -81,3 +81,70 @@ def test_variance_report_c2():
         with open("gpurun_out/variance_c2.json", "w") as f:
             json.dump(out, f, indent=1)
     ctx.close()
+
+
+def test_variance_report_c3():
+    """The same analysis on the 16^3x32 operator (Section 6.2's procedure at the
+    third configuration): k = 200 vectors from the preconditioned block
+    eigensolver (FP32 storage, Galerkin M), 40 runs of 256 hierarchical-probing
+    probes, 256 plain Z4 probes for V_stoc; V_hp(s) and R_s at s = 1 .. 256,
+    undeflated and deflated, and playback at s = 256 over k = 0 .. 200.  Written
+    to gpurun_out/variance_c3.json when that directory exists.  Asserted as for
+    8^3x16: playback with all vectors reproduces the records, with none the
+    undeflated forms, and the two estimates agree within their errors."""
+    from paper_1603_05988_amd import _lib as L
+    w = WORKLOADS["c3"]
+    U = gauge_links(w.L, w.eps, w.seed)
+    ctx = L.Context(w.L, w.mass)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    sig, res, st, TD = ctx.lobpcg(w.k, L.FP32, tol=1e-9, max_iter=2000, block=64, precond=True, seed=5)
+    assert st["converged"] == w.k
+    H, G5, diag = ctx.deflation_galerkin()
+    prm = ctx.params(L.SOLVER_DC_BICGSTAB, inner=L.BF16, tol=1e-8, maxiter=5000)
+    R, S, B = 40, w.nprobe, w.batch
+    q = np.zeros((R, S), dtype=np.complex128)
+    qd = np.zeros((R, S), dtype=np.complex128)
+    coef = np.zeros((R, 2, w.k, S), dtype=np.complex128)
+    for r in range(R):
+        for b in range(0, S, B):
+            recs, c1, c2 = ctx.trace_batch(w.seed, 100 + r, True, b, B, prm, want_coef=True)
+            q[r, b:b + B] = [x["q"] for x in recs]
+            qd[r, b:b + B] = [x["q_defl"] for x in recs]
+            coef[r, 0, :, b:b + B], coef[r, 1, :, b:b + B] = c1, c2
+    mc = []
+    for b in range(0, 256, B):
+        mc += [x["q"] for x in ctx.trace_batch(w.seed, 7, False, b, B, prm)]
+    mc = np.array(mc)
+    v_stoc = float(np.sum(np.abs(mc - mc.mean()) ** 2) / (len(mc) - 1))
+    s_list = [1, 2, 4, 8, 16, 32, 64, 128, 256]
+    und = L.hp_variance(q, s_list, v_stoc)
+    dfl = L.hp_variance(qd, s_list, v_stoc)
+    k_list = [0, 25, 50, 100, 150, 200]
+    t_runs = {kk: [] for kk in k_list}
+    for r in range(R):
+        pq, ptd = L.playback(H, G5, coef[r], q[r], k_list, diagonal=diag)
+        if r == 0:
+            assert np.abs(pq[-1] - qd[r]).max() <= 1e-10 * np.abs(q[r]).max()
+            assert abs(ptd[-1] - TD) <= 1e-12 * abs(TD)
+            assert np.array_equal(pq[0], q[r])
+        for a, kk in enumerate(k_list):
+            t_runs[kk].append(pq[a])
+    play = []
+    for kk in k_list:
+        o = L.hp_variance(np.array(t_runs[kk]), [S], v_stoc)[0]
+        play.append({"k": kk, "var": o["var"], "var_err": o["var_err"], "rs": o["rs"], "rs_err": o["rs_err"]})
+    m_u = complex(und[-1]["mean_re"], und[-1]["mean_im"])
+    m_d = complex(dfl[-1]["mean_re"], dfl[-1]["mean_im"]) + TD
+    assert abs(m_u - m_d) <= 5 * np.hypot(und[-1]["mean_err"], dfl[-1]["mean_err"]), (m_u, m_d)
+    out = {"lattice": list(w.L), "runs": R, "probes_per_run": S, "k": w.k, "T_D": [TD.real, TD.imag],
+           "sigma_min": float(np.min(sig)), "v_stoc": v_stoc, "mc_probes": len(mc),
+           "trace_undeflated": [m_u.real, m_u.imag], "trace_deflated": [m_d.real, m_d.imag],
+           "hp": [{"s": a["s"], "var": a["var"], "var_err": a["var_err"], "rs": a["rs"], "rs_err": a["rs_err"],
+                   "var_defl": b["var"], "var_defl_err": b["var_err"], "rs_defl": b["rs"], "rs_defl_err": b["rs_err"]}
+                  for a, b in zip(und, dfl)],
+           "playback_s%d" % S: play}
+    print(json.dumps(out)[:2000])
+    if os.path.isdir("gpurun_out"):
+        with open("gpurun_out/variance_c3.json", "w") as f:
+            json.dump(out, f, indent=1)
+    ctx.close()
