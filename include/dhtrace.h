@@ -297,9 +297,13 @@ int dht_deflation_eigensolve(dht_ctx* ctx, const dht_eig_params* prm, double* la
  * follow).  sigma_host and resid_host (k doubles each, may be NULL) receive
  * sigma and the relative residual of each locked vector in locking order.
  * Returns DHT_ERR_NOT_CONVERGED (basis filled with the best Ritz vectors) if
- * fewer than k converged within max_iter iterations.  Errors:
- * DHT_ERR_INVALID_ARG for bad parameters, DHT_ERR_STATE without gauge field
- * or dht_deflation_begin, DHT_ERR_BREAKDOWN if a block loses rank. */
+ * fewer than k converged within max_iter iterations.  Its working fields
+ * (13 FP64 blocks of N x block complex, and the locked vectors in FP64,
+ * ceil(k / block) more) are library-owned workspace outside the plan of
+ * dht_workspace_size.  Errors: DHT_ERR_INVALID_ARG for bad parameters,
+ * DHT_ERR_STATE without gauge field or dht_deflation_begin,
+ * DHT_ERR_BREAKDOWN if a block loses rank, DHT_ERR_OOM if the fields do not
+ * fit. */
 typedef struct dht_lobpcg_params {
     double tol;          /* locking threshold, relative to ||Q||^2          */
     int max_iter;        /* cap on block iterations                         */
