@@ -91,7 +91,11 @@ def test_variance_report_c3():
     undeflated and deflated, and playback at s = 256 over k = 0 .. 200.  Written
     to gpurun_out/variance_c3.json when that directory exists.  Asserted as for
     8^3x16: playback with all vectors reproduces the records, with none the
-    undeflated forms, and the two estimates agree within their errors."""
+    undeflated forms, and the two estimates agree within their errors.  Also
+    reported: W_d of 10 sampled rows (plain, deflated, masked to 32 HP vectors,
+    both; the mask leaves no entry at distance 1) and Theorem 2's predicted
+    Monte Carlo variances from ||D^-1||_F^2 (N x the sampled mean squared row
+    norm) and the 200 deflated values 1 / sigma, beside the measured ones."""
     from paper_1603_05988_amd import _lib as L
     w = WORKLOADS["c3"]
     U = gauge_links(w.L, w.eps, w.seed)
@@ -111,11 +115,14 @@ def test_variance_report_c3():
             q[r, b:b + B] = [x["q"] for x in recs]
             qd[r, b:b + B] = [x["q_defl"] for x in recs]
             coef[r, 0, :, b:b + B], coef[r, 1, :, b:b + B] = c1, c2
-    mc = []
+    mc, mcd = [], []
     for b in range(0, 256, B):
-        mc += [x["q"] for x in ctx.trace_batch(w.seed, 7, False, b, B, prm)]
-    mc = np.array(mc)
+        recs = ctx.trace_batch(w.seed, 7, False, b, B, prm)
+        mc += [x["q"] for x in recs]
+        mcd += [x["q_defl"] for x in recs]
+    mc, mcd = np.array(mc), np.array(mcd)
     v_stoc = float(np.sum(np.abs(mc - mc.mean()) ** 2) / (len(mc) - 1))
+    v_stoc_defl = float(np.sum(np.abs(mcd - mcd.mean()) ** 2) / (len(mcd) - 1))
     s_list = [1, 2, 4, 8, 16, 32, 64, 128, 256]
     und = L.hp_variance(q, s_list, v_stoc)
     dfl = L.hp_variance(qd, s_list, v_stoc)
@@ -136,13 +143,33 @@ def test_variance_report_c3():
     m_u = complex(und[-1]["mean_re"], und[-1]["mean_im"])
     m_d = complex(dfl[-1]["mean_re"], dfl[-1]["mean_im"]) + TD
     assert abs(m_u - m_d) <= 5 * np.hypot(und[-1]["mean_err"], dfl[-1]["mean_err"]), (m_u, m_d)
+    # W_d profiles of 10 sampled rows (Section 6.2) and Theorem 2's prediction
+    # (Section 2.1) from what one knows in practice: ||D^-1||_F^2 estimated as N
+    # times the mean squared row norm of the sampled rows, and the k deflated
+    # singular values 1 / sigma of D^-1
+    rows = np.random.default_rng(12).choice(w.N, 10, replace=False)
+    prof = {}
+    for name, defl, hp in (("monte_carlo", False, 0), ("deflation", True, 0), ("hp32", False, 32),
+                           ("hp32_deflation", True, 32)):
+        Wg, m = ctx.distance_profile(rows, prm, deflate=defl, hp_vectors=hp)
+        prof[name] = Wg.mean(axis=0).tolist()
+    frob2 = float(w.N * np.dot(prof["monte_carlo"], m))   # N x the mean squared row norm
+    frob2_defl = float(w.N * np.dot(prof["deflation"], m))
+    thm = L.theorem2(w.N, w.k, False, float("nan"), frob2, 1.0 / np.sort(sig))
+    assert prof["hp32"][1] == 0.0 and prof["hp32"][0] > 0.0
     out = {"lattice": list(w.L), "runs": R, "probes_per_run": S, "k": w.k, "T_D": [TD.real, TD.imag],
-           "sigma_min": float(np.min(sig)), "v_stoc": v_stoc, "mc_probes": len(mc),
+           "sigma_min": float(np.min(sig)), "v_stoc": v_stoc, "v_stoc_deflated": v_stoc_defl, "mc_probes": len(mc),
            "trace_undeflated": [m_u.real, m_u.imag], "trace_deflated": [m_d.real, m_d.imag],
            "hp": [{"s": a["s"], "var": a["var"], "var_err": a["var_err"], "rs": a["rs"], "rs_err": a["rs_err"],
                    "var_defl": b["var"], "var_defl_err": b["var_err"], "rs_defl": b["rs"], "rs_defl_err": b["rs_err"]}
                   for a, b in zip(und, dfl)],
-           "playback_s%d" % S: play}
+           "playback_s%d" % S: play,
+           "wd_rows": rows.tolist(), "wd_m": m.tolist(), "wd": prof,
+           "theorem2": {"frob2_sampled": frob2, "frob2_deflated_sampled": frob2_defl,
+                        "frob2_minus_deflated_sigma2": frob2 - float(np.sum(1.0 / np.asarray(sig) ** 2)),
+                        "predicted_var_0": thm["var_0"], "predicted_var_k": thm["var_k"], "predicted_ratio": thm["ratio"],
+                        "measured_var_0": v_stoc, "measured_var_k": v_stoc_defl,
+                        "measured_ratio": v_stoc_defl / v_stoc}}
     print(json.dumps(out)[:2000])
     if os.path.isdir("gpurun_out"):
         with open("gpurun_out/variance_c3.json", "w") as f:
