@@ -241,3 +241,32 @@ def test_two_row_tiles_and_four_slices(c1):
         bound = mfma_bound(Wr, M, g5, Z, G[g]) + 1e-12 * np.abs(q[g]).max()
         assert np.all(np.abs((q[g] - qd[g]) - d_ref) <= bound), g
     ctx.clear_deflation()
+
+
+def test_largest_batch_and_most_matrices(c1):
+    """DHT_MAX_BATCH probes in one call (FP64 basis: one generic spin-pair pass over
+    256 columns) and DHT_MAX_GAMMA random matrices at once."""
+    w, D, Dinv, g5, W, ctx = c1
+    L = _lib()
+    ctx.set_deflation(cuda(W.T), L.FP64)
+    M = estimator.galerkin_M(W, D, g5)
+    rs = np.random.default_rng(29)
+    G = rs.standard_normal((64, 4, 4)) + 1j * rs.standard_normal((64, 4, 4))
+    td = ctx.gamma_set(G)
+    for g in (0, 31, 63):
+        ref = gamma.gamma_deflated_trace(W, M, g5, G[g])
+        assert abs(td[g] - ref) <= 1e-10 * max(1.0, abs(ref))
+    prm = ctx.params(L.SOLVER_BICGSTAB_FP64, tol=1e-12)
+    q, qd, stats = ctx.trace_gamma_batch(w.seed, 5, False, 0, 256, prm)
+    assert q.shape == (64, 256)
+    Z = rng.probes(w.L, w.seed, 5, False, 0, 256)
+    X = Z @ Dinv.T
+    for g in (0, 17, 63):
+        q_ref = gamma.gamma_quadratic_forms(Z, X, G[g])
+        d_ref = gamma.gamma_corrections(W, M, g5, Z, G[g])
+        scale = np.abs(q_ref).max()
+        assert np.abs(q[g] - q_ref).max() <= 1e-10 * scale
+        assert np.abs((q[g] - qd[g]) - d_ref).max() <= 1e-10 * scale
+    with pytest.raises(RuntimeError):
+        ctx.gamma_set(np.zeros((65, 4, 4)))
+    ctx.clear_deflation()

@@ -70,6 +70,17 @@ def test_lobpcg_c1_matches_dense_svd(c1, k):
     ctx.clear_deflation()
 
 
+def test_lobpcg_c1_window_of_64(c1):
+    """A window wider than k (64 vectors for k = 16), without the preconditioner."""
+    w, D, ctx = c1
+    L = _lib()
+    s_ref = np.sort(np.linalg.svd(D, compute_uv=False))[:16]
+    sig, res, st, td = ctx.lobpcg(16, L.FP32, tol=1e-10, max_iter=400, block=64, precond=False, seed=9)
+    assert st["status"] == 0 and st["converged"] == 16, st
+    assert np.abs(np.sort(sig) - s_ref).max() <= 1e-8 * s_ref.max()
+    ctx.clear_deflation()
+
+
 def test_lobpcg_invalid_arguments(c1):
     w, D, ctx = c1
     with pytest.raises(RuntimeError):
