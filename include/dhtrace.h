@@ -525,18 +525,35 @@ int dht_bench_hop(dht_ctx* ctx, int prec, int nrhs, int warmup, int reps, double
  *                     site's links loaded once per 16-lane row (the row's 16
  *                     right-hand sides) and broadcast within the row; BF16
  *                     sweeps of >= 16 right-hand sides only (other precisions
- *                     and smaller sweeps run the plain form).
+ *                     and smaller sweeps run the plain form);
+ *   DHT_HOP_TSKEW, DHT_HOP_TSKEW_ROWL  as TMARCH / TMARCH_ROWL, skewed so that
+ *                     each step reads one input slice: step t completes
+ *                     output t and starts output t + 1, whose accumulator is
+ *                     carried to the next step (same t_chunk rules).
  * streaming_stores = 1 writes the output with non-temporal stores.
  * rhs_group = G (a power of two dividing nrhs; 0 = nrhs): the lattice is swept
  * once per group of G right-hand sides, the groups side by side on the chip,
  * so fewer bytes per site share the caches while the links are read once per
- * group (the LDS form needs G >= 8). */
-enum { DHT_HOP_SITE = 0, DHT_HOP_SITE_LDS = 1, DHT_HOP_TMARCH = 2, DHT_HOP_SITE_ROWL = 3, DHT_HOP_TMARCH_ROWL = 4 };
+ * group (the LDS form needs G >= 8).
+ * z_block = Z (t-marching forms; a power of two dividing Lz, 0 or 1 = none):
+ * the x-rows of a chunk are walked in blocks of Z consecutive z planes, y
+ * next, so that the workgroups resident together hold the z neighbours of
+ * their rows as well as the y neighbours. */
+enum {
+    DHT_HOP_SITE = 0,
+    DHT_HOP_SITE_LDS = 1,
+    DHT_HOP_TMARCH = 2,
+    DHT_HOP_SITE_ROWL = 3,
+    DHT_HOP_TMARCH_ROWL = 4,
+    DHT_HOP_TSKEW = 5,
+    DHT_HOP_TSKEW_ROWL = 6
+};
 typedef struct dht_hop_config {
     int form;
     int streaming_stores;
     int t_chunk;
     int rhs_group;
+    int z_block;
 } dht_hop_config;
 
 /* Epilogue classes, tuned separately: DHT_HOP_PLAIN launches compute
@@ -558,7 +575,7 @@ typedef struct dht_tune_result {
     dht_hop_config best[3];  /* per epilogue class: fastest candidate that passed the parity check */
     double best_ms[3];       /* its mean time per hop application */
     double default_ms[3];    /* the built-in default's time */
-    int candidates;          /* shapes timed per class */
+    int candidates;          /* shapes of the grid timed per class (z blocks excluded) */
     int rejected;            /* shapes whose output differed from the default's beyond rounding */
     double max_rel_diff;     /* largest max|out - out_default| / max|out_default| among accepted shapes */
 } dht_tune_result;
@@ -568,14 +585,17 @@ typedef struct dht_tune_result {
  * context stream, after warm-up; the fused class with an x-pay operand and the
  * fused (out, x), (out, out) sums), check each output against the default
  * shape's (relative max-norm difference <= 1e-12 FP64, 1e-5 FP32, 1.6e-2 BF16,
- * i.e. a few units in the last place of the storage format), and install the
- * fastest accepted shape per class on the context.  Needs the gauge field;
+ * i.e. a few units in the last place of the storage format), then time the
+ * fastest shape of each t-marching form again with z blocks of 2, 4 and 8
+ * (those dividing Lz), and install the fastest accepted shape per class on
+ * the context.  Needs the gauge field;
  * uses the context workspace (four half fields of nrhs RHS). */
 int dht_autotune_hop(dht_ctx* ctx, int prec, int nrhs, int reps, dht_tune_result* out);
 /* The autotuner with a cache file: if `cache_path` (may be NULL) holds shapes
  * for this lattice, prec and nrhs they are installed without timing
  * (out->candidates = 0); otherwise dht_autotune_hop runs and its shapes are
- * appended to the file (one text line per epilogue class). */
+ * appended to the file (one text line per epilogue class; lines written in
+ * another layout are skipped). */
 int dht_autotune(dht_ctx* ctx, int prec, int nrhs, int reps, const char* cache_path, dht_tune_result* out);
 
 /* ---- variance analysis (Sections 6.1-6.3; host arrays, no device) -------- */

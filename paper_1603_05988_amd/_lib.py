@@ -69,7 +69,12 @@ class EigStats(ctypes.Structure):
 
 class HopConfig(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("streaming_stores", ctypes.c_int), ("t_chunk", ctypes.c_int),
-                ("rhs_group", ctypes.c_int)]
+                ("rhs_group", ctypes.c_int), ("z_block", ctypes.c_int)]
+
+
+def _hop_dict(h) -> dict:
+    return {"form": h.form, "streaming_stores": h.streaming_stores, "t_chunk": h.t_chunk,
+            "rhs_group": h.rhs_group, "z_block": h.z_block}
 
 
 class TuneResult(ctypes.Structure):
@@ -77,11 +82,11 @@ class TuneResult(ctypes.Structure):
                 ("candidates", ctypes.c_int), ("rejected", ctypes.c_int), ("max_rel_diff", ctypes.c_double)]
 
 
-HOP_SITE, HOP_SITE_LDS, HOP_TMARCH, HOP_SITE_ROWL, HOP_TMARCH_ROWL = 0, 1, 2, 3, 4
+HOP_SITE, HOP_SITE_LDS, HOP_TMARCH, HOP_SITE_ROWL, HOP_TMARCH_ROWL, HOP_TSKEW, HOP_TSKEW_ROWL = 0, 1, 2, 3, 4, 5, 6
 HOP_PLAIN, HOP_FUSED, HOP_FUSED_A = 0, 1, 2
 HOP_CLASSES = {HOP_PLAIN: "plain", HOP_FUSED: "fused", HOP_FUSED_A: "fused_a"}
 HOP_FORMS = {HOP_SITE: "site", HOP_SITE_LDS: "site_lds", HOP_TMARCH: "tmarch", HOP_SITE_ROWL: "site_rowl",
-             HOP_TMARCH_ROWL: "tmarch_rowl"}
+             HOP_TMARCH_ROWL: "tmarch_rowl", HOP_TSKEW: "tskew", HOP_TSKEW_ROWL: "tskew_rowl"}
 
 
 class BatchTune(ctypes.Structure):
@@ -635,8 +640,7 @@ class Context:
     def hop_config(self, prec: int, nrhs: int, epilogue: int = HOP_PLAIN) -> dict:
         h = HopConfig()
         check(load().dht_hop_config_get(self.h, prec, nrhs, epilogue, ctypes.byref(h)))
-        return {"form": h.form, "streaming_stores": h.streaming_stores, "t_chunk": h.t_chunk,
-                "rhs_group": h.rhs_group}
+        return _hop_dict(h)
 
     def set_hop_config(self, prec: int, nrhs: int, cfg: dict | None, epilogue: int | None = None):
         """Install a hopping-kernel shape for (prec, nrhs) and one epilogue
@@ -646,7 +650,7 @@ class Context:
                 check(load().dht_hop_config_set(self.h, prec, nrhs, cls, None))
                 continue
             h = HopConfig(int(cfg["form"]), int(cfg.get("streaming_stores", 1)), int(cfg.get("t_chunk", 0)),
-                          int(cfg.get("rhs_group", 0)))
+                          int(cfg.get("rhs_group", 0)), int(cfg.get("z_block", 0)))
             check(load().dht_hop_config_set(self.h, prec, nrhs, cls, ctypes.byref(h)))
 
     def autotune_hop(self, prec: int, nrhs: int, reps: int = 10) -> dict:
@@ -655,9 +659,7 @@ class Context:
         rounding."""
         r = TuneResult()
         check(load().dht_autotune_hop(self.h, prec, nrhs, reps, ctypes.byref(r)))
-        best = {HOP_CLASSES[k]: {"form": r.best[k].form, "streaming_stores": r.best[k].streaming_stores,
-                                 "t_chunk": r.best[k].t_chunk, "rhs_group": r.best[k].rhs_group}
-                for k in HOP_CLASSES}
+        best = {HOP_CLASSES[k]: _hop_dict(r.best[k]) for k in HOP_CLASSES}
         out = {"prec": prec, "nrhs": nrhs, "best": best,
                "best_form": {c: HOP_FORMS[b["form"]] for c, b in best.items()},
                "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in HOP_CLASSES},
@@ -672,9 +674,7 @@ class Context:
         r = TuneResult()
         cp = cache_path.encode() if cache_path else None
         check(load().dht_autotune(self.h, prec, nrhs, reps, cp, ctypes.byref(r)))
-        return {"best": {HOP_CLASSES[k]: {"form": r.best[k].form, "streaming_stores": r.best[k].streaming_stores,
-                                          "t_chunk": r.best[k].t_chunk, "rhs_group": r.best[k].rhs_group}
-                         for k in HOP_CLASSES},
+        return {"best": {HOP_CLASSES[k]: _hop_dict(r.best[k]) for k in HOP_CLASSES},
                 "best_ms": {HOP_CLASSES[k]: r.best_ms[k] for k in HOP_CLASSES},
                 "candidates": r.candidates, "rejected": r.rejected}
 

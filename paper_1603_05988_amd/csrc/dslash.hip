@@ -47,6 +47,7 @@ struct HopArgs {
     double ca, cb, cz;   // out = ca * x + cb * Hop(in) + cz * z
     void* out16;         // HOP_OUT16: s16[r] * out also stored in BF16 (an inner right-hand side)
     const double* s16;
+    int zbs;             // t-marching: log2 of the z block of the row order
 };
 
 static constexpr int HOP_THREADS = HOP_LANES;
@@ -600,6 +601,21 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_kernel(HopArgs a) {
     hop_block_reduce<NP>(a, blk, g, d0, d1);
 }
 
+// Column of a t-marching lane from its index j in the chunk: x-rows (16 lanes
+// per row at 16 RHS) in blocks of 2^zbs consecutive z, y next, z blocks last,
+// so that the workgroups resident on one XCD at a time (dispatched in index
+// order) hold both the y and the z neighbours of most rows and the neighbour
+// reads meet in its L2 (2^zbs = 1: y fastest, z neighbours Ly rows apart).
+__device__ inline void tm_column(const HopArgs& a, int j, int& s3, int& xh, int& y, int& z) {
+    xh = j % a.Lxh;
+    const int rho = j / a.Lxh;
+    const int zl = rho & ((1 << a.zbs) - 1);
+    const int rest = rho >> a.zbs;
+    y = rest % a.Ly;
+    z = ((rest / a.Ly) << a.zbs) | zl;
+    s3 = xh + a.Lxh * (y + a.Ly * z);
+}
+
 // ---------------------------------------------------------------------------
 // t-marching form.  A lane owns one (x, y, z) column of the output parity and
 // one RHS and walks t upward through a chunk of tc slices.  The t-forward
@@ -730,10 +746,8 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
     const int chunk = col / V3;
     Cx<double> d0 = cmake(0.0, 0.0), d1 = cmake(0.0, 0.0);
     if (chunk < a.nchunk) {
-        const int s3 = col - chunk * V3;
-        const int xh = s3 % a.Lxh;
-        const int y = (s3 / a.Lxh) % a.Ly;
-        const int z = s3 / (a.Lxh * a.Ly);
+        int s3, xh, y, z;
+        tm_column(a, col - chunk * V3, s3, xh, y, z);
         const int sy = a.Lxh, sz = a.Lxh * a.Ly;
         const int yf = y == a.Ly - 1 ? -(a.Ly - 1) * sy : sy, yb = y == 0 ? (a.Ly - 1) * sy : -sy;
         const int zf = z == a.Lz - 1 ? -(a.Lz - 1) * sz : sz, zb = z == 0 ? (a.Lz - 1) * sz : -sz;
@@ -750,6 +764,160 @@ __global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
             tm_step<S, DAG, G5OUT, XPAY, DOT, MIX, ROWL>(a, t, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb0, d0, d1);
             tm_step<S, DAG, G5OUT, XPAY, DOT, MIX, ROWL>(a, t + 1, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb1, d0,
                                                          d1);
+        }
+    }
+    hop_block_reduce<NP>(a, blk, g, d0, d1);
+}
+
+// ---------------------------------------------------------------------------
+// Skewed t-marching form.  As above, a lane owns one (x, y, z) column and one
+// RHS and walks a chunk of t slices, but step t reads a single input slice,
+// t + 1: the column's own spinor there completes output t (its forward t-hop)
+// and gives the backward t-hop of output t + 2, and the x, y, z neighbours
+// there start output t + 1, whose accumulator is carried into the next step.
+// The plain t-march reads slice t + 1 at step t (the own column) and again at
+// step t + 1 (as the spatial neighbours of the next output), one step of
+// every resident workgroup's traffic apart; here both reads fall in one step,
+// so the neighbour reuse between columns meets in the caches sooner.
+// ---------------------------------------------------------------------------
+
+// row-shared links of a skewed step: the spatial slots (forward at s, backward
+// at sbx, sby, sbz) belong to output t + 1, the forward t slot to output t
+// (site sft) and the backward t slot to the input site sbt of slice t + 1
+__device__ inline void row_links_load_skew(const void* U, int Vh, int p, int s, int sft, int sbx, int sby, int sbz,
+                                           int sbt, RowLinks& rl) {
+    const int q = threadIdx.x & 15, d = q >> 1, mu = d >> 1;
+    const bool bwd = d & 1;
+    int site = mu == 3 ? sft : s;
+    if (bwd) site = mu == 0 ? sbx : (mu == 1 ? sby : (mu == 2 ? sbz : sbt));
+    const int64_t v = ((int64_t)(mu * 2 + (bwd ? 1 - p : p)) * Vh + site) * 3;   // 3 vectors per BF16 link
+    const uint2* ptr = (const uint2*)((const uint4*)U + v) + 3 * (q & 1);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const uint2 d2 = ptr[k];
+        rl.w[2 * k] = d2.x;
+        rl.w[2 * k + 1] = d2.y;
+    }
+}
+
+// One skewed step t (OPEN: the step before the chunk's first output, which
+// only starts output t + 1 = t0).  acc carries output t in and output t + 1
+// out; wprod receives the backward t-hop of output t + 2, wcons holds that of
+// output t + 1.
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, int MIX, bool ROWL, bool OPEN>
+__device__ inline void tsk_step(const HopArgs& a, int t, int t1, int s3, int xh, int y, int z, int r, int V3, int yf,
+                                int yb, int zf, int zb, Cx<typename Store<S>::acc>* wprod,
+                                const Cx<typename Store<S>::acc>* wcons, Cx<typename Store<S>::acc>* acc,
+                                Cx<double>& d0, Cx<double>& d1) {
+    typedef typename Store<S>::acc T;
+    constexpr int NV = (9 + Store<S>::VW - 1) / Store<S>::VW;
+    constexpr int SF = DAG ? -1 : 1;
+    const int p = a.out_parity;
+    const int64_t vstride = (int64_t)a.Vh << a.bshift;
+    const int tn = t + 1 == a.Lt ? 0 : t + 1;   // the input slice of this step
+    int sn = tn * V3 + s3;                      // own column there; also output t + 1's site
+    int s0 = OPEN ? sn : t * V3 + s3;           // output t
+    asm volatile("" : "+v"(sn), "+v"(s0));
+    const int x = 2 * xh + ((p + y + z + tn) & 1);
+    const int row = sn - xh;
+    const int xf = x + 1 == a.Lx ? 0 : x + 1, xb = x == 0 ? a.Lx - 1 : x - 1;
+    const int sx = row + (xb >> 1), sy = sn + yb, sz = sn + zb;
+    RowLinks rl;
+    if constexpr (ROWL) row_links_load_skew(a.U, a.Vh, p, sn, s0, sx, sy, sz, sn, rl);
+    const bool more = t + 1 < t1, more2 = t + 2 < t1;
+    if constexpr (std::is_same<S, bf16x2>::value) {
+        uint32_t psi[12], u[12];
+        Cx<float> w[6];
+        load_packed_spinor(a.in, ((int64_t)sn << a.bshift) + r, vstride, psi);
+        if constexpr (!OPEN) {   // forward t-hop completes output t
+            if constexpr (ROWL) row_link_get<6>(rl, u);
+            else load_packed_link(a.U, ((int64_t)(6 + p) * a.Vh + s0) * NV, u);
+            link_mult_bf16<3, SF, false>(psi, u, w);
+            reconstruct<3, SF>(acc, w, (a.antiperiodic && t == a.Lt - 1) ? -1.f : 1.f);
+            fence_acc(acc);
+        }
+        if (more2) {   // backward t-hop of output t + 2, from the same input spinor
+            if constexpr (ROWL) row_link_get<7>(rl, u);
+            else load_packed_link(a.U, ((int64_t)(6 + 1 - p) * a.Vh + sn) * NV, u);
+            link_mult_bf16<3, -SF, true>(psi, u, w);
+            wb_store(wprod, w);
+        }
+    } else {
+        Cx<T> psi[12], h[6], u[9], w[6];
+        load_operand<S, (MIX & HOP_IN16) != 0, false>(a.in, ((int64_t)sn << a.bshift) + r, vstride, psi);
+        if constexpr (!OPEN) {
+            project<3, SF>(psi, h);
+            load_link<S>(a.U, ((int64_t)(6 + p) * a.Vh + s0) * NV, u);
+            mul_link<false>(u, h, w);
+            reconstruct<3, SF>(acc, w, (a.antiperiodic && t == a.Lt - 1) ? T(-1) : T(1));
+            fence_acc(acc);
+        }
+        if (more2) {
+            project<3, -SF>(psi, h);
+            load_link<S>(a.U, ((int64_t)(6 + 1 - p) * a.Vh + sn) * NV, u);
+            mul_link<true>(u, h, w);
+            wb_store(wprod, w);
+        }
+    }
+    if constexpr (!OPEN) {
+        hop_epilogue<S, G5OUT, XPAY, DOT, MIX>(a, s0, r, acc, d0, d1);
+        fence_acc(acc);
+    }
+    if (more) {   // start output t + 1: its pending backward t-hop, then x, y, z from this slice
+        Cx<T> wb[6];
+        wb_load(wcons, wb);
+#pragma unroll
+        for (int i = 0; i < 12; i++) acc[i] = cmake<T>(0, 0);
+        reconstruct<3, -SF>(acc, wb, T(1));
+        fence_acc(acc);
+        hop_dir<S, 0, DAG, MIX, ROWL>(a, row + (xf >> 1), sx, r, false, false, a.U, ((int64_t)p * a.Vh + sn) * NV, a.U,
+                                      ((int64_t)(1 - p) * a.Vh + sx) * NV, acc, &rl);
+        hop_dir<S, 1, DAG, MIX, ROWL>(a, sn + yf, sy, r, false, false, a.U, ((int64_t)(2 + p) * a.Vh + sn) * NV, a.U,
+                                      ((int64_t)(3 - p) * a.Vh + sy) * NV, acc, &rl);
+        hop_dir<S, 2, DAG, MIX, ROWL>(a, sn + zf, sz, r, false, false, a.U, ((int64_t)(4 + p) * a.Vh + sn) * NV, a.U,
+                                      ((int64_t)(5 - p) * a.Vh + sz) * NV, acc, &rl);
+    }
+}
+
+template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, int MIX, bool ROWL = false>
+__global__ __launch_bounds__(HOP_THREADS) void hop_tsk_kernel(HopArgs a) {
+    typedef typename Store<S>::acc T;
+    extern __shared__ uint4 hop_lds[];   // [2][6][HOP_THREADS] Cx<T>
+    constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : ((DOT == HOPDOT_OUT_X || DOT == HOPDOT_NORM_ZX) ? 2 : 0);
+    constexpr int SF = DAG ? -1 : 1;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = blk / a.bpg;                 // RHS group
+    const int gid = (blk - g * a.bpg) * HOP_THREADS + threadIdx.x;
+    const int G = 1 << a.gshift;
+    const int col = gid >> a.gshift;   // chunk * V3 + column
+    const int r = g * G + (gid & (G - 1));
+    const int V3 = a.Vh / a.Lt;
+    const int chunk = col / V3;
+    Cx<double> d0 = cmake(0.0, 0.0), d1 = cmake(0.0, 0.0);
+    if (chunk < a.nchunk) {
+        int s3, xh, y, z;
+        tm_column(a, col - chunk * V3, s3, xh, y, z);
+        const int sy = a.Lxh, sz = a.Lxh * a.Ly;
+        const int yf = y == a.Ly - 1 ? -(a.Ly - 1) * sy : sy, yb = y == 0 ? (a.Ly - 1) * sy : -sy;
+        const int zf = z == a.Lz - 1 ? -(a.Lz - 1) * sz : sz, zb = z == 0 ? (a.Lz - 1) * sz : -sz;
+        const int64_t vstride = (int64_t)a.Vh << a.bshift;
+        const int t0 = chunk * a.tc, t1 = t0 + a.tc;
+        // step k of the chunk (k = t - t0, from -1) leaves the backward t-hop
+        // of output t + 2 in slot k & 1 and takes that of output t + 1 from
+        // slot (k + 1) & 1
+        Cx<T>* wb0 = (Cx<T>*)hop_lds;
+        Cx<T>* wb1 = wb0 + 6 * HOP_THREADS;
+        t_back<S, -SF, MIX>(a, (t0 == 0 ? a.Lt - 1 : t0 - 1) * V3 + s3, r, vstride,
+                            (a.antiperiodic && t0 == 0) ? T(-1) : T(1), wb0);
+        Cx<T> acc[12];
+        tsk_step<S, DAG, G5OUT, XPAY, DOT, MIX, ROWL, true>(a, t0 - 1, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb1,
+                                                             wb0, acc, d0, d1);
+#pragma nounroll
+        for (int t = t0; t < t1; t += 2) {
+            tsk_step<S, DAG, G5OUT, XPAY, DOT, MIX, ROWL, false>(a, t, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb, wb0,
+                                                                  wb1, acc, d0, d1);
+            tsk_step<S, DAG, G5OUT, XPAY, DOT, MIX, ROWL, false>(a, t + 1, t1, s3, xh, y, z, r, V3, yf, yb, zf, zb,
+                                                                  wb1, wb0, acc, d0, d1);
         }
     }
     hop_block_reduce<NP>(a, blk, g, d0, d1);
@@ -775,7 +943,7 @@ static int auto_chunk(const dht_ctx* c, int nrhs) {
 
 int hop_config_check(const dht_ctx* c, int nrhs, const HopConfig& h) {
     if (log2_batch(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
-    if (h.form < DHT_HOP_SITE || h.form > DHT_HOP_TMARCH_ROWL || (h.nt != 0 && h.nt != 1))
+    if (h.form < DHT_HOP_SITE || h.form > DHT_HOP_TSKEW_ROWL || (h.nt != 0 && h.nt != 1))
         return set_error(DHT_ERR_INVALID_ARG, "bad hop form");
     const int G = h.rg > 0 ? h.rg : nrhs;
     if (log2_batch(G) < 0 || G > nrhs) return set_error(DHT_ERR_INVALID_ARG, "RHS group must be a power of two <= nrhs");
@@ -783,6 +951,8 @@ int hop_config_check(const dht_ctx* c, int nrhs, const HopConfig& h) {
         return set_error(DHT_ERR_INVALID_ARG, "LDS-link form needs at least 8 right-hand sides per sweep");
     if (hop_form_tmarch(h.form) && h.tc != 0 && (h.tc < 2 || (h.tc & 1) || c->g.L[3] % h.tc))
         return set_error(DHT_ERR_INVALID_ARG, "t chunk must be even and divide Lt");
+    if (h.zb < 0 || h.zb > 8 || (h.zb > 0 && (!hop_form_tmarch(h.form) || c->g.L[2] % (1 << h.zb))))
+        return set_error(DHT_ERR_INVALID_ARG, "z block must be a power of two dividing Lz (t-marching forms only)");
     return DHT_OK;
 }
 
@@ -854,12 +1024,15 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     const HopConfig cfg = hop_config(c, prec_of<S>(), nrhs, cls);
     a.tc = cfg.tc;
     a.nchunk = a.Lt / cfg.tc;
+    a.zbs = hop_form_tmarch(cfg.form) ? cfg.zb : 0;
     a.nt = cfg.nt;
     // the row-shared forms need BF16 rows of one site (>= 16 RHS per sweep);
     // otherwise they run as their plain form
     const int G0 = cfg.rg > 0 ? cfg.rg : nrhs;
     const bool rowl = std::is_same<S, bf16x2>::value && G0 >= 16 &&
-                      (cfg.form == DHT_HOP_SITE_ROWL || cfg.form == DHT_HOP_TMARCH_ROWL);
+                      (cfg.form == DHT_HOP_SITE_ROWL || cfg.form == DHT_HOP_TMARCH_ROWL ||
+                       cfg.form == DHT_HOP_TSKEW_ROWL);
+    const bool skew = cfg.form == DHT_HOP_TSKEW || cfg.form == DHT_HOP_TSKEW_ROWL;
     const int mode = hop_form_tmarch(cfg.form) ? DHT_HOP_TMARCH : (cfg.form == DHT_HOP_SITE_ROWL ? DHT_HOP_SITE : cfg.form);
     const int G = cfg.rg > 0 ? cfg.rg : nrhs;   // RHS per sweep
     a.gshift = log2_batch(G);
@@ -878,7 +1051,10 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
     if (dagger == D_ && g5out == G_ && xp == X_ && kind == K_ && mix == (M_)) {                              \
         if constexpr (std::is_same<S, bf16x2>::value) {                                                      \
             if (rowl) {                                                                                      \
-                if (mode == DHT_HOP_TMARCH)                                                                  \
+                if (skew)                                                                                    \
+                    hipLaunchKernelGGL((hop_tsk_kernel<S, D_, G_, X_, K_, M_, true>), grid, block, tm_lds,   \
+                                       c->stream, a);                                                        \
+                else if (mode == DHT_HOP_TMARCH)                                                             \
                     hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_, M_, true>), grid, block, tm_lds,    \
                                        c->stream, a);                                                        \
                 else                                                                                         \
@@ -887,7 +1063,9 @@ static int launch_hop(dht_ctx* c, int out_parity, const void* in, void* out, con
                 goto launched;                                                                               \
             }                                                                                                \
         }                                                                                                    \
-        if (mode == DHT_HOP_TMARCH)                                                                          \
+        if (skew)                                                                                            \
+            hipLaunchKernelGGL((hop_tsk_kernel<S, D_, G_, X_, K_, M_>), grid, block, tm_lds, c->stream, a);  \
+        else if (mode == DHT_HOP_TMARCH)                                                                     \
             hipLaunchKernelGGL((hop_tm_kernel<S, D_, G_, X_, K_, M_>), grid, block, tm_lds, c->stream, a);   \
         else if (mode == DHT_HOP_SITE_LDS)                                                                   \
             hipLaunchKernelGGL((hop_kernel<S, D_, G_, X_, K_, true, M_>), grid, block, lds, c->stream, a);   \

@@ -247,12 +247,15 @@ struct ProfStat {
 
 // learned preconditioner weights (device)
 // hopping-kernel launch shape (dht_hop_config); form < 0: unset
-inline bool hop_form_tmarch(int form) { return form == DHT_HOP_TMARCH || form == DHT_HOP_TMARCH_ROWL; }
+inline bool hop_form_tmarch(int form) {
+    return form == DHT_HOP_TMARCH || form == DHT_HOP_TMARCH_ROWL || form == DHT_HOP_TSKEW || form == DHT_HOP_TSKEW_ROWL;
+}
 struct HopConfig {
     int form = -1;
     int nt = 1;
     int tc = 0;
     int rg = 0;   // RHS per sweep of the lattice (0: all)
+    int zb = 0;   // t-marching: log2 of the z block of the row order
 };
 
 struct NNState {

@@ -151,22 +151,26 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
                 h.form = DHT_HOP_SITE_LDS;
                 cand.push_back(h);
             }
-            h.form = DHT_HOP_TMARCH;
-            for (int tc = 2; tc <= c->g.L[3]; tc += 2)
-                if (c->g.L[3] % tc == 0) {
-                    h.tc = tc;
-                    cand.push_back(h);
-                }
-            if (prec == DHT_BF16 && G >= 16) {   // links shared across each site's row of 16 lanes
-                h.tc = 0;
-                h.form = DHT_HOP_SITE_ROWL;
-                cand.push_back(h);
-                h.form = DHT_HOP_TMARCH_ROWL;
+            for (int f : {DHT_HOP_TMARCH, DHT_HOP_TSKEW}) {
+                h.form = f;
                 for (int tc = 2; tc <= c->g.L[3]; tc += 2)
                     if (c->g.L[3] % tc == 0) {
                         h.tc = tc;
                         cand.push_back(h);
                     }
+            }
+            if (prec == DHT_BF16 && G >= 16) {   // links shared across each site's row of 16 lanes
+                h.tc = 0;
+                h.form = DHT_HOP_SITE_ROWL;
+                cand.push_back(h);
+                for (int f : {DHT_HOP_TMARCH_ROWL, DHT_HOP_TSKEW_ROWL}) {
+                    h.form = f;
+                    for (int tc = 2; tc <= c->g.L[3]; tc += 2)
+                        if (c->g.L[3] % tc == 0) {
+                            h.tc = tc;
+                            cand.push_back(h);
+                        }
+                }
             }
         }
     int rejected = 0;
@@ -184,21 +188,45 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
         DHT_TRY(time_hop(c, prec, nrhs, L, reps, e0, e1, &def_ms));
         HopConfig best = def;
         double best_ms = def_ms;
-        for (const HopConfig& h : cand) {
+        // the fastest shape of each t-marching form, then tried with z blocks
+        HopConfig form_best[8];
+        double form_ms[8];
+        for (int f = 0; f < 8; f++) form_ms[f] = -1.0;
+        auto try_shape = [&](const HopConfig& h, double* ms_out) -> int {
+            *ms_out = -1.0;
             c->hop_forced = h;
             DHT_TRY(tune_hop(c, prec, nrhs, L));
             double rd = 0.0;
             DHT_TRY(rel_maxdiff(c, prec, fo, fr, nrhs, red, &rd));
             if (!(rd <= tune_tolerance(prec))) {
                 rejected++;
-                continue;
+                return DHT_OK;
             }
             worst_ok = std::max(worst_ok, rd);
             double ms = 0.0;
             DHT_TRY(time_hop(c, prec, nrhs, L, reps, e0, e1, &ms));
+            *ms_out = ms;
             if (ms < best_ms) {
                 best_ms = ms;
                 best = h;
+            }
+            return DHT_OK;
+        };
+        for (const HopConfig& h : cand) {
+            double ms;
+            DHT_TRY(try_shape(h, &ms));
+            if (ms >= 0.0 && hop_form_tmarch(h.form) && (form_ms[h.form] < 0.0 || ms < form_ms[h.form])) {
+                form_ms[h.form] = ms;
+                form_best[h.form] = h;
+            }
+        }
+        for (int f = 0; f < 8; f++) {
+            if (form_ms[f] < 0.0) continue;
+            for (int zb = 1; zb <= 3 && c->g.L[2] % (1 << zb) == 0; zb++) {
+                HopConfig h = form_best[f];
+                h.zb = zb;
+                double ms;
+                DHT_TRY(try_shape(h, &ms));
             }
         }
         c->hop_force = false;
@@ -208,6 +236,7 @@ static int autotune(dht_ctx* c, int prec, int nrhs, int reps, dht_tune_result* r
         res->best[cls].streaming_stores = best.nt;
         res->best[cls].t_chunk = hop_form_tmarch(best.form) ? best.tc : 0;
         res->best[cls].rhs_group = best.rg > 0 ? best.rg : nrhs;
+        res->best[cls].z_block = 1 << best.zb;
         res->best_ms[cls] = best_ms;
         res->default_ms[cls] = def_ms;
     }
@@ -368,6 +397,10 @@ int dht_hop_config_set(dht_ctx* c, int prec, int nrhs, int epilogue, const dht_h
     h.nt = cfg->streaming_stores;
     h.tc = hop_form_tmarch(cfg->form) ? cfg->t_chunk : 0;
     h.rg = cfg->rhs_group == nrhs ? 0 : cfg->rhs_group;
+    if (cfg->z_block < 0 || (cfg->z_block & (cfg->z_block - 1)))
+        return set_error(DHT_ERR_INVALID_ARG, "z block must be 0 or a power of two");
+    h.zb = 0;
+    while ((2 << h.zb) <= cfg->z_block) h.zb++;
     DHT_TRY(hop_config_check(c, nrhs, h));
     c->hop_cfg[prec][b][epilogue] = h;
     return DHT_OK;
@@ -383,6 +416,7 @@ int dht_hop_config_get(dht_ctx* c, int prec, int nrhs, int epilogue, dht_hop_con
     out->streaming_stores = h.nt;
     out->t_chunk = hop_form_tmarch(h.form) ? h.tc : 0;
     out->rhs_group = h.rg > 0 ? h.rg : nrhs;
+    out->z_block = 1 << h.zb;
     return DHT_OK;
 }
 
@@ -410,21 +444,24 @@ int dht_autotune(dht_ctx* c, int prec, int nrhs, int reps, const char* cache_pat
     if (!c || !out) return set_error(DHT_ERR_INVALID_ARG, "null argument");
     if (prec < DHT_FP64 || prec > DHT_BF16) return set_error(DHT_ERR_INVALID_ARG, "bad precision");
     if (log2_pow2(nrhs) < 0) return set_error(DHT_ERR_INVALID_ARG, "batch must be a power of two <= 256");
-    // cache lines: "hop Lx Ly Lz Lt prec nrhs class form streaming_stores t_chunk rhs_group ms"
+    // cache lines: "hop2 Lx Ly Lz Lt prec nrhs class form streaming_stores t_chunk rhs_group z_block ms"
+    // (lines of any other form are skipped)
     if (cache_path) {
         FILE* f = fopen(cache_path, "r");
         if (f) {
             dht_hop_config found[HOP_NCLASS];
             double ms[HOP_NCLASS] = {0, 0, 0};
             bool have[HOP_NCLASS] = {false, false, false};
-            char tag[8];
-            int L[4], p, n, cls, form, nt, tc, rg;
+            char line[512], tag[8];
+            int L[4], p, n, cls, form, nt, tc, rg, zb;
             double t;
-            while (fscanf(f, "%7s %d %d %d %d %d %d %d %d %d %d %d %lf", tag, &L[0], &L[1], &L[2], &L[3], &p, &n, &cls,
-                          &form, &nt, &tc, &rg, &t) == 13) {
-                if (strcmp(tag, "hop") != 0 || p != prec || n != nrhs || cls < 0 || cls >= HOP_NCLASS) continue;
+            while (fgets(line, sizeof(line), f)) {
+                if (sscanf(line, "%7s %d %d %d %d %d %d %d %d %d %d %d %d %lf", tag, &L[0], &L[1], &L[2], &L[3], &p, &n,
+                           &cls, &form, &nt, &tc, &rg, &zb, &t) != 14)
+                    continue;
+                if (strcmp(tag, "hop2") != 0 || p != prec || n != nrhs || cls < 0 || cls >= HOP_NCLASS) continue;
                 if (L[0] != c->g.L[0] || L[1] != c->g.L[1] || L[2] != c->g.L[2] || L[3] != c->g.L[3]) continue;
-                found[cls] = dht_hop_config{form, nt, tc, rg};
+                found[cls] = dht_hop_config{form, nt, tc, rg, zb};
                 ms[cls] = t;
                 have[cls] = true;
             }
@@ -448,9 +485,9 @@ int dht_autotune(dht_ctx* c, int prec, int nrhs, int reps, const char* cache_pat
         FILE* f = fopen(cache_path, "a");
         if (!f) return set_error(DHT_ERR_INVALID_ARG, std::string("cannot write ") + cache_path);
         for (int cls = 0; cls < HOP_NCLASS; cls++)
-            fprintf(f, "hop %d %d %d %d %d %d %d %d %d %d %d %.6g\n", c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3],
+            fprintf(f, "hop2 %d %d %d %d %d %d %d %d %d %d %d %d %.6g\n", c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3],
                     prec, nrhs, cls, out->best[cls].form, out->best[cls].streaming_stores, out->best[cls].t_chunk,
-                    out->best[cls].rhs_group, out->best_ms[cls]);
+                    out->best[cls].rhs_group, out->best[cls].z_block, out->best_ms[cls]);
         if (fclose(f) != 0) return set_error(DHT_ERR_INVALID_ARG, std::string("cannot write ") + cache_path);
     }
     return DHT_OK;

@@ -3,7 +3,8 @@ autotuner that chooses among them.
 
 The forms (one lane per site with links per lane, staged in LDS or shared
 across the 16-lane row of a site; one lane per (x, y, z) column walking t in
-chunks, with links per lane or row-shared, with or without streaming stores,
+chunks, plain or skewed by one slice, rows in y-fastest order or in z blocks,
+with links per lane or row-shared, with or without streaming stores,
 sweeping the lattice once for all right-hand sides or once per group of them)
 accumulate the same 8 neighbour terms in different orders, so each must match
 the dense Wilson matrix to the storage precision: FP64 1e-13 relative
@@ -41,14 +42,28 @@ def forms(L, nrhs, rowl=True):
             out.append({"form": 0, "streaming_stores": nt, "t_chunk": 0, "rhs_group": G})
             if G >= 8:
                 out.append({"form": 1, "streaming_stores": nt, "t_chunk": 0, "rhs_group": G})
-            for tc in range(2, L[3] + 1, 2):
-                if L[3] % tc == 0:
-                    out.append({"form": 2, "streaming_stores": nt, "t_chunk": tc, "rhs_group": G})
-            if G >= 16 and rowl:   # links shared across the 16-lane row of a site (BF16; plain forms otherwise)
-                out.append({"form": 3, "streaming_stores": nt, "t_chunk": 0, "rhs_group": G})
+            for form in (2, 5):   # t-marching, plain and skewed
                 for tc in range(2, L[3] + 1, 2):
                     if L[3] % tc == 0:
-                        out.append({"form": 4, "streaming_stores": nt, "t_chunk": tc, "rhs_group": G})
+                        out.append({"form": form, "streaming_stores": nt, "t_chunk": tc, "rhs_group": G})
+            if G >= 16 and rowl:   # links shared across the 16-lane row of a site (BF16; plain forms otherwise)
+                out.append({"form": 3, "streaming_stores": nt, "t_chunk": 0, "rhs_group": G})
+                for form in (4, 6):
+                    for tc in range(2, L[3] + 1, 2):
+                        if L[3] % tc == 0:
+                            out.append({"form": form, "streaming_stores": nt, "t_chunk": tc, "rhs_group": G})
+    return out
+
+
+def zforms(L, nrhs, rowl=True):
+    """The t-marching forms with their rows walked in z blocks (z_block = 2, 4
+    where they divide Lz), at the shortest chunk and streaming stores on."""
+    out = []
+    tc = min(tc for tc in range(2, L[3] + 1, 2) if L[3] % tc == 0)
+    for form in ((2, 5, 4, 6) if nrhs >= 16 and rowl else (2, 5)):
+        for zb in (2, 4):
+            if L[2] % zb == 0:
+                out.append({"form": form, "streaming_stores": 1, "t_chunk": tc, "rhs_group": nrhs, "z_block": zb})
     return out
 
 
@@ -76,13 +91,13 @@ def test_every_form_matches_dense(L, nrhs):
     Dabs = {Lb.OP_D: np.abs(D), Lb.OP_DDAG: np.abs(D.conj().T), Lb.OP_Q: np.abs(D)}
     Xabs = np.abs(Xv)
     for prec in (0, 1, 2):
-        for cfg in forms(L, nrhs):
+        for cfg in forms(L, nrhs) + zforms(L, nrhs):
             ctx.set_hop_config(prec, nrhs, cfg)     # both epilogue classes
             for cls in Lb.HOP_CLASSES:
                 got = ctx.hop_config(prec, nrhs, cls)
                 assert got["form"] == cfg["form"] and got["streaming_stores"] == cfg["streaming_stores"]
-                assert got["rhs_group"] == cfg["rhs_group"]
-                if cfg["form"] in (2, 4):
+                assert got["rhs_group"] == cfg["rhs_group"] and got["z_block"] == max(1, cfg.get("z_block", 0))
+                if cfg["form"] in (2, 4, 5, 6):
                     assert got["t_chunk"] == cfg["t_chunk"]
             for op, ref in refs.items():
                 Y = ctx.apply(cuda(X), op, prec).cpu().numpy().reshape(nrhs, -1)
@@ -97,7 +112,11 @@ def test_every_form_matches_dense(L, nrhs):
                                  {"form": 2, "streaming_stores": 1, "t_chunk": 2},
                                  {"form": 2, "streaming_stores": 0, "t_chunk": 4},
                                  {"form": 0, "streaming_stores": 1, "t_chunk": 0, "rhs_group": 2},
-                                 {"form": 2, "streaming_stores": 1, "t_chunk": 2, "rhs_group": 4}])
+                                 {"form": 2, "streaming_stores": 1, "t_chunk": 2, "rhs_group": 4},
+                                 {"form": 5, "streaming_stores": 1, "t_chunk": 2},
+                                 {"form": 5, "streaming_stores": 0, "t_chunk": 4, "rhs_group": 4},
+                                 {"form": 2, "streaming_stores": 1, "t_chunk": 2, "z_block": 4},
+                                 {"form": 5, "streaming_stores": 1, "t_chunk": 4, "z_block": 2}])
 def test_solves_in_every_form(cfg):
     """BiCGStab (FP64, and FP32 inside FP64 defect correction) with the fused
     hop+dot kernels in one forced shape, against the LU inverse."""
@@ -139,6 +158,12 @@ def test_invalid_shapes_rejected():
         ctx.set_hop_config(1, 16, {"form": 0, "rhs_group": 32})        # group larger than the batch
     with pytest.raises(Lb.DhtError):
         ctx.set_hop_config(1, 16, {"form": 1, "rhs_group": 4})         # LDS links need >= 8 RHS per sweep
+    with pytest.raises(Lb.DhtError):
+        ctx.set_hop_config(1, 16, {"form": 2, "t_chunk": 2, "z_block": 3})   # z block not a power of two
+    with pytest.raises(Lb.DhtError):
+        ctx.set_hop_config(1, 16, {"form": 5, "t_chunk": 2, "z_block": 8})   # 8 does not divide Lz = 4
+    with pytest.raises(Lb.DhtError):
+        ctx.set_hop_config(1, 16, {"form": 0, "z_block": 2})                 # z blocks only in the t-marching forms
     with pytest.raises(Lb.DhtError):
         ctx.autotune_hop(1, 16, 2)                                       # no gauge field yet
     ctx.close()

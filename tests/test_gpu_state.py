@@ -74,12 +74,15 @@ def test_autotune_cache_file(tmp_path):
     w = WORKLOADS["c2"]
     U = gauge_links(w.L, w.eps, w.seed)
     cache = str(tmp_path / "tune.txt")
+    # a line in the layout without z blocks is skipped, not installed
+    with open(cache, "w") as f:
+        f.write("hop %d %d %d %d 2 16 0 0 1 0 16 0.1\n" % tuple(w.L))
     a = _ctx(w, U)
     r1 = a.autotune(Lb.BF16, 16, reps=2, cache_path=cache)
     assert r1["candidates"] > 0
     a.close()
     lines = open(cache).read().split("\n")
-    assert sum(1 for x in lines if x.startswith("hop ")) == len(Lb.HOP_CLASSES)
+    assert sum(1 for x in lines if x.startswith("hop2 ")) == len(Lb.HOP_CLASSES)
     b = _ctx(w, U)
     r2 = b.autotune(Lb.BF16, 16, reps=2, cache_path=cache)
     assert r2["candidates"] == 0 and r2["best"] == r1["best"]
@@ -87,5 +90,5 @@ def test_autotune_cache_file(tmp_path):
         assert b.hop_config(Lb.BF16, 16, cls) == r1["best"][name]
     r3 = b.autotune(Lb.FP32, 16, reps=2, cache_path=cache)     # not cached yet: tuned and appended
     assert r3["candidates"] > 0
-    assert sum(1 for x in open(cache).read().split("\n") if x.startswith("hop ")) == 2 * len(Lb.HOP_CLASSES)
+    assert sum(1 for x in open(cache).read().split("\n") if x.startswith("hop2 ")) == 2 * len(Lb.HOP_CLASSES)
     b.close()
