@@ -159,7 +159,7 @@ __device__ inline void mul_link(const Cx<T>* u, const Cx<T>* h, Cx<T>* w) {
 // straight from the packed link entry and the packed pair, so neither operand
 // is unpacked and each pair of products costs one instruction (the products of
 // two BF16 values are exact in FP32).  The pairs are signed selections of the
-// stored (vr, vi) of v with x = i^K v: one half swap and one sign-bit xor at
+// stored (vr, vi) of v with x = i^K v: one half swap and per-half signs at
 // most, fixed at compile time.
 //   Re(U x) = Ur xr - Ui xi -> (xr, -xi)      Im(U x) = Ur xi + Ui xr -> (xi, xr)
 //   Re(U* x) = Ur xr + Ui xi -> (xr, xi)      Im(U* x) = Ur xi - Ui xr -> (xi, -xr)
@@ -178,25 +178,42 @@ struct PairForm {
     static constexpr bool swap = lo_sel == 1;
     static constexpr uint32_t mask = (lo_sgn < 0 ? 0x8000u : 0u) | (hi_sgn < 0 ? 0x80000000u : 0u);
 };
-// acc + Lr a + Li b for the pair (a, b) of PairForm, built from v and its half
-// swap vs (the sign bits by xor).  A chain that starts at zero uses the VOP3
-// form with the inline constant 0 as its accumulator (the compiler's VOP2
-// v_dot2c form accumulates into its destination, which then needs a zeroing
-// move per chain).
-template <bool ADJ, bool IMPART, int K, bool FIRST>
+// acc + Lr a + Li b for the pair (a, b) of PairForm, built from v or its half
+// swap vs; the signs are the instruction's per-half negation modifiers on the
+// operand (neg_lo / neg_hi), so a sign flip costs no instruction.  Every link
+// product is one chain of these instructions, written here as inline asm (the
+// compiler folds no negation into the BF16 dot2 and emits its own
+// accumulate-in-place v_dot2c form otherwise): a chain starts from the inline
+// constant 0, passes its partial sum from one instruction to the next as the
+// accumulator (same opcode, accumulator operand: forwarded without wait
+// states), and its last instruction is followed by s_nop 2, the three wait
+// states that a dot2 result needs before any other vector instruction may
+// read it (the compiler cannot see that an asm block holds a dot2, so it does
+// not insert them; a dot2c of its own reading an asm result read stale values).
+#define DHT_DOT2(MODS)                                                                                  \
+    if constexpr (FIRST) asm("v_dot2_f32_bf16 %0, %1, %2, 0" MODS : "=v"(d) : "v"(l), "v"(x));       \
+    else if constexpr (LAST)                                                                         \
+        asm("v_dot2_f32_bf16 %0, %1, %2, %3" MODS "\n\ts_nop 2" : "=v"(d) : "v"(l), "v"(x), "v"(acc)); \
+    else asm("v_dot2_f32_bf16 %0, %1, %2, %3" MODS : "=v"(d) : "v"(l), "v"(x), "v"(acc));
+template <bool ADJ, bool IMPART, int K, bool FIRST, bool LAST = false>
 __device__ inline float dot2_form(uint32_t l, uint32_t v, uint32_t vs, float acc) {
     typedef PairForm<ADJ, IMPART, K> F;
-    uint32_t x = F::swap ? vs : v;
-    if constexpr (F::mask != 0u) x ^= F::mask;
-    if constexpr (FIRST) {
-        float d;
-        asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(d) : "v"(l), "v"(x));
-        return d;
+    static_assert(!(FIRST && LAST), "a chain has more than one product");
+    const uint32_t x = F::swap ? vs : v;
+    constexpr bool nlo = (F::mask & 0x8000u) != 0u, nhi = (F::mask & 0x80000000u) != 0u;
+    float d;
+    if constexpr (nlo && nhi) {
+        DHT_DOT2(" neg_lo:[0,1,0] neg_hi:[0,1,0]")
+    } else if constexpr (nlo) {
+        DHT_DOT2(" neg_lo:[0,1,0]")
+    } else if constexpr (nhi) {
+        DHT_DOT2(" neg_hi:[0,1,0]")
     } else {
-        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_vec_t, l), __builtin_bit_cast(bf16x2_vec_t, x),
-                                               acc, false);
+        DHT_DOT2("")
     }
+    return d;
 }
+#undef DHT_DOT2
 __device__ inline uint32_t half_swap(uint32_t v) { return (v >> 16) | (v << 16); }
 
 // The projected half spinor of (1 - SGN g_mu) is h_sp = u_sp + i^K_sp l_(pi_sp)
@@ -229,13 +246,14 @@ __device__ inline void link_mult_spin(const uint32_t* p, const uint32_t* u, Cx<f
         im = dot2_form<ADJ, true, 0, true>(DHT_L(0), p[3 * SP], us[0], 0.f);
         re = dot2_form<ADJ, false, K, false>(DHT_L(0), p[3 * LO], ls[0], re);
         im = dot2_form<ADJ, true, K, false>(DHT_L(0), p[3 * LO], ls[0], im);
-#pragma unroll
-        for (int b = 1; b < 3; b++) {
-            re = dot2_form<ADJ, false, 0, false>(DHT_L(b), p[3 * SP + b], us[b], re);
-            im = dot2_form<ADJ, true, 0, false>(DHT_L(b), p[3 * SP + b], us[b], im);
-            re = dot2_form<ADJ, false, K, false>(DHT_L(b), p[3 * LO + b], ls[b], re);
-            im = dot2_form<ADJ, true, K, false>(DHT_L(b), p[3 * LO + b], ls[b], im);
-        }
+        re = dot2_form<ADJ, false, 0, false>(DHT_L(1), p[3 * SP + 1], us[1], re);
+        im = dot2_form<ADJ, true, 0, false>(DHT_L(1), p[3 * SP + 1], us[1], im);
+        re = dot2_form<ADJ, false, K, false>(DHT_L(1), p[3 * LO + 1], ls[1], re);
+        im = dot2_form<ADJ, true, K, false>(DHT_L(1), p[3 * LO + 1], ls[1], im);
+        re = dot2_form<ADJ, false, 0, false>(DHT_L(2), p[3 * SP + 2], us[2], re);
+        im = dot2_form<ADJ, true, 0, false>(DHT_L(2), p[3 * SP + 2], us[2], im);
+        re = dot2_form<ADJ, false, K, false, true>(DHT_L(2), p[3 * LO + 2], ls[2], re);
+        im = dot2_form<ADJ, true, K, false, true>(DHT_L(2), p[3 * LO + 2], ls[2], im);
 #undef DHT_L
         w[a] = cmake(re, im);
     }
@@ -300,7 +318,9 @@ __device__ inline void row_links_load(const void* U, int Vh, int p, int s, int s
 template <int D, int K>
 __device__ inline uint32_t row_link_word(const RowLinks& rl) {   // word K of slot D, from its owner lane
     constexpr int lane = 2 * D + (K < 6 ? 0 : 1), slot = K < 6 ? K : K - 6;
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)rl.w[slot], 0x150 + lane, 0xf, 0xf, false);
+    // every lane of the row reads an active lane of its row, so the old value
+    // is never used (bound_ctrl set: no move to initialise it)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)rl.w[slot], 0x150 + lane, 0xf, 0xf, true);
 }
 template <int D>
 __device__ inline void row_link_get(const RowLinks& rl, uint32_t* u) {
