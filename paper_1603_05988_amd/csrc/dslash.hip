@@ -457,75 +457,116 @@ __device__ inline int xcd_remap(int bid, int nblocks) {
 // t-marching default: halve the chunk while the grid holds fewer lanes than this
 static constexpr int64_t HOP_MIN_LANES = 1 << 20;
 
+// components NG c .. NG c + NG - 1 (NG a multiple of 4) of an operand of
+// (site, rhs) at vector v0, stored in S or, with B16, held in BF16 (4
+// components per vector) and widened exactly; NT: non-temporal loads
+template <typename S, int NG, bool B16, bool NT>
+__device__ inline void load_operand_group(const void* base, int64_t v0, int64_t vstride, int c,
+                                          Cx<typename Store<S>::acc>* p) {
+    typedef typename Store<S>::acc T;
+    if constexpr (B16 && !std::is_same<S, bf16x2>::value) {
+#pragma unroll
+        for (int g = 0; g < NG / 4; g++) {
+            Cx<float> q[4];
+            const int64_t v = v0 + (c * (NG / 4) + g) * vstride;
+            if (NT) Store<bf16x2>::ldv_nt(base, v, q);
+            else Store<bf16x2>::ldv(base, v, q);
+#pragma unroll
+            for (int i = 0; i < 4; i++) p[4 * g + i] = cmake<T>((T)q[i].re, (T)q[i].im);
+        }
+    } else {
+        constexpr int VW = Store<S>::VW, NV = NG / VW;
+#pragma unroll
+        for (int j = 0; j < NV; j++) {
+            const int64_t v = v0 + (c * NV + j) * vstride;
+            if (NT) Store<S>::ldv_nt(base, v, p + j * VW);
+            else Store<S>::ldv(base, v, p + j * VW);
+        }
+    }
+}
+
 // out = cb * acc + ca * x (g5 applied on request), stored; the fused dot
-// products use the stored (rounded) values, so they match a separate pass
+// products use the stored (rounded) values, so they match a separate pass.
+// BF16 hops take the 12 components in three groups of 4 (one vector each),
+// holding only a group of each operand at a time, which keeps the BF16
+// t-marching (a, out) form at 4 waves per SIMD; FP32 / FP64 hops, with one or
+// two waves per SIMD, load all 12 at once to overlap the loads.  The sums keep
+// the order of a one-component loop.
 template <typename S, bool G5OUT, bool XPAY, int DOT, int MIX>
 __device__ inline void hop_epilogue(const HopArgs& a, int s, int r, Cx<typename Store<S>::acc>* acc, Cx<double>& d0,
                                     Cx<double>& d1) {
     typedef typename Store<S>::acc T;
     constexpr int VW = Store<S>::VW;
+    constexpr int NG = std::is_same<S, bf16x2>::value ? 4 : 12;   // components per group
     const int64_t vstride = (int64_t)a.Vh << a.bshift;
     const int64_t v0 = ((int64_t)s << a.bshift) + r;
     const T cb = (T)a.cb, ca = (T)a.ca;
     fence_acc(acc);   // the epilogue's operand loads stay below the stencil arithmetic
-    Cx<T> xv[12];
-    if (XPAY) load_operand<S, (MIX & HOP_X16) != 0, true>(a.x, v0, vstride, xv);
 #pragma unroll
-    for (int i = 0; i < 12; i++) {
-        Cx<T> v = cb * acc[i];
-        if (XPAY) v = v + ca * xv[i];
-        acc[i] = v;
-    }
-    Cx<T> zv[12];
-    if (XPAY && a.z) {   // out += cz * z (residuals z - D x in one pass)
-        const T cz = (T)a.cz;
-        load_operand<S, (MIX & HOP_Z16) != 0, true>(a.z, v0, vstride, zv);
+    for (int c = 0; c < 12 / NG; c++) {
+        Cx<T>* o = acc + NG * c;
+        Cx<T> xv[NG], zv[NG];
+        if (XPAY) load_operand_group<S, NG, (MIX & HOP_X16) != 0, true>(a.x, v0, vstride, c, xv);
 #pragma unroll
-        for (int i = 0; i < 12; i++) acc[i] = acc[i] + cz * zv[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 12; i++)
-        if (G5OUT && i >= 6) acc[i] = neg(acc[i]);
-    if constexpr ((MIX & HOP_OUT16) != 0) {
-        const double sc = a.s16[r];
-        Cx<float> o16[12];
-#pragma unroll
-        for (int i = 0; i < 12; i++) o16[i] = cmake<float>((float)(sc * acc[i].re), (float)(sc * acc[i].im));
-#pragma unroll
-        for (int j = 0; j < 3; j++) Store<bf16x2>::stv(a.out16, v0 + j * vstride, o16 + 4 * j);
-    }
-    if constexpr ((MIX & HOP_NOOUT) == 0) {   // else only the epilogue sums are wanted
-#pragma unroll
-        for (int j = 0; j < 12 / VW; j++) {
-            if (a.nt) Store<S>::stv_nt(a.out, v0 + j * vstride, acc + j * VW);
-            else Store<S>::stv(a.out, v0 + j * vstride, acc + j * VW);
+        for (int q = 0; q < NG; q++) {
+            Cx<T> v = cb * o[q];
+            if (XPAY) v = v + ca * xv[q];
+            o[q] = v;
         }
-    }
-    if (DOT != HOPDOT_NONE) {
-        Cx<T> ov[12];
+        if (XPAY && a.z) {   // out += cz * z (residuals z - D x in one pass)
+            const T cz = (T)a.cz;
+            load_operand_group<S, NG, (MIX & HOP_Z16) != 0, true>(a.z, v0, vstride, c, zv);
 #pragma unroll
-        for (int i = 0; i < 12; i++) ov[i] = Store<S>::round(acc[i]);
-        if (DOT == HOPDOT_A_OUT) {
-            Cx<T> av[12];
-            load_spinor_nt<S>(a.da, v0, vstride, av);
+            for (int q = 0; q < NG; q++) o[q] = o[q] + cz * zv[q];
+        }
 #pragma unroll
-            for (int i = 0; i < 12; i++)
-                d0 = d0 + conjmul(cmake<double>(av[i].re, av[i].im), cmake<double>(ov[i].re, ov[i].im));
-        } else if (DOT == HOPDOT_NORM) {
+        for (int q = 0; q < NG; q++)
+            if (G5OUT && NG * c + q >= 6) o[q] = neg(o[q]);
+        if constexpr ((MIX & HOP_OUT16) != 0) {
+            const double sc = a.s16[r];
 #pragma unroll
-            for (int i = 0; i < 12; i++) d0.re += (double)ov[i].re * ov[i].re + (double)ov[i].im * ov[i].im;
-        } else if (DOT == HOPDOT_NORM_ZX) {
+            for (int g = 0; g < NG / 4; g++) {
+                Cx<float> o16[4];
 #pragma unroll
-            for (int i = 0; i < 12; i++) {
-                d0.re += (double)ov[i].re * ov[i].re + (double)ov[i].im * ov[i].im;
-                d1 = d1 + conjmul(cmake<double>(zv[i].re, zv[i].im), cmake<double>(xv[i].re, xv[i].im));
+                for (int q = 0; q < 4; q++)
+                    o16[q] = cmake<float>((float)(sc * o[4 * g + q].re), (float)(sc * o[4 * g + q].im));
+                Store<bf16x2>::stv(a.out16, v0 + (c * (NG / 4) + g) * vstride, o16);
             }
-        } else {
+        }
+        if constexpr ((MIX & HOP_NOOUT) == 0) {   // else only the epilogue sums are wanted
 #pragma unroll
-            for (int i = 0; i < 12; i++) {
-                Cx<double> o = cmake<double>(ov[i].re, ov[i].im);
-                d0 = d0 + conjmul(o, cmake<double>(xv[i].re, xv[i].im));
-                d1.re += o.re * o.re + o.im * o.im;
+            for (int j = 0; j < NG / VW; j++) {
+                const int64_t v = v0 + (c * (NG / VW) + j) * vstride;
+                if (a.nt) Store<S>::stv_nt(a.out, v, o + j * VW);
+                else Store<S>::stv(a.out, v, o + j * VW);
+            }
+        }
+        if (DOT != HOPDOT_NONE) {
+            Cx<T> ov[NG];
+#pragma unroll
+            for (int q = 0; q < NG; q++) ov[q] = Store<S>::round(o[q]);
+            if (DOT == HOPDOT_A_OUT) {
+                Cx<T> av[NG];
+                load_operand_group<S, NG, false, true>(a.da, v0, vstride, c, av);
+#pragma unroll
+                for (int q = 0; q < NG; q++)
+                    d0 = d0 + conjmul(cmake<double>(av[q].re, av[q].im), cmake<double>(ov[q].re, ov[q].im));
+            } else if (DOT == HOPDOT_NORM) {
+#pragma unroll
+                for (int q = 0; q < NG; q++) d0.re += (double)ov[q].re * ov[q].re + (double)ov[q].im * ov[q].im;
+            } else if (DOT == HOPDOT_NORM_ZX) {
+#pragma unroll
+                for (int q = 0; q < NG; q++) {
+                    d0.re += (double)ov[q].re * ov[q].re + (double)ov[q].im * ov[q].im;
+                    d1 = d1 + conjmul(cmake<double>(zv[q].re, zv[q].im), cmake<double>(xv[q].re, xv[q].im));
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < NG; q++) {
+                    Cx<double> oo = cmake<double>(ov[q].re, ov[q].im);
+                    d0 = d0 + conjmul(oo, cmake<double>(xv[q].re, xv[q].im));
+                    d1.re += oo.re * oo.re + oo.im * oo.im;
+                }
             }
         }
     }
@@ -750,8 +791,17 @@ __device__ inline void tm_step(const HopArgs& a, int t, int t1, int s3, int xh, 
     fence_acc(acc);   // the next step's loads stay below this step's arithmetic
 }
 
+// BF16 with no fused sums or the single (a, out) sum: held to 128 registers,
+// i.e. 4 waves per SIMD (the (a, out) row-link form needs 129 otherwise;
+// neither then spills); the two-sum forms would spill and keep 2-3 waves
+template <typename S, int DOT>
+constexpr int tm_min_waves() {
+    return (std::is_same<S, bf16x2>::value && (DOT == HOPDOT_NONE || DOT == HOPDOT_A_OUT)) ? 4 : 1;
+}
+
 template <typename S, bool DAG, bool G5OUT, bool XPAY, int DOT, int MIX, bool ROWL = false>
-__global__ __launch_bounds__(HOP_THREADS) void hop_tm_kernel(HopArgs a) {
+__global__ __launch_bounds__(HOP_THREADS) __attribute__((amdgpu_waves_per_eu(tm_min_waves<S, DOT>(), 8)))
+void hop_tm_kernel(HopArgs a) {
     typedef typename Store<S>::acc T;
     extern __shared__ uint4 hop_lds[];   // [2][6][HOP_THREADS] Cx<T>
     constexpr int NP = (DOT == HOPDOT_A_OUT || DOT == HOPDOT_NORM) ? 1 : ((DOT == HOPDOT_OUT_X || DOT == HOPDOT_NORM_ZX) ? 2 : 0);
