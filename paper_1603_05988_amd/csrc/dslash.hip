@@ -178,42 +178,66 @@ struct PairForm {
     static constexpr bool swap = lo_sel == 1;
     static constexpr uint32_t mask = (lo_sgn < 0 ? 0x8000u : 0u) | (hi_sgn < 0 ? 0x80000000u : 0u);
 };
-// acc + Lr a + Li b for the pair (a, b) of PairForm, built from v or its half
-// swap vs; the signs are the instruction's per-half negation modifiers on the
-// operand (neg_lo / neg_hi), so a sign flip costs no instruction.  Every link
-// product is one chain of these instructions, written here as inline asm (the
-// compiler folds no negation into the BF16 dot2 and emits its own
-// accumulate-in-place v_dot2c form otherwise): a chain starts from the inline
-// constant 0, passes its partial sum from one instruction to the next as the
-// accumulator (same opcode, accumulator operand: forwarded without wait
-// states), and its last instruction is followed by s_nop 2, the three wait
-// states that a dot2 result needs before any other vector instruction may
-// read it (the compiler cannot see that an asm block holds a dot2, so it does
-// not insert them; a dot2c of its own reading an asm result read stale values).
-#define DHT_DOT2(MODS)                                                                                  \
-    if constexpr (FIRST) asm("v_dot2_f32_bf16 %0, %1, %2, 0" MODS : "=v"(d) : "v"(l), "v"(x));       \
-    else if constexpr (LAST)                                                                         \
-        asm("v_dot2_f32_bf16 %0, %1, %2, %3" MODS "\n\ts_nop 2" : "=v"(d) : "v"(l), "v"(x), "v"(acc)); \
-    else asm("v_dot2_f32_bf16 %0, %1, %2, %3" MODS : "=v"(d) : "v"(l), "v"(x), "v"(acc));
-template <bool ADJ, bool IMPART, int K, bool FIRST, bool LAST = false>
-__device__ inline float dot2_form(uint32_t l, uint32_t v, uint32_t vs, float acc) {
-    typedef PairForm<ADJ, IMPART, K> F;
-    static_assert(!(FIRST && LAST), "a chain has more than one product");
-    const uint32_t x = F::swap ? vs : v;
-    constexpr bool nlo = (F::mask & 0x8000u) != 0u, nhi = (F::mask & 0x80000000u) != 0u;
+// One chain: sum over b = 0..2 of Lr a + Li b for the pairs (a, b) of the
+// upper-spin operand u_b (form UF, K = 0) and of the lower-spin operand w_b
+// (form WF), Re or Im per IMPART, in FP32 from the packed BF16 words.  The
+// signs of a pair are the instruction's per-half negation modifiers on the
+// operand (neg_lo / neg_hi), so a sign flip costs no instruction (the
+// compiler folds no negation into the BF16 dot2 itself).  The six products
+// are one asm block: the chain starts from the inline constant 0 and keeps
+// its partial sum in the block's own output register, passed from one dot2
+// to the next as the accumulator (same opcode, accumulator operand: forwarded
+// without wait states), and the block ends with s_nop 2, the three wait
+// states a dot2 result needs before another vector instruction may read or
+// overwrite its register.  The compiler sees neither the dot2s nor that
+// rule, so it must not place its own instructions between them: with the
+// products as separate statements, a compiler v_dot2c reading an asm dot2
+// result one or two cycles later read a stale value.
+#define DHT_MOD0 ""
+#define DHT_MOD1 " neg_lo:[0,1,0]"
+#define DHT_MOD2 " neg_hi:[0,1,0]"
+#define DHT_MOD3 " neg_lo:[0,1,0] neg_hi:[0,1,0]"
+#define DHT_CHAIN(MU_, MW_)                                                                          \
+    asm("v_dot2_f32_bf16 %0, %1, %4, 0" MU_ "\n\t"                                                   \
+        "v_dot2_f32_bf16 %0, %1, %7, %0" MW_ "\n\t"                                                  \
+        "v_dot2_f32_bf16 %0, %2, %5, %0" MU_ "\n\t"                                                  \
+        "v_dot2_f32_bf16 %0, %2, %8, %0" MW_ "\n\t"                                                  \
+        "v_dot2_f32_bf16 %0, %3, %6, %0" MU_ "\n\t"                                                  \
+        "v_dot2_f32_bf16 %0, %3, %9, %0" MW_ "\n\t"                                                  \
+        "s_nop 2"                                                                                    \
+        : "=&v"(d)                                                                                   \
+        : "v"(l0), "v"(l1), "v"(l2), "v"(u0), "v"(u1), "v"(u2), "v"(w0), "v"(w1), "v"(w2))
+#define DHT_CHAIN_W(MU_)                                                                             \
+    if constexpr (MW == 0) DHT_CHAIN(MU_, DHT_MOD0);                                                 \
+    else if constexpr (MW == 1) DHT_CHAIN(MU_, DHT_MOD1);                                            \
+    else if constexpr (MW == 2) DHT_CHAIN(MU_, DHT_MOD2);                                            \
+    else DHT_CHAIN(MU_, DHT_MOD3);
+template <int MUM, int MW>
+__device__ inline float dot2_chain(uint32_t l0, uint32_t l1, uint32_t l2, uint32_t u0, uint32_t u1, uint32_t u2,
+                                   uint32_t w0, uint32_t w1, uint32_t w2) {
     float d;
-    if constexpr (nlo && nhi) {
-        DHT_DOT2(" neg_lo:[0,1,0] neg_hi:[0,1,0]")
-    } else if constexpr (nlo) {
-        DHT_DOT2(" neg_lo:[0,1,0]")
-    } else if constexpr (nhi) {
-        DHT_DOT2(" neg_hi:[0,1,0]")
+    if constexpr (MUM == 0) {
+        DHT_CHAIN_W(DHT_MOD0)
+    } else if constexpr (MUM == 1) {
+        DHT_CHAIN_W(DHT_MOD1)
+    } else if constexpr (MUM == 2) {
+        DHT_CHAIN_W(DHT_MOD2)
     } else {
-        DHT_DOT2("")
+        DHT_CHAIN_W(DHT_MOD3)
     }
     return d;
 }
-#undef DHT_DOT2
+#undef DHT_CHAIN_W
+#undef DHT_CHAIN
+#undef DHT_MOD0
+#undef DHT_MOD1
+#undef DHT_MOD2
+#undef DHT_MOD3
+// the negation modifiers of a pair form: bit 0 neg_lo, bit 1 neg_hi
+template <bool ADJ, bool IMPART, int K>
+constexpr int pair_mods() {
+    return ((PairForm<ADJ, IMPART, K>::mask & 0x8000u) ? 1 : 0) | ((PairForm<ADJ, IMPART, K>::mask & 0x80000000u) ? 2 : 0);
+}
 __device__ inline uint32_t half_swap(uint32_t v) { return (v >> 16) | (v << 16); }
 
 // The projected half spinor of (1 - SGN g_mu) is h_sp = u_sp + i^K_sp l_(pi_sp)
@@ -238,25 +262,26 @@ __device__ inline void link_mult_spin(const uint32_t* p, const uint32_t* u, Cx<f
         us[b] = half_swap(p[3 * SP + b]);
         ls[b] = half_swap(p[3 * LO + b]);
     }
+    typedef PairForm<ADJ, false, 0> UR;
+    typedef PairForm<ADJ, true, 0> UI;
+    typedef PairForm<ADJ, false, K> WR;
+    typedef PairForm<ADJ, true, K> WI;
+#define DHT_U(F, b) (F::swap ? us[b] : p[3 * SP + (b)])
+#define DHT_W(F, b) (F::swap ? ls[b] : p[3 * LO + (b)])
+#define DHT_L(b) (ADJ ? u[3 * (b) + a] : u[3 * a + (b)])
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        float re, im;
-#define DHT_L(b) (ADJ ? u[3 * (b) + a] : u[3 * a + (b)])
-        re = dot2_form<ADJ, false, 0, true>(DHT_L(0), p[3 * SP], us[0], 0.f);
-        im = dot2_form<ADJ, true, 0, true>(DHT_L(0), p[3 * SP], us[0], 0.f);
-        re = dot2_form<ADJ, false, K, false>(DHT_L(0), p[3 * LO], ls[0], re);
-        im = dot2_form<ADJ, true, K, false>(DHT_L(0), p[3 * LO], ls[0], im);
-        re = dot2_form<ADJ, false, 0, false>(DHT_L(1), p[3 * SP + 1], us[1], re);
-        im = dot2_form<ADJ, true, 0, false>(DHT_L(1), p[3 * SP + 1], us[1], im);
-        re = dot2_form<ADJ, false, K, false>(DHT_L(1), p[3 * LO + 1], ls[1], re);
-        im = dot2_form<ADJ, true, K, false>(DHT_L(1), p[3 * LO + 1], ls[1], im);
-        re = dot2_form<ADJ, false, 0, false>(DHT_L(2), p[3 * SP + 2], us[2], re);
-        im = dot2_form<ADJ, true, 0, false>(DHT_L(2), p[3 * SP + 2], us[2], im);
-        re = dot2_form<ADJ, false, K, false, true>(DHT_L(2), p[3 * LO + 2], ls[2], re);
-        im = dot2_form<ADJ, true, K, false, true>(DHT_L(2), p[3 * LO + 2], ls[2], im);
-#undef DHT_L
+        const float re = dot2_chain<pair_mods<ADJ, false, 0>(), pair_mods<ADJ, false, K>()>(
+            DHT_L(0), DHT_L(1), DHT_L(2), DHT_U(UR, 0), DHT_U(UR, 1), DHT_U(UR, 2), DHT_W(WR, 0), DHT_W(WR, 1),
+            DHT_W(WR, 2));
+        const float im = dot2_chain<pair_mods<ADJ, true, 0>(), pair_mods<ADJ, true, K>()>(
+            DHT_L(0), DHT_L(1), DHT_L(2), DHT_U(UI, 0), DHT_U(UI, 1), DHT_U(UI, 2), DHT_W(WI, 0), DHT_W(WI, 1),
+            DHT_W(WI, 2));
         w[a] = cmake(re, im);
     }
+#undef DHT_L
+#undef DHT_W
+#undef DHT_U
 }
 
 // w = L h of both half-spinor spins, L = U or U^H (ADJ), h of (1 - SGN g_mu),
