@@ -543,16 +543,16 @@ __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* 
     const size_t stride = (size_t)gridDim.x * RED_THREADS;
     const size_t v0 = (size_t)blockIdx.x * RED_THREADS + threadIdx.x;
     StridePos pos(v0, stride, SB);   // pos.cv = m
-    // two items per step, both loaded before either is used (sums in the
-    // order of a one-item loop)
-    for (size_t v = v0; v < nitem; v += 2 * stride) {
-        const bool two = v + stride < nitem;
-        Cx<float> wv[2][4];
-        Cx<double> ri[2][4];
-        int64_t e0[2];
+    // four items per step, all loaded before any is used (sums in the order
+    // of a one-item loop)
+    constexpr int U = 4;
+    for (size_t v = v0; v < nitem; v += U * stride) {
+        Cx<float> wv[U][4];
+        Cx<double> ri[U][4];
+        int64_t e0[U];
 #pragma unroll
-        for (int u = 0; u < 2; u++) {
-            if (u == 0 || two) {
+        for (int u = 0; u < U; u++) {
+            if (v + u * stride < nitem) {
                 const int64_t w0 = pos.cv * 2 * SB + pos.sr;
                 Store<float>::ldv(w, w0, wv[u]);
                 Store<float>::ldv(w, w0 + SB, wv[u] + 2);
@@ -563,8 +563,8 @@ __global__ __launch_bounds__(RED_THREADS) void residual_step_kernel(Cx<double>* 
             pos.next();
         }
 #pragma unroll
-        for (int u = 0; u < 2; u++)
-            if (u == 0 || two) {
+        for (int u = 0; u < U; u++)
+            if (v + u * stride < nitem) {
                 Cx<float> o16[4];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
