@@ -13,17 +13,17 @@ method reaches the tolerance.  Measured and reported, never asserted (the
 paper has no number for it: parity unpinned): the iteration gain of FGMRES +
 network over FGMRES alone, which may come out negative, and the times of all
 four solvers (one network application costs as much as tens of stencil
-applications on this lattice).  Results go to gpurun_out/nn_gain.json when
-that directory exists.
+applications on this lattice).  Results go to nn_gain.json in the directory
+DHT_REPORT_DIR names, if it is set.
 """
 import json
-import os
 import time
 
 import numpy as np
 import pytest
 
 from paper_1603_05988_amd.workloads import WORKLOADS, gauge_links
+from reports import write_report
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -89,7 +89,5 @@ def test_learned_preconditioner_gain():
            "iteration_gain_vs_fgmres": 1.0 - results["fgmres_nn"]["mean_iters"] / results["fgmres_identity"]["mean_iters"],
            "solves_16_probes": results}
     print(json.dumps(out, indent=1))
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/nn_gain.json", "w") as f:
-            json.dump(out, f, indent=1)
+    write_report("nn_gain.json", out)
     ctx.close()

@@ -12,11 +12,10 @@ space) against the oracle.
   1e-7 ||Q||^2 with Q applied by the C oracle's stencil, and sigma agrees with
   the |lambda| of the Chebyshev solver to 1e-7 (a consistency check between
   the two GPU solvers, not a pin).  Report: block iterations, applications of
-  Q and wall time of both solvers, to gpurun_out/lobpcg_c2.json when that
-  directory exists.
+  Q and wall time of both solvers, written to lobpcg_c2.json in the
+  directory that DHT_REPORT_DIR names, if it is set.
 """
 import json
-import os
 import time
 
 import numpy as np
@@ -24,6 +23,7 @@ import pytest
 
 from oracle import estimator, lattice, stencil
 from paper_1603_05988_amd.workloads import WORKLOADS, gauge_links
+from reports import write_report
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -126,7 +126,5 @@ def test_lobpcg_c2_residuals_by_c_stencil():
                          "seconds": t_cheb, "T_D": [td_c.real, td_c.imag]},
            "sigma_min": float(np.min(sig)), "sigma_k": float(np.max(sig))}
     print(json.dumps(out))
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/lobpcg_c2.json", "w") as f:
-            json.dump(out, f, indent=1)
+    write_report("lobpcg_c2.json", out)
     ctx.close()

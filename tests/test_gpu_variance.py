@@ -3,7 +3,7 @@
 (FP64 storage, Galerkin M), 40 runs (base vectors z0) of 32 hierarchical-
 probing probes each, solved in mixed precision to 1e-8, with their projection
 coefficients; 256 plain Z4 probes give the Monte Carlo variance V_stoc.
-The report (gpurun_out/variance_c2.json when that directory exists) holds
+The report (variance_c2.json in the directory DHT_REPORT_DIR names, if set) holds
 V_hp(s) with Jackknife errors and R_s at s = 1 .. 32, undeflated and
 deflated, and the playback of the deflated estimate with k = 0 .. 64.
 
@@ -13,12 +13,12 @@ deflated quadratures and T_D; with none, the undeflated ones; the deflated
 estimate equals the undeflated one within their errors (both are unbiased).
 """
 import json
-import os
 
 import numpy as np
 import pytest
 
 from paper_1603_05988_amd.workloads import WORKLOADS, gauge_links
+from reports import write_report
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -77,9 +77,7 @@ def test_variance_report_c2():
                   for a, b in zip(und, dfl)],
            "playback_s32": play}
     print(json.dumps(out)[:2000])
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/variance_c2.json", "w") as f:
-            json.dump(out, f, indent=1)
+    write_report("variance_c2.json", out)
     ctx.close()
 
 
@@ -89,7 +87,7 @@ def test_variance_report_c3():
     eigensolver (FP32 storage, Galerkin M), 40 runs of 256 hierarchical-probing
     probes, 256 plain Z4 probes for V_stoc; V_hp(s) and R_s at s = 1 .. 256,
     undeflated and deflated, and playback at s = 256 over k = 0 .. 200.  Written
-    to gpurun_out/variance_c3.json when that directory exists.  Asserted as for
+    to variance_c3.json in the directory DHT_REPORT_DIR names, if set.  Asserted as for
     8^3x16: playback with all vectors reproduces the records, with none the
     undeflated forms, and the two estimates agree within their errors.  Also
     reported: W_d of 10 sampled rows (plain, deflated, masked to 32 HP vectors,
@@ -171,7 +169,5 @@ def test_variance_report_c3():
                         "measured_var_0": v_stoc, "measured_var_k": v_stoc_defl,
                         "measured_ratio": v_stoc_defl / v_stoc}}
     print(json.dumps(out)[:2000])
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/variance_c3.json", "w") as f:
-            json.dump(out, f, indent=1)
+    write_report("variance_c3.json", out)
     ctx.close()

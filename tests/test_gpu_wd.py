@@ -11,16 +11,16 @@ sum rule, the probing mask's pattern and g5-hermiticity).
   term, to 1e-7 of the row's largest (mixed-precision solves to 1e-10).
 - report: the four profiles of the paper's figure (plain, deflated, 32 HP
   vectors, both) at 8^3 x 16 with 64 eigenvectors of Q, written to
-  gpurun_out/wd_profile_c2.json when that directory exists.
+  wd_profile_c2.json in the directory DHT_REPORT_DIR names, if it is set.
 """
 import json
-import os
 
 import numpy as np
 import pytest
 
 from oracle import estimator, lattice, stencil, theory
 from paper_1603_05988_amd.workloads import WORKLOADS, gauge_links
+from reports import write_report
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -132,9 +132,7 @@ def test_report_profiles_c2():
     out["row_norm2"] = tot
     print(json.dumps(out))
     assert tot["deflation"] < tot["monte_carlo"] and tot["hp32"] < tot["monte_carlo"]
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/wd_profile_c2.json", "w") as f:
-            json.dump(out, f, indent=1)
+    write_report("wd_profile_c2.json", out)
     ctx.close()
 
 
