@@ -14,7 +14,7 @@ performs exactly the flops of a k = 1000 eigenvector basis, and the estimator
 stays unbiased for any basis; computing 1000 eigenvectors at this size is
 setup outside the measured path.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -234,7 +234,7 @@ def main():
                     help="FGMRES restart at 32^3x64 (its FP32 bases must fit beside the 100 GB deflation basis)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); probes shard across GPUs "
+        print("bench.py: the library runs on one GPU only (--gpus %d requested); probes shard across GPUs "
               "by design, but no multi-GPU path is built" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
